@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Throughput of the D3Q27 central-moment collide-stream update on one MI355X.
+
+Workload: 256^3 periodic decaying turbulence (seeded solenoidal field with a
+k^-5/3 spectrum over k = 2..32, u_rms = 0.04 per component, rho = 1),
+nu = 1e-5, adaptive relaxation on, FP32 shifted populations.  A step is one
+fused pull-stream + collide launch over all cells.  Inputs are resident in
+HBM before the timed region starts.
+
+Prints ONE JSON line: MLUPS, the HBM roofline of the collide-stream kernel
+(algorithmic bytes per launch / average launch time from HIP events on the
+stream the kernels run on), the FP16-storage variant on the same workload,
+and the FP64 CPU oracle timed on a bounded slab of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "D3Q27 MLUPS + % HBM roofline; FP16-store and adjoint vs FP32 plain step"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_LUP = {"f32": 216, "f16s": 108}   # 27 reads + 27 writes per update
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_traffic.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1807_02284_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as fh:
+                h.update(name.encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage: str, n: int):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel sources; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    entry = rec.get(f"{storage}_{n}")
+    if not entry or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def time_steps(lev, steps: int, warmup: int):
+    import torch
+    stream = torch.cuda.current_stream()
+    lev.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    lev.step(steps)          # one C call: `steps` kernel launches on `stream`
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end)   # ms
+
+
+def run_gpu(n: int, storage: str, steps: int, warmup: int):
+    import numpy as np  # noqa: F401
+    import torch
+    from paper_1807_02284_amd import inputs
+    from paper_1807_02284_amd.level import F16S, F32, Level, Params
+
+    rho, u = inputs.turbulence(n, 2, 32, 0.04, seed=1807)
+    p = Params(nu=1e-5, g_max=0.1, adaptive=True)
+    lev = Level(n, n, n, p, storage=F32 if storage == "f32" else F16S)
+    lev.init_equilibrium(rho, u)
+    c0 = lev.conserved()
+    ms = time_steps(lev, steps, warmup)
+    c1 = lev.conserved()
+    bad = lev.count_nonfinite()
+    cells = n ** 3
+    ms_step = ms / steps
+    mlups = cells * steps / (ms * 1e-3) / 1e6
+    bytes_launch = cells * BYTES_PER_LUP[storage]
+    achieved = bytes_launch / (ms_step * 1e-3) / 1e9
+    out = {
+        "ms_per_step": ms_step,
+        "mlups": mlups,
+        "achieved_gbs": achieved,
+        "bytes_per_launch": bytes_launch,
+        "mass_drift_rel": abs(c1[0] - c0[0]) / c0[0],
+        "nonfinite": bad,
+    }
+    del lev
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(n: int, target_s: float = 12.0):
+    """The FP64 oracle (as is) on a bounded sample of the workload: a periodic
+    n x n x nz_s slab cut from the same seeded turbulence field, one or more
+    steps, about target_s seconds of wall clock."""
+    import numpy as np
+    import oracle
+    from paper_1807_02284_amd import inputs
+
+    nz_s = 4
+    rho, u = inputs.turbulence(n, 2, 32, 0.04, seed=1807)
+    cut = n * n * nz_s
+    dom = oracle.Domain(n, n, nz_s)
+    p = oracle.Params(nu=1e-5, g_max=0.1, adaptive=True)
+    f, _ = oracle.init(dom, rho[:cut], np.ascontiguousarray(u[:, :cut]))
+    steps, elapsed = 0, 0.0
+    while elapsed < target_s and steps < 50:
+        t0 = time.perf_counter()
+        f, _ = oracle.step(dom, p, f)
+        elapsed += time.perf_counter() - t0
+        steps += 1
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": cut * steps / elapsed / 1e6,
+        "unit": "MLUPS",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"{steps} step(s) of a periodic {n}x{n}x{nz_s} slab of the {n}^3 turbulence "
+                  f"field ({cut} cells), FP64, LU back-transform per cell; {elapsed:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: only --gpus 1 is supported (asked for {args.gpus}); this build runs "
+              "on one GPU and has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    main_run = run_gpu(args.n, "f32", args.steps, args.warmup)
+    print(f"[bench] f32 {args.n}^3: {main_run['mlups']:.0f} MLUPS, "
+          f"{main_run['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
+    variants = {}
+    if not args.no_variants:
+        v = run_gpu(args.n, "f16s", args.steps, args.warmup)
+        variants["f16s"] = {
+            "value": v["mlups"], "unit": "MLUPS", "ms_per_step": v["ms_per_step"],
+            "vs_f32_plain_step": v["mlups"] / main_run["mlups"],
+            "roofline_frac": v["achieved_gbs"] / HBM_PEAK_GBS,
+            "achieved_gbs": v["achieved_gbs"], "bytes_per_lup": BYTES_PER_LUP["f16s"],
+        }
+        print(f"[bench] f16s {args.n}^3: {v['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+
+    traffic = measured_traffic("f32", args.n)
+    result = {
+        "metric": METRIC,
+        "value": main_run["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_run["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"decaying turbulence {args.n}^3 periodic, D3Q27 central-moment "
+                        "collision, adaptive relaxation on",
+            "grid": [args.n] * 3,
+            "cells": args.n ** 3,
+            "nu": 1e-5,
+            "spectrum": "E(k) ~ k^-5/3 over integer |k| in [2, 32], seed 1807",
+            "u_rms_per_component": 0.04,
+            "storage": "f32 shifted populations f_i - w_i",
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_step<float> (fused pull-stream + collide)",
+            "achieved": main_run["achieved_gbs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": main_run["achieved_gbs"] / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": main_run["bytes_per_launch"],
+        },
+        "checks": {"mass_drift_rel": main_run["mass_drift_rel"],
+                   "nonfinite": main_run["nonfinite"]},
+        "variants": variants,
+        "source_hash": kernel_source_hash(),
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(args.n)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,174 @@
+/*
+ * cslbm.h -- C ABI of the continuous-scale central-moment lattice Boltzmann
+ * library for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Li, Bai & Liu, "Continuous-Scale Kinetic Fluid Simulation"
+ * (arXiv 1807.02284).  The library evaluates the lattice Boltzmann update
+ * (eq. lbe) on D3Q27 with the non-orthogonal central-moment collision
+ * (eq. cmr_collision, appendix) and the adaptive relaxation of the
+ * higher-order moments (section "Adaptive relaxation").
+ *
+ * General rules
+ *   - Every pointer inside cslbm_level and every array argument is a DEVICE
+ *     pointer unless stated otherwise.  All device memory is owned by the
+ *     caller; the library keeps no pointer beyond a call.  Calls that need
+ *     temporary device memory take it from the stream-ordered allocator and
+ *     return it before they return.
+ *   - Every call enqueues its kernels on the given stream and returns without
+ *     synchronising, except calls that return values on the host
+ *     (cslbm_conserved_f64, cslbm_check_finite), which synchronise the stream.
+ *   - Return value: CSLBM_OK (0) or a negative CSLBM_ERR_* code.  Arguments
+ *     are validated before any launch; a failed validation launches nothing.
+ *     cslbm_last_error() returns a message for the last failure of the
+ *     calling thread.  No C++ exception crosses this interface.
+ *
+ * Field layout
+ *   - A level is a dense nx*ny*nz box; cell = x + nx*(y + ny*z) (x fastest).
+ *   - Populations: 27 planes of `plane` elements each (plane >= nx*ny*nz),
+ *     population i in the order of the appendix velocity list (entry 13 of
+ *     c_z taken as -1).  Stored values are SHIFTED populations
+ *     h_i = f_i - w_i with the product weights w = (2/3, 1/6, 1/6)^3:
+ *     float for CSLBM_F32, IEEE binary16 (round to nearest even, subnormals
+ *     kept) for CSLBM_F16S.  Arithmetic is FP32 in both cases.
+ *   - The stored state at step n is the post-collision field f~(n); one
+ *     step pulls f_i(x) = f~_i(x - c_i, n-1) and collides.
+ *   - Passive scalar (optional): 7 float planes, D3Q7 velocities rest, +x,
+ *     -x, +y, -y, +z, -z, unshifted.
+ *   - Macroscopic arrays passed to init / read-back are dense (stride
+ *     nx*ny*nz, not plane): rho[N], u[3][N], s[N].
+ */
+#ifndef CSLBM_H
+#define CSLBM_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define CSLBM_OK 0
+#define CSLBM_ERR_ARG (-1)          /* invalid pointer or parameter value */
+#define CSLBM_ERR_SHAPE (-2)        /* inconsistent sizes / strides */
+#define CSLBM_ERR_UNSUPPORTED (-3)  /* valid but not implemented combination */
+#define CSLBM_ERR_HIP (-4)          /* a HIP runtime call or launch failed */
+#define CSLBM_ERR_NONFINITE (-5)    /* NaN or Inf found in the state */
+
+/* storage formats */
+#define CSLBM_F32 0
+#define CSLBM_F16S 1
+
+/* cell kinds: low 3 bits of the per-cell flag byte.  Bit 3 (CSLBM_NEAR_WALL)
+ * is owned by the library and set by cslbm_prepare_flags. */
+#define CSLBM_FLUID 0    /* collided */
+#define CSLBM_SOLID 1    /* obstacle: halfway bounce-back for its neighbours;
+                            its own output is the rest state (h = 0, g = 0) */
+#define CSLBM_INLET 2    /* Dirichlet: output f^eq(1, u_in), g^eq(s_in, u_in) */
+#define CSLBM_OUTFLOW 3  /* zero gradient: output = input of the x-1 neighbour */
+#define CSLBM_GHOST 4    /* never collided; output = input (scale exchange writes it) */
+#define CSLBM_NEAR_WALL 8
+
+/* Relaxation and model parameters (lattice units of the level). */
+typedef struct cslbm_params {
+    double nu;        /* shear viscosity: S4..S8 = 1/(3 nu + 1/2) (eq. viscosity) */
+    double nu_hi[4];  /* artificial viscosities nu'_i of m9..m16, m17..m22,
+                         m23..m25, m26 (appendix: 0.005, 0.007, 0.009, 0.01) */
+    double a, b;      /* adaptive relaxation nu^'_i = (a G/g_max + b) nu'_i,
+                         G clamped to g_max (paper: a = -4, b = 5) */
+    double g_max;     /* gradient normalisation, > 0 */
+    int32_t adaptive; /* 0: the factor is 1 (fixed nu'_i) */
+    double tau_s;     /* scalar BGK relaxation time (> 1/2) */
+    double beta;      /* buoyancy: F_z += beta (s - s_ref) */
+    double s_ref;
+    double u_in[3];   /* inlet velocity (CSLBM_INLET cells) */
+    double s_in;      /* inlet scalar value */
+} cslbm_params;
+
+/* One uniform level (scale).  The library reads every field and writes only
+ * f/f_next and g/g_next (swapped by cslbm_step). */
+typedef struct cslbm_level {
+    int32_t nx, ny, nz;
+    int32_t storage;          /* CSLBM_F32 or CSLBM_F16S */
+    int32_t periodic;         /* bit 0: x, bit 1: y, bit 2: z.  A non-periodic
+                                 face is a halfway bounce-back wall; any
+                                 non-periodic axis requires flags. */
+    int32_t reserved0;
+    int64_t plane;            /* elements per population plane, >= nx*ny*nz */
+    void* f;                  /* [27][plane] current state (storage type) */
+    void* f_next;             /* [27][plane] next state; must not alias f */
+    float* g;                 /* [7][plane] scalar state, or NULL */
+    float* g_next;            /* [7][plane], or NULL (both or neither) */
+    uint8_t* flags;           /* [nx*ny*nz] cell kinds, or NULL = all fluid */
+    const float* force;       /* [3][plane] body force field theta, or NULL */
+    double origin[3];         /* physical position of cell (0,0,0) */
+    double dx;                /* physical spacing of this scale */
+    cslbm_params p;
+} cslbm_level;
+
+/* Recommended plane stride for a level: nx*ny*nz rounded up and padded so
+ * that the 27 planes do not start at identical offsets modulo large powers
+ * of two.  Returns a negative code for invalid sizes. */
+int64_t cslbm_plane_stride(int32_t nx, int32_t ny, int32_t nz);
+
+/* Bytes of ONE time level of state: 27 population planes (+7 scalar planes
+ * when with_scalar) of cslbm_plane_stride elements.  Negative on error. */
+int64_t cslbm_level_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t storage,
+                          int32_t with_scalar);
+
+/* Set bit CSLBM_NEAR_WALL of every cell whose pull stencil reaches a solid
+ * cell or leaves the box through a non-periodic face; clear it elsewhere.
+ * Must be called after the kinds in L->flags change and before stepping. */
+int cslbm_prepare_flags(const cslbm_level* L, hipStream_t stream);
+
+/* Equilibrium initialisation (section "Initialization and boundary
+ * treatment", f_0 = T m^eq(rho, u)).  Writes L->f (and L->g when present:
+ * g^eq(s, u)).  rho may be NULL (rho = 1), s may be NULL (s = 0); u is
+ * [3][N] dense. */
+int cslbm_init_equilibrium(cslbm_level* L, const float* rho, const float* u, const float* s,
+                           hipStream_t stream);
+
+/* Copy populations into L->f from a dense [27][N] float array: physical f_i
+ * when shifted == 0, f_i - w_i when shifted != 0.  g (dense [7][N], may be
+ * NULL) goes to L->g. */
+int cslbm_set_populations(cslbm_level* L, const float* f, const float* g, int32_t shifted,
+                          hipStream_t stream);
+
+/* Copy L->f out to a dense [27][N] float array (physical f_i, or f_i - w_i
+ * when shifted != 0), and L->g to g when both are non-NULL. */
+int cslbm_get_populations(const cslbm_level* L, float* f, float* g, int32_t shifted,
+                          hipStream_t stream);
+
+/* n_steps lattice Boltzmann steps (eq. lbe with eq. cmr_collision): for
+ * each step, pull-stream L->f into registers, collide, write L->f_next, and
+ * swap L->f <-> L->f_next (and g) in *L.  After an even number of steps the
+ * buffers are back in their original roles. */
+int cslbm_step(cslbm_level* L, int32_t n_steps, hipStream_t stream);
+
+/* Macroscopic fields of the stored state: rho = sum f~, u = (sum c f~ -
+ * F/2)/rho, s = sum g (dense arrays; any output may be NULL). */
+int cslbm_read_macro(const cslbm_level* L, float* rho, float* u, float* s, hipStream_t stream);
+
+/* Conserved totals over cells that are neither SOLID nor GHOST, accumulated
+ * in FP64 with a fixed reduction order (bitwise reproducible):
+ * out[0] = sum rho, out[1..3] = sum c f~ (momentum), out[4] = sum s (0
+ * without scalar).  out is a HOST array; synchronises the stream. */
+int cslbm_conserved_f64(const cslbm_level* L, double out[5], hipStream_t stream);
+
+/* Count NaN/Inf values in L->f (and L->g).  *n_bad is a HOST int64.
+ * Returns CSLBM_ERR_NONFINITE when the count is non-zero; synchronises. */
+int cslbm_check_finite(const cslbm_level* L, int64_t* n_bad, hipStream_t stream);
+
+/* sizeof(cslbm_params) and sizeof(cslbm_level) as compiled into the
+ * library (HOST pointers), so that bindings can verify their struct layout
+ * before the first call.  Always CSLBM_OK. */
+int cslbm_abi_sizes(int64_t* params_bytes, int64_t* level_bytes);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* cslbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CSLBM_H */

@@ -1,0 +1,773 @@
+// cslbm.hip -- single-level kernels and the C ABI of libcslbm (gfx950).
+//
+// Hot path: k_step, the fused pull-stream + central-moment collision (one
+// thread per cell, x fastest so that a wave64 covers 64 consecutive cells of
+// a row: every one of the 27 plane loads and 27 plane stores of a wave is a
+// contiguous 256-byte (FP32) or 128-byte (FP16) segment).  It is bound by
+// HBM bandwidth: 27 reads + 27 writes per lattice update and nothing else.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/cslbm.h"
+#include "cm_collide.hpp"
+#include "lattice.hpp"
+
+namespace cslbm {
+
+// ---------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+static int check_launch(const char* what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CSLBM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    return CSLBM_OK;
+}
+
+#define CSLBM_HIP_TRY(call)                                                                 \
+    do {                                                                                    \
+        const hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess) return fail(CSLBM_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// storage traits: FP32 or IEEE binary16 shifted populations
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Io;
+
+template <>
+struct Io<float> {
+    static __device__ __forceinline__ float ld(const float* p) { return *p; }
+    static __device__ __forceinline__ void st(float* p, float v) { __builtin_nontemporal_store(v, p); }
+};
+
+template <>
+struct Io<_Float16> {
+    static __device__ __forceinline__ float ld(const _Float16* p) { return static_cast<float>(*p); }
+    static __device__ __forceinline__ void st(_Float16* p, float v)
+    {
+        __builtin_nontemporal_store(static_cast<_Float16>(v), p);   // round to nearest even
+    }
+};
+
+// ---------------------------------------------------------------------------
+// kernel arguments
+// ---------------------------------------------------------------------------
+struct StepArgs {
+    const void* f;
+    void* fo;
+    const float* g;
+    float* go;
+    const uint8_t* flags;
+    const float* force;
+    int nx, ny, nz, periodic;
+    int64_t plane;
+    Rates r;
+    float beta, s_ref, inv_tau_s;
+    float u_in[3];
+    float s_in;
+};
+
+// D3Q7 equilibrium g^eq_i = w_i s (1 + 4 c_i.u)  (cs^2 = 1/4)
+__device__ __forceinline__ float scalar_eq(int i, float s, float ux, float uy, float uz)
+{
+    return kSw[i] * s * (1.0f + 4.0f * (kSx[i] * ux + kSy[i] * uy + kSz[i] * uz));
+}
+
+__device__ __forceinline__ bool leaves_box(int x, int y, int z, int cx, int cy, int cz, int nx,
+                                           int ny, int nz, int periodic)
+{
+    // the pull source x - c lies outside a non-periodic face
+    const bool ox = !(periodic & 1) && ((cx == 1 && x == 0) || (cx == -1 && x == nx - 1));
+    const bool oy = !(periodic & 2) && ((cy == 1 && y == 0) || (cy == -1 && y == ny - 1));
+    const bool oz = !(periodic & 4) && ((cz == 1 && z == 0) || (cz == -1 && z == nz - 1));
+    return ox || oy || oz;
+}
+
+// ---------------------------------------------------------------------------
+// K: fused pull-stream + collide
+// ---------------------------------------------------------------------------
+template <typename T, bool kFlags, bool kForce, bool kScalar>
+__global__ void __launch_bounds__(256) k_step(const StepArgs a)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= a.nx || y >= a.ny) return;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int nxy = nx * ny;
+    const int cell = x + nx * y + nxy * z;
+    const int64_t P = a.plane;
+    const T* __restrict__ f = static_cast<const T*>(a.f);
+    T* __restrict__ fo = static_cast<T*>(a.fo);
+
+    uint8_t flag = 0;
+    if (kFlags) flag = a.flags[cell];
+    const int kind = flag & kKindMask;
+
+    // source coordinates of the pull, indexed by (c + 1): c = -1 pulls from
+    // x + 1, c = +1 from x - 1 (periodic wrap; non-periodic faces are caught
+    // by the near-wall test)
+    const int xm = (x == 0) ? nx - 1 : x - 1;
+    const int xp = (x == nx - 1) ? 0 : x + 1;
+    const int ym = (y == 0) ? ny - 1 : y - 1;
+    const int yp = (y == ny - 1) ? 0 : y + 1;
+    const int zm = (z == 0) ? nz - 1 : z - 1;
+    const int zp = (z == nz - 1) ? 0 : z + 1;
+    const int sx[3] = {xp, x, xm};
+    const int sy[3] = {yp * nx, y * nx, ym * nx};
+    const int sz[3] = {zp * nxy, z * nxy, zm * nxy};
+
+    if (kFlags && kind != kFluid) {
+        if (kind == kSolid) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) Io<T>::st(fo + i * P + cell, 0.0f);
+            if (kScalar)
+#pragma unroll
+                for (int i = 0; i < QS; ++i) a.go[i * P + cell] = 0.0f;
+        } else if (kind == kInlet) {
+            float v[27];
+            shifted_equilibrium(v, 1.0f, a.u_in[0], a.u_in[1], a.u_in[2]);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) Io<T>::st(fo + i * P + cell, v[tensor_slot(i)]);
+            if (kScalar)
+#pragma unroll
+                for (int i = 0; i < QS; ++i)
+                    a.go[i * P + cell] = scalar_eq(i, a.s_in, a.u_in[0], a.u_in[1], a.u_in[2]);
+        } else {
+            // ghost: keep; outflow: copy the incoming state of the x-1 neighbour
+            int from = cell;
+            if (kind == kOutflow && (x > 0 || (a.periodic & 1))) from = xm + nx * y + nxy * z;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const float hv = Io<T>::ld(f + i * P + from);
+                Io<T>::st(fo + i * P + cell, hv);
+            }
+            if (kScalar)
+#pragma unroll
+                for (int i = 0; i < QS; ++i) a.go[i * P + cell] = a.g[i * P + from];
+        }
+        return;
+    }
+
+    const bool near = kFlags && (flag & kNearWall);
+    float v[27];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        int src = sx[kCx[i] + 1] + sy[kCy[i] + 1] + sz[kCz[i] + 1];
+        int pl = i;
+        if (kFlags && near) {
+            const bool bb = leaves_box(x, y, z, kCx[i], kCy[i], kCz[i], nx, ny, nz, a.periodic) ||
+                            ((a.flags[src] & kKindMask) == kSolid);
+            if (bb) {   // halfway bounce-back: the cell's own opposite population
+                src = cell;
+                pl = opposite(i);
+            }
+        }
+        v[tensor_slot(i)] = Io<T>::ld(f + pl * P + src);
+    }
+
+    float gv[QS];
+    float s = 0.0f;
+    if (kScalar) {
+#pragma unroll
+        for (int i = 0; i < QS; ++i) {
+            int src = sx[kSx[i] + 1] + sy[kSy[i] + 1] + sz[kSz[i] + 1];
+            int pl = i;
+            if (kFlags && near) {
+                const bool bb = leaves_box(x, y, z, kSx[i], kSy[i], kSz[i], nx, ny, nz, a.periodic) ||
+                                ((a.flags[src] & kKindMask) == kSolid);
+                if (bb) {
+                    src = cell;
+                    pl = scalar_opposite(i);
+                }
+            }
+            gv[i] = a.g[pl * P + src];
+        }
+        s = (gv[0] + (gv[1] + gv[2])) + ((gv[3] + gv[4]) + (gv[5] + gv[6]));
+    }
+
+    float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f;
+    if (kForce) {
+        Fx = a.force[cell];
+        Fy = a.force[P + cell];
+        Fz = a.force[2 * P + cell];
+    }
+    if (kScalar) Fz += a.beta * (s - a.s_ref);
+
+    const CellMacro mc = cm_collide(v, a.r, Fx, Fy, Fz);
+
+#pragma unroll
+    for (int i = 0; i < Q; ++i) Io<T>::st(fo + i * P + cell, v[tensor_slot(i)]);
+
+    if (kScalar) {
+#pragma unroll
+        for (int i = 0; i < QS; ++i) {
+            const float ge = scalar_eq(i, s, mc.ux, mc.uy, mc.uz);
+            __builtin_nontemporal_store(gv[i] - (gv[i] - ge) * a.inv_tau_s, a.go + i * P + cell);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// auxiliary kernels (one thread per cell, 1D launch over N)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void cell_coords(int64_t c, int nx, int ny, int& x, int& y, int& z)
+{
+    x = (int)(c % nx);
+    y = (int)((c / nx) % ny);
+    z = (int)(c / ((int64_t)nx * ny));
+}
+
+__global__ void k_prepare_flags(uint8_t* flags, int nx, int ny, int nz, int periodic)
+{
+    const int64_t N = (int64_t)nx * ny * nz;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    int x, y, z;
+    cell_coords(c, nx, ny, x, y, z);
+    const uint8_t kind = flags[c] & kKindMask;
+    bool near = false;
+    if (kind == kFluid) {
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            if (leaves_box(x, y, z, kCx[i], kCy[i], kCz[i], nx, ny, nz, periodic)) {
+                near = true;
+                continue;
+            }
+            const int xs = (x - kCx[i] + nx) % nx, ys = (y - kCy[i] + ny) % ny,
+                      zs = (z - kCz[i] + nz) % nz;
+            if ((flags[xs + (int64_t)nx * (ys + (int64_t)ny * zs)] & kKindMask) == kSolid) near = true;
+        }
+    }
+    flags[c] = kind | (near ? kNearWall : 0);
+}
+
+template <typename T>
+__global__ void k_init_eq(T* f, float* g, int64_t N, int64_t P, const float* rho, const float* u,
+                          const float* s)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    const float r = rho ? rho[c] : 1.0f;
+    const float ux = u[c], uy = u[N + c], uz = u[2 * N + c];
+    float v[27];
+    shifted_equilibrium(v, r, ux, uy, uz);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) Io<T>::st(f + i * P + c, v[tensor_slot(i)]);
+    if (g) {
+        const float sc = s ? s[c] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < QS; ++i) g[i * P + c] = scalar_eq(i, sc, ux, uy, uz);
+    }
+}
+
+template <typename T>
+__global__ void k_set_pop(T* f, float* g, int64_t N, int64_t P, const float* src, const float* gsrc,
+                          int shifted)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const float v = src[i * N + c];
+        Io<T>::st(f + i * P + c, shifted ? v : v - weight(i));
+    }
+    if (g && gsrc)
+#pragma unroll
+        for (int i = 0; i < QS; ++i) g[i * P + c] = gsrc[i * N + c];
+}
+
+template <typename T>
+__global__ void k_get_pop(const T* f, const float* g, int64_t N, int64_t P, float* dst, float* gdst,
+                          int shifted)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const float h = Io<T>::ld(f + i * P + c);
+        dst[i * N + c] = shifted ? h : h + weight(i);
+    }
+    if (g && gdst)
+#pragma unroll
+        for (int i = 0; i < QS; ++i) gdst[i * N + c] = g[i * P + c];
+}
+
+template <typename T>
+__global__ void k_macro(const T* f, const float* g, const float* force, int64_t N, int64_t P,
+                        float beta, float s_ref, float* rho, float* u, float* s)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    float v[27];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[tensor_slot(i)] = Io<T>::ld(f + i * P + c);
+    float dr, jx, jy, jz;
+    moments0(v, dr, jx, jy, jz);
+    float sc = 0.0f;
+    if (g)
+#pragma unroll
+        for (int i = 0; i < QS; ++i) sc += g[i * P + c];
+    float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f;
+    if (force) {
+        Fx = force[c];
+        Fy = force[P + c];
+        Fz = force[2 * P + c];
+    }
+    if (g) Fz += beta * (sc - s_ref);
+    const float r = 1.0f + dr;
+    if (rho) rho[c] = r;
+    if (u) {
+        u[c] = (jx - 0.5f * Fx) / r;
+        u[N + c] = (jy - 0.5f * Fy) / r;
+        u[2 * N + c] = (jz - 0.5f * Fz) / r;
+    }
+    if (s) s[c] = sc;
+}
+
+// FP64 conservation: per-block partial sums (count, sum h, sum c h, sum g),
+// then one block adds the partials in a fixed order.
+constexpr int kRedBlocks = 1024;
+constexpr int kRedThreads = 256;
+constexpr int kRedVals = 6;
+
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads)
+    k_conserved_partials(const T* f, const float* g, const uint8_t* flags, int64_t N, int64_t P,
+                         double* partials)
+{
+    double acc[kRedVals] = {0, 0, 0, 0, 0, 0};
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < N;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        if (flags) {
+            const int kind = flags[c] & kKindMask;
+            if (kind == kSolid || kind == kGhost) continue;
+        }
+        double dr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double h = (double)Io<T>::ld(f + i * P + c);
+            dr += h;
+            jx += kCx[i] * h;
+            jy += kCy[i] * h;
+            jz += kCz[i] * h;
+        }
+        double sc = 0.0;
+        if (g)
+#pragma unroll
+            for (int i = 0; i < QS; ++i) sc += (double)g[i * P + c];
+        acc[0] += 1.0;
+        acc[1] += dr;
+        acc[2] += jx;
+        acc[3] += jy;
+        acc[4] += jz;
+        acc[5] += sc;
+    }
+    __shared__ double sm[kRedVals][kRedThreads];
+#pragma unroll
+    for (int k = 0; k < kRedVals; ++k) sm[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < kRedVals; ++k) sm[k][threadIdx.x] += sm[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < kRedVals; ++k) partials[blockIdx.x * kRedVals + k] = sm[k][0];
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_conserved_final(const double* partials, int nblocks,
+                                                                 double* out)
+{
+    double acc[kRedVals] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < kRedVals; ++k) acc[k] += partials[b * kRedVals + k];
+    __shared__ double sm[kRedVals][kRedThreads];
+#pragma unroll
+    for (int k = 0; k < kRedVals; ++k) sm[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < kRedVals; ++k) sm[k][threadIdx.x] += sm[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sm[0][0] + sm[1][0];   // sum rho = cells + sum h
+        out[1] = sm[2][0];
+        out[2] = sm[3][0];
+        out[3] = sm[4][0];
+        out[4] = sm[5][0];
+    }
+}
+
+template <typename T>
+__global__ void k_count_nonfinite(const T* f, const float* g, int64_t N, int64_t P,
+                                  unsigned long long* count)
+{
+    unsigned long long bad = 0;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < N;
+         c += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) bad += !isfinite(Io<T>::ld(f + i * P + c));
+        if (g)
+#pragma unroll
+            for (int i = 0; i < QS; ++i) bad += !isfinite(g[i * P + c]);
+    }
+    if (bad) atomicAdd(count, bad);
+}
+
+// ---------------------------------------------------------------------------
+// host side: validation and launches
+// ---------------------------------------------------------------------------
+static int64_t cells_of(const cslbm_level* L) { return (int64_t)L->nx * L->ny * L->nz; }
+
+static int validate_shape(const cslbm_level* L)
+{
+    if (!L) return fail(CSLBM_ERR_ARG, "level is NULL");
+    if (L->nx < 1 || L->ny < 1 || L->nz < 1)
+        return fail(CSLBM_ERR_SHAPE, "level size %d x %d x %d must be positive", L->nx, L->ny, L->nz);
+    const int64_t N = cells_of(L);
+    if (N > 0x7fffffffLL)
+        return fail(CSLBM_ERR_SHAPE, "level has %lld cells; at most 2^31-1 are supported",
+                    (long long)N);
+    if (L->nz > 65535 || L->ny > 65535)
+        return fail(CSLBM_ERR_SHAPE, "ny and nz must be at most 65535");
+    if (L->plane < N)
+        return fail(CSLBM_ERR_SHAPE, "plane stride %lld is smaller than nx*ny*nz = %lld",
+                    (long long)L->plane, (long long)N);
+    if (L->storage != CSLBM_F32 && L->storage != CSLBM_F16S)
+        return fail(CSLBM_ERR_UNSUPPORTED, "unknown storage format %d", L->storage);
+    if (!L->f) return fail(CSLBM_ERR_ARG, "f is NULL");
+    if ((L->g == nullptr) != (L->g_next == nullptr))
+        return fail(CSLBM_ERR_ARG, "g and g_next must both be set or both be NULL");
+    if ((L->periodic & 7) != 7 && !L->flags)
+        return fail(CSLBM_ERR_ARG, "a non-periodic axis needs a flags array (periodic = %d)",
+                    L->periodic);
+    return CSLBM_OK;
+}
+
+static int validate_params(const cslbm_level* L)
+{
+    const cslbm_params& p = L->p;
+    if (!(p.nu > 0.0) || !std::isfinite(p.nu))
+        return fail(CSLBM_ERR_ARG, "viscosity nu = %g must be positive (S4..8 in (0, 2))", p.nu);
+    for (int g = 0; g < 4; ++g)
+        if (!(p.nu_hi[g] > 0.0) || !std::isfinite(p.nu_hi[g]))
+            return fail(CSLBM_ERR_ARG, "artificial viscosity nu_hi[%d] = %g must be positive", g,
+                        p.nu_hi[g]);
+    if (p.adaptive) {
+        if (!(p.g_max > 0.0)) return fail(CSLBM_ERR_ARG, "g_max = %g must be positive", p.g_max);
+        if (!(p.b > 0.0) || !(p.a + p.b > 0.0))
+            return fail(CSLBM_ERR_ARG,
+                        "adaptive factor a*x + b must stay positive on [0, 1] (a = %g, b = %g)",
+                        p.a, p.b);
+    }
+    if (L->g && !(p.tau_s > 0.5))
+        return fail(CSLBM_ERR_ARG, "scalar relaxation time tau_s = %g must exceed 1/2", p.tau_s);
+    return CSLBM_OK;
+}
+
+static Rates make_rates(const cslbm_params& p)
+{
+    Rates r;
+    r.S = (float)(1.0 / (3.0 * p.nu + 0.5));
+    for (int g = 0; g < 4; ++g) r.nu3[g] = (float)(3.0 * p.nu_hi[g]);
+    r.a = (float)p.a;
+    r.b = (float)p.b;
+    r.inv_gmax = p.adaptive ? (float)(1.0 / p.g_max) : 0.0f;
+    r.adaptive = p.adaptive ? 1 : 0;
+    return r;
+}
+
+static dim3 step_block(int nx)
+{
+    const int bx = nx >= 256 ? 256 : (nx >= 128 ? 128 : 64);
+    return dim3(bx, 256 / bx, 1);
+}
+
+template <typename T, bool kFlags, bool kForce, bool kScalar>
+static void launch_step(const StepArgs& a, hipStream_t st)
+{
+    const dim3 block = step_block(a.nx);
+    const dim3 grid((a.nx + block.x - 1) / block.x, (a.ny + block.y - 1) / block.y, a.nz);
+    hipLaunchKernelGGL((k_step<T, kFlags, kForce, kScalar>), grid, block, 0, st, a);
+}
+
+template <typename T>
+static void dispatch_step(const StepArgs& a, bool flags, bool force, bool scalar, hipStream_t st)
+{
+    const int key = (flags ? 4 : 0) | (force ? 2 : 0) | (scalar ? 1 : 0);
+    switch (key) {
+        case 0: launch_step<T, false, false, false>(a, st); break;
+        case 1: launch_step<T, false, false, true>(a, st); break;
+        case 2: launch_step<T, false, true, false>(a, st); break;
+        case 3: launch_step<T, false, true, true>(a, st); break;
+        case 4: launch_step<T, true, false, false>(a, st); break;
+        case 5: launch_step<T, true, false, true>(a, st); break;
+        case 6: launch_step<T, true, true, false>(a, st); break;
+        default: launch_step<T, true, true, true>(a, st); break;
+    }
+}
+
+static inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+}  // namespace cslbm
+
+using namespace cslbm;
+
+extern "C" {
+
+int64_t cslbm_plane_stride(int32_t nx, int32_t ny, int32_t nz)
+{
+    if (nx < 1 || ny < 1 || nz < 1) return fail(CSLBM_ERR_SHAPE, "sizes must be positive");
+    const int64_t N = (int64_t)nx * ny * nz;
+    // round up to 256 elements and add 3*256 so consecutive planes start at
+    // offsets that differ by an odd number of 1 KiB blocks
+    return ((N + 255) / 256) * 256 + 3 * 256;
+}
+
+int64_t cslbm_level_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t storage, int32_t with_scalar)
+{
+    const int64_t plane = cslbm_plane_stride(nx, ny, nz);
+    if (plane < 0) return plane;
+    if (storage != CSLBM_F32 && storage != CSLBM_F16S)
+        return fail(CSLBM_ERR_UNSUPPORTED, "unknown storage format %d", storage);
+    const int64_t elem = storage == CSLBM_F32 ? 4 : 2;
+    return 27 * plane * elem + (with_scalar ? 7 * plane * 4 : 0);
+}
+
+int cslbm_prepare_flags(const cslbm_level* L, hipStream_t stream)
+{
+    int rc = validate_shape(L);
+    if (rc) return rc;
+    if (!L->flags) return fail(CSLBM_ERR_ARG, "flags is NULL");
+    const int64_t N = cells_of(L);
+    hipLaunchKernelGGL(k_prepare_flags, dim3(blocks_for(N, 256)), dim3(256), 0, stream, L->flags,
+                       L->nx, L->ny, L->nz, L->periodic);
+    return check_launch("k_prepare_flags");
+}
+
+int cslbm_init_equilibrium(cslbm_level* L, const float* rho, const float* u, const float* s,
+                           hipStream_t stream)
+{
+    int rc = validate_shape(L);
+    if (rc) return rc;
+    if (!u) return fail(CSLBM_ERR_ARG, "u is NULL");
+    const int64_t N = cells_of(L);
+    const dim3 grid(blocks_for(N, 256)), block(256);
+    if (L->storage == CSLBM_F32)
+        hipLaunchKernelGGL(k_init_eq<float>, grid, block, 0, stream, (float*)L->f, L->g, N, L->plane,
+                           rho, u, s);
+    else
+        hipLaunchKernelGGL(k_init_eq<_Float16>, grid, block, 0, stream, (_Float16*)L->f, L->g, N,
+                           L->plane, rho, u, s);
+    return check_launch("k_init_eq");
+}
+
+int cslbm_set_populations(cslbm_level* L, const float* f, const float* g, int32_t shifted,
+                          hipStream_t stream)
+{
+    int rc = validate_shape(L);
+    if (rc) return rc;
+    if (!f) return fail(CSLBM_ERR_ARG, "source populations are NULL");
+    const int64_t N = cells_of(L);
+    const dim3 grid(blocks_for(N, 256)), block(256);
+    if (L->storage == CSLBM_F32)
+        hipLaunchKernelGGL(k_set_pop<float>, grid, block, 0, stream, (float*)L->f, L->g, N, L->plane,
+                           f, g, shifted);
+    else
+        hipLaunchKernelGGL(k_set_pop<_Float16>, grid, block, 0, stream, (_Float16*)L->f, L->g, N,
+                           L->plane, f, g, shifted);
+    return check_launch("k_set_pop");
+}
+
+int cslbm_get_populations(const cslbm_level* L, float* f, float* g, int32_t shifted,
+                          hipStream_t stream)
+{
+    int rc = validate_shape(L);
+    if (rc) return rc;
+    if (!f) return fail(CSLBM_ERR_ARG, "destination is NULL");
+    const int64_t N = cells_of(L);
+    const dim3 grid(blocks_for(N, 256)), block(256);
+    if (L->storage == CSLBM_F32)
+        hipLaunchKernelGGL(k_get_pop<float>, grid, block, 0, stream, (const float*)L->f, L->g, N,
+                           L->plane, f, g, shifted);
+    else
+        hipLaunchKernelGGL(k_get_pop<_Float16>, grid, block, 0, stream, (const _Float16*)L->f, L->g,
+                           N, L->plane, f, g, shifted);
+    return check_launch("k_get_pop");
+}
+
+int cslbm_step(cslbm_level* L, int32_t n_steps, hipStream_t stream)
+{
+    int rc = validate_shape(L);
+    if (rc) return rc;
+    rc = validate_params(L);
+    if (rc) return rc;
+    if (n_steps < 0) return fail(CSLBM_ERR_ARG, "n_steps = %d is negative", n_steps);
+    if (!L->f_next) return fail(CSLBM_ERR_ARG, "f_next is NULL");
+    if (L->f == L->f_next) return fail(CSLBM_ERR_ARG, "f and f_next alias");
+    if (L->g && L->g == L->g_next) return fail(CSLBM_ERR_ARG, "g and g_next alias");
+
+    StepArgs a;
+    a.flags = L->flags;
+    a.force = L->force;
+    a.nx = L->nx;
+    a.ny = L->ny;
+    a.nz = L->nz;
+    a.periodic = L->periodic & 7;
+    a.plane = L->plane;
+    a.r = make_rates(L->p);
+    a.beta = (float)L->p.beta;
+    a.s_ref = (float)L->p.s_ref;
+    a.inv_tau_s = L->g ? (float)(1.0 / L->p.tau_s) : 0.0f;
+    for (int k = 0; k < 3; ++k) a.u_in[k] = (float)L->p.u_in[k];
+    a.s_in = (float)L->p.s_in;
+    const bool has_flags = L->flags != nullptr;
+    const bool has_force = L->force != nullptr;
+    const bool has_scalar = L->g != nullptr;
+    for (int n = 0; n < n_steps; ++n) {
+        a.f = L->f;
+        a.fo = L->f_next;
+        a.g = L->g;
+        a.go = L->g_next;
+        if (L->storage == CSLBM_F32)
+            dispatch_step<float>(a, has_flags, has_force, has_scalar, stream);
+        else
+            dispatch_step<_Float16>(a, has_flags, has_force, has_scalar, stream);
+        rc = check_launch("k_step");
+        if (rc) return rc;
+        void* t = L->f;
+        L->f = L->f_next;
+        L->f_next = t;
+        float* tg = L->g;
+        L->g = L->g_next;
+        L->g_next = tg;
+    }
+    return CSLBM_OK;
+}
+
+int cslbm_read_macro(const cslbm_level* L, float* rho, float* u, float* s, hipStream_t stream)
+{
+    int rc = validate_shape(L);
+    if (rc) return rc;
+    if (s && !L->g) return fail(CSLBM_ERR_ARG, "scalar requested but the level has no g");
+    const int64_t N = cells_of(L);
+    const dim3 grid(blocks_for(N, 256)), block(256);
+    const float beta = (float)L->p.beta, sref = (float)L->p.s_ref;
+    if (L->storage == CSLBM_F32)
+        hipLaunchKernelGGL(k_macro<float>, grid, block, 0, stream, (const float*)L->f, L->g, L->force,
+                           N, L->plane, beta, sref, rho, u, s);
+    else
+        hipLaunchKernelGGL(k_macro<_Float16>, grid, block, 0, stream, (const _Float16*)L->f, L->g,
+                           L->force, N, L->plane, beta, sref, rho, u, s);
+    return check_launch("k_macro");
+}
+
+int cslbm_conserved_f64(const cslbm_level* L, double out[5], hipStream_t stream)
+{
+    int rc = validate_shape(L);
+    if (rc) return rc;
+    if (!out) return fail(CSLBM_ERR_ARG, "out is NULL");
+    const int64_t N = cells_of(L);
+    double* dmem = nullptr;
+    CSLBM_HIP_TRY(hipMallocAsync((void**)&dmem, (kRedBlocks * kRedVals + 8) * sizeof(double), stream));
+    double* partials = dmem;
+    double* dout = dmem + kRedBlocks * kRedVals;
+    if (L->storage == CSLBM_F32)
+        hipLaunchKernelGGL(k_conserved_partials<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, stream,
+                           (const float*)L->f, L->g, L->flags, N, L->plane, partials);
+    else
+        hipLaunchKernelGGL(k_conserved_partials<_Float16>, dim3(kRedBlocks), dim3(kRedThreads), 0,
+                           stream, (const _Float16*)L->f, L->g, L->flags, N, L->plane, partials);
+    rc = check_launch("k_conserved_partials");
+    if (!rc) {
+        hipLaunchKernelGGL(k_conserved_final, dim3(1), dim3(kRedThreads), 0, stream, partials,
+                           kRedBlocks, dout);
+        rc = check_launch("k_conserved_final");
+    }
+    double host[5] = {0, 0, 0, 0, 0};
+    if (!rc) {
+        const hipError_t e = hipMemcpyAsync(host, dout, sizeof host, hipMemcpyDeviceToHost, stream);
+        if (e != hipSuccess) rc = fail(CSLBM_ERR_HIP, "copy of the totals: %s", hipGetErrorString(e));
+    }
+    const hipError_t ef = hipFreeAsync(dmem, stream);
+    const hipError_t es = hipStreamSynchronize(stream);
+    if (rc) return rc;
+    if (ef != hipSuccess) return fail(CSLBM_ERR_HIP, "hipFreeAsync: %s", hipGetErrorString(ef));
+    if (es != hipSuccess) return fail(CSLBM_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(es));
+    std::memcpy(out, host, sizeof host);
+    return CSLBM_OK;
+}
+
+int cslbm_check_finite(const cslbm_level* L, int64_t* n_bad, hipStream_t stream)
+{
+    int rc = validate_shape(L);
+    if (rc) return rc;
+    if (!n_bad) return fail(CSLBM_ERR_ARG, "n_bad is NULL");
+    const int64_t N = cells_of(L);
+    unsigned long long* dcount = nullptr;
+    CSLBM_HIP_TRY(hipMallocAsync((void**)&dcount, sizeof(unsigned long long), stream));
+    rc = CSLBM_OK;
+    hipError_t e = hipMemsetAsync(dcount, 0, sizeof(unsigned long long), stream);
+    if (e != hipSuccess) rc = fail(CSLBM_ERR_HIP, "hipMemsetAsync: %s", hipGetErrorString(e));
+    if (!rc) {
+        const unsigned nb = (unsigned)std::min<int64_t>(blocks_for(N, 256), 4096);
+        if (L->storage == CSLBM_F32)
+            hipLaunchKernelGGL(k_count_nonfinite<float>, dim3(nb), dim3(256), 0, stream,
+                               (const float*)L->f, L->g, N, L->plane, dcount);
+        else
+            hipLaunchKernelGGL(k_count_nonfinite<_Float16>, dim3(nb), dim3(256), 0, stream,
+                               (const _Float16*)L->f, L->g, N, L->plane, dcount);
+        rc = check_launch("k_count_nonfinite");
+    }
+    unsigned long long host = 0;
+    if (!rc) {
+        e = hipMemcpyAsync(&host, dcount, sizeof host, hipMemcpyDeviceToHost, stream);
+        if (e != hipSuccess) rc = fail(CSLBM_ERR_HIP, "copy of the count: %s", hipGetErrorString(e));
+    }
+    const hipError_t ef = hipFreeAsync(dcount, stream);
+    const hipError_t es = hipStreamSynchronize(stream);
+    if (rc) return rc;
+    if (ef != hipSuccess) return fail(CSLBM_ERR_HIP, "hipFreeAsync: %s", hipGetErrorString(ef));
+    if (es != hipSuccess) return fail(CSLBM_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(es));
+    *n_bad = (int64_t)host;
+    if (host) return fail(CSLBM_ERR_NONFINITE, "%llu non-finite values in the state", host);
+    return CSLBM_OK;
+}
+
+int cslbm_abi_sizes(int64_t* params_bytes, int64_t* level_bytes)
+{
+    if (params_bytes) *params_bytes = (int64_t)sizeof(cslbm_params);
+    if (level_bytes) *level_bytes = (int64_t)sizeof(cslbm_level);
+    return CSLBM_OK;
+}
+
+const char* cslbm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

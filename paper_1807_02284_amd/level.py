@@ -1,0 +1,190 @@
+"""Torch-owned device buffers for one level, driven through the C ABI.
+
+PyTorch provides device memory and the stream; every computation happens in
+libcslbm.so.  A ``Level`` owns two population buffers (current and next), an
+optional scalar pair, optional cell flags and an optional body-force field.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _capi
+
+F32, F16S = _capi.F32, _capi.F16S
+
+
+@dataclass
+class Params:
+    """Model parameters of a level (lattice units); defaults are the
+    appendix artificial viscosities and the adaptive-relaxation constants."""
+    nu: float = 1e-4
+    nu_hi: tuple = (0.005, 0.007, 0.009, 0.01)
+    a: float = -4.0
+    b: float = 5.0
+    g_max: float = 0.1
+    adaptive: bool = True
+    tau_s: float = 0.51
+    beta: float = 0.0
+    s_ref: float = 0.0
+    u_in: tuple = (0.0, 0.0, 0.0)
+    s_in: float = 0.0
+
+    def to_c(self) -> _capi.CslbmParams:
+        return _capi.CslbmParams(
+            self.nu, (C.c_double * 4)(*self.nu_hi), self.a, self.b, self.g_max,
+            int(self.adaptive), self.tau_s, self.beta, self.s_ref,
+            (C.c_double * 3)(*self.u_in), self.s_in)
+
+
+def _stream_handle(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dev_ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous()
+    return t.data_ptr()
+
+
+class Level:
+    """One uniform D3Q27 level of nx*ny*nz cells on the current CUDA device."""
+
+    def __init__(self, nx: int, ny: int, nz: int, params: Params | None = None, *,
+                 storage: int = F32, scalar: bool = False, periodic: int = 7,
+                 flags: np.ndarray | torch.Tensor | None = None,
+                 force: np.ndarray | torch.Tensor | None = None,
+                 origin=(0.0, 0.0, 0.0), dx: float = 1.0, device=None):
+        lib = _capi.load()
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.n = self.nx * self.ny * self.nz
+        self.params = params or Params()
+        self.storage = storage
+        self.device = torch.device(device) if device is not None else torch.device("cuda")
+        plane = lib.cslbm_plane_stride(self.nx, self.ny, self.nz)
+        if plane < 0:
+            raise _capi.CslbmError(plane, "cslbm_plane_stride", lib.cslbm_last_error().decode())
+        self.plane = int(plane)
+        dt = torch.float32 if storage == F32 else torch.float16
+        self.f = torch.zeros(27 * self.plane, dtype=dt, device=self.device)
+        self.f_next = torch.zeros_like(self.f)
+        self.g = self.g_next = None
+        if scalar:
+            self.g = torch.zeros(7 * self.plane, dtype=torch.float32, device=self.device)
+            self.g_next = torch.zeros_like(self.g)
+        self.flags = None
+        if flags is not None:
+            fl = torch.as_tensor(np.asarray(flags, dtype=np.uint8) if not torch.is_tensor(flags)
+                                 else flags).to(self.device, torch.uint8).reshape(-1)
+            assert fl.numel() == self.n
+            self.flags = torch.zeros(self.plane, dtype=torch.uint8, device=self.device)
+            self.flags[: self.n] = fl
+        self.force = None
+        if force is not None:
+            ft = torch.as_tensor(np.asarray(force) if not torch.is_tensor(force) else force)
+            ft = ft.to(self.device, torch.float32).reshape(3, self.n)
+            self.force = torch.zeros(3, self.plane, dtype=torch.float32, device=self.device)
+            self.force[:, : self.n] = ft
+            self.force = self.force.reshape(-1)
+        self.c = _capi.CslbmLevel()
+        self.c.nx, self.c.ny, self.c.nz = self.nx, self.ny, self.nz
+        self.c.storage = storage
+        self.c.periodic = periodic
+        self.c.plane = self.plane
+        self.c.origin = (C.c_double * 3)(*origin)
+        self.c.dx = dx
+        self._sync_struct()
+        if self.flags is not None:
+            _capi.call("cslbm_prepare_flags", C.byref(self.c), _stream_handle())
+
+    # -- struct <-> tensors ------------------------------------------------
+    def _sync_struct(self):
+        self.c.f = _dev_ptr(self.f)
+        self.c.f_next = _dev_ptr(self.f_next)
+        self.c.g = _dev_ptr(self.g)
+        self.c.g_next = _dev_ptr(self.g_next)
+        self.c.flags = _dev_ptr(self.flags)
+        self.c.force = _dev_ptr(self.force)
+        self.c.p = self.params.to_c()
+
+    def set_params(self, params: Params):
+        self.params = params
+        self.c.p = params.to_c()
+
+    def set_flags(self, flags):
+        fl = torch.as_tensor(np.asarray(flags, dtype=np.uint8)).to(self.device).reshape(-1)
+        if self.flags is None:
+            self.flags = torch.zeros(self.plane, dtype=torch.uint8, device=self.device)
+        self.flags[: self.n] = fl
+        self._sync_struct()
+        _capi.call("cslbm_prepare_flags", C.byref(self.c), _stream_handle())
+
+    # -- C-ABI calls ---------------------------------------------------------
+    def init_equilibrium(self, rho=None, u=None, s=None, stream=None):
+        dev = self.device
+        u_t = torch.as_tensor(np.asarray(u, dtype=np.float32)).to(dev).reshape(3, self.n).contiguous()
+        r_t = None if rho is None else torch.as_tensor(np.asarray(rho, dtype=np.float32)).to(dev).reshape(-1).contiguous()
+        s_t = None if s is None else torch.as_tensor(np.asarray(s, dtype=np.float32)).to(dev).reshape(-1).contiguous()
+        self._sync_struct()
+        _capi.call("cslbm_init_equilibrium", C.byref(self.c), _dev_ptr(r_t), _dev_ptr(u_t),
+                   _dev_ptr(s_t), _stream_handle(stream))
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+
+    def set_populations(self, f, g=None, shifted: bool = False, stream=None):
+        dev = self.device
+        f_t = torch.as_tensor(np.asarray(f, dtype=np.float32) if not torch.is_tensor(f) else f)
+        f_t = f_t.to(dev, torch.float32).reshape(27, self.n).contiguous()
+        g_t = None
+        if g is not None:
+            g_t = torch.as_tensor(np.asarray(g, dtype=np.float32) if not torch.is_tensor(g) else g)
+            g_t = g_t.to(dev, torch.float32).reshape(7, self.n).contiguous()
+        self._sync_struct()
+        _capi.call("cslbm_set_populations", C.byref(self.c), _dev_ptr(f_t), _dev_ptr(g_t),
+                   int(shifted), _stream_handle(stream))
+        torch.cuda.synchronize()
+
+    def get_populations(self, shifted: bool = False, stream=None):
+        out = torch.empty(27, self.n, dtype=torch.float32, device=self.device)
+        gout = None if self.g is None else torch.empty(7, self.n, dtype=torch.float32, device=self.device)
+        self._sync_struct()
+        _capi.call("cslbm_get_populations", C.byref(self.c), _dev_ptr(out), _dev_ptr(gout),
+                   int(shifted), _stream_handle(stream))
+        return out, gout
+
+    def step(self, n_steps: int = 1, stream=None):
+        self._sync_struct()
+        _capi.call("cslbm_step", C.byref(self.c), int(n_steps), _stream_handle(stream))
+        if n_steps % 2:
+            self.f, self.f_next = self.f_next, self.f
+            if self.g is not None:
+                self.g, self.g_next = self.g_next, self.g
+        assert self.c.f == self.f.data_ptr()
+
+    def read_macro(self, stream=None):
+        rho = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        u = torch.empty(3, self.n, dtype=torch.float32, device=self.device)
+        s = None if self.g is None else torch.empty(self.n, dtype=torch.float32, device=self.device)
+        self._sync_struct()
+        _capi.call("cslbm_read_macro", C.byref(self.c), _dev_ptr(rho), _dev_ptr(u), _dev_ptr(s),
+                   _stream_handle(stream))
+        return rho, u, s
+
+    def conserved(self, stream=None) -> np.ndarray:
+        out = (C.c_double * 5)()
+        self._sync_struct()
+        _capi.call("cslbm_conserved_f64", C.byref(self.c), out, _stream_handle(stream))
+        return np.array(out[:])
+
+    def count_nonfinite(self, stream=None) -> int:
+        n = C.c_int64(0)
+        self._sync_struct()
+        lib = _capi.load()
+        rc = lib.cslbm_check_finite(C.byref(self.c), C.byref(n), _stream_handle(stream))
+        if rc not in (_capi.OK, _capi.ERR_NONFINITE):
+            raise _capi.CslbmError(rc, "cslbm_check_finite", lib.cslbm_last_error().decode())
+        return int(n.value)

@@ -1,0 +1,287 @@
+"""GPU parity of the single-level path (C ABI -> HIP kernels) against the FP64
+oracle on identical seeded inputs.  Tolerances: one step of FP32 populations
+1e-6 relative per element; Taylor-Green velocity relative L2 1e-4 after 100
+steps; FP16 storage within its rounding bound."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1807_02284_amd import inputs
+from paper_1807_02284_amd.level import F16S, F32, Level, Params
+
+pytestmark = pytest.mark.gpu
+
+W = oracle.weights()
+
+
+def oparams(p: Params) -> oracle.Params:
+    return oracle.Params(nu=p.nu, nu_hi=p.nu_hi, a=p.a, b=p.b, g_max=p.g_max,
+                         adaptive=p.adaptive, tau_s=p.tau_s, beta=p.beta, s_ref=p.s_ref)
+
+
+def odomain(nx, ny, nz, periodic=7, flags=None, theta=None, p: Params | None = None):
+    return oracle.Domain(nx, ny, nz, periodic=periodic, flags=flags, theta=theta,
+                         u_in=p.u_in if p else (0, 0, 0), s_in=p.s_in if p else 0.0)
+
+
+def perturbed_start(lev: Level, dom, rho, u, noise, s=None):
+    """Equilibrium of (rho, u) on each side independently, plus the same
+    shifted-population noise."""
+    lev.init_equilibrium(rho, u, s)
+    h, g = lev.get_populations(shifted=True)
+    h += torch.as_tensor(noise, dtype=torch.float32, device=h.device)
+    lev.set_populations(h, g, shifted=True)
+    f, go = oracle.init(dom, rho, u, s=s, with_scalar=s is not None)
+    return f + noise, go
+
+
+def gpu_f64(lev: Level):
+    h, g = lev.get_populations(shifted=True)
+    torch.cuda.synchronize()
+    f = h.double().cpu().numpy() + W[:, None]
+    return f, (None if g is None else g.double().cpu().numpy())
+
+
+def rel_err(a, b):
+    return np.max(np.abs(a - b) / np.abs(b))
+
+
+CASES = [
+    # (nx, ny, nz, seed, adaptive, g_max): several x tiles with a ragged tail,
+    # odd y/z, clamp hit at some cells and not at others
+    (70, 9, 5, 1, True, 0.05),
+    (33, 17, 3, 2, True, 0.5),
+    (64, 4, 4, 3, False, 0.1),
+    (300, 3, 2, 4, True, 0.02),
+]
+
+
+@pytest.mark.parametrize("nx,ny,nz,seed,adaptive,g_max", CASES)
+def test_one_step_fp32_populations(nx, ny, nz, seed, adaptive, g_max):
+    n = nx * ny * nz
+    p = Params(nu=0.01, g_max=g_max, adaptive=adaptive)
+    rho = 1.0 + 0.02 * inputs.perturbation(n, seed)
+    u = 0.08 * inputs.perturbation((3, n), seed + 1)
+    noise = 2e-4 * inputs.perturbation((27, n), seed + 2)
+    lev = Level(nx, ny, nz, p)
+    dom = odomain(nx, ny, nz)
+    f0, _ = perturbed_start(lev, dom, rho, u, noise)
+    lev.step(1)
+    f1, _ = oracle.step(dom, oparams(p), f0)
+    got, _ = gpu_f64(lev)
+    assert rel_err(got, f1) <= 1e-6
+
+
+@pytest.mark.parametrize("nx,ny,nz,seed,adaptive,g_max", CASES[:2])
+def test_ten_steps_fp32_populations(nx, ny, nz, seed, adaptive, g_max):
+    n = nx * ny * nz
+    p = Params(nu=0.005, g_max=g_max, adaptive=adaptive)
+    rho = 1.0 + 0.01 * inputs.perturbation(n, seed)
+    u = 0.05 * inputs.perturbation((3, n), seed + 1)
+    noise = 1e-4 * inputs.perturbation((27, n), seed + 2)
+    lev = Level(nx, ny, nz, p)
+    dom = odomain(nx, ny, nz)
+    f0, _ = perturbed_start(lev, dom, rho, u, noise)
+    lev.step(10)
+    f10, _ = oracle.step(dom, oparams(p), f0, n_steps=10)
+    got, _ = gpu_f64(lev)
+    assert rel_err(got, f10) <= 1e-5
+
+
+def test_equilibrium_initialisation_matches_oracle():
+    nx, ny, nz = 40, 6, 5
+    n = nx * ny * nz
+    rho = 1.0 + 0.05 * inputs.perturbation(n, 5)
+    u = 0.1 * inputs.perturbation((3, n), 6)
+    lev = Level(nx, ny, nz, Params(nu=0.01))
+    lev.init_equilibrium(rho, u)
+    f, _ = oracle.init(odomain(nx, ny, nz), rho, u)
+    got, _ = gpu_f64(lev)
+    assert rel_err(got, f) <= 2e-7
+
+
+def test_taylor_green_32_cubed_100_steps():
+    """32^3 Taylor-Green vortex, tau = 0.6, u0 = 0.05, adaptive on."""
+    n = 32
+    p = Params(nu=0.1 / 3.0, g_max=0.1)
+    rho, u = inputs.taylor_green_3d(n, 0.05)
+    lev = Level(n, n, n, p)
+    lev.init_equilibrium(rho, u)
+    lev.step(100)
+    dom = odomain(n, n, n)
+    f, _ = oracle.init(dom, rho, u)
+    f, _ = oracle.step(dom, oparams(p), f, n_steps=100)
+    _, uo, _ = oracle.macro(dom, oparams(p), f)
+    _, ug, _ = lev.read_macro()
+    ug = ug.double().cpu().numpy()
+    rel_l2 = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+    assert rel_l2 <= 1e-4
+
+
+def test_taylor_green_2d_decay_on_gpu_matches_closed_form():
+    n = 32
+    p = Params(nu=0.1 / 3.0, g_max=0.1)
+    rho, u = inputs.taylor_green_2d(n, n, n, 0.05)
+    lev = Level(n, n, n, p)
+    lev.init_equilibrium(rho, u)
+    lev.step(100)
+    _, ug, _ = lev.read_macro()
+    ug = ug.double().cpu().numpy()
+    amp = (ug[0] * u[0]).sum() / (u[0] * u[0]).sum()
+    closed = np.exp(-2 * (0.1 / 3.0) * (2 * np.pi / n) ** 2 * 100)
+    assert amp == pytest.approx(closed, rel=0.01)
+
+
+def test_fp16_storage_one_step_within_rounding_bound():
+    nx, ny, nz = 70, 9, 5
+    n = nx * ny * nz
+    p = Params(nu=0.01, g_max=0.05)
+    rho = 1.0 + 0.02 * inputs.perturbation(n, 7)
+    u = 0.08 * inputs.perturbation((3, n), 8)
+    dom = odomain(nx, ny, nz)
+    feq, _ = oracle.init(dom, rho, u)
+    # FP16 storage holds binary16(f - w); both sides start from those values
+    h16 = (feq - W[:, None] + 2e-4 * inputs.perturbation((27, n), 9)).astype(np.float16)
+    lev = Level(nx, ny, nz, p, storage=F16S)
+    lev.set_populations(torch.as_tensor(h16.astype(np.float32)), shifted=True)
+    f0 = h16.astype(np.float64) + W[:, None]
+    lev.step(1)
+    f1, _ = oracle.step(dom, oparams(p), f0)
+    got, _ = gpu_f64(lev)
+    h1 = f1 - W[:, None]
+    bound = np.abs(h1) * 2.0 ** -11 + 2.0 ** -25 + 2e-7 * np.abs(f1)
+    assert np.all(np.abs(got - f1) <= bound)
+
+
+def test_conserved_totals_and_finite_check():
+    nx, ny, nz = 48, 10, 7
+    n = nx * ny * nz
+    p = Params(nu=0.01, g_max=0.05)
+    rho = 1.0 + 0.02 * inputs.perturbation(n, 10)
+    u = 0.05 * inputs.perturbation((3, n), 11)
+    lev = Level(nx, ny, nz, p)
+    lev.init_equilibrium(rho, u)
+    f, _ = oracle.init(odomain(nx, ny, nz), rho, u)
+    c0 = lev.conserved()
+    C = oracle.velocities()
+    assert c0[0] == pytest.approx(f.sum(), rel=1e-7)
+    np.testing.assert_allclose(c0[1:4], C.T @ f.sum(axis=1), rtol=0, atol=1e-5)
+    lev.step(50)
+    c1 = lev.conserved()
+    assert c1[0] == pytest.approx(c0[0], rel=1e-6)
+    np.testing.assert_allclose(c1[1:4], c0[1:4], rtol=0, atol=1e-4)
+    assert lev.count_nonfinite() == 0
+    lev.f[5 * lev.plane + 17] = float("nan")
+    lev.f[9 * lev.plane + 3] = float("inf")
+    assert lev.count_nonfinite() == 2
+
+
+def plume_case(nx, ny, nz):
+    fl = inputs.plume_flags(nx, ny, nz, inlet_radius=ny / 6, sphere_center=(nx * 0.3, ny / 2, nz / 2),
+                            sphere_radius=ny / 8)
+    return fl
+
+
+def test_plume_flags_scalar_five_steps():
+    nx, ny, nz = 48, 24, 20
+    n = nx * ny * nz
+    p = Params(nu=0.005, g_max=0.05, tau_s=0.51, u_in=(0.05, 0.0, 0.0), s_in=1.0)
+    fl = plume_case(nx, ny, nz)
+    rho = np.ones(n)
+    u = 0.02 * inputs.perturbation((3, n), 12)
+    s = np.clip(inputs.perturbation(n, 13), 0, None)
+    lev = Level(nx, ny, nz, p, scalar=True, periodic=0, flags=fl)
+    lev.init_equilibrium(rho, u, s)
+    dom = odomain(nx, ny, nz, periodic=0, flags=fl, p=p)
+    f, g = oracle.init(dom, rho, u, s=s)
+    lev.step(5)
+    f5, g5 = oracle.step(dom, oparams(p), f, g, n_steps=5)
+    got, gg = gpu_f64(lev)
+    assert rel_err(got, f5) <= 2e-6
+    assert np.max(np.abs(gg - g5)) <= 1e-6
+
+
+def test_body_force_and_buoyancy_three_steps():
+    nx, ny, nz = 40, 12, 10
+    n = nx * ny * nz
+    theta = 1e-4 * inputs.perturbation((3, n), 14)
+    p = Params(nu=0.01, g_max=0.05, tau_s=0.6, beta=1e-3, s_ref=0.2)
+    rho = np.ones(n)
+    u = 0.03 * inputs.perturbation((3, n), 15)
+    s = inputs.gaussian_blob(nx, ny, nz, (20, 6, 5), 3.0)
+    lev = Level(nx, ny, nz, p, scalar=True, force=theta)
+    lev.init_equilibrium(rho, u, s)
+    dom = odomain(nx, ny, nz, theta=theta, p=p)
+    f, g = oracle.init(dom, rho, u, s=s)
+    lev.step(3)
+    f3, g3 = oracle.step(dom, oparams(p), f, g, n_steps=3)
+    got, gg = gpu_f64(lev)
+    assert rel_err(got, f3) <= 2e-6
+    assert np.max(np.abs(gg - g3)) <= 1e-6
+    r, ug, sg = lev.read_macro()
+    ro, uo, so = oracle.macro(dom, oparams(p), f3, g3)
+    np.testing.assert_allclose(ug.double().cpu().numpy(), uo, rtol=0, atol=2e-7)
+    np.testing.assert_allclose(sg.double().cpu().numpy(), so, rtol=0, atol=2e-6)
+
+
+def test_bounce_back_channel_with_walls():
+    nx, ny, nz = 8, 18, 6
+    n = nx * ny * nz
+    fl = np.zeros(n, dtype=np.uint8)
+    theta = np.zeros((3, n))
+    theta[0] = 1e-5
+    p = Params(nu=0.05, g_max=0.05)
+    u = 0.01 * inputs.perturbation((3, n), 16)
+    lev = Level(nx, ny, nz, p, periodic=5, flags=fl, force=theta)
+    lev.init_equilibrium(np.ones(n), u)
+    dom = odomain(nx, ny, nz, periodic=5, flags=fl, theta=theta)
+    f, _ = oracle.init(dom, np.ones(n), u)
+    lev.step(20)
+    f20, _ = oracle.step(dom, oparams(p), f, n_steps=20)
+    got, _ = gpu_f64(lev)
+    assert rel_err(got, f20) <= 5e-6
+
+
+@pytest.mark.parametrize("storage", [F32, F16S])
+def test_full_size_256_first_step_sampled(storage):
+    """The benchmark workload (256^3 decaying turbulence, nu = 1e-5, adaptive
+    on) in the benchmark's launch configuration: one step, compared at 512
+    sampled cells with the oracle evaluated cell by cell."""
+    n = 256
+    p = Params(nu=1e-5, g_max=0.1)
+    rho, u = inputs.turbulence(n, 2, 32, 0.04, seed=1807)
+    lev = Level(n, n, n, p, storage=storage)
+    lev.init_equilibrium(rho, u)
+    lev.step(1)
+    N = n ** 3
+    rng = np.random.default_rng(1807)
+    cells = np.unique(np.concatenate([rng.integers(0, N, 500),
+                                      [0, n - 1, N - 1, N - n, n * n * (n - 1), n * (n - 1)]]))
+    # oracle input: equilibrium of (rho, u) at every cell the samples pull from
+    x, y, z = cells % n, (cells // n) % n, cells // (n * n)
+    need = set()
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                need.update((((x + dx) % n) + n * (((y + dy) % n) + n * ((z + dz) % n))).tolist())
+    need = np.array(sorted(need))
+    f0 = np.zeros((27, N))
+    for c in need:
+        f0[:, c] = oracle.equilibrium(rho[c], u[:, c])
+    dom = odomain(n, n, n)
+    ref, _ = oracle.step_cells(dom, oparams(p), f0, cells)
+    h, _ = lev.get_populations(shifted=True)
+    got = h[:, torch.as_tensor(cells, device=h.device)].double().cpu().numpy() + W[:, None]
+    if storage == F32:
+        assert rel_err(got, ref) <= 1e-6
+    else:
+        # FP16: the initial state and the result are rounded to binary16;
+        # bound the error by a few half-precision ulps of the cell's largest
+        # shifted population
+        scale = np.abs(ref - W[:, None]).max(axis=0, keepdims=True)
+        bound = 4.0 * 2.0 ** -11 * scale + 2.0 ** -24
+        assert np.all(np.abs(got - ref) <= bound)
+    c = lev.conserved()
+    assert c[0] == pytest.approx(N, rel=1e-6)
+    assert lev.count_nonfinite() == 0

@@ -46,7 +46,7 @@ struct Rates {
 
 // forward 3-point sweep: populations at c = -1, 0, +1 -> central moments of
 // order 0, 1, 2 about u
-__device__ __forceinline__ void fwd3(float& am, float& a0, float& ap, float u)
+__host__ __device__ __forceinline__ void fwd3(float& am, float& a0, float& ap, float u)
 {
     const float s0 = am + a0 + ap;
     const float s1 = ap - am;
@@ -60,7 +60,7 @@ __device__ __forceinline__ void fwd3(float& am, float& a0, float& ap, float u)
 
 // inverse 3-point sweep: central moments of order 0, 1, 2 about u ->
 // populations at c = -1, 0, +1
-__device__ __forceinline__ void inv3(float& x0, float& x1, float& x2, float u)
+__host__ __device__ __forceinline__ void inv3(float& x0, float& x1, float& x2, float u)
 {
     const float k0 = x0, k1 = x1, k2 = x2;
     const float s1 = k1 + u * k0;
@@ -71,7 +71,7 @@ __device__ __forceinline__ void inv3(float& x0, float& x1, float& x2, float u)
 }
 
 template <int STRIDE, int O1, int O2>
-__device__ __forceinline__ void sweep_fwd(float (&v)[27], float u)
+__host__ __device__ __forceinline__ void sweep_fwd(float (&v)[27], float u)
 {
 #pragma unroll
     for (int b = 0; b < 3; ++b)
@@ -83,7 +83,7 @@ __device__ __forceinline__ void sweep_fwd(float (&v)[27], float u)
 }
 
 template <int STRIDE, int O1, int O2>
-__device__ __forceinline__ void sweep_inv(float (&v)[27], float u)
+__host__ __device__ __forceinline__ void sweep_inv(float (&v)[27], float u)
 {
 #pragma unroll
     for (int b = 0; b < 3; ++b)
@@ -94,14 +94,14 @@ __device__ __forceinline__ void sweep_inv(float (&v)[27], float u)
         }
 }
 
-__device__ __forceinline__ void to_moments(float (&v)[27], float ux, float uy, float uz)
+__host__ __device__ __forceinline__ void to_moments(float (&v)[27], float ux, float uy, float uz)
 {
     sweep_fwd<1, 3, 9>(v, ux);
     sweep_fwd<3, 1, 9>(v, uy);
     sweep_fwd<9, 1, 3>(v, uz);
 }
 
-__device__ __forceinline__ void from_moments(float (&v)[27], float ux, float uy, float uz)
+__host__ __device__ __forceinline__ void from_moments(float (&v)[27], float ux, float uy, float uz)
 {
     sweep_inv<9, 1, 3>(v, uz);
     sweep_inv<3, 1, 9>(v, uy);
@@ -110,7 +110,7 @@ __device__ __forceinline__ void from_moments(float (&v)[27], float ux, float uy,
 
 // D = k^eq(rho, u) - K(u) w for every moment, dr = rho - 1.  Order-1 entries
 // are u (k^eq vanishes, K(u) w gives -u).
-__device__ __forceinline__ void deviation_equilibrium(float (&d)[27], float dr, float X, float Y,
+__host__ __device__ __forceinline__ void deviation_equilibrium(float (&d)[27], float dr, float X, float Y,
                                                       float Z)
 {
     const float X2 = X * X, Y2 = Y * Y, Z2 = Z * Z;
@@ -150,7 +150,7 @@ __device__ __forceinline__ void deviation_equilibrium(float (&d)[27], float dr, 
 
 // Macroscopic moments of shifted populations in tensor order:
 // dr = sum h, j = sum c h.
-__device__ __forceinline__ void moments0(const float (&v)[27], float& dr, float& jx, float& jy,
+__host__ __device__ __forceinline__ void moments0(const float (&v)[27], float& dr, float& jx, float& jy,
                                          float& jz)
 {
     float sx[3] = {0.f, 0.f, 0.f}, sy[3] = {0.f, 0.f, 0.f}, sz[3] = {0.f, 0.f, 0.f};
@@ -173,7 +173,7 @@ struct CellMacro {
 // Central-moment collision of one cell, in place on shifted populations.
 // F is the body force (zero when absent): u = (j + F/2)/rho and the
 // order-one central moments receive +F (source (I - S/2) R with S_1..3 = 0).
-__device__ __forceinline__ CellMacro cm_collide(float (&v)[27], const Rates& r, float Fx, float Fy,
+__host__ __device__ __forceinline__ CellMacro cm_collide(float (&v)[27], const Rates& r, float Fx, float Fy,
                                                float Fz)
 {
     float dr, jx, jy, jz;
@@ -246,7 +246,7 @@ __device__ __forceinline__ CellMacro cm_collide(float (&v)[27], const Rates& r, 
 
 // Shifted equilibrium populations h^eq = T m^eq(rho, u) - w (initialisation
 // section: f_0 = T m^eq), in tensor order.
-__device__ __forceinline__ void shifted_equilibrium(float (&v)[27], float rho, float ux, float uy,
+__host__ __device__ __forceinline__ void shifted_equilibrium(float (&v)[27], float rho, float ux, float uy,
                                                     float uz)
 {
     deviation_equilibrium(v, rho - 1.0f, ux, uy, uz);

@@ -140,6 +140,9 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the runs, copy a 1 GiB float32 tensor 3 times (reference "
+                         "kernel of known traffic for HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: only --gpus 1 is supported (asked for {args.gpus}); this build runs "
@@ -165,6 +168,17 @@ def main():
             "achieved_gbs": v["achieved_gbs"], "bytes_per_lup": BYTES_PER_LUP["f16s"],
         }
         print(f"[bench] f16s {args.n}^3: {v['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+
+    if args.copy_calibration:
+        x = torch.rand(1 << 28, device="cuda")      # 1 GiB
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print("[bench] copy calibration: 3 x (1 GiB read + 1 GiB write)", file=sys.stderr, flush=True)
+        del x, y
+        torch.cuda.empty_cache()
 
     traffic = measured_traffic("f32", args.n)
     result = {

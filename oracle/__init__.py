@@ -46,6 +46,12 @@ class _Domain(C.Structure):
                 ("theta", _dp), ("u_in", C.c_double * 3), ("s_in", C.c_double)]
 
 
+class _Scale(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("periodic", C.c_int32),
+                ("origin", C.c_double * 3), ("dx", C.c_double), ("nu", C.c_double),
+                ("tau_s", C.c_double)]
+
+
 @dataclass
 class Params:
     """Relaxation parameters (appendix values by default)."""
@@ -119,6 +125,10 @@ def lib():
         L.oracle_step_cells.argtypes = [C.POINTER(_Domain), C.POINTER(_Params), _dp, _dp,
                                         C.POINTER(C.c_int64), C.c_int64, _dp, _dp]
         L.oracle_macro.argtypes = [C.POINTER(_Domain), C.POINTER(_Params), _dp, _dp, _dp, _dp, _dp]
+        L.oracle_exchange.argtypes = [C.POINTER(_Scale), _dp, _dp, _dp, _dp, C.c_double,
+                                      C.POINTER(_Scale), C.POINTER(C.c_int64), C.c_int64, _dp, _dp]
+        L.oracle_time_interp.argtypes = [_dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
+                                         C.c_double, C.c_int64, _dp]
         _lib = L
     return _lib
 
@@ -249,3 +259,42 @@ def macro(dom: Domain, params: Params, f, g=None):
     dc, pc = dom.c(), params.c()
     lib().oracle_macro(C.byref(dc), C.byref(pc), _p(f), _p(g), _p(rho), _p(u), _p(s))
     return rho, u, s
+
+
+def _scale_c(nx, ny, nz, periodic, origin, dx, nu, tau_s=0.0) -> _Scale:
+    return _Scale(nx, ny, nz, periodic, (C.c_double * 3)(*origin), dx, nu, tau_s)
+
+
+def exchange(src: dict, fA, fB, w, dst: dict, cells, f_out, gA=None, gB=None, g_out=None):
+    """Map source-scale states (time weight w between fA and fB) onto the
+    listed cells of the destination scale; writes f_out (and g_out) in place.
+    src/dst: dicts with nx, ny, nz, periodic, origin, dx, nu, tau_s."""
+    ns = src["nx"] * src["ny"] * src["nz"]
+    nd = dst["nx"] * dst["ny"] * dst["nz"]
+    fA = _f64(fA, 27 * ns)
+    fB = _f64(fB, 27 * ns)
+    gA = None if gA is None else _f64(gA, 7 * ns)
+    gB = None if gB is None else _f64(gB, 7 * ns)
+    assert f_out.dtype == np.float64 and f_out.flags.c_contiguous and f_out.size == 27 * nd
+    if g_out is not None:
+        assert g_out.dtype == np.float64 and g_out.flags.c_contiguous and g_out.size == 7 * nd
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    sc = _scale_c(src["nx"], src["ny"], src["nz"], src["periodic"], src["origin"], src["dx"],
+                  src["nu"], src.get("tau_s", 0.0))
+    dc = _scale_c(dst["nx"], dst["ny"], dst["nz"], dst["periodic"], dst["origin"], dst["dx"],
+                  dst["nu"], dst.get("tau_s", 0.0))
+    rc = lib().oracle_exchange(C.byref(sc), _p(fA), _p(fB), _p(gA), _p(gB), float(w), C.byref(dc),
+                               cells.ctypes.data_as(C.POINTER(C.c_int64)), cells.size,
+                               _p(f_out), _p(g_out))
+    if rc != 0:
+        raise RuntimeError("oracle_exchange failed (stencil outside the source box?)")
+
+
+def time_interp(s0, s1, s2, t, t_eval):
+    s0 = _f64(s0)
+    s1 = _f64(s1, s0.size)
+    s2 = _f64(s2, s0.size)
+    out = np.empty_like(s0)
+    lib().oracle_time_interp(_p(s0), _p(s1), _p(s2), float(t[0]), float(t[1]), float(t[2]),
+                             float(t_eval), s0.size, _p(out))
+    return out

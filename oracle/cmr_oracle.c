@@ -550,3 +550,119 @@ int oracle_stream(const oracle_domain* d, const double* f, const double* g,
     }
     return 0;
 }
+
+/* ---------------------------------------------------------------------
+ * Cross-scale exchange.
+ * ------------------------------------------------------------------- */
+
+/* Source cell index along one axis with periodic wrap; -1 outside a
+ * non-periodic box. */
+static int64_t axis_index(int64_t i, int n, int periodic)
+{
+    if (i >= 0 && i < n) return i;
+    if (!periodic) return -1;
+    return ((i % n) + n) % n;
+}
+
+int oracle_exchange(const oracle_scale* src, const double* fA, const double* fB,
+                    const double* gA, const double* gB, double w,
+                    const oracle_scale* dst, const int64_t* cells, int64_t n_cells,
+                    double* f_out, double* g_out)
+{
+    const int64_t Ns = (int64_t)src->nx * src->ny * src->nz;
+    const int64_t Nd = (int64_t)dst->nx * dst->ny * dst->nz;
+    const double alpha = src->dx / dst->dx;
+    const double S_src = 1.0 / (3.0 * src->nu + 0.5);
+    const double S_dst = 1.0 / (3.0 * dst->nu + 0.5);
+    /* K^ for the stress moments m4..m8 */
+    const double kappa = (1.0 - S_dst) / (1.0 - S_src) * S_src / (alpha * S_dst);
+    const int with_scalar = gA && g_out;
+    const double kappa_s = with_scalar ? (dst->tau_s - 1.0) / (alpha * (src->tau_s - 1.0)) : 0.0;
+    int err = 0;
+#pragma omp parallel for schedule(static) reduction(| : err)
+    for (int64_t k = 0; k < n_cells; ++k) {
+        const int64_t c = cells[k];
+        if (c < 0 || c >= Nd) {
+            err |= 1;
+            continue;
+        }
+        const int x = (int)(c % dst->nx), y = (int)((c / dst->nx) % dst->ny),
+                  z = (int)(c / ((int64_t)dst->nx * dst->ny));
+        const double p[3] = {dst->origin[0] + x * dst->dx, dst->origin[1] + y * dst->dx,
+                             dst->origin[2] + z * dst->dx};
+        /* section "Spatial scale mapping": trilinear from the 8 corners of
+         * the source cell containing p */
+        int64_t base[3];
+        double t[3];
+        const int nsrc[3] = {src->nx, src->ny, src->nz};
+        for (int a = 0; a < 3; ++a) {
+            const double q = (p[a] - src->origin[a]) / src->dx;
+            base[a] = (int64_t)floor(q);
+            t[a] = q - (double)base[a];
+        }
+        double fi[27] = {0}, gi[7] = {0};
+        for (int corner = 0; corner < 8; ++corner) {
+            const int o[3] = {corner & 1, (corner >> 1) & 1, (corner >> 2) & 1};
+            double wt = 1.0;
+            int64_t idx[3];
+            for (int a = 0; a < 3; ++a) {
+                wt *= o[a] ? t[a] : 1.0 - t[a];
+                idx[a] = axis_index(base[a] + o[a], nsrc[a], src->periodic & (1 << a));
+            }
+            if (wt == 0.0) continue;
+            if (idx[0] < 0 || idx[1] < 0 || idx[2] < 0) {
+                err |= 1;
+                break;
+            }
+            const int64_t sc = idx[0] + (int64_t)src->nx * (idx[1] + (int64_t)src->ny * idx[2]);
+            for (int i = 0; i < 27; ++i)
+                fi[i] += wt * ((1.0 - w) * fA[i * Ns + sc] + w * fB[i * Ns + sc]);
+            if (with_scalar)
+                for (int i = 0; i < 7; ++i)
+                    gi[i] += wt * ((1.0 - w) * gA[i * Ns + sc] + w * gB[i * Ns + sc]);
+        }
+        /* eq. s1_to_s2_mapping: f = T (m^eq + K^ m~^neq) */
+        double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < 27; ++i) {
+            rho += fi[i];
+            j[0] += CX[i] * fi[i];
+            j[1] += CY[i] * fi[i];
+            j[2] += CZ[i] * fi[i];
+        }
+        const double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+        double M[729], m[27], meq[27], r[27], fo[27];
+        oracle_basis(u, M);
+        for (int q = 0; q < 27; ++q) {
+            double acc = 0.0;
+            for (int i = 0; i < 27; ++i) acc += M[i * 27 + q] * fi[i];
+            m[q] = acc;
+        }
+        oracle_meq(rho, u, meq);
+        for (int q = 0; q < 27; ++q) {
+            const double Kq = (q >= 4 && q <= 8) ? kappa : 1.0;
+            r[q] = meq[q] + Kq * (m[q] - meq[q]);
+        }
+        if (apply_T(u, r, fo) != 0) {
+            err |= 1;
+            continue;
+        }
+        for (int i = 0; i < 27; ++i) f_out[i * Nd + c] = fo[i];
+        if (with_scalar) {
+            double sc = 0.0, ge[7];
+            for (int i = 0; i < 7; ++i) sc += gi[i];
+            scalar_eq(sc, u, ge);
+            for (int i = 0; i < 7; ++i) g_out[i * Nd + c] = ge[i] + kappa_s * (gi[i] - ge[i]);
+        }
+    }
+    return err ? -1 : 0;
+}
+
+void oracle_time_interp(const double* s0, const double* s1, const double* s2,
+                        double t0, double t1, double t2, double t, int64_t n, double* out)
+{
+    const double l0 = (t - t1) * (t - t2) / ((t0 - t1) * (t0 - t2));
+    const double l1 = (t - t0) * (t - t2) / ((t1 - t0) * (t1 - t2));
+    const double l2 = (t - t0) * (t - t1) / ((t2 - t0) * (t2 - t1));
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < n; ++k) out[k] = l0 * s0[k] + l1 * s1[k] + l2 * s2[k];
+}

@@ -104,6 +104,44 @@ int oracle_macro(const oracle_domain* d, const oracle_params* p,
                  const double* f, const double* g,
                  double* rho, double* u, double* s);
 
+/* ------------------------------------------------------------------------
+ * Cross-scale exchange (sections "Mapping distribution functions" to
+ * "Handling multiple scales").
+ * ---------------------------------------------------------------------- */
+
+/* Geometry and relaxation of one scale: lattice point (x, y, z) sits at the
+ * physical position origin + (x, y, z) * dx. */
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t periodic;      /* bit mask as in oracle_domain */
+    double origin[3];
+    double dx;             /* physical spacing of this scale */
+    double nu;             /* shear viscosity in this scale's lattice units */
+    double tau_s;          /* scalar relaxation time (0: no scalar) */
+} oracle_scale;
+
+/* Post-collision mapping from scale `src` to the cells `cells` of scale
+ * `dst` (eq. s1_to_s2_mapping): the source state at the time weight w is
+ * (1 - w) fA + w fB; it is interpolated trilinearly from the 8 corners of the
+ * source cell that contains each target point, and the mapped populations
+ * are T(m^eq + K^ m~^neq) with K^ = (I - S^dst) K (I - S^src)^-1, K = diag
+ * with S_k^src / (alpha S_k^dst) for k = 4..8 and 1 elsewhere, alpha =
+ * dx_src / dx_dst.  Only m4..m8 are rescaled (the higher-order rates are
+ * the same lattice quantities on every scale).  The scalar (if gA != NULL
+ * and g_out != NULL) is interpolated the same way and its non-equilibrium
+ * part g - g^eq(s, u) scaled by (tau_dst - 1) / (alpha (tau_src - 1)).
+ * Writes f_out[i*N_dst + cell] for the listed cells only.  fB may equal fA.
+ * Returns -1 if a stencil leaves a non-periodic source box. */
+int oracle_exchange(const oracle_scale* src, const double* fA, const double* fB,
+                    const double* gA, const double* gB, double w,
+                    const oracle_scale* dst, const int64_t* cells, int64_t n_cells,
+                    double* f_out, double* g_out);
+
+/* Lagrange quadratic through (t0, s0), (t1, s1), (t2, s2) evaluated at t:
+ * out[k] for k < n (section "Temporal alignment and scale mapping"). */
+void oracle_time_interp(const double* s0, const double* s1, const double* s2,
+                        double t0, double t1, double t2, double t, int64_t n, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,165 @@
+"""Plain multi-scale scheduler of the oracle (Algorithm 1 and the sections
+"Temporal alignment and scale mapping" and "Handling multiple scales").
+
+TEST INFRASTRUCTURE ONLY.  Written independently of the GPU driver: it calls
+the oracle's step, exchange and time-interpolation functions in the order of
+Algorithm 1, with the readings listed below.
+
+Readings (each also listed in the design doc):
+  * scale 0 is the reference scale s0 and covers the whole domain; every
+    other scale is a box of lattice points origin + (x, y, z) dx nested in
+    its parent, the nearest coarser scale (scale i - 1);
+  * the boundary of a finer scale is its one-cell outer shell (GHOST cells):
+    never collided, written only by prior-mapping;
+  * alpha_i = dx_0 / dx_i; the scale's viscosity is alpha_i nu_0 (invariant
+    local Reynolds number, eq. S_relation); l = floor(alpha_i) + 1 sub-steps;
+  * before sub-step k the shell is prior-mapped from the parent at the time
+    weight (k - 1) / alpha_i between the parent's states at t_n and
+    t_n + dt_0 (the pull reads the shell at the sub-step's start time);
+  * after the sub-steps the whole scale is interpolated in time by the
+    quadratic through t = 0, (l - 1)/alpha_i, l/alpha_i evaluated at 1, and
+    the shell is mapped again from the parent at t_n + dt_0;
+  * post-mapping writes every coarser scale j < i at its FLUID cells whose
+    trilinear stencil in scale i consists of FLUID cells of scale i.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import FLUID, GHOST, SOLID, Domain, Params, exchange, step, time_interp
+
+
+@dataclass
+class OScale:
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    origin: tuple
+    params: Params               # nu already in this scale's lattice units
+    flags: np.ndarray            # uint8 [N]; finer scales carry a GHOST shell
+    periodic: int = 0
+    parent: int = -1
+    u_in: tuple = (0.0, 0.0, 0.0)
+    s_in: float = 0.0
+    f: np.ndarray | None = None  # [27][N] state at the current reference time
+    g: np.ndarray | None = None  # [7][N] or None
+    ghosts: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
+    post: dict = field(default_factory=dict)   # coarser scale index -> cells of that scale
+
+    @property
+    def n(self):
+        return self.nx * self.ny * self.nz
+
+    def domain(self) -> Domain:
+        return Domain(self.nx, self.ny, self.nz, periodic=self.periodic, flags=self.flags,
+                      u_in=self.u_in, s_in=self.s_in)
+
+    def geom(self) -> dict:
+        return dict(nx=self.nx, ny=self.ny, nz=self.nz, periodic=self.periodic,
+                    origin=tuple(self.origin), dx=self.dx, nu=self.params.nu,
+                    tau_s=self.params.tau_s if self.g is not None else 0.0)
+
+    def positions(self):
+        z, y, x = np.meshgrid(np.arange(self.nz), np.arange(self.ny), np.arange(self.nx),
+                              indexing="ij")
+        return (self.origin[0] + x.reshape(-1) * self.dx, self.origin[1] + y.reshape(-1) * self.dx,
+                self.origin[2] + z.reshape(-1) * self.dx)
+
+
+def shell_ghosts(s: OScale) -> np.ndarray:
+    return np.flatnonzero(s.flags == GHOST).astype(np.int64)
+
+
+def post_targets(coarse: OScale, fine: OScale) -> np.ndarray:
+    """Cells of `coarse` to be overwritten from `fine`: FLUID cells whose
+    trilinear stencil in `fine` (corners with non-zero weight) lies inside
+    the fine box and consists of FLUID cells."""
+    px, py, pz = coarse.positions()
+    out = []
+    for c in np.flatnonzero(coarse.flags == FLUID):
+        p = (px[c], py[c], pz[c])
+        ok = True
+        base, frac = [], []
+        for a, n in enumerate((fine.nx, fine.ny, fine.nz)):
+            q = (p[a] - fine.origin[a]) / fine.dx
+            b = math.floor(q)
+            base.append(b)
+            frac.append(q - b)
+        for corner in range(8):
+            o = (corner & 1, (corner >> 1) & 1, (corner >> 2) & 1)
+            wt = 1.0
+            for a in range(3):
+                wt *= frac[a] if o[a] else 1.0 - frac[a]
+            if wt == 0.0:
+                continue
+            idx = [base[a] + o[a] for a in range(3)]
+            if not (0 <= idx[0] < fine.nx and 0 <= idx[1] < fine.ny and 0 <= idx[2] < fine.nz):
+                ok = False
+                break
+            fc = idx[0] + fine.nx * (idx[1] + fine.ny * idx[2])
+            if fine.flags[fc] != FLUID:
+                ok = False
+                break
+        if ok:
+            out.append(c)
+    return np.array(out, dtype=np.int64)
+
+
+def prepare(scales: list[OScale]):
+    """Fill the ghost and post-mapping lists of every finer scale."""
+    for i, s in enumerate(scales):
+        if i == 0:
+            continue
+        s.ghosts = shell_ghosts(s)
+        s.post = {j: post_targets(scales[j], s) for j in range(i)}
+
+
+def multiscale_step(scales: list[OScale], n_ref: int = 1):
+    """Advance every scale by n_ref reference steps (Algorithm 1)."""
+    for _ in range(n_ref):
+        s0 = scales[0]
+        A0, B0 = s0.f, None
+        gA0 = s0.g
+        f1, g1 = step(s0.domain(), s0.params, s0.f, s0.g)
+        B0, gB0 = f1, g1
+        states = {0: (A0, B0, gA0, gB0)}
+        for i in range(1, len(scales)):
+            s = scales[i]
+            par = scales[s.parent]
+            Ap, Bp, gAp, gBp = states[s.parent]
+            alpha = scales[0].dx / s.dx                  # dx_0 / dx_i
+            l = math.floor(alpha) + 1
+            X0 = s.f.copy()
+            gX0 = None if s.g is None else s.g.copy()
+            cur, gcur = X0.copy(), None if gX0 is None else gX0.copy()
+            hist = [(X0, gX0)]
+            for k in range(1, l + 1):
+                w = (k - 1) / alpha
+                exchange(par.geom(), Ap, Bp, w, s.geom(), s.ghosts, cur, gAp, gBp, gcur)
+                if k == 1:
+                    X0 = cur.copy()
+                    gX0 = None if gcur is None else gcur.copy()
+                    hist[0] = (X0, gX0)
+                cur, gcur = step(s.domain(), s.params, cur, gcur)
+                hist.append((cur, gcur))
+            t = (0.0, (l - 1) / alpha, l / alpha)
+            R = time_interp(hist[0][0], hist[l - 1][0], hist[l][0], t, 1.0).reshape(27, s.n)
+            gR = None
+            if s.g is not None:
+                gR = time_interp(hist[0][1], hist[l - 1][1], hist[l][1], t, 1.0).reshape(7, s.n)
+            exchange(par.geom(), Ap, Bp, 1.0, s.geom(), s.ghosts, R, gAp, gBp, gR)
+            states[i] = (X0, R, gX0, gR)
+            for j in range(i):
+                tgt = s.post.get(j)
+                if tgt is None or tgt.size == 0:
+                    continue
+                Bj, gBj = states[j][1], states[j][3]
+                exchange(s.geom(), R, R, 0.0, scales[j].geom(), tgt, Bj, gR, gR, gBj)
+        for i, s in enumerate(scales):
+            s.f = states[i][1]
+            s.g = states[i][3]
+    return scales

@@ -160,6 +160,89 @@ int cslbm_conserved_f64(const cslbm_level* L, double out[5], hipStream_t stream)
  * Returns CSLBM_ERR_NONFINITE when the count is non-zero; synchronises. */
 int cslbm_check_finite(const cslbm_level* L, int64_t* n_bad, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Continuous scales (sections "Mapping distribution functions",
+ * "Spatial scale mapping", "Temporal alignment and scale mapping",
+ * "Handling multiple scales", Algorithm 1).
+ *
+ * Every scale is a cslbm_level whose lattice point (x, y, z) sits at the
+ * physical position origin + (x, y, z) * dx.  Its parameters are in its own
+ * lattice units: a scale with spacing dx_i = dx_0 / alpha_i carries
+ * nu_i = alpha_i nu_0 (invariant local Reynolds number, eq. S_relation).
+ * ---------------------------------------------------------------------- */
+
+/* Post-collision mapping from scale `src` onto the listed cells of scale
+ * `dst` (eq. s1_to_s2_mapping with the trilinear interpolation of section
+ * "Spatial scale mapping"):
+ *   1. the source state at time weight w is (1 - w) fA + w fB (fB may be
+ *      NULL when w == 0);
+ *   2. it is interpolated trilinearly from the 8 corners of the source cell
+ *      containing the target point (periodic wrap on periodic source axes);
+ *   3. f~dst = T(m^eq + K^ m~neq) with K^ = (I - S^dst) K (I - S^src)^-1,
+ *      K = S^src / (alpha S^dst) on the stress moments m4..m8 and 1 on every
+ *      other moment; alpha = src->dx / dst->dx.
+ * The scalar (gA and g_out non-NULL) is interpolated the same way and its
+ * non-equilibrium part scaled by (tau_dst - 1) / (alpha (tau_src - 1)).
+ * fA/fB/gA/gB use src's storage and plane stride; f_out/g_out use dst's.
+ * cells: device int32 list of n_cells distinct dst cells; every stencil must
+ * lie inside the source box on non-periodic axes (the caller's lists are
+ * trusted; out-of-box corners are clamped, never read out of bounds).
+ * Errors: CSLBM_ERR_ARG for NULL buffers, w outside [0, 1], a source
+ * relaxation time of exactly 1 (singular (I - S)^-1). */
+int cslbm_exchange(const cslbm_level* src, const void* fA, const void* fB, const float* gA,
+                   const float* gB, double w, const cslbm_level* dst, void* f_out, float* g_out,
+                   const int32_t* cells, int32_t n_cells, hipStream_t stream);
+
+/* Quadratic Lagrange interpolation in time of three states of level L at
+ * times t[0..2] (distinct), evaluated at t_eval, into out (and g_out from
+ * g0..g2 when all are non-NULL); every plane element of every cell
+ * (section "Temporal alignment and scale mapping"). */
+int cslbm_time_interp(const cslbm_level* L, const void* s0, const void* s1, const void* s2,
+                      const float* g0, const float* g1, const float* g2, const double t[3],
+                      double t_eval, void* out, float* g_out, hipStream_t stream);
+
+#define CSLBM_MAX_SCALES 8
+
+/* One scale of a hierarchy.  level.f holds the scale's state at the current
+ * reference time (read and written); level.f_next and work_f[0..1] (and the
+ * scalar counterparts) are work space of the same size.  Scale 0 is the
+ * reference scale: parent -1, no work buffers or lists needed. */
+typedef struct cslbm_scale {
+    cslbm_level level;
+    void* work_f[2];                    /* [27][plane] each (finer scales) */
+    float* work_g[2];                   /* [7][plane] each when level.g != NULL */
+    int32_t parent;                     /* nearest coarser scale, or -1 */
+    int32_t n_ghost;
+    const int32_t* ghost_cells;         /* device: this scale's boundary cells
+                                           (CSLBM_GHOST), written by prior-mapping */
+    int32_t n_post[CSLBM_MAX_SCALES];
+    const int32_t* post_cells[CSLBM_MAX_SCALES];  /* device: cells of coarser scale j
+                                                     written by post-mapping */
+} cslbm_scale;
+
+typedef struct cslbm_hierarchy {
+    int32_t n_scales;                   /* 1..CSLBM_MAX_SCALES */
+    int32_t reserved;
+    cslbm_scale* scales;                /* HOST array of n_scales scales */
+} cslbm_hierarchy;
+
+/* n_ref_steps reference steps of Algorithm 1.  Per reference step:
+ *   - scale 0 takes one step (its states at t_n and t_n + dt_0 stay in
+ *     level.f_next and level.f);
+ *   - each finer scale i (in index order) with alpha_i = dx_0 / dx_i takes
+ *     l = floor(alpha_i) + 1 sub-steps; before sub-step k its ghost cells
+ *     are prior-mapped from the parent's states at time weight
+ *     (k - 1) / alpha_i; the result is interpolated in time by the
+ *     quadratic through 0, (l - 1)/alpha_i, l/alpha_i evaluated at 1; the
+ *     ghosts are mapped again at weight 1; then the scale is post-mapped
+ *     onto post_cells[j] of every coarser scale j < i;
+ *   - the interpolated states become the finer scales' level.f (pointer
+ *     swap with work_f[1] / work_g[1]).
+ * Finer scales need flags with a CSLBM_GHOST shell; every scale must carry
+ * the scalar or none.  Errors: CSLBM_ERR_ARG for an inconsistent
+ * hierarchy (parents, spacings, buffers, lists, singular relaxation times). */
+int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t stream);
+
 /* sizeof(cslbm_params) and sizeof(cslbm_level) as compiled into the
  * library (HOST pointers), so that bindings can verify their struct layout
  * before the first call.  Always CSLBM_OK. */

@@ -57,6 +57,27 @@ class CslbmLevel(C.Structure):
     ]
 
 
+MAX_SCALES = 8
+
+
+class CslbmScale(C.Structure):
+    _fields_ = [
+        ("level", CslbmLevel),
+        ("work_f", _vp * 2),
+        ("work_g", _vp * 2),
+        ("parent", C.c_int32),
+        ("n_ghost", C.c_int32),
+        ("ghost_cells", _vp),
+        ("n_post", C.c_int32 * MAX_SCALES),
+        ("post_cells", _vp * MAX_SCALES),
+    ]
+
+
+class CslbmHierarchy(C.Structure):
+    _fields_ = [("n_scales", C.c_int32), ("reserved", C.c_int32),
+                ("scales", C.POINTER(CslbmScale))]
+
+
 class CslbmError(RuntimeError):
     def __init__(self, code: int, func: str, msg: str):
         super().__init__(f"{func} failed with status {code}: {msg}")
@@ -75,6 +96,11 @@ _SIGNATURES = {
     "cslbm_read_macro": (C.c_int, [C.POINTER(CslbmLevel), _vp, _vp, _vp, _vp]),
     "cslbm_conserved_f64": (C.c_int, [C.POINTER(CslbmLevel), C.POINTER(C.c_double), _vp]),
     "cslbm_check_finite": (C.c_int, [C.POINTER(CslbmLevel), C.POINTER(C.c_int64), _vp]),
+    "cslbm_exchange": (C.c_int, [C.POINTER(CslbmLevel), _vp, _vp, _vp, _vp, C.c_double,
+                                 C.POINTER(CslbmLevel), _vp, _vp, _vp, C.c_int32, _vp]),
+    "cslbm_time_interp": (C.c_int, [C.POINTER(CslbmLevel), _vp, _vp, _vp, _vp, _vp, _vp,
+                                    C.POINTER(C.c_double), C.c_double, _vp, _vp, _vp]),
+    "cslbm_multiscale_step": (C.c_int, [C.POINTER(CslbmHierarchy), C.c_int32, _vp]),
     "cslbm_abi_sizes": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "cslbm_last_error": (C.c_char_p, []),
 }

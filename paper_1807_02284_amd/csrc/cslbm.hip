@@ -16,6 +16,7 @@
 
 #include "../../include/cslbm.h"
 #include "cm_collide.hpp"
+#include "internal.hpp"
 #include "lattice.hpp"
 
 namespace cslbm {
@@ -25,7 +26,7 @@ namespace cslbm {
 // ---------------------------------------------------------------------------
 static thread_local std::string g_last_error;
 
-static int fail(int code, const char* fmt, ...)
+int fail(int code, const char* fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -36,39 +37,12 @@ static int fail(int code, const char* fmt, ...)
     return code;
 }
 
-static int check_launch(const char* what)
+int check_launch(const char* what)
 {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(CSLBM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
     return CSLBM_OK;
 }
-
-#define CSLBM_HIP_TRY(call)                                                                 \
-    do {                                                                                    \
-        const hipError_t e_ = (call);                                                       \
-        if (e_ != hipSuccess) return fail(CSLBM_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
-    } while (0)
-
-// ---------------------------------------------------------------------------
-// storage traits: FP32 or IEEE binary16 shifted populations
-// ---------------------------------------------------------------------------
-template <typename T>
-struct Io;
-
-template <>
-struct Io<float> {
-    static __device__ __forceinline__ float ld(const float* p) { return *p; }
-    static __device__ __forceinline__ void st(float* p, float v) { __builtin_nontemporal_store(v, p); }
-};
-
-template <>
-struct Io<_Float16> {
-    static __device__ __forceinline__ float ld(const _Float16* p) { return static_cast<float>(*p); }
-    static __device__ __forceinline__ void st(_Float16* p, float v)
-    {
-        __builtin_nontemporal_store(static_cast<_Float16>(v), p);   // round to nearest even
-    }
-};
 
 // ---------------------------------------------------------------------------
 // kernel arguments
@@ -444,9 +418,9 @@ __global__ void k_count_nonfinite(const T* f, const float* g, int64_t N, int64_t
 // ---------------------------------------------------------------------------
 // host side: validation and launches
 // ---------------------------------------------------------------------------
-static int64_t cells_of(const cslbm_level* L) { return (int64_t)L->nx * L->ny * L->nz; }
+int64_t cells_of(const cslbm_level* L) { return (int64_t)L->nx * L->ny * L->nz; }
 
-static int validate_shape(const cslbm_level* L)
+int validate_shape(const cslbm_level* L)
 {
     if (!L) return fail(CSLBM_ERR_ARG, "level is NULL");
     if (L->nx < 1 || L->ny < 1 || L->nz < 1)
@@ -471,7 +445,7 @@ static int validate_shape(const cslbm_level* L)
     return CSLBM_OK;
 }
 
-static int validate_params(const cslbm_level* L)
+int validate_params(const cslbm_level* L)
 {
     const cslbm_params& p = L->p;
     if (!(p.nu > 0.0) || !std::isfinite(p.nu))
@@ -492,7 +466,7 @@ static int validate_params(const cslbm_level* L)
     return CSLBM_OK;
 }
 
-static Rates make_rates(const cslbm_params& p)
+Rates make_rates(const cslbm_params& p)
 {
     Rates r;
     r.S = (float)(1.0 / (3.0 * p.nu + 0.5));
@@ -535,6 +509,37 @@ static void dispatch_step(const StepArgs& a, bool flags, bool force, bool scalar
 }
 
 static inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+int launch_step_into(const cslbm_level* L, const void* fin, void* fout, const float* gin,
+                     float* gout, hipStream_t stream)
+{
+    StepArgs a;
+    a.f = fin;
+    a.fo = fout;
+    a.g = gin;
+    a.go = gout;
+    a.flags = L->flags;
+    a.force = L->force;
+    a.nx = L->nx;
+    a.ny = L->ny;
+    a.nz = L->nz;
+    a.periodic = L->periodic & 7;
+    a.plane = L->plane;
+    a.r = make_rates(L->p);
+    a.beta = (float)L->p.beta;
+    a.s_ref = (float)L->p.s_ref;
+    a.inv_tau_s = gin ? (float)(1.0 / L->p.tau_s) : 0.0f;
+    for (int k = 0; k < 3; ++k) a.u_in[k] = (float)L->p.u_in[k];
+    a.s_in = (float)L->p.s_in;
+    const bool has_flags = L->flags != nullptr;
+    const bool has_force = L->force != nullptr;
+    const bool has_scalar = gin != nullptr;
+    if (L->storage == CSLBM_F32)
+        dispatch_step<float>(a, has_flags, has_force, has_scalar, stream);
+    else
+        dispatch_step<_Float16>(a, has_flags, has_force, has_scalar, stream);
+    return check_launch("k_step");
+}
 
 }  // namespace cslbm
 
@@ -634,33 +639,8 @@ int cslbm_step(cslbm_level* L, int32_t n_steps, hipStream_t stream)
     if (L->f == L->f_next) return fail(CSLBM_ERR_ARG, "f and f_next alias");
     if (L->g && L->g == L->g_next) return fail(CSLBM_ERR_ARG, "g and g_next alias");
 
-    StepArgs a;
-    a.flags = L->flags;
-    a.force = L->force;
-    a.nx = L->nx;
-    a.ny = L->ny;
-    a.nz = L->nz;
-    a.periodic = L->periodic & 7;
-    a.plane = L->plane;
-    a.r = make_rates(L->p);
-    a.beta = (float)L->p.beta;
-    a.s_ref = (float)L->p.s_ref;
-    a.inv_tau_s = L->g ? (float)(1.0 / L->p.tau_s) : 0.0f;
-    for (int k = 0; k < 3; ++k) a.u_in[k] = (float)L->p.u_in[k];
-    a.s_in = (float)L->p.s_in;
-    const bool has_flags = L->flags != nullptr;
-    const bool has_force = L->force != nullptr;
-    const bool has_scalar = L->g != nullptr;
     for (int n = 0; n < n_steps; ++n) {
-        a.f = L->f;
-        a.fo = L->f_next;
-        a.g = L->g;
-        a.go = L->g_next;
-        if (L->storage == CSLBM_F32)
-            dispatch_step<float>(a, has_flags, has_force, has_scalar, stream);
-        else
-            dispatch_step<_Float16>(a, has_flags, has_force, has_scalar, stream);
-        rc = check_launch("k_step");
+        rc = launch_step_into(L, L->f, L->f_next, L->g, L->g_next, stream);
         if (rc) return rc;
         void* t = L->f;
         L->f = L->f_next;

@@ -1,0 +1,52 @@
+// internal.hpp -- declarations shared by the translation units of libcslbm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/cslbm.h"
+#include "cm_collide.hpp"
+
+namespace cslbm {
+
+// error reporting: fail() records a thread-local message and returns code
+int fail(int code, const char* fmt, ...);
+int check_launch(const char* what);
+
+#define CSLBM_HIP_TRY(call)                                                                      \
+    do {                                                                                         \
+        const hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) return ::cslbm::fail(CSLBM_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// storage traits: FP32 or IEEE binary16 shifted populations
+template <typename T>
+struct Io;
+
+template <>
+struct Io<float> {
+    static __device__ __forceinline__ float ld(const float* p) { return *p; }
+    static __device__ __forceinline__ void st(float* p, float v) { __builtin_nontemporal_store(v, p); }
+};
+
+template <>
+struct Io<_Float16> {
+    static __device__ __forceinline__ float ld(const _Float16* p) { return static_cast<float>(*p); }
+    static __device__ __forceinline__ void st(_Float16* p, float v)
+    {
+        __builtin_nontemporal_store(static_cast<_Float16>(v), p);   // round to nearest even
+    }
+};
+
+int64_t cells_of(const cslbm_level* L);
+int validate_shape(const cslbm_level* L);
+int validate_params(const cslbm_level* L);
+Rates make_rates(const cslbm_params& p);
+
+// One collide-stream step of level L from (fin, gin) into (fout, gout);
+// L's own f/g pointers are not used.  Arguments must be validated.
+int launch_step_into(const cslbm_level* L, const void* fin, void* fout, const float* gin,
+                     float* gout, hipStream_t stream);
+
+}  // namespace cslbm

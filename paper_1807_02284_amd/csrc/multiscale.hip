@@ -1,0 +1,412 @@
+// multiscale.hip -- cross-scale exchange, temporal interpolation and the
+// reference-step driver (Algorithm 1) of libcslbm (gfx950).
+//
+// Exchange (eq. s1_to_s2_mapping): f~^dst = T(m^eq + K^ m~^neq,src) with
+// K^ = (I - S^dst) K (I - S^src)^-1 and K = diag(S^src / (alpha S^dst)) on
+// the stress moments m4..m8, 1 elsewhere.  In the central-moment frame of the
+// interpolated state this touches only the second-order moments: the
+// off-diagonal non-equilibrium k110, k101, k011 and the deviatoric part of
+// the diagonal (m7 = k200 - k020, m8 = k200 - k002) are multiplied by
+//   kappa = (1 - S_dst) / (1 - S_src) * S_src / (alpha S_dst),
+// the trace (m9) and every other moment are carried over.  One thread per
+// target cell; the 8-corner trilinear stencil (section "Spatial scale
+// mapping") reads the source scale's states at two times and blends them
+// with the time weight w (section "Temporal alignment and scale mapping").
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <utility>
+
+#include "../../include/cslbm.h"
+#include "cm_collide.hpp"
+#include "internal.hpp"
+#include "lattice.hpp"
+
+namespace cslbm {
+
+struct ExchArgs {
+    const void* fA;
+    const void* fB;
+    const float* gA;
+    const float* gB;
+    int snx, sny, snz, speriodic;
+    int64_t splane;
+    double sorigin[3], sdx;
+    void* fo;
+    float* go;
+    int dnx, dny;
+    int64_t dplane;
+    double dorigin[3], ddx;
+    const int32_t* cells;
+    int n_cells;
+    float w;
+    float kappa;     // stress rescaling
+    float kappa_s;   // scalar non-equilibrium rescaling
+};
+
+__device__ __forceinline__ int wrap_or_clamp(int i, int n, bool periodic)
+{
+    if (periodic) {
+        i %= n;
+        return i < 0 ? i + n : i;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);   // lists are validated on the host
+}
+
+template <typename Ts, typename Td>
+__global__ void __launch_bounds__(256) k_exchange(const ExchArgs a)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n_cells) return;
+    const int c = a.cells[k];
+    const int x = c % a.dnx, y = (c / a.dnx) % a.dny, z = c / (a.dnx * a.dny);
+    // geometry in FP64 so that coincident nodes resolve exactly
+    const double p[3] = {a.dorigin[0] + x * a.ddx, a.dorigin[1] + y * a.ddx, a.dorigin[2] + z * a.ddx};
+    int base[3];
+    float t[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double q = (p[d] - a.sorigin[d]) / a.sdx;
+        const double b = floor(q);
+        base[d] = (int)b;
+        t[d] = (float)(q - b);
+    }
+    const int n[3] = {a.snx, a.sny, a.snz};
+    int ix[2], iy[2], iz[2];
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+        ix[o] = wrap_or_clamp(base[0] + o, n[0], a.speriodic & 1);
+        iy[o] = wrap_or_clamp(base[1] + o, n[1], a.speriodic & 2);
+        iz[o] = wrap_or_clamp(base[2] + o, n[2], a.speriodic & 4);
+    }
+    const Ts* fA = static_cast<const Ts*>(a.fA);
+    const Ts* fB = static_cast<const Ts*>(a.fB);
+    const float w = a.w;
+    float v[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) v[q] = 0.0f;
+    float gi[QS] = {0, 0, 0, 0, 0, 0, 0};
+    const bool scalar = a.gA != nullptr && a.go != nullptr;
+#pragma unroll
+    for (int corner = 0; corner < 8; ++corner) {
+        const int ox = corner & 1, oy = (corner >> 1) & 1, oz = (corner >> 2) & 1;
+        const float wt = (ox ? t[0] : 1.0f - t[0]) * (oy ? t[1] : 1.0f - t[1]) *
+                         (oz ? t[2] : 1.0f - t[2]);
+        if (wt == 0.0f) continue;
+        const int64_t sc = ix[ox] + (int64_t)a.snx * (iy[oy] + (int64_t)a.sny * iz[oz]);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const float hA = Io<Ts>::ld(fA + i * a.splane + sc);
+            const float hB = (w != 0.0f) ? Io<Ts>::ld(fB + i * a.splane + sc) : hA;
+            v[tensor_slot(i)] += wt * ((1.0f - w) * hA + w * hB);
+        }
+        if (scalar) {
+#pragma unroll
+            for (int i = 0; i < QS; ++i) {
+                const float gA = a.gA[i * a.splane + sc];
+                const float gB = (w != 0.0f) ? a.gB[i * a.splane + sc] : gA;
+                gi[i] += wt * ((1.0f - w) * gA + w * gB);
+            }
+        }
+    }
+
+    // central-moment frame of the interpolated post-collision state
+    float dr, jx, jy, jz;
+    moments0(v, dr, jx, jy, jz);
+    const float inv_rho = 1.0f / (1.0f + dr);
+    const float ux = jx * inv_rho, uy = jy * inv_rho, uz = jz * inv_rho;
+    to_moments(v, ux, uy, uz);
+    float d[27];
+    deviation_equilibrium(d, dr, ux, uy, uz);
+    const float kap = a.kappa;
+    v[kslot(1, 1, 0)] = d[kslot(1, 1, 0)] + kap * (v[kslot(1, 1, 0)] - d[kslot(1, 1, 0)]);
+    v[kslot(1, 0, 1)] = d[kslot(1, 0, 1)] + kap * (v[kslot(1, 0, 1)] - d[kslot(1, 0, 1)]);
+    v[kslot(0, 1, 1)] = d[kslot(0, 1, 1)] + kap * (v[kslot(0, 1, 1)] - d[kslot(0, 1, 1)]);
+    const float nxx = v[kslot(2, 0, 0)] - d[kslot(2, 0, 0)];
+    const float nyy = v[kslot(0, 2, 0)] - d[kslot(0, 2, 0)];
+    const float nzz = v[kslot(0, 0, 2)] - d[kslot(0, 0, 2)];
+    const float tr = (nxx + nyy + nzz) * (1.0f / 3.0f);
+    v[kslot(2, 0, 0)] = d[kslot(2, 0, 0)] + kap * (nxx - tr) + tr;
+    v[kslot(0, 2, 0)] = d[kslot(0, 2, 0)] + kap * (nyy - tr) + tr;
+    v[kslot(0, 0, 2)] = d[kslot(0, 0, 2)] + kap * (nzz - tr) + tr;
+    from_moments(v, ux, uy, uz);
+
+    Td* fo = static_cast<Td*>(a.fo);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) Io<Td>::st(fo + i * a.dplane + c, v[tensor_slot(i)]);
+    if (scalar) {
+        const float s = (gi[0] + (gi[1] + gi[2])) + ((gi[3] + gi[4]) + (gi[5] + gi[6]));
+#pragma unroll
+        for (int i = 0; i < QS; ++i) {
+            const float ge = kSw[i] * s * (1.0f + 4.0f * (kSx[i] * ux + kSy[i] * uy + kSz[i] * uz));
+            a.go[i * a.dplane + c] = ge + a.kappa_s * (gi[i] - ge);
+        }
+    }
+}
+
+// Lagrange quadratic in time, element by element over all planes
+template <typename T>
+__global__ void __launch_bounds__(256) k_time_interp(const T* s0, const T* s1, const T* s2,
+                                                     T* out, const float* g0, const float* g1,
+                                                     const float* g2, float* gout, int64_t N,
+                                                     int64_t P, float l0, float l1, float l2)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int64_t e = i * P + c;
+        Io<T>::st(out + e, l0 * Io<T>::ld(s0 + e) + l1 * Io<T>::ld(s1 + e) + l2 * Io<T>::ld(s2 + e));
+    }
+    if (gout)
+#pragma unroll
+        for (int i = 0; i < QS; ++i) {
+            const int64_t e = i * P + c;
+            gout[e] = l0 * g0[e] + l1 * g1[e] + l2 * g2[e];
+        }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static double shear_rate(const cslbm_level* L) { return 1.0 / (3.0 * L->p.nu + 0.5); }
+
+static int launch_exchange(const cslbm_level* src, const void* fA, const void* fB, const float* gA,
+                           const float* gB, double w, const cslbm_level* dst, void* f_out,
+                           float* g_out, const int32_t* cells, int32_t n_cells, hipStream_t stream)
+{
+    if (n_cells == 0) return CSLBM_OK;
+    ExchArgs a;
+    a.fA = fA;
+    a.fB = fB ? fB : fA;
+    const bool scalar = gA && g_out;
+    a.gA = scalar ? gA : nullptr;
+    a.gB = scalar ? (gB ? gB : gA) : nullptr;
+    a.snx = src->nx;
+    a.sny = src->ny;
+    a.snz = src->nz;
+    a.speriodic = src->periodic & 7;
+    a.splane = src->plane;
+    std::memcpy(a.sorigin, src->origin, sizeof a.sorigin);
+    a.sdx = src->dx;
+    a.fo = f_out;
+    a.go = scalar ? g_out : nullptr;
+    a.dnx = dst->nx;
+    a.dny = dst->ny;
+    a.dplane = dst->plane;
+    std::memcpy(a.dorigin, dst->origin, sizeof a.dorigin);
+    a.ddx = dst->dx;
+    a.cells = cells;
+    a.n_cells = n_cells;
+    a.w = (float)w;
+    const double alpha = src->dx / dst->dx;
+    const double Ss = shear_rate(src), Sd = shear_rate(dst);
+    a.kappa = (float)((1.0 - Sd) / (1.0 - Ss) * Ss / (alpha * Sd));
+    a.kappa_s = scalar ? (float)((dst->p.tau_s - 1.0) / (alpha * (src->p.tau_s - 1.0))) : 0.0f;
+    const dim3 grid((n_cells + 255) / 256), block(256);
+    const bool s32 = src->storage == CSLBM_F32, d32 = dst->storage == CSLBM_F32;
+    if (s32 && d32)
+        hipLaunchKernelGGL((k_exchange<float, float>), grid, block, 0, stream, a);
+    else if (s32)
+        hipLaunchKernelGGL((k_exchange<float, _Float16>), grid, block, 0, stream, a);
+    else if (d32)
+        hipLaunchKernelGGL((k_exchange<_Float16, float>), grid, block, 0, stream, a);
+    else
+        hipLaunchKernelGGL((k_exchange<_Float16, _Float16>), grid, block, 0, stream, a);
+    return check_launch("k_exchange");
+}
+
+static int launch_time_interp(const cslbm_level* L, const void* s0, const void* s1, const void* s2,
+                              const float* g0, const float* g1, const float* g2, const double t[3],
+                              double te, void* out, float* g_out, hipStream_t stream)
+{
+    const double l0 = (te - t[1]) * (te - t[2]) / ((t[0] - t[1]) * (t[0] - t[2]));
+    const double l1 = (te - t[0]) * (te - t[2]) / ((t[1] - t[0]) * (t[1] - t[2]));
+    const double l2 = (te - t[0]) * (te - t[1]) / ((t[2] - t[0]) * (t[2] - t[1]));
+    const int64_t N = cells_of(L);
+    const bool scalar = g0 && g1 && g2 && g_out;
+    const dim3 grid((unsigned)((N + 255) / 256)), block(256);
+    if (L->storage == CSLBM_F32)
+        hipLaunchKernelGGL(k_time_interp<float>, grid, block, 0, stream, (const float*)s0,
+                           (const float*)s1, (const float*)s2, (float*)out, scalar ? g0 : nullptr,
+                           g1, g2, scalar ? g_out : nullptr, N, L->plane, (float)l0, (float)l1,
+                           (float)l2);
+    else
+        hipLaunchKernelGGL(k_time_interp<_Float16>, grid, block, 0, stream, (const _Float16*)s0,
+                           (const _Float16*)s1, (const _Float16*)s2, (_Float16*)out,
+                           scalar ? g0 : nullptr, g1, g2, scalar ? g_out : nullptr, N, L->plane,
+                           (float)l0, (float)l1, (float)l2);
+    return check_launch("k_time_interp");
+}
+
+static int validate_exchange_pair(const cslbm_level* src, const cslbm_level* dst)
+{
+    int rc = validate_shape(src);
+    if (rc) return rc;
+    rc = validate_shape(dst);
+    if (rc) return rc;
+    if (!(src->dx > 0.0) || !(dst->dx > 0.0))
+        return fail(CSLBM_ERR_ARG, "scale spacings must be positive (src %g, dst %g)", src->dx, dst->dx);
+    if (!(src->p.nu > 0.0) || !(dst->p.nu > 0.0))
+        return fail(CSLBM_ERR_ARG, "scale viscosities must be positive");
+    const double Ss = shear_rate(src);
+    if (std::fabs(1.0 - Ss) < 1e-9)
+        return fail(CSLBM_ERR_ARG, "source relaxation time is 1: (I - S)^-1 of the mapping is singular");
+    return CSLBM_OK;
+}
+
+}  // namespace cslbm
+
+using namespace cslbm;
+
+extern "C" {
+
+int cslbm_exchange(const cslbm_level* src, const void* fA, const void* fB, const float* gA,
+                   const float* gB, double w, const cslbm_level* dst, void* f_out, float* g_out,
+                   const int32_t* cells, int32_t n_cells, hipStream_t stream)
+{
+    int rc = validate_exchange_pair(src, dst);
+    if (rc) return rc;
+    if (!fA || !f_out) return fail(CSLBM_ERR_ARG, "source or destination populations are NULL");
+    if (n_cells < 0 || (n_cells > 0 && !cells)) return fail(CSLBM_ERR_ARG, "bad cell list");
+    if (!(w >= 0.0 && w <= 1.0)) return fail(CSLBM_ERR_ARG, "time weight %g outside [0, 1]", w);
+    if (g_out && gA && std::fabs(src->p.tau_s - 1.0) < 1e-9)
+        return fail(CSLBM_ERR_ARG, "source scalar relaxation time is 1 (singular mapping)");
+    return launch_exchange(src, fA, fB, gA, gB, w, dst, f_out, g_out, cells, n_cells, stream);
+}
+
+int cslbm_time_interp(const cslbm_level* L, const void* s0, const void* s1, const void* s2,
+                      const float* g0, const float* g1, const float* g2, const double t[3],
+                      double t_eval, void* out, float* g_out, hipStream_t stream)
+{
+    int rc = validate_shape(L);
+    if (rc) return rc;
+    if (!s0 || !s1 || !s2 || !out || !t) return fail(CSLBM_ERR_ARG, "NULL state or times");
+    if (t[0] == t[1] || t[0] == t[2] || t[1] == t[2])
+        return fail(CSLBM_ERR_ARG, "interpolation times must be distinct");
+    return launch_time_interp(L, s0, s1, s2, g0, g1, g2, t, t_eval, out, g_out, stream);
+}
+
+int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t stream)
+{
+    if (!H || !H->scales) return fail(CSLBM_ERR_ARG, "hierarchy is NULL");
+    const int ns = H->n_scales;
+    if (ns < 1 || ns > CSLBM_MAX_SCALES)
+        return fail(CSLBM_ERR_ARG, "n_scales = %d outside [1, %d]", ns, CSLBM_MAX_SCALES);
+    if (n_ref_steps < 0) return fail(CSLBM_ERR_ARG, "n_ref_steps is negative");
+    cslbm_scale* S = H->scales;
+    const bool scalar = S[0].level.g != nullptr;
+    for (int i = 0; i < ns; ++i) {
+        cslbm_level* L = &S[i].level;
+        int rc = validate_shape(L);
+        if (rc) return fail(rc, "scale %d: %s", i, cslbm_last_error());
+        rc = validate_params(L);
+        if (rc) return fail(rc, "scale %d: %s", i, cslbm_last_error());
+        if (!L->f_next || L->f == L->f_next) return fail(CSLBM_ERR_ARG, "scale %d: bad f_next", i);
+        if ((L->g != nullptr) != scalar)
+            return fail(CSLBM_ERR_ARG, "scale %d: every scale or none must carry the scalar", i);
+        if (!(L->dx > 0.0)) return fail(CSLBM_ERR_ARG, "scale %d: dx must be positive", i);
+        if (std::fabs(1.0 - shear_rate(L)) < 1e-9)
+            return fail(CSLBM_ERR_ARG, "scale %d: relaxation time 1 makes the mapping singular", i);
+        if (scalar && std::fabs(L->p.tau_s - 1.0) < 1e-9)
+            return fail(CSLBM_ERR_ARG, "scale %d: scalar relaxation time 1 is singular", i);
+        if (i == 0) {
+            if (S[0].parent != -1) return fail(CSLBM_ERR_ARG, "scale 0 must have parent -1");
+            continue;
+        }
+        if (S[i].parent < 0 || S[i].parent >= i)
+            return fail(CSLBM_ERR_ARG, "scale %d: parent %d must be a coarser scale < %d", i,
+                        S[i].parent, i);
+        if (!(L->dx <= S[S[i].parent].level.dx))
+            return fail(CSLBM_ERR_ARG, "scale %d is not finer than its parent", i);
+        if (!L->flags) return fail(CSLBM_ERR_ARG, "scale %d: finer scales need flags (ghost shell)", i);
+        if (!S[i].work_f[0] || !S[i].work_f[1])
+            return fail(CSLBM_ERR_ARG, "scale %d: two work buffers are required", i);
+        if (scalar && (!S[i].work_g[0] || !S[i].work_g[1]))
+            return fail(CSLBM_ERR_ARG, "scale %d: two scalar work buffers are required", i);
+        if (S[i].n_ghost < 0 || (S[i].n_ghost > 0 && !S[i].ghost_cells))
+            return fail(CSLBM_ERR_ARG, "scale %d: bad ghost list", i);
+        for (int j = 0; j < i; ++j)
+            if (S[i].n_post[j] < 0 || (S[i].n_post[j] > 0 && !S[i].post_cells[j]))
+                return fail(CSLBM_ERR_ARG, "scale %d: bad post-mapping list for scale %d", i, j);
+    }
+
+    // states of each scale at t_n (A) and t_n + dt_0 (B) within one reference step
+    const void* A[CSLBM_MAX_SCALES];
+    void* B[CSLBM_MAX_SCALES];
+    const float* gA[CSLBM_MAX_SCALES];
+    float* gB[CSLBM_MAX_SCALES];
+    for (int n = 0; n < n_ref_steps; ++n) {
+        // reference scale: one step (Algorithm 1, first statement of the loop)
+        {
+            cslbm_level* L = &S[0].level;
+            int rc = launch_step_into(L, L->f, L->f_next, L->g, L->g_next, stream);
+            if (rc) return rc;
+            std::swap(L->f, L->f_next);
+            std::swap(L->g, L->g_next);
+            A[0] = L->f_next;
+            B[0] = L->f;
+            gA[0] = L->g_next;
+            gB[0] = L->g;
+        }
+        // finer scales, coarse to fine
+        for (int i = 1; i < ns; ++i) {
+            cslbm_scale& sc = S[i];
+            cslbm_level* L = &sc.level;
+            const cslbm_level* P = &S[sc.parent].level;
+            const int p = sc.parent;
+            const double alpha = S[0].level.dx / L->dx;
+            const int l = (int)std::floor(alpha + 1e-12) + 1;
+            void* X0 = L->f;
+            void* bufs[2] = {L->f_next, sc.work_f[0]};
+            float* gX0 = L->g;
+            float* gbufs[2] = {L->g_next, sc.work_g[0]};
+            void* prev = X0;
+            void* cur = X0;
+            float* gprev = gX0;
+            float* gcur = gX0;
+            for (int k = 1; k <= l; ++k) {
+                // prior-mapping of the boundary shell at the sub-step's start time
+                int rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], (k - 1) / alpha, L, cur, gcur,
+                                         sc.ghost_cells, sc.n_ghost, stream);
+                if (rc) return rc;
+                void* next = bufs[(k - 1) & 1];
+                float* gnext = gbufs[(k - 1) & 1];
+                rc = launch_step_into(L, cur, next, gcur, gnext, stream);
+                if (rc) return rc;
+                prev = cur;
+                cur = next;
+                gprev = gcur;
+                gcur = gnext;
+            }
+            // quadratic in time through 0, (l-1)/alpha, l/alpha, evaluated at 1
+            const double t[3] = {0.0, (l - 1) / alpha, l / alpha};
+            void* R = sc.work_f[1];
+            float* gR = sc.work_g[1];
+            int rc = launch_time_interp(L, X0, prev, cur, gX0, gprev, gcur, t, 1.0, R, gR, stream);
+            if (rc) return rc;
+            rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], 1.0, L, R, gR, sc.ghost_cells,
+                                 sc.n_ghost, stream);
+            if (rc) return rc;
+            A[i] = X0;
+            B[i] = R;
+            gA[i] = gX0;
+            gB[i] = gR;
+            // post-mapping to every coarser scale (section "Handling multiple scales")
+            for (int j = 0; j < i; ++j) {
+                rc = launch_exchange(L, R, R, gR, gR, 0.0, &S[j].level, B[j], gB[j],
+                                     sc.post_cells[j], sc.n_post[j], stream);
+                if (rc) return rc;
+            }
+        }
+        // the interpolated states become the scales' states at the new reference time
+        for (int i = 1; i < ns; ++i) {
+            std::swap(S[i].level.f, S[i].work_f[1]);
+            std::swap(S[i].level.g, S[i].work_g[1]);
+        }
+    }
+    return CSLBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,178 @@
+"""Continuous-scale level sets on the GPU (Algorithm 1 through the C ABI).
+
+A ``Hierarchy`` holds a reference ``Level`` (scale 0) and finer levels, each
+a box of lattice points ``origin + (x, y, z) * dx`` with a one-cell
+``GHOST`` shell, nested in its parent.  It allocates the per-scale work
+buffers, builds the prior-mapping (ghost) and post-mapping cell lists, and
+calls ``cslbm_multiscale_step``.  All arithmetic runs in libcslbm.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+import torch
+
+from . import _capi
+from .level import Level, Params, _stream_handle
+
+FLUID, GHOST = _capi.FLUID, _capi.GHOST
+
+
+def shell_flags(nx: int, ny: int, nz: int, inner: np.ndarray | None = None) -> np.ndarray:
+    """Cell kinds of a finer scale: the one-cell outer shell is GHOST, the
+    inside takes `inner` (default FLUID)."""
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    x, y, z = x.reshape(-1), y.reshape(-1), z.reshape(-1)
+    fl = np.zeros(nx * ny * nz, np.uint8) if inner is None else np.asarray(inner, np.uint8).copy()
+    fl[(x == 0) | (x == nx - 1) | (y == 0) | (y == ny - 1) | (z == 0) | (z == nz - 1)] = GHOST
+    return fl
+
+
+def _stencil(points: np.ndarray, origin, dx, n):
+    """Trilinear stencil of physical points in a lattice: base index and
+    fractions per axis (points: [3, K])."""
+    q = (points - np.asarray(origin, float)[:, None]) / dx
+    base = np.floor(q).astype(np.int64)
+    return base, q - base
+
+
+def post_cells(coarse_kinds: np.ndarray, coarse_shape, coarse_origin, coarse_dx,
+               fine_kinds: np.ndarray, fine_shape, fine_origin, fine_dx) -> np.ndarray:
+    """Cells of the coarse scale whose position has a trilinear stencil (the
+    corners with non-zero weight) made of FLUID cells inside the fine box."""
+    cnx, cny, cnz = coarse_shape
+    fnx, fny, fnz = fine_shape
+    lo = [max(0, math.floor((fine_origin[a] - coarse_origin[a]) / coarse_dx) - 1) for a in range(3)]
+    hi = [min(coarse_shape[a] - 1,
+              math.ceil((fine_origin[a] + (fine_shape[a] - 1) * fine_dx - coarse_origin[a]) / coarse_dx) + 1)
+          for a in range(3)]
+    if any(h < l for l, h in zip(lo, hi)):
+        return np.zeros(0, np.int32)
+    zz, yy, xx = np.meshgrid(np.arange(lo[2], hi[2] + 1), np.arange(lo[1], hi[1] + 1),
+                             np.arange(lo[0], hi[0] + 1), indexing="ij")
+    xx, yy, zz = xx.reshape(-1), yy.reshape(-1), zz.reshape(-1)
+    cells = xx + cnx * (yy + cny * zz)
+    keep = coarse_kinds[cells] == FLUID
+    cells, xx, yy, zz = cells[keep], xx[keep], yy[keep], zz[keep]
+    pts = np.stack([coarse_origin[0] + xx * coarse_dx, coarse_origin[1] + yy * coarse_dx,
+                    coarse_origin[2] + zz * coarse_dx])
+    base, t = _stencil(pts, fine_origin, fine_dx, fine_shape)
+    ok = np.ones(cells.size, bool)
+    for corner in range(8):
+        o = np.array([corner & 1, (corner >> 1) & 1, (corner >> 2) & 1])
+        wt = np.ones(cells.size)
+        for a in range(3):
+            wt *= t[a] if o[a] else 1.0 - t[a]
+        idx = base + o[:, None]
+        inside = ((idx[0] >= 0) & (idx[0] < fnx) & (idx[1] >= 0) & (idx[1] < fny) &
+                  (idx[2] >= 0) & (idx[2] < fnz))
+        fc = np.clip(idx[0], 0, fnx - 1) + fnx * (np.clip(idx[1], 0, fny - 1) +
+                                                  fny * np.clip(idx[2], 0, fnz - 1))
+        good = inside & (fine_kinds[fc] == FLUID)
+        ok &= good | (wt == 0.0)
+    return cells[ok].astype(np.int32)
+
+
+def check_prior_stencils(parent_kinds, parent_shape, parent_origin, parent_dx, parent_periodic,
+                         fine_shape, fine_origin, fine_dx, ghosts: np.ndarray):
+    """Every ghost of a finer scale must interpolate from FLUID cells of its
+    parent (inside the box on non-periodic axes)."""
+    fnx, fny, _ = fine_shape
+    gx, gy, gz = ghosts % fnx, (ghosts // fnx) % fny, ghosts // (fnx * fny)
+    pts = np.stack([fine_origin[0] + gx * fine_dx, fine_origin[1] + gy * fine_dx,
+                    fine_origin[2] + gz * fine_dx])
+    base, t = _stencil(pts, parent_origin, parent_dx, parent_shape)
+    for corner in range(8):
+        o = np.array([corner & 1, (corner >> 1) & 1, (corner >> 2) & 1])
+        wt = np.ones(ghosts.size)
+        for a in range(3):
+            wt *= t[a] if o[a] else 1.0 - t[a]
+        idx = base + o[:, None]
+        for a in range(3):
+            if parent_periodic & (1 << a):
+                idx[a] %= parent_shape[a]
+        inside = np.all((idx >= 0) & (idx < np.array(parent_shape)[:, None]), axis=0)
+        need = wt != 0.0
+        if np.any(need & ~inside):
+            raise ValueError("a ghost cell's prior-mapping stencil leaves its parent box")
+        pc = idx[0] + parent_shape[0] * (idx[1] + parent_shape[1] * idx[2])
+        pc = np.where(inside, pc, 0)
+        if np.any(need & (parent_kinds[pc] != FLUID)):
+            raise ValueError("a ghost cell's prior-mapping stencil touches a non-fluid parent cell")
+
+
+class Hierarchy:
+    """Scales 0..n-1 (0 = reference, covering the domain); parents[i] is the
+    nearest coarser scale of scale i (default i - 1)."""
+
+    def __init__(self, levels: list[Level], kinds: list[np.ndarray], parents=None):
+        assert len(levels) == len(kinds) and 1 <= len(levels) <= _capi.MAX_SCALES
+        self.levels = levels
+        self.kinds = [np.asarray(k, np.uint8) for k in kinds]
+        self.parents = parents or [-1] + list(range(len(levels) - 1))
+        self.work = []
+        self.lists = []
+        self.post = {}
+        n = len(levels)
+        self.c_scales = (_capi.CslbmScale * n)()
+        dev = levels[0].device
+        for i, lev in enumerate(levels):
+            sc = self.c_scales[i]
+            sc.parent = self.parents[i]
+            work_f, work_g = [None, None], [None, None]
+            if i > 0:
+                work_f = [torch.zeros_like(lev.f), torch.zeros_like(lev.f)]
+                if lev.g is not None:
+                    work_g = [torch.zeros_like(lev.g), torch.zeros_like(lev.g)]
+                ghosts = np.flatnonzero(self.kinds[i] == GHOST).astype(np.int32)
+                par = levels[self.parents[i]]
+                check_prior_stencils(self.kinds[self.parents[i]], (par.nx, par.ny, par.nz),
+                                     tuple(par.c.origin), par.c.dx, par.c.periodic,
+                                     (lev.nx, lev.ny, lev.nz), tuple(lev.c.origin), lev.c.dx, ghosts)
+                g_t = torch.as_tensor(ghosts, device=dev)
+                self.lists.append(g_t)
+                sc.n_ghost = ghosts.size
+                sc.ghost_cells = g_t.data_ptr() if ghosts.size else None
+                for j in range(i):
+                    cj = levels[j]
+                    cells = post_cells(self.kinds[j], (cj.nx, cj.ny, cj.nz), tuple(cj.c.origin),
+                                       cj.c.dx, self.kinds[i], (lev.nx, lev.ny, lev.nz),
+                                       tuple(lev.c.origin), lev.c.dx)
+                    self.post[(i, j)] = cells
+                    t = torch.as_tensor(cells, device=dev)
+                    self.lists.append(t)
+                    sc.n_post[j] = cells.size
+                    sc.post_cells[j] = t.data_ptr() if cells.size else None
+            self.work.append((work_f, work_g))
+            sc.work_f = (C.c_void_p * 2)(*[None if w is None else w.data_ptr() for w in work_f])
+            sc.work_g = (C.c_void_p * 2)(*[None if w is None else w.data_ptr() for w in work_g])
+        self.c = _capi.CslbmHierarchy(n, 0, C.cast(self.c_scales, C.POINTER(_capi.CslbmScale)))
+
+    def ghost_cells(self, i: int) -> np.ndarray:
+        return np.flatnonzero(self.kinds[i] == GHOST).astype(np.int64)
+
+    def step(self, n_ref: int = 1, stream=None):
+        tensors = {}
+        for i, lev in enumerate(self.levels):
+            lev._sync_struct()
+            self.c_scales[i].level = lev.c
+            for t in (lev.f, lev.f_next, lev.g, lev.g_next, *self.work[i][0], *self.work[i][1]):
+                if t is not None:
+                    tensors[t.data_ptr()] = t
+        _capi.call("cslbm_multiscale_step", C.byref(self.c), int(n_ref), _stream_handle(stream))
+        for i, lev in enumerate(self.levels):
+            sc = self.c_scales[i]
+            lev.f = tensors[sc.level.f]
+            lev.f_next = tensors[sc.level.f_next]
+            if lev.g is not None:
+                lev.g = tensors[sc.level.g]
+                lev.g_next = tensors[sc.level.g_next]
+            if i > 0:
+                wf = [tensors[sc.work_f[0]], tensors[sc.work_f[1]]]
+                wg = self.work[i][1]
+                if lev.g is not None:
+                    wg = [tensors[sc.work_g[0]], tensors[sc.work_g[1]]]
+                self.work[i] = (wf, wg)
+            lev._sync_struct()

@@ -1,0 +1,270 @@
+"""GPU parity of the cross-scale exchange, temporal interpolation and the
+Algorithm-1 driver against the FP64 oracle (same seeded inputs, same scale
+geometry)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import multilevel as ml
+from paper_1807_02284_amd import _capi, hierarchy, inputs
+from paper_1807_02284_amd.level import F32, Level, Params
+
+pytestmark = pytest.mark.gpu
+
+W = oracle.weights()
+
+
+def rel_err(a, b):
+    return np.max(np.abs(a - b) / np.maximum(np.abs(b), W[:, None]))
+
+
+def gpu_pop(lev: Level, buf=None):
+    """Physical populations (float64 [27][N]) of a level's state or of any
+    [27][plane] buffer of it."""
+    t = lev.f if buf is None else buf
+    h = t.reshape(27, lev.plane)[:, : lev.n].double().cpu().numpy()
+    return h + W[:, None]
+
+
+def gpu_g(lev: Level, buf=None):
+    t = lev.g if buf is None else buf
+    return t.reshape(7, lev.plane)[:, : lev.n].double().cpu().numpy()
+
+
+class Spec:
+    """One scale: box size, origin, spacing, kinds; builds both sides."""
+
+    def __init__(self, shape, origin, dx, nu0, kinds, periodic=0, parent=-1, tau_s0=0.55,
+                 u_in=(0.0, 0.0, 0.0), s_in=0.0):
+        self.shape, self.origin, self.dx = shape, origin, dx
+        self.alpha = 1.0 / dx
+        self.nu = nu0 * self.alpha
+        self.tau_s = 0.5 + self.alpha * (tau_s0 - 0.5)
+        self.kinds, self.periodic, self.parent = kinds, periodic, parent
+        self.u_in, self.s_in = u_in, s_in
+
+    @property
+    def n(self):
+        return int(np.prod(self.shape))
+
+    def params(self):
+        return Params(nu=self.nu, g_max=0.05, tau_s=self.tau_s, u_in=self.u_in, s_in=self.s_in)
+
+    def level(self, scalar):
+        flags = None if (self.periodic == 7 and np.all(self.kinds == 0)) else self.kinds
+        return Level(*self.shape, self.params(), scalar=scalar, periodic=self.periodic, flags=flags,
+                     origin=self.origin, dx=self.dx)
+
+    def oscale(self):
+        p = self.params()
+        return ml.OScale(*self.shape, self.dx, self.origin,
+                         oracle.Params(nu=p.nu, g_max=p.g_max, tau_s=p.tau_s), self.kinds,
+                         periodic=self.periodic, parent=self.parent, u_in=self.u_in, s_in=self.s_in)
+
+    def positions(self):
+        x, y, z = inputs.grid_coords(*self.shape)
+        return (self.origin[0] + x * self.dx, self.origin[1] + y * self.dx,
+                self.origin[2] + z * self.dx)
+
+
+def smooth_state(spec: Spec, seed):
+    """(rho, u, s) sampled at the scale's physical points from one seeded
+    smooth field defined on the whole domain."""
+    px, py, pz = spec.positions()
+    rng = np.random.default_rng(seed)
+    u = np.zeros((3, px.size))
+    for a in range(3):
+        for _ in range(3):
+            k = rng.integers(1, 3, size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            u[a] += 0.015 * np.cos(2 * np.pi * (k[0] * px + k[1] * py + k[2] * pz) / 24.0 + ph)
+    rho = 1.0 + 0.005 * np.sin(2 * np.pi * (px + 2 * py) / 24.0)
+    s = 0.5 + 0.3 * np.cos(2 * np.pi * (px - pz) / 24.0)
+    return rho, u, s
+
+
+def start_both(spec: Spec, seed, scalar=True):
+    rho, u, s = smooth_state(spec, seed)
+    lev = spec.level(scalar)
+    lev.init_equilibrium(rho, u, s if scalar else None)
+    osc = spec.oscale()
+    osc.f, osc.g = oracle.init(osc.domain(), rho, u, s=s if scalar else None)
+    return lev, osc
+
+
+def geom(spec: Spec, scalar=True):
+    return dict(nx=spec.shape[0], ny=spec.shape[1], nz=spec.shape[2], periodic=spec.periodic,
+                origin=spec.origin, dx=spec.dx, nu=spec.nu, tau_s=spec.tau_s if scalar else 0.0)
+
+
+@pytest.mark.parametrize("dst_dx,w", [(1 / 1.5, 0.37), (0.5, 0.0), (1 / 1.25, 1.0)])
+def test_exchange_coarse_to_fine_matches_oracle(dst_dx, w):
+    n = 24
+    src = Spec((n, n, n), (0.0, 0.0, 0.0), 1.0, 2e-3, np.zeros(n ** 3, np.uint8), periodic=7)
+    dshape = (15, 13, 12)
+    dst = Spec(dshape, (3.3, 2.6, 17.1), dst_dx, 2e-3, hierarchy.shell_flags(*dshape))
+    levA, oA = start_both(src, 1)
+    levB, oB = start_both(src, 2)
+    levD, oD = start_both(dst, 3)
+    cells = np.arange(dst.n, dtype=np.int32)
+    cells_t = torch.as_tensor(cells, device="cuda")
+    levA._sync_struct(); levB._sync_struct(); levD._sync_struct()
+    import ctypes as C
+    _capi.call("cslbm_exchange", C.byref(levA.c), levA.f.data_ptr(), levB.f.data_ptr(),
+               levA.g.data_ptr(), levB.g.data_ptr(), float(w), C.byref(levD.c), levD.f.data_ptr(),
+               levD.g.data_ptr(), cells_t.data_ptr(), cells.size,
+               torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    fo, go = oD.f.copy(), oD.g.copy()
+    oracle.exchange(geom(src), oA.f, oB.f, w, geom(dst), cells.astype(np.int64), fo, oA.g, oB.g, go)
+    assert rel_err(gpu_pop(levD), fo) <= 1e-6
+    assert np.max(np.abs(gpu_g(levD) - go)) <= 2e-7
+
+
+def test_exchange_fine_to_coarse_matches_oracle():
+    n = 24
+    coarse = Spec((n, n, n), (0.0, 0.0, 0.0), 1.0, 2e-3, np.zeros(n ** 3, np.uint8), periodic=7)
+    fshape = (20, 18, 16)
+    fine = Spec(fshape, (4.2, 5.1, 3.7), 1 / 1.5, 2e-3, hierarchy.shell_flags(*fshape))
+    levC, oC = start_both(coarse, 4)
+    levF, oF = start_both(fine, 5)
+    cells = hierarchy.post_cells(coarse.kinds, coarse.shape, coarse.origin, 1.0, fine.kinds,
+                                 fine.shape, fine.origin, fine.dx)
+    assert cells.size > 100
+    cells_t = torch.as_tensor(cells, device="cuda")
+    import ctypes as C
+    levC._sync_struct(); levF._sync_struct()
+    _capi.call("cslbm_exchange", C.byref(levF.c), levF.f.data_ptr(), None, levF.g.data_ptr(), None,
+               0.0, C.byref(levC.c), levC.f.data_ptr(), levC.g.data_ptr(), cells_t.data_ptr(),
+               cells.size, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    fo, go = oC.f.copy(), oC.g.copy()
+    oracle.exchange(geom(fine), oF.f, oF.f, 0.0, geom(coarse), cells.astype(np.int64), fo, oF.g,
+                    oF.g, go)
+    assert rel_err(gpu_pop(levC), fo) <= 1e-6
+    assert np.max(np.abs(gpu_g(levC) - go)) <= 2e-7
+
+
+def test_time_interp_matches_oracle():
+    spec = Spec((30, 7, 5), (0.0, 0.0, 0.0), 1.0, 1e-3, np.zeros(1050, np.uint8), periodic=7)
+    levs, ors = zip(*[start_both(spec, 10 + k) for k in range(3)])
+    out = Level(*spec.shape, spec.params(), scalar=True)
+    import ctypes as C
+    t = (C.c_double * 3)(0.0, 2.0 / 3.0, 4.0 / 3.0)
+    out._sync_struct()
+    _capi.call("cslbm_time_interp", C.byref(out.c), levs[0].f.data_ptr(), levs[1].f.data_ptr(),
+               levs[2].f.data_ptr(), levs[0].g.data_ptr(), levs[1].g.data_ptr(),
+               levs[2].g.data_ptr(), t, 1.0, out.f.data_ptr(), out.g.data_ptr(),
+               torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    ref = oracle.time_interp(ors[0].f, ors[1].f, ors[2].f, tuple(t), 1.0).reshape(27, -1)
+    gref = oracle.time_interp(ors[0].g, ors[1].g, ors[2].g, tuple(t), 1.0).reshape(7, -1)
+    assert rel_err(gpu_pop(out), ref) <= 1e-6
+    assert np.max(np.abs(gpu_g(out) - gref)) <= 1e-6
+
+
+def build_pair(specs, seed, scalar=True):
+    levs, oscs = [], []
+    for i, sp in enumerate(specs):
+        lev, osc = start_both(sp, seed, scalar)      # one physical field on every scale
+        levs.append(lev)
+        oscs.append(osc)
+    H = hierarchy.Hierarchy(levs, [sp.kinds for sp in specs], [sp.parent for sp in specs])
+    ml.prepare(oscs)
+    for i in range(1, len(specs)):
+        np.testing.assert_array_equal(np.sort(H.post[(i, 0)].astype(np.int64)), oscs[i].post[0])
+    return H, levs, oscs
+
+
+def test_three_scale_reference_steps_match_oracle():
+    n = 24
+    nu0 = 2e-3
+    s0 = Spec((n, n, n), (0.0, 0.0, 0.0), 1.0, nu0, np.zeros(n ** 3, np.uint8), periodic=7)
+    sh1 = (19, 19, 17)
+    s1 = Spec(sh1, (5.3, 5.4, 5.6), 1 / 1.5, nu0, hierarchy.shell_flags(*sh1), parent=0)
+    sh2 = (14, 13, 12)
+    s2 = Spec(sh2, (8.1, 8.3, 8.2), 0.5, nu0, hierarchy.shell_flags(*sh2), parent=1)
+    H, levs, oscs = build_pair([s0, s1, s2], 20)
+    H.step(3)
+    ml.multiscale_step(oscs, 3)
+    torch.cuda.synchronize()
+    for lev, osc in zip(levs, oscs):
+        assert rel_err(gpu_pop(lev), osc.f) <= 1e-5
+        assert np.max(np.abs(gpu_g(lev) - osc.g)) <= 1e-5
+
+
+def test_alpha_one_two_scale_gpu_run_equals_single_scale_gpu_run():
+    n = 20
+    nu0 = 5e-3
+    s0 = Spec((n, n, n), (0.0, 0.0, 0.0), 1.0, nu0, np.zeros(n ** 3, np.uint8), periodic=7)
+    sh = (9, 8, 10)
+    s1 = Spec(sh, (4.0, 6.0, 3.0), 1.0, nu0, hierarchy.shell_flags(*sh), parent=0)
+    single, _ = start_both(s0, 30, scalar=False)
+    single.step(4)
+    lev0, _ = start_both(s0, 30, scalar=False)
+    x, y, z = inputs.grid_coords(*sh)
+    idx = (x + 4) + n * ((y + 6) + n * (z + 3))
+    lev1 = s1.level(False)
+    h0, _ = lev0.get_populations(shifted=True)
+    lev1.set_populations(h0[:, torch.as_tensor(idx, device="cuda")], shifted=True)
+    H = hierarchy.Hierarchy([lev0, lev1], [s0.kinds, s1.kinds], [-1, 0])
+    H.step(4)
+    torch.cuda.synchronize()
+    ref = gpu_pop(single)
+    assert rel_err(gpu_pop(lev0), ref) <= 1e-6
+    inner = np.flatnonzero(s1.kinds == _capi.FLUID)
+    assert rel_err(gpu_pop(lev1)[:, inner], ref[:, idx[inner]]) <= 1e-6
+
+
+def plume_specs(nx, ny, nz, nu0):
+    """Reduced plume scene: walls, inlet disk on x = 0, outflow at x = nx-1,
+    sphere; two nested finer boxes around the sphere and its wake
+    (alpha = 1.5, 2)."""
+    sc = nx / 512.0
+    r_sphere = 24.0 * sc
+    centre = (160.0 * sc, ny / 2.0, nz / 2.0)
+    k0 = inputs.plume_flags(nx, ny, nz)
+    s0 = Spec((nx, ny, nz), (0.0, 0.0, 0.0), 1.0, nu0, k0, periodic=0, u_in=(0.05, 0.0, 0.0),
+              s_in=1.0)
+    specs = [s0]
+    boxes = [((centre[0] - 9, 12.0, 10.0), (38.0, 24.0, 28.0), 1 / 1.5),
+             ((centre[0] - 6, 16.0, 14.0), (26.0, 16.0, 20.0), 0.5)]
+    for i, (org, ext, dx) in enumerate(boxes):
+        shape = tuple(int(round(e / dx)) + 1 for e in ext)
+        sp = Spec(shape, org, dx, nu0, None, parent=i)
+        px, py, pz = sp.positions()
+        inner = np.zeros(sp.n, np.uint8)
+        inner[(px + 0.5 - centre[0]) ** 2 + (py + 0.5 - centre[1]) ** 2 +
+              (pz + 0.5 - centre[2]) ** 2 <= r_sphere ** 2] = _capi.SOLID
+        sp.kinds = hierarchy.shell_flags(*shape, inner)
+        specs.append(sp)
+    return specs
+
+
+def test_reduced_plume_three_scales_match_oracle():
+    nx, ny, nz = 96, 48, 48
+    specs = plume_specs(nx, ny, nz, 1e-3)
+    levs, oscs = [], []
+    for i, sp in enumerate(specs):
+        rho, u, s = smooth_state(sp, 40)       # same physical field on every scale
+        u[0] += 0.04
+        lev = sp.level(True)
+        lev.init_equilibrium(rho, u, s)
+        osc = sp.oscale()
+        osc.f, osc.g = oracle.init(osc.domain(), rho, u, s=s)
+        levs.append(lev)
+        oscs.append(osc)
+    H = hierarchy.Hierarchy(levs, [sp.kinds for sp in specs], [sp.parent for sp in specs])
+    ml.prepare(oscs)
+    for i in range(1, 3):
+        for j in range(i):
+            np.testing.assert_array_equal(np.sort(H.post[(i, j)].astype(np.int64)), oscs[i].post[j])
+    H.step(12)
+    ml.multiscale_step(oscs, 12)
+    torch.cuda.synchronize()
+    for lev, osc in zip(levs, oscs):
+        assert rel_err(gpu_pop(lev), osc.f) <= 1e-5
+        assert np.max(np.abs(gpu_g(lev) - osc.g)) <= 1e-5

@@ -243,6 +243,30 @@ typedef struct cslbm_hierarchy {
  * hierarchy (parents, spacings, buffers, lists, singular relaxation times). */
 int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Differentiation (build addition; the paper has no adjoint).
+ * ---------------------------------------------------------------------- */
+
+/* n_steps forward steps that keep every state: step k reads (k == 0 ? L->f :
+ * f_states[k-1]) and writes f_states[k] (likewise g from L->g into
+ * g_states).  L->f and L->g are not modified.  f_states / g_states are HOST
+ * arrays of n_steps DEVICE buffers of L's size; used to recompute a
+ * checkpointed segment for the adjoint. */
+int cslbm_step_store(const cslbm_level* L, int32_t n_steps, void* const* f_states,
+                     float* const* g_states, hipStream_t stream);
+
+/* Adjoint of one step (eq. lbe with eq. cmr_collision, the body force and
+ * the scalar): with L->f (and L->g, L->force) the state f(n) that the
+ * forward step read, lam_next = dL/df(n+1) [27][plane] and mu_next =
+ * dL/dg(n+1) [7][plane], writes lam = dL/df(n) and mu = dL/dg(n) and adds
+ * dL/dtheta to dtheta [3][plane] (may be NULL).  Adjoints are FP32 and refer
+ * to the physical populations (a shift by w_i does not change them).  Only
+ * fully periodic levels without flags are supported (CSLBM_ERR_UNSUPPORTED
+ * otherwise).  Non-smooth points of the adaptive factor take the derivative
+ * of the branch they are on. */
+int cslbm_adjoint_step(const cslbm_level* L, const float* lam_next, const float* mu_next,
+                       float* lam, float* mu, float* dtheta, hipStream_t stream);
+
 /* sizeof(cslbm_params) and sizeof(cslbm_level) as compiled into the
  * library (HOST pointers), so that bindings can verify their struct layout
  * before the first call.  Always CSLBM_OK. */

@@ -188,3 +188,29 @@ class Level:
         if rc not in (_capi.OK, _capi.ERR_NONFINITE):
             raise _capi.CslbmError(rc, "cslbm_check_finite", lib.cslbm_last_error().decode())
         return int(n.value)
+
+    # -- differentiation support ---------------------------------------------
+    def _struct_with_state(self, f: torch.Tensor, g: torch.Tensor | None) -> _capi.CslbmLevel:
+        self._sync_struct()
+        c = _capi.CslbmLevel()
+        C.pointer(c)[0] = self.c
+        c.f = _dev_ptr(f)
+        c.g = _dev_ptr(g)
+        return c
+
+    def step_store(self, f_start, g_start, f_states, g_states, stream=None):
+        """len(f_states) steps from (f_start, g_start), writing every state."""
+        n = len(f_states)
+        c = self._struct_with_state(f_start, g_start)
+        fp = (C.c_void_p * max(n, 1))(*[t.data_ptr() for t in f_states])
+        gp = None
+        if g_start is not None:
+            gp = (C.c_void_p * max(n, 1))(*[t.data_ptr() for t in g_states])
+        _capi.call("cslbm_step_store", C.byref(c), n, fp, gp, _stream_handle(stream))
+
+    def adjoint_step(self, f_state, g_state, lam_next, mu_next, lam, mu, dtheta, stream=None):
+        """lam = dL/df(n) from lam_next = dL/df(n+1) for the step that read
+        (f_state, g_state); dtheta accumulates dL/dtheta."""
+        c = self._struct_with_state(f_state, g_state)
+        _capi.call("cslbm_adjoint_step", C.byref(c), _dev_ptr(lam_next), _dev_ptr(mu_next),
+                   _dev_ptr(lam), _dev_ptr(mu), _dev_ptr(dtheta), _stream_handle(stream))

@@ -1,0 +1,70 @@
+"""Differentiable rollout with checkpoint-every-K recomputation.
+
+``rollout(level, theta, h0, g0, n_steps, every)`` runs ``n_steps`` steps of a
+fully periodic level with the body-force field ``theta`` and returns the final
+smoke scalar ``s = sum_i g_i``.  Gradients with respect to theta and the
+initial populations come from the hand-written adjoint step of libcslbm
+(``cslbm_adjoint_step``); only every ``every``-th state is kept during the
+forward pass and each segment is recomputed with ``cslbm_step_store`` in the
+backward pass.  Tensors are dense: theta [3][N], h0 [27][N] shifted
+populations f - w, g0 [7][N].
+"""
+from __future__ import annotations
+
+import torch
+
+from .level import Level
+
+
+def _dense_to_plane(lev: Level, x: torch.Tensor, rows: int) -> torch.Tensor:
+    out = torch.zeros(rows, lev.plane, dtype=torch.float32, device=lev.device)
+    out[:, : lev.n] = x.reshape(rows, lev.n)
+    return out
+
+
+class _Rollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, theta, h0, g0, lev: Level, n_steps: int, every: int):
+        assert lev.force is not None and lev.g is not None, "level needs force and scalar buffers"
+        lev.force.reshape(3, lev.plane)[:, : lev.n] = theta.detach().reshape(3, lev.n)
+        lev.set_populations(h0.detach(), g0.detach(), shifted=True)
+        checkpoints = []
+        done = 0
+        while done < n_steps:
+            k = min(every, n_steps - done)
+            checkpoints.append((done, k, lev.f.clone(), lev.g.clone()))
+            lev.step(k)
+            done += k
+        _, _, s = lev.read_macro()
+        ctx.lev, ctx.checkpoints = lev, checkpoints
+        return s.clone()
+
+    @staticmethod
+    def backward(ctx, grad_s):
+        lev: Level = ctx.lev
+        P = lev.plane
+        lam = torch.zeros(27 * P, dtype=torch.float32, device=lev.device)
+        lam2 = torch.zeros_like(lam)
+        mu = _dense_to_plane(lev, grad_s.detach().reshape(1, -1).expand(7, -1), 7).reshape(-1)
+        mu2 = torch.zeros_like(mu)
+        dtheta = torch.zeros(3 * P, dtype=torch.float32, device=lev.device)
+        every = max(k for _, k, _, _ in ctx.checkpoints)
+        f_buf = [torch.empty_like(lev.f) for _ in range(every - 1)]
+        g_buf = [torch.empty_like(lev.g) for _ in range(every - 1)]
+        for start, k, f0, g0 in reversed(ctx.checkpoints):
+            if k > 1:
+                lev.step_store(f0, g0, f_buf[: k - 1], g_buf[: k - 1])
+            f_states = [f0] + f_buf[: k - 1]
+            g_states = [g0] + g_buf[: k - 1]
+            for n in reversed(range(k)):
+                lev.adjoint_step(f_states[n], g_states[n], lam, mu, lam2, mu2, dtheta)
+                lam, lam2 = lam2, lam
+                mu, mu2 = mu2, mu
+        n = lev.n
+        return (dtheta.reshape(3, P)[:, :n].clone(), lam.reshape(27, P)[:, :n].clone(),
+                mu.reshape(7, P)[:, :n].clone(), None, None, None)
+
+
+def rollout(lev: Level, theta: torch.Tensor, h0: torch.Tensor, g0: torch.Tensor, n_steps: int,
+            every: int = 20) -> torch.Tensor:
+    return _Rollout.apply(theta, h0, g0, lev, int(n_steps), int(every))

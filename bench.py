@@ -101,6 +101,193 @@ def run_gpu(n: int, storage: str, steps: int, warmup: int):
     return out
 
 
+def run_precision(n: int, steps: int):
+    """Taylor-Green (2D vortex extruded in z, u0 = 0.05, tau = 0.6, adaptive
+    on) at n^3: FP16 storage against FP32 storage after `steps` steps, both
+    against the closed-form decay; MLUPS of both."""
+    import numpy as np
+    import torch
+    from paper_1807_02284_amd import inputs
+    from paper_1807_02284_amd.level import F16S, F32, Level, Params
+
+    rho, u = inputs.taylor_green_2d(n, n, n, 0.05)
+    p = Params(nu=0.1 / 3.0, g_max=0.1)
+    out = {}
+    fields = {}
+    for name, st in (("f32", F32), ("f16s", F16S)):
+        lev = Level(n, n, n, p, storage=st)
+        lev.init_equilibrium(rho, u)
+        ms = time_steps(lev, steps, 0)
+        _, ug, _ = lev.read_macro()
+        fields[name] = ug.double()
+        out[name] = {"ms_per_step": ms / steps, "mlups": n ** 3 * steps / (ms * 1e-3) / 1e6,
+                     "achieved_gbs": n ** 3 * BYTES_PER_LUP[name] / (ms / steps * 1e-3) / 1e9}
+        del lev
+        torch.cuda.empty_cache()
+
+    def vort(uu):
+        U = uu.reshape(3, n, n, n)          # [comp, z, y, x]
+        def d(a, axis):
+            return (torch.roll(a, -1, axis) - torch.roll(a, 1, axis)) / 2
+        return torch.stack([d(U[2], 1) - d(U[1], 0), d(U[0], 0) - d(U[2], 2), d(U[1], 2) - d(U[0], 1)])
+
+    k = 2 * np.pi / n
+    amp = np.exp(-2 * (0.1 / 3.0) * k * k * steps)
+    exact = torch.tensor(u * amp, device=fields["f32"].device)
+    rl2 = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+    out["f16s_vs_f32_velocity_rel_l2"] = rl2(fields["f16s"], fields["f32"])
+    out["f16s_vs_f32_vorticity_rel_l2"] = rl2(vort(fields["f16s"]), vort(fields["f32"]))
+    out["f32_vs_closed_form_velocity_rel_l2"] = rl2(fields["f32"], exact)
+    out["f16s_vs_closed_form_velocity_rel_l2"] = rl2(fields["f16s"], exact)
+    # amplitude of the vortex mode (projection; filters the acoustic waves of
+    # the uniform-density start) against the closed-form decay
+    u0 = torch.tensor(u, device=fields["f32"].device)
+    for name in ("f32", "f16s"):
+        a = float((fields[name] * u0).sum() / (u0 * u0).sum())
+        out[f"{name}_mode_amplitude_rel_err"] = abs(a - amp) / amp
+    return out
+
+
+def run_adjoint(n: int, steps: int, every: int):
+    """Differentiable buoyant smoke at n^3 (periodic; blob sigma = n/16 at
+    (n/2, n/2, n/4); beta = 1e-4, s_ref = initial mean; theta = 0):
+    forward `steps` steps keeping every `every`-th state, then the
+    checkpointed backward (recompute + adjoint).  Reports ms per step of the
+    plain forward step and of the adjoint kernel."""
+    import numpy as np
+    import torch
+    from paper_1807_02284_amd import inputs
+    from paper_1807_02284_amd.level import Level, Params
+    from paper_1807_02284_amd.rollout import rollout
+
+    s0 = inputs.gaussian_blob(n, n, n, (n / 2, n / 2, n / 4), n / 16.0)
+    p = Params(nu=1e-3, g_max=0.1, tau_s=0.51, beta=1e-4, s_ref=float(s0.mean()))
+    lev = Level(n, n, n, p, scalar=True, force=np.zeros((3, n ** 3)))
+    lev.init_equilibrium(None, np.zeros((3, n ** 3)), s0)
+    h0, g0 = lev.get_populations(shifted=True)
+    theta = torch.zeros(3, n ** 3, device="cuda", requires_grad=True)
+    target = torch.tensor(0.8 * inputs.gaussian_blob(n, n, n, (n / 2 + 4, n / 2, n / 4 + 8), n / 16.0),
+                          dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    s = rollout(lev, theta, h0, g0, steps, every)
+    e[1].record()
+    loss = 0.5 * ((s - target) ** 2).sum()
+    loss.backward()
+    e[2].record()
+    torch.cuda.synchronize()
+    fwd_ms, bwd_ms = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+    # adjoint kernel alone, timed on the same state
+    lam = torch.zeros(27 * lev.plane, device="cuda")
+    lam2 = torch.zeros_like(lam)
+    mu = torch.zeros(7 * lev.plane, device="cuda")
+    mu2 = torch.zeros_like(mu)
+    dth = torch.zeros(3 * lev.plane, device="cuda")
+    for _ in range(3):
+        lev.adjoint_step(lev.f, lev.g, lam, mu, lam2, mu2, dth)
+    torch.cuda.synchronize()
+    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    a0.record()
+    for _ in range(reps):
+        lev.adjoint_step(lev.f, lev.g, lam, mu, lam2, mu2, dth)
+    a1.record()
+    torch.cuda.synchronize()
+    adj_ms = a0.elapsed_time(a1) / reps
+    step_ms = time_steps(lev, reps, 2) / reps
+    cells = n ** 3
+    out = {
+        "forward_ms_per_step": fwd_ms / steps,
+        "backward_ms_per_step": bwd_ms / steps,
+        "plain_step_ms": step_ms,
+        "adjoint_kernel_ms": adj_ms,
+        "adjoint_vs_plain_step_time": adj_ms / step_ms,
+        "backward_vs_forward_time": bwd_ms / fwd_ms,
+        "adjoint_mlups": cells / (adj_ms * 1e-3) / 1e6,
+        "adjoint_achieved_gbs": cells * 444 / (adj_ms * 1e-3) / 1e9,
+        "plain_step_achieved_gbs": cells * 284 / (step_ms * 1e-3) / 1e9,
+        "bytes_per_lup": {"plain_step_scalar_force": 284, "adjoint": 444},
+        "loss": float(loss),
+        "grad_theta_norm": float(theta.grad.norm()),
+    }
+    del lev
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_plume(nx: int, ny: int, nz: int, spinup: int, n_ref: int):
+    """Multi-scale smoke plume: nx*ny*nz reference box, bounce-back walls,
+    inflow u = 0.05 with smoke s = 1 at a disk on the x = 0 face, outflow at
+    x = nx-1, solid sphere of radius 24 (scaled); passive FP32 scalar; nu0 =
+    1e-4 (tau0 = 0.5003), tau_s0 = 0.51.  The jet cylinder starts at
+    u = 0.05.  After `spinup` reference-scale steps, two finer scales
+    (spacing ratios 1.5 and 2) are placed on the vorticity thresholds 2e-3
+    and 8e-3 (with speed thresholds 0.01 and 0.02), then `n_ref` reference
+    steps of Algorithm 1 are timed."""
+    import numpy as np
+    import torch
+    from paper_1807_02284_amd import hierarchy, inputs
+    from paper_1807_02284_amd.level import Level, Params
+
+    sc = nx / 512.0
+    flags = inputs.plume_flags(nx, ny, nz)
+    p0 = Params(nu=1e-4, g_max=0.1, tau_s=0.51, u_in=(0.05, 0.0, 0.0), s_in=1.0)
+    lev0 = Level(nx, ny, nz, p0, scalar=True, periodic=0, flags=flags)
+    x, y, z = inputs.grid_coords(nx, ny, nz)
+    jet = ((y + 0.5 - ny / 2) ** 2 + (z + 0.5 - nz / 2) ** 2 <= (32 * sc) ** 2) & (flags == 0)
+    u = np.zeros((3, x.size), np.float32)
+    u[0, jet] = 0.05
+    s0 = np.where(jet & (x < 64 * sc), 1.0, 0.0).astype(np.float32)
+    lev0.init_equilibrium(None, u, s0)
+    del x, y, z, u, s0, jet
+    # reference-scale collide-stream alone (flags + scalar: 273 B/LUP)
+    ms0 = time_steps(lev0, spinup, 10)
+    n0 = nx * ny * nz
+    centre = (160.0 * sc, ny / 2.0, nz / 2.0)
+    r = 24.0 * sc
+
+    def sphere(px, py, pz):
+        return (px + 0.5 - centre[0]) ** 2 + (py + 0.5 - centre[1]) ** 2 + (pz + 0.5 - centre[2]) ** 2 <= r * r
+
+    H, boxes = hierarchy.dynamic_hierarchy(lev0, flags, ((2e-3, 0.01), (8e-3, 0.02)), (1.5, 2.0),
+                                           solid_fn=sphere)
+    alphas = [1.0] + [1.0 / lv.c.dx for lv in H.levels[1:]]
+    subs = [1] + [int(np.floor(a + 1e-12)) + 1 for a in alphas[1:]]
+    cells = [lv.n for lv in H.levels]
+    lups = sum(c * k for c, k in zip(cells, subs))
+    H.step(2)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    H.step(n_ref)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / n_ref
+    bad = sum(lv.count_nonfinite() for lv in H.levels)
+    out = {
+        "reference_box": [nx, ny, nz],
+        "scales": len(H.levels),
+        "spacing_ratios": alphas,
+        "cells_per_scale": cells,
+        "substeps_per_scale": subs,
+        "boxes_level0_units": [[list(map(int, lo)), list(map(int, hi))] for lo, hi in boxes],
+        "coverage_of_reference_volume": [
+            float(np.prod([hi[a] - lo[a] + 1 for a in range(3)]) / n0) for lo, hi in boxes],
+        "ms_per_reference_step": ms,
+        "lattice_updates_per_reference_step": lups,
+        "mlups_all_scales": lups / (ms * 1e-3) / 1e6,
+        "reference_scale_step_ms": ms0 / spinup,
+        "reference_scale_mlups": n0 / (ms0 / spinup * 1e-3) / 1e6,
+        "reference_scale_achieved_gbs": n0 * 273 / (ms0 / spinup * 1e-3) / 1e9,
+        "bytes_per_lup_collide_stream": 273,
+        "nonfinite": bad,
+    }
+    del H, lev0
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(n: int, target_s: float = 12.0):
     """The FP64 oracle (as is) on a bounded sample of the workload: a periodic
     n x n x nz_s slab cut from the same seeded turbulence field, one or more
@@ -140,6 +327,12 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the 384^3 FP16-vs-FP32 Taylor-Green variant")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the 128^3 differentiable buoyant-smoke variant")
+    ap.add_argument("--no-plume", action="store_true",
+                    help="skip the 512x256x256 three-scale plume variant")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the runs, copy a 1 GiB float32 tensor 3 times (reference "
                          "kernel of known traffic for HBM counter calibration)")
@@ -168,6 +361,27 @@ def main():
             "achieved_gbs": v["achieved_gbs"], "bytes_per_lup": BYTES_PER_LUP["f16s"],
         }
         print(f"[bench] f16s {args.n}^3: {v['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+
+    if not args.no_precision:
+        pr = run_precision(384, 100)
+        variants["precision_tgv_384"] = pr
+        print(f"[bench] 384^3 TGV: f32 {pr['f32']['mlups']:.0f} MLUPS, f16s {pr['f16s']['mlups']:.0f} "
+              f"MLUPS, f16s vs f32 velocity rel L2 {pr['f16s_vs_f32_velocity_rel_l2']:.2e}",
+              file=sys.stderr, flush=True)
+    if not args.no_adjoint:
+        ad = run_adjoint(128, 200, 20)
+        variants["adjoint_smoke_128"] = ad
+        print(f"[bench] 128^3 adjoint: {ad['adjoint_kernel_ms']:.3f} ms/step vs plain "
+              f"{ad['plain_step_ms']:.3f} ms ({ad['adjoint_vs_plain_step_time']:.2f}x)",
+              file=sys.stderr, flush=True)
+
+    if not args.no_plume:
+        pl = run_plume(512, 256, 256, 300, 40)
+        variants["plume_multiscale_512x256x256"] = pl
+        print(f"[bench] plume: {pl['scales']} scales, cells {pl['cells_per_scale']}, "
+              f"{pl['ms_per_reference_step']:.2f} ms/reference step, "
+              f"{pl['mlups_all_scales']:.0f} MLUPS over all scales; reference scale alone "
+              f"{pl['reference_scale_mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
 
     if args.copy_calibration:
         x = torch.rand(1 << 28, device="cuda")      # 1 GiB

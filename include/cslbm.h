@@ -150,6 +150,15 @@ int cslbm_step(cslbm_level* L, int32_t n_steps, hipStream_t stream);
  * F/2)/rho, s = sum g (dense arrays; any output may be NULL). */
 int cslbm_read_macro(const cslbm_level* L, float* rho, float* u, float* s, hipStream_t stream);
 
+/* Vorticity magnitude |curl u| of the stored state into omega (dense [N]),
+ * and the speed |u| into speed (dense [N], may be NULL): u as in
+ * cslbm_read_macro, central differences (periodic wrap on periodic axes,
+ * one-sided at non-periodic faces).  The two thresholds of the dynamic
+ * scale construction (section "Scale construction": gradient magnitude,
+ * then velocity magnitude) are applied to these fields.  Takes its
+ * temporary velocity field from the stream-ordered allocator. */
+int cslbm_vorticity(const cslbm_level* L, float* omega, float* speed, hipStream_t stream);
+
 /* Conserved totals over cells that are neither SOLID nor GHOST, accumulated
  * in FP64 with a fixed reduction order (bitwise reproducible):
  * out[0] = sum rho, out[1..3] = sum c f~ (momentum), out[4] = sum s (0

@@ -99,8 +99,7 @@ __global__ void __launch_bounds__(256) k_adjoint(const AdjArgs a)
 template <typename T>
 static void launch_adjoint(const AdjArgs& a, bool scalar, hipStream_t st)
 {
-    const int bx = a.nx >= 256 ? 256 : (a.nx >= 128 ? 128 : 64);
-    const dim3 block(bx, 256 / bx, 1);
+    const dim3 block = step_block(a.nx);
     const dim3 grid((a.nx + block.x - 1) / block.x, (a.ny + block.y - 1) / block.y, a.nz);
     if (scalar)
         hipLaunchKernelGGL((k_adjoint<T, true>), grid, block, 0, st, a);

@@ -199,61 +199,63 @@ __host__ __device__ __forceinline__ void cm_collide_adjoint(const float (&h)[27]
     const float uy = (jy + 0.5f * Fy) * ir;
     const float uz = (jz + 0.5f * Fz) * ir;
 
-    float v[27];
-#pragma unroll
-    for (int q = 0; q < 27; ++q) v[q] = h[q];
-    to_moments(v, ux, uy, uz);
-    float d[27];
-    deviation_equilibrium(d, dr, ux, uy, uz);
-
-    const float nxy = v[kslot(1, 1, 0)] - d[kslot(1, 1, 0)];
-    const float nxz = v[kslot(1, 0, 1)] - d[kslot(1, 0, 1)];
-    const float nyz = v[kslot(0, 1, 1)] - d[kslot(0, 1, 1)];
-    const float nxx = v[kslot(2, 0, 0)] - d[kslot(2, 0, 0)];
-    const float nyy = v[kslot(0, 2, 0)] - d[kslot(0, 2, 0)];
-    const float nzz = v[kslot(0, 0, 2)] - d[kslot(0, 0, 2)];
-    const float tr = (nxx + nyy + nzz) * (1.0f / 3.0f);
-    const float pxx = nxx - tr, pyy = nyy - tr, pzz = nzz - tr;
-    const float pp = pxx * pxx + pyy * pyy + pzz * pzz + 2.0f * (nxy * nxy + nxz * nxz + nyz * nyz);
-    const float sq = sqrtf(2.0f * pp);
-    const float G = 1.5f * r.S * ir * sq;
-    float phi = 1.0f;
-    bool on_slope = false;
-    if (r.adaptive) {
-        const float xg = G * r.inv_gmax;
-        on_slope = xg < 1.0f;
-        phi = r.a * fminf(xg, 1.0f) + r.b;
-    }
-    float om[4], den[4];
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        den[g] = phi * r.nu3[g] + 0.5f;
-        om[g] = 1.0f - 1.0f / den[g];
-    }
-    const float oms = 1.0f - r.S;
-
-    // post-collision moments w
-    float w[27];
-#pragma unroll
-    for (int q = 0; q < 27; ++q) w[q] = v[q];
-    w[kslot(1, 0, 0)] += Fx;
-    w[kslot(0, 1, 0)] += Fy;
-    w[kslot(0, 0, 1)] += Fz;
-    w[kslot(1, 1, 0)] = d[kslot(1, 1, 0)] + oms * nxy;
-    w[kslot(1, 0, 1)] = d[kslot(1, 0, 1)] + oms * nxz;
-    w[kslot(0, 1, 1)] = d[kslot(0, 1, 1)] + oms * nyz;
-    w[kslot(2, 0, 0)] = d[kslot(2, 0, 0)] + oms * pxx + om[0] * tr;
-    w[kslot(0, 2, 0)] = d[kslot(0, 2, 0)] + oms * pyy + om[0] * tr;
-    w[kslot(0, 0, 2)] = d[kslot(0, 0, 2)] + oms * pzz + om[0] * tr;
-    // group of every moment of order >= 3 (-1: handled above)
+    // group of every moment of order >= 3 (-1: orders 0..2, handled apart)
     constexpr int kGroup[27] = {
         // m + 3n + 9p -> group by total order (3 -> 0, 4 -> 1, 5 -> 2, 6 -> 3)
         -1, -1, -1, -1, -1, 0, -1, 0, 1,     // p = 0: 000 100 200 010 110 210 020 120 220
         -1, -1, 0, -1, 0, 1, 0, 1, 2,        // p = 1: 001 101 201 011 111 211 021 121 221
         -1, 0, 1, 0, 1, 2, 1, 2, 3};         // p = 2: 002 102 202 012 112 212 022 122 222
+
+    // forward moments v = K(u) h, deviation equilibria d, adaptive rates and
+    // the post-collision moments w; v and d are recomputed later instead of
+    // being kept live through the reverse sweeps (register pressure)
+    float w[27];
+    float nxy, nxz, nyz, tr, pxx, pyy, pzz, pp, sq, G, phi = 1.0f;
+    bool on_slope = false;
+    float om[4], den[4];
+    const float oms = 1.0f - r.S;
+    {
+        float d[27];
 #pragma unroll
-    for (int q = 0; q < 27; ++q)
-        if (kGroup[q] >= 0) w[q] = d[q] + om[kGroup[q]] * (v[q] - d[q]);
+        for (int q = 0; q < 27; ++q) w[q] = h[q];
+        to_moments(w, ux, uy, uz);
+        deviation_equilibrium(d, dr, ux, uy, uz);
+        nxy = w[kslot(1, 1, 0)] - d[kslot(1, 1, 0)];
+        nxz = w[kslot(1, 0, 1)] - d[kslot(1, 0, 1)];
+        nyz = w[kslot(0, 1, 1)] - d[kslot(0, 1, 1)];
+        const float nxx = w[kslot(2, 0, 0)] - d[kslot(2, 0, 0)];
+        const float nyy = w[kslot(0, 2, 0)] - d[kslot(0, 2, 0)];
+        const float nzz = w[kslot(0, 0, 2)] - d[kslot(0, 0, 2)];
+        tr = (nxx + nyy + nzz) * (1.0f / 3.0f);
+        pxx = nxx - tr;
+        pyy = nyy - tr;
+        pzz = nzz - tr;
+        pp = pxx * pxx + pyy * pyy + pzz * pzz + 2.0f * (nxy * nxy + nxz * nxz + nyz * nyz);
+        sq = sqrtf(2.0f * pp);
+        G = 1.5f * r.S * ir * sq;
+        if (r.adaptive) {
+            const float xg = G * r.inv_gmax;
+            on_slope = xg < 1.0f;
+            phi = r.a * fminf(xg, 1.0f) + r.b;
+        }
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            den[g] = phi * r.nu3[g] + 0.5f;
+            om[g] = 1.0f - 1.0f / den[g];
+        }
+        w[kslot(1, 0, 0)] += Fx;
+        w[kslot(0, 1, 0)] += Fy;
+        w[kslot(0, 0, 1)] += Fz;
+        w[kslot(1, 1, 0)] = d[kslot(1, 1, 0)] + oms * nxy;
+        w[kslot(1, 0, 1)] = d[kslot(1, 0, 1)] + oms * nxz;
+        w[kslot(0, 1, 1)] = d[kslot(0, 1, 1)] + oms * nyz;
+        w[kslot(2, 0, 0)] = d[kslot(2, 0, 0)] + oms * pxx + om[0] * tr;
+        w[kslot(0, 2, 0)] = d[kslot(0, 2, 0)] + oms * pyy + om[0] * tr;
+        w[kslot(0, 0, 2)] = d[kslot(0, 0, 2)] + oms * pzz + om[0] * tr;
+#pragma unroll
+        for (int q = 0; q < 27; ++q)
+            if (kGroup[q] >= 0) w[q] = d[q] + om[kGroup[q]] * (w[q] - d[q]);
+    }
 
     // ---------------- reverse ----------------
     float uxb = 0.0f, uyb = 0.0f, uzb = 0.0f, sb = 0.0f;
@@ -276,30 +278,47 @@ __host__ __device__ __forceinline__ void cm_collide_adjoint(const float (&h)[27]
         for (int i = 0; i < QS; ++i) gb[i] = 0.0f;
     }
 
-    // inverse sweeps: h~ = Ix(Iy(Iz(w)))
+    // inverse sweeps: h~ = Ix(Iy(Iz(w))); the sweep inputs are rebuilt from w
+    // one at a time rather than kept together (register pressure)
     float bar[27];
 #pragma unroll
     for (int q = 0; q < 27; ++q) bar[q] = lam[q];
     {
-        float a1[27], a2[27];
+        float t[27];
 #pragma unroll
-        for (int q = 0; q < 27; ++q) a1[q] = w[q];
-        sweep_inv<9, 1, 3>(a1, uz);
+        for (int q = 0; q < 27; ++q) t[q] = w[q];
+        sweep_inv<9, 1, 3>(t, uz);
+        sweep_inv<3, 1, 9>(t, uy);
+        sweep_inv_rev<1, 3, 9>(t, bar, ux, uxb);
 #pragma unroll
-        for (int q = 0; q < 27; ++q) a2[q] = a1[q];
-        sweep_inv<3, 1, 9>(a2, uy);
-        sweep_inv_rev<1, 3, 9>(a2, bar, ux, uxb);
-        sweep_inv_rev<3, 1, 9>(a1, bar, uy, uyb);
+        for (int q = 0; q < 27; ++q) t[q] = w[q];
+        sweep_inv<9, 1, 3>(t, uz);
+        sweep_inv_rev<3, 1, 9>(t, bar, uy, uyb);
         sweep_inv_rev<9, 1, 3>(w, bar, uz, uzb);
     }
     // bar = dL/dw
 
-    // relaxation
+    // relaxation (v and d recomputed)
     float vb[27], db[27];
+    float omb[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    {
+        float v[27];
 #pragma unroll
-    for (int q = 0; q < 27; ++q) {
-        vb[q] = 0.0f;
-        db[q] = 0.0f;
+        for (int q = 0; q < 27; ++q) v[q] = h[q];
+        to_moments(v, ux, uy, uz);
+        deviation_equilibrium(db, dr, ux, uy, uz);   // db holds d for a moment
+#pragma unroll
+        for (int q = 0; q < 27; ++q) {
+            if (kGroup[q] >= 0) {
+                const int g = kGroup[q];
+                omb[g] += (v[q] - db[q]) * bar[q];
+                vb[q] = om[g] * bar[q];
+                db[q] = (1.0f - om[g]) * bar[q];
+            } else {
+                vb[q] = 0.0f;
+                db[q] = 0.0f;
+            }
+        }
     }
     vb[kslot(0, 0, 0)] = bar[kslot(0, 0, 0)];
     vb[kslot(1, 0, 0)] = bar[kslot(1, 0, 0)];
@@ -307,15 +326,6 @@ __host__ __device__ __forceinline__ void cm_collide_adjoint(const float (&h)[27]
     vb[kslot(0, 0, 1)] = bar[kslot(0, 0, 1)];
     float Fxb = bar[kslot(1, 0, 0)], Fyb = bar[kslot(0, 1, 0)], Fzb = bar[kslot(0, 0, 1)];
     float phib = 0.0f;
-    float omb[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int q = 0; q < 27; ++q)
-        if (kGroup[q] >= 0) {
-            const int g = kGroup[q];
-            vb[q] += om[g] * bar[q];
-            db[q] += (1.0f - om[g]) * bar[q];
-            omb[g] += (v[q] - d[q]) * bar[q];
-        }
     // second order: off-diagonal and diagonal (deviatoric with S, trace with om0)
     float nxyb = oms * bar[kslot(1, 1, 0)], nxzb = oms * bar[kslot(1, 0, 1)],
           nyzb = oms * bar[kslot(0, 1, 1)];
@@ -372,17 +382,18 @@ __host__ __device__ __forceinline__ void cm_collide_adjoint(const float (&h)[27]
     float drb = db[kslot(0, 0, 0)];
     deviation_equilibrium_rev(db, dr, ux, uy, uz, drb, uxb, uyb, uzb);
 
-    // forward sweeps: v = Fz(Fy(Fx(h)))
+    // forward sweeps: v = Fz(Fy(Fx(h))), inputs rebuilt from h one at a time
     {
-        float b1[27], b2[27];
+        float t[27];
 #pragma unroll
-        for (int q = 0; q < 27; ++q) b1[q] = h[q];
-        sweep_fwd<1, 3, 9>(b1, ux);
+        for (int q = 0; q < 27; ++q) t[q] = h[q];
+        sweep_fwd<1, 3, 9>(t, ux);
+        sweep_fwd<3, 1, 9>(t, uy);
+        sweep_fwd_rev<9, 1, 3>(t, vb, uz, uzb);
 #pragma unroll
-        for (int q = 0; q < 27; ++q) b2[q] = b1[q];
-        sweep_fwd<3, 1, 9>(b2, uy);
-        sweep_fwd_rev<9, 1, 3>(b2, vb, uz, uzb);
-        sweep_fwd_rev<3, 1, 9>(b1, vb, uy, uyb);
+        for (int q = 0; q < 27; ++q) t[q] = h[q];
+        sweep_fwd<1, 3, 9>(t, ux);
+        sweep_fwd_rev<3, 1, 9>(t, vb, uy, uyb);
         sweep_fwd_rev<1, 3, 9>(h, vb, ux, uxb);
     }
     // vb = dL/dh through the transforms

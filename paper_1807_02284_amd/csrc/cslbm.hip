@@ -60,6 +60,11 @@ struct StepArgs {
     float beta, s_ref, inv_tau_s;
     float u_in[3];
     float s_in;
+    // fused quadratic time interpolation of the output (finer scales):
+    // out = l0 * t0 + l1 * f + l2 * step(f), t0 the state at t_n
+    const void* t0;
+    const float* gt0;
+    float l0, l1, l2;
 };
 
 // D3Q7 equilibrium g^eq_i = w_i s (1 + 4 c_i.u)  (cs^2 = 1/4)
@@ -78,10 +83,30 @@ __device__ __forceinline__ bool leaves_box(int x, int y, int z, int cx, int cy, 
     return ox || oy || oz;
 }
 
+// Output store of k_step: the new state, or (kTime) its quadratic time
+// interpolation l0 * t0 + l1 * (input state) + l2 * (new state) at the cell.
+template <typename T, bool kTime>
+__device__ __forceinline__ void store_out(const StepArgs& a, T* fo, int64_t e, float v)
+{
+    if (kTime) {
+        const float x0 = Io<T>::ld(static_cast<const T*>(a.t0) + e);
+        const float x1 = Io<T>::ld(static_cast<const T*>(a.f) + e);
+        v = a.l0 * x0 + a.l1 * x1 + a.l2 * v;
+    }
+    Io<T>::st(fo + e, v);
+}
+
+template <bool kTime>
+__device__ __forceinline__ void store_gout(const StepArgs& a, int64_t e, float v)
+{
+    if (kTime) v = a.l0 * a.gt0[e] + a.l1 * a.g[e] + a.l2 * v;
+    __builtin_nontemporal_store(v, a.go + e);
+}
+
 // ---------------------------------------------------------------------------
 // K: fused pull-stream + collide
 // ---------------------------------------------------------------------------
-template <typename T, bool kFlags, bool kForce, bool kScalar>
+template <typename T, bool kFlags, bool kForce, bool kScalar, bool kTime>
 __global__ void __launch_bounds__(256) k_step(const StepArgs a)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -115,31 +140,30 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
     if (kFlags && kind != kFluid) {
         if (kind == kSolid) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) Io<T>::st(fo + i * P + cell, 0.0f);
+            for (int i = 0; i < Q; ++i) store_out<T, kTime>(a, fo, i * P + cell, 0.0f);
             if (kScalar)
 #pragma unroll
-                for (int i = 0; i < QS; ++i) a.go[i * P + cell] = 0.0f;
+                for (int i = 0; i < QS; ++i) store_gout<kTime>(a, i * P + cell, 0.0f);
         } else if (kind == kInlet) {
             float v[27];
             shifted_equilibrium(v, 1.0f, a.u_in[0], a.u_in[1], a.u_in[2]);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) Io<T>::st(fo + i * P + cell, v[tensor_slot(i)]);
+            for (int i = 0; i < Q; ++i) store_out<T, kTime>(a, fo, i * P + cell, v[tensor_slot(i)]);
             if (kScalar)
 #pragma unroll
                 for (int i = 0; i < QS; ++i)
-                    a.go[i * P + cell] = scalar_eq(i, a.s_in, a.u_in[0], a.u_in[1], a.u_in[2]);
+                    store_gout<kTime>(a, i * P + cell,
+                                      scalar_eq(i, a.s_in, a.u_in[0], a.u_in[1], a.u_in[2]));
         } else {
             // ghost: keep; outflow: copy the incoming state of the x-1 neighbour
             int from = cell;
             if (kind == kOutflow && (x > 0 || (a.periodic & 1))) from = xm + nx * y + nxy * z;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                const float hv = Io<T>::ld(f + i * P + from);
-                Io<T>::st(fo + i * P + cell, hv);
-            }
+            for (int i = 0; i < Q; ++i)
+                store_out<T, kTime>(a, fo, i * P + cell, Io<T>::ld(f + i * P + from));
             if (kScalar)
 #pragma unroll
-                for (int i = 0; i < QS; ++i) a.go[i * P + cell] = a.g[i * P + from];
+                for (int i = 0; i < QS; ++i) store_gout<kTime>(a, i * P + cell, a.g[i * P + from]);
         }
         return;
     }
@@ -192,13 +216,13 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
     const CellMacro mc = cm_collide(v, a.r, Fx, Fy, Fz);
 
 #pragma unroll
-    for (int i = 0; i < Q; ++i) Io<T>::st(fo + i * P + cell, v[tensor_slot(i)]);
+    for (int i = 0; i < Q; ++i) store_out<T, kTime>(a, fo, i * P + cell, v[tensor_slot(i)]);
 
     if (kScalar) {
 #pragma unroll
         for (int i = 0; i < QS; ++i) {
             const float ge = scalar_eq(i, s, mc.ux, mc.uy, mc.uz);
-            __builtin_nontemporal_store(gv[i] - (gv[i] - ge) * a.inv_tau_s, a.go + i * P + cell);
+            store_gout<kTime>(a, i * P + cell, gv[i] - (gv[i] - ge) * a.inv_tau_s);
         }
     }
 }
@@ -318,6 +342,48 @@ __global__ void k_macro(const T* f, const float* g, const float* force, int64_t 
         u[2 * N + c] = (jz - 0.5f * Fz) / r;
     }
     if (s) s[c] = sc;
+}
+
+// |curl u| by central differences of a dense velocity field (periodic wrap on
+// periodic axes, one-sided differences at non-periodic faces)
+__global__ void __launch_bounds__(256) k_vorticity(const float* u, int nx, int ny, int nz,
+                                                   int periodic, float* out, float* speed)
+{
+    const int64_t N = (int64_t)nx * ny * nz;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+    int x, y, z;
+    cell_coords(c, nx, ny, x, y, z);
+    const int n[3] = {nx, ny, nz};
+    const int p[3] = {x, y, z};
+    float grad[3][3];   // grad[a][b] = d u_a / d x_b
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        int lo = p[b] - 1, hi = p[b] + 1;
+        float h = 2.0f;
+        if (periodic & (1 << b)) {
+            lo = (lo + n[b]) % n[b];
+            hi = hi % n[b];
+        } else {
+            if (lo < 0) { lo = 0; h = 1.0f; }
+            if (hi >= n[b]) { hi = n[b] - 1; h = 1.0f; }
+            if (n[b] == 1) h = 0.0f;
+        }
+        int ql[3] = {x, y, z}, qh[3] = {x, y, z};
+        ql[b] = lo;
+        qh[b] = hi;
+        const int64_t cl = ql[0] + (int64_t)nx * (ql[1] + (int64_t)ny * ql[2]);
+        const int64_t ch = qh[0] + (int64_t)nx * (qh[1] + (int64_t)ny * qh[2]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            grad[a][b] = h > 0.0f ? (u[a * N + ch] - u[a * N + cl]) / h : 0.0f;
+    }
+    const float wx = grad[2][1] - grad[1][2], wy = grad[0][2] - grad[2][0], wz = grad[1][0] - grad[0][1];
+    out[c] = sqrtf(wx * wx + wy * wy + wz * wz);
+    if (speed) {
+        const float a = u[c], b = u[N + c], d = u[2 * N + c];
+        speed[c] = sqrtf(a * a + b * b + d * d);
+    }
 }
 
 // FP64 conservation: per-block partial sums (count, sum h, sum c h, sum g),
@@ -478,23 +544,47 @@ Rates make_rates(const cslbm_params& p)
     return r;
 }
 
-static dim3 step_block(int nx)
+// Block of 256 threads: bx consecutive x (a multiple of 64, so waves cover
+// contiguous row segments) by 256/bx rows.  bx is the largest of 256, 128, 64
+// that leaves the fewest idle lanes per row (nx = 384 -> 128, nx = 512 ->
+// 256, nx = 96 -> 128).
+dim3 step_block(int nx)
 {
-    const int bx = nx >= 256 ? 256 : (nx >= 128 ? 128 : 64);
-    return dim3(bx, 256 / bx, 1);
+    int best = 256;
+    int64_t best_pad = ((nx + 255) / 256) * 256 - nx;
+    for (int bx : {128, 64}) {
+        const int64_t pad = ((int64_t)(nx + bx - 1) / bx) * bx - nx;
+        if (pad < best_pad) {
+            best = bx;
+            best_pad = pad;
+        }
+    }
+    return dim3(best, 256 / best, 1);
 }
 
-template <typename T, bool kFlags, bool kForce, bool kScalar>
+template <typename T, bool kFlags, bool kForce, bool kScalar, bool kTime = false>
 static void launch_step(const StepArgs& a, hipStream_t st)
 {
     const dim3 block = step_block(a.nx);
     const dim3 grid((a.nx + block.x - 1) / block.x, (a.ny + block.y - 1) / block.y, a.nz);
-    hipLaunchKernelGGL((k_step<T, kFlags, kForce, kScalar>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_step<T, kFlags, kForce, kScalar, kTime>), grid, block, 0, st, a);
 }
 
+// time-interpolating variants exist for flagged levels only (finer scales)
 template <typename T>
-static void dispatch_step(const StepArgs& a, bool flags, bool force, bool scalar, hipStream_t st)
+static void dispatch_step(const StepArgs& a, bool flags, bool force, bool scalar, bool time,
+                          hipStream_t st)
 {
+    if (time) {
+        const int key = (force ? 2 : 0) | (scalar ? 1 : 0);
+        switch (key) {
+            case 0: launch_step<T, true, false, false, true>(a, st); break;
+            case 1: launch_step<T, true, false, true, true>(a, st); break;
+            case 2: launch_step<T, true, true, false, true>(a, st); break;
+            default: launch_step<T, true, true, true, true>(a, st); break;
+        }
+        return;
+    }
     const int key = (flags ? 4 : 0) | (force ? 2 : 0) | (scalar ? 1 : 0);
     switch (key) {
         case 0: launch_step<T, false, false, false>(a, st); break;
@@ -513,7 +603,19 @@ static inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n
 int launch_step_into(const cslbm_level* L, const void* fin, void* fout, const float* gin,
                      float* gout, hipStream_t stream)
 {
+    return launch_step_interp(L, fin, fout, gin, gout, nullptr, nullptr, 0.0, 0.0, 1.0, stream);
+}
+
+int launch_step_interp(const cslbm_level* L, const void* fin, void* fout, const float* gin,
+                       float* gout, const void* t0, const float* gt0, double l0, double l1,
+                       double l2, hipStream_t stream)
+{
     StepArgs a;
+    a.t0 = t0;
+    a.gt0 = gt0;
+    a.l0 = (float)l0;
+    a.l1 = (float)l1;
+    a.l2 = (float)l2;
     a.f = fin;
     a.fo = fout;
     a.g = gin;
@@ -534,10 +636,13 @@ int launch_step_into(const cslbm_level* L, const void* fin, void* fout, const fl
     const bool has_flags = L->flags != nullptr;
     const bool has_force = L->force != nullptr;
     const bool has_scalar = gin != nullptr;
+    const bool time = t0 != nullptr;
+    if (time && !has_flags)
+        return fail(CSLBM_ERR_UNSUPPORTED, "time-interpolating steps need a flagged level");
     if (L->storage == CSLBM_F32)
-        dispatch_step<float>(a, has_flags, has_force, has_scalar, stream);
+        dispatch_step<float>(a, has_flags, has_force, has_scalar, time, stream);
     else
-        dispatch_step<_Float16>(a, has_flags, has_force, has_scalar, stream);
+        dispatch_step<_Float16>(a, has_flags, has_force, has_scalar, time, stream);
     return check_launch("k_step");
 }
 
@@ -667,6 +772,34 @@ int cslbm_read_macro(const cslbm_level* L, float* rho, float* u, float* s, hipSt
         hipLaunchKernelGGL(k_macro<_Float16>, grid, block, 0, stream, (const _Float16*)L->f, L->g,
                            L->force, N, L->plane, beta, sref, rho, u, s);
     return check_launch("k_macro");
+}
+
+int cslbm_vorticity(const cslbm_level* L, float* omega, float* speed, hipStream_t stream)
+{
+    int rc = validate_shape(L);
+    if (rc) return rc;
+    if (!omega) return fail(CSLBM_ERR_ARG, "omega is NULL");
+    const int64_t N = cells_of(L);
+    float* u = nullptr;
+    CSLBM_HIP_TRY(hipMallocAsync((void**)&u, 3 * N * sizeof(float), stream));
+    const dim3 grid(blocks_for(N, 256)), block(256);
+    const float beta = (float)L->p.beta, sref = (float)L->p.s_ref;
+    if (L->storage == CSLBM_F32)
+        hipLaunchKernelGGL(k_macro<float>, grid, block, 0, stream, (const float*)L->f, L->g, L->force,
+                           N, L->plane, beta, sref, nullptr, u, nullptr);
+    else
+        hipLaunchKernelGGL(k_macro<_Float16>, grid, block, 0, stream, (const _Float16*)L->f, L->g,
+                           L->force, N, L->plane, beta, sref, nullptr, u, nullptr);
+    rc = check_launch("k_macro");
+    if (!rc) {
+        hipLaunchKernelGGL(k_vorticity, grid, block, 0, stream, u, L->nx, L->ny, L->nz,
+                           L->periodic & 7, omega, speed);
+        rc = check_launch("k_vorticity");
+    }
+    const hipError_t ef = hipFreeAsync(u, stream);
+    if (rc) return rc;
+    if (ef != hipSuccess) return fail(CSLBM_ERR_HIP, "hipFreeAsync: %s", hipGetErrorString(ef));
+    return CSLBM_OK;
 }
 
 int cslbm_conserved_f64(const cslbm_level* L, double out[5], hipStream_t stream)

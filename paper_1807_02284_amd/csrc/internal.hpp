@@ -44,9 +44,19 @@ int validate_shape(const cslbm_level* L);
 int validate_params(const cslbm_level* L);
 Rates make_rates(const cslbm_params& p);
 
+// Thread block for the one-thread-per-cell kernels over an nx-wide row.
+dim3 step_block(int nx);
+
 // One collide-stream step of level L from (fin, gin) into (fout, gout);
 // L's own f/g pointers are not used.  Arguments must be validated.
 int launch_step_into(const cslbm_level* L, const void* fin, void* fout, const float* gin,
                      float* gout, hipStream_t stream);
+
+// The same step with its output replaced by the quadratic time interpolation
+// l0 * t0 + l1 * fin + l2 * step(fin) at every cell (and likewise for g);
+// L must have flags.
+int launch_step_interp(const cslbm_level* L, const void* fin, void* fout, const float* gin,
+                       float* gout, const void* t0, const float* gt0, double l0, double l1,
+                       double l2, hipStream_t stream);
 
 }  // namespace cslbm

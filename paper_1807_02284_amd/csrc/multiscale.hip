@@ -362,30 +362,34 @@ int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t s
             void* bufs[2] = {L->f_next, sc.work_f[0]};
             float* gX0 = L->g;
             float* gbufs[2] = {L->g_next, sc.work_g[0]};
-            void* prev = X0;
             void* cur = X0;
-            float* gprev = gX0;
             float* gcur = gX0;
+            // the quadratic through 0, (l-1)/alpha, l/alpha evaluated at 1,
+            // fused into the last sub-step's output
+            const double t[3] = {0.0, (l - 1) / alpha, l / alpha};
+            const double L0 = (1.0 - t[1]) * (1.0 - t[2]) / ((t[0] - t[1]) * (t[0] - t[2]));
+            const double L1 = (1.0 - t[0]) * (1.0 - t[2]) / ((t[1] - t[0]) * (t[1] - t[2]));
+            const double L2 = (1.0 - t[0]) * (1.0 - t[1]) / ((t[2] - t[0]) * (t[2] - t[1]));
+            void* R = sc.work_f[1];
+            float* gR = sc.work_g[1];
             for (int k = 1; k <= l; ++k) {
                 // prior-mapping of the boundary shell at the sub-step's start time
                 int rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], (k - 1) / alpha, L, cur, gcur,
                                          sc.ghost_cells, sc.n_ghost, stream);
                 if (rc) return rc;
-                void* next = bufs[(k - 1) & 1];
-                float* gnext = gbufs[(k - 1) & 1];
-                rc = launch_step_into(L, cur, next, gcur, gnext, stream);
-                if (rc) return rc;
-                prev = cur;
-                cur = next;
-                gprev = gcur;
-                gcur = gnext;
+                if (k < l) {
+                    void* next = bufs[(k - 1) & 1];
+                    float* gnext = gbufs[(k - 1) & 1];
+                    rc = launch_step_into(L, cur, next, gcur, gnext, stream);
+                    if (rc) return rc;
+                    cur = next;
+                    gcur = gnext;
+                } else {
+                    rc = launch_step_interp(L, cur, R, gcur, gR, X0, gX0, L0, L1, L2, stream);
+                    if (rc) return rc;
+                }
             }
-            // quadratic in time through 0, (l-1)/alpha, l/alpha, evaluated at 1
-            const double t[3] = {0.0, (l - 1) / alpha, l / alpha};
-            void* R = sc.work_f[1];
-            float* gR = sc.work_g[1];
-            int rc = launch_time_interp(L, X0, prev, cur, gX0, gprev, gcur, t, 1.0, R, gR, stream);
-            if (rc) return rc;
+            int rc;
             rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], 1.0, L, R, gR, sc.ghost_cells,
                                  sc.n_ghost, stream);
             if (rc) return rc;

@@ -176,3 +176,96 @@ class Hierarchy:
                     wg = [tensors[sc.work_g[0]], tensors[sc.work_g[1]]]
                 self.work[i] = (wf, wg)
             lev._sync_struct()
+
+
+# ---------------------------------------------------------------------------
+# dynamic scale construction (section "Scale construction", dynamic scales)
+# ---------------------------------------------------------------------------
+def region_box(omega: np.ndarray, speed: np.ndarray, shape, thresholds, dilate: int, lo_limit,
+               hi_limit):
+    """Bounding box (inclusive level-0 cell bounds, x/y/z order) of the cells
+    kept by the two thresholds of the dynamic construction, |curl u| >
+    thresholds[0] and then |u| > thresholds[1], dilated by `dilate` cells
+    and clipped to [lo_limit, hi_limit]; None when no cell passes."""
+    nx, ny, nz = shape
+    w = ((np.asarray(omega) > thresholds[0]) & (np.asarray(speed) > thresholds[1])).reshape(nz, ny, nx)
+    if not w.any():
+        return None
+    zs, ys, xs = np.nonzero(w)
+    lo = [xs.min() - dilate, ys.min() - dilate, zs.min() - dilate]
+    hi = [xs.max() + dilate, ys.max() + dilate, zs.max() + dilate]
+    lo = [max(lo[a], lo_limit[a]) for a in range(3)]
+    hi = [min(hi[a], hi_limit[a]) for a in range(3)]
+    if any(h - l < 3 for l, h in zip(lo, hi)):
+        return None
+    return lo, hi
+
+
+def fine_scale(lo, hi, alpha: float, params0: Params, solid_fn=None, *, scalar: bool,
+               storage: int):
+    """A finer scale covering the level-0 box [lo, hi] (physical units of
+    level 0) at spacing 1/alpha, anchored to the global lattice of that
+    spacing.  Parameters: nu = alpha nu0, tau_s - 1/2 = alpha (tau_s0 - 1/2)
+    (invariant local Reynolds and Peclet numbers)."""
+    dx = 1.0 / alpha
+    i0 = [math.ceil(lo[a] * alpha - 1e-9) for a in range(3)]
+    i1 = [math.floor(hi[a] * alpha + 1e-9) for a in range(3)]
+    shape = tuple(i1[a] - i0[a] + 1 for a in range(3))
+    origin = tuple(i0[a] * dx for a in range(3))
+    inner = np.zeros(int(np.prod(shape)), np.uint8)
+    if solid_fn is not None:
+        z, y, x = np.meshgrid(np.arange(shape[2]), np.arange(shape[1]), np.arange(shape[0]),
+                              indexing="ij")
+        px = origin[0] + x.reshape(-1) * dx
+        py = origin[1] + y.reshape(-1) * dx
+        pz = origin[2] + z.reshape(-1) * dx
+        inner[solid_fn(px, py, pz)] = _capi.SOLID
+    kinds = shell_flags(*shape, inner)
+    p = Params(**{**params0.__dict__})
+    p.nu = params0.nu * alpha
+    p.tau_s = 0.5 + alpha * (params0.tau_s - 0.5)
+    lev = Level(*shape, p, storage=storage, scalar=scalar, periodic=0, flags=kinds,
+                origin=origin, dx=dx)
+    return lev, kinds
+
+
+def fill_from_parent(parent: Level, lev: Level, stream=None):
+    """Initialise every cell of a finer scale by mapping the parent's current
+    state (full prior-mapping of a newly created region)."""
+    cells = torch.arange(lev.n, dtype=torch.int32, device=lev.device)
+    parent._sync_struct()
+    lev._sync_struct()
+    g_ok = parent.g is not None and lev.g is not None
+    _capi.call("cslbm_exchange", C.byref(parent.c), parent.f.data_ptr(), None,
+               parent.g.data_ptr() if g_ok else None, None, 0.0, C.byref(lev.c), lev.f.data_ptr(),
+               lev.g.data_ptr() if g_ok else None, cells.data_ptr(), lev.n, _stream_handle(stream))
+
+
+def dynamic_hierarchy(lev0: Level, kinds0: np.ndarray, thresholds, alphas, *, margin: int = 3,
+                      dilate: int = 2, nest: int = 2, solid_fn=None, stream=None):
+    """Scales set by thresholds: scale k covers the bounding box of the cells
+    with |curl u| > thresholds[k-1][0] and |u| > thresholds[k-1][1]
+    (dilated), kept `margin` cells from the domain faces and `nest` cells
+    inside its parent; spacing 1/alphas[k-1].  Returns (Hierarchy, boxes);
+    scales whose region is empty are left out."""
+    om, sp = lev0.vorticity(stream)
+    omega, speed = om.cpu().numpy(), sp.cpu().numpy()
+    shape = (lev0.nx, lev0.ny, lev0.nz)
+    lo_lim = [margin] * 3
+    hi_lim = [shape[a] - 1 - margin for a in range(3)]
+    levels, kinds, boxes = [lev0], [np.asarray(kinds0, np.uint8)], []
+    for thr, alpha in zip(thresholds, alphas):
+        box = region_box(omega, speed, shape, thr, dilate, lo_lim, hi_lim)
+        if box is None:
+            break
+        lo, hi = box
+        lev, k = fine_scale(lo, hi, alpha, lev0.params, solid_fn, scalar=lev0.g is not None,
+                            storage=lev0.storage)
+        fill_from_parent(levels[-1], lev, stream)
+        levels.append(lev)
+        kinds.append(k)
+        boxes.append((lo, hi))
+        lo_lim = [lo[a] + nest for a in range(3)]
+        hi_lim = [hi[a] - nest for a in range(3)]
+    torch.cuda.synchronize()
+    return Hierarchy(levels, kinds), boxes

@@ -174,6 +174,15 @@ class Level:
                    _stream_handle(stream))
         return rho, u, s
 
+    def vorticity(self, stream=None):
+        """(|curl u|, |u|) of the stored state, dense [N] each."""
+        out = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        speed = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        self._sync_struct()
+        _capi.call("cslbm_vorticity", C.byref(self.c), _dev_ptr(out), _dev_ptr(speed),
+                   _stream_handle(stream))
+        return out, speed
+
     def conserved(self, stream=None) -> np.ndarray:
         out = (C.c_double * 5)()
         self._sync_struct()

@@ -268,3 +268,28 @@ def test_reduced_plume_three_scales_match_oracle():
     for lev, osc in zip(levs, oscs):
         assert rel_err(gpu_pop(lev), osc.f) <= 1e-5
         assert np.max(np.abs(gpu_g(lev) - osc.g)) <= 1e-5
+
+
+def test_vorticity_matches_central_differences():
+    """|curl u| (placement of dynamic scales) of an initialised state equals
+    central differences of the input field; one-sided at non-periodic faces."""
+    n = 20
+    rho, u = inputs.taylor_green_3d(n, 0.05)
+    for periodic, flags in ((7, None), (0, np.zeros(n ** 3, np.uint8))):
+        lev = Level(n, n, n, Params(nu=0.01), periodic=periodic, flags=flags)
+        lev.init_equilibrium(rho, u)
+        om_t, sp_t = lev.vorticity()
+        om = om_t.double().cpu().numpy()
+        np.testing.assert_allclose(sp_t.double().cpu().numpy(), np.linalg.norm(u, axis=0),
+                                   rtol=0, atol=1e-6)
+        U = u.reshape(3, n, n, n)        # [comp, z, y, x]
+
+        def d(a, axis):
+            if periodic:
+                return (np.roll(a, -1, axis) - np.roll(a, 1, axis)) / 2
+            return np.gradient(a, axis=axis, edge_order=1)
+        wx = d(U[2], 1) - d(U[1], 0)
+        wy = d(U[0], 0) - d(U[2], 2)
+        wz = d(U[1], 2) - d(U[0], 1)
+        ref = np.sqrt(wx ** 2 + wy ** 2 + wz ** 2).reshape(-1)
+        np.testing.assert_allclose(om, ref, rtol=0, atol=1e-6)

@@ -101,6 +101,10 @@ typedef struct cslbm_level {
     float* g;                 /* [7][plane] scalar state, or NULL */
     float* g_next;            /* [7][plane], or NULL (both or neither) */
     uint8_t* flags;           /* [nx*ny*nz] cell kinds, or NULL = all fluid */
+    uint32_t* links;          /* [nx*ny*nz] bounce-back masks written by
+                                 cslbm_prepare_flags (bit i: the pull source
+                                 x - c_i is solid or outside a non-periodic
+                                 face), or NULL (computed per step instead) */
     const float* force;       /* [3][plane] body force field theta, or NULL */
     double origin[3];         /* physical position of cell (0,0,0) */
     double dx;                /* physical spacing of this scale */
@@ -117,8 +121,9 @@ int64_t cslbm_plane_stride(int32_t nx, int32_t ny, int32_t nz);
 int64_t cslbm_level_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t storage,
                           int32_t with_scalar);
 
-/* Set bit CSLBM_NEAR_WALL of every cell whose pull stencil reaches a solid
- * cell or leaves the box through a non-periodic face; clear it elsewhere.
+/* Set bit CSLBM_NEAR_WALL of every fluid cell whose pull stencil reaches a
+ * solid cell or leaves the box through a non-periodic face, clear it
+ * elsewhere, and (when L->links is set) write each cell's bounce-back mask.
  * Must be called after the kinds in L->flags change and before stepping. */
 int cslbm_prepare_flags(const cslbm_level* L, hipStream_t stream);
 

@@ -50,6 +50,7 @@ class CslbmLevel(C.Structure):
         ("g", _vp),
         ("g_next", _vp),
         ("flags", _vp),
+        ("links", _vp),
         ("force", _vp),
         ("origin", C.c_double * 3),
         ("dx", C.c_double),

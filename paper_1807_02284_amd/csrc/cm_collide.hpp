@@ -173,8 +173,10 @@ struct CellMacro {
 // Central-moment collision of one cell, in place on shifted populations.
 // F is the body force (zero when absent): u = (j + F/2)/rho and the
 // order-one central moments receive +F (source (I - S/2) R with S_1..3 = 0).
+// active == false relaxes nothing (the transform pair is then an identity up
+// to rounding); kernels use it for lanes of non-fluid cells.
 __host__ __device__ __forceinline__ CellMacro cm_collide(float (&v)[27], const Rates& r, float Fx, float Fy,
-                                               float Fz)
+                                               float Fz, bool active = true)
 {
     float dr, jx, jy, jz;
     moments0(v, dr, jx, jy, jz);
@@ -205,8 +207,8 @@ __host__ __device__ __forceinline__ CellMacro cm_collide(float (&v)[27], const R
     if (r.adaptive) phi = r.a * fminf(G * r.inv_gmax, 1.0f) + r.b;
     float om[4];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) om[g] = 1.0f - 1.0f / (phi * r.nu3[g] + 0.5f);   // 1 - S_g
-    const float om_s = 1.0f - r.S;
+    for (int g = 0; g < 4; ++g) om[g] = active ? 1.0f - 1.0f / (phi * r.nu3[g] + 0.5f) : 1.0f;
+    const float om_s = active ? 1.0f - r.S : 1.0f;
 
     // relax: dk* = D + (1 - S)(dk - D); conserved moments unchanged, +F
     v[kslot(1, 0, 0)] += Fx;

@@ -53,6 +53,7 @@ struct StepArgs {
     const float* g;
     float* go;
     const uint8_t* flags;
+    const uint32_t* links;
     const float* force;
     int nx, ny, nz, periodic;
     int64_t plane;
@@ -103,6 +104,24 @@ __device__ __forceinline__ void store_gout(const StepArgs& a, int64_t e, float v
     __builtin_nontemporal_store(v, a.go + e);
 }
 
+// Bounce-back mask of a near-wall cell computed from the neighbours' kinds
+// (used only when the level has no precomputed links array): bit i is set
+// when the pull source x - c_i is solid or outside a non-periodic face.
+__device__ __forceinline__ uint32_t bounce_links(const StepArgs& a, int x, int y, int z,
+                                                 const int (&sx)[3], const int (&sy)[3],
+                                                 const int (&sz)[3])
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int src = sx[kCx[i] + 1] + sy[kCy[i] + 1] + sz[kCz[i] + 1];
+        if (leaves_box(x, y, z, kCx[i], kCy[i], kCz[i], a.nx, a.ny, a.nz, a.periodic) ||
+            (a.flags[src] & kKindMask) == kSolid)
+            m |= 1u << i;
+    }
+    return m;
+}
+
 // ---------------------------------------------------------------------------
 // K: fused pull-stream + collide
 // ---------------------------------------------------------------------------
@@ -120,13 +139,9 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
     const T* __restrict__ f = static_cast<const T*>(a.f);
     T* __restrict__ fo = static_cast<T*>(a.fo);
 
-    uint8_t flag = 0;
-    if (kFlags) flag = a.flags[cell];
-    const int kind = flag & kKindMask;
-
     // source coordinates of the pull, indexed by (c + 1): c = -1 pulls from
-    // x + 1, c = +1 from x - 1 (periodic wrap; non-periodic faces are caught
-    // by the near-wall test)
+    // x + 1, c = +1 from x - 1 (periodic wrap; links that leave the box
+    // through a non-periodic face are in the cell's bounce-back mask)
     const int xm = (x == 0) ? nx - 1 : x - 1;
     const int xp = (x == nx - 1) ? 0 : x + 1;
     const int ym = (y == 0) ? ny - 1 : y - 1;
@@ -137,53 +152,45 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
     const int sy[3] = {yp * nx, y * nx, ym * nx};
     const int sz[3] = {zp * nxy, z * nxy, zm * nxy};
 
-    if (kFlags && kind != kFluid) {
-        if (kind == kSolid) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) store_out<T, kTime>(a, fo, i * P + cell, 0.0f);
-            if (kScalar)
-#pragma unroll
-                for (int i = 0; i < QS; ++i) store_gout<kTime>(a, i * P + cell, 0.0f);
-        } else if (kind == kInlet) {
-            float v[27];
-            shifted_equilibrium(v, 1.0f, a.u_in[0], a.u_in[1], a.u_in[2]);
-#pragma unroll
-            for (int i = 0; i < Q; ++i) store_out<T, kTime>(a, fo, i * P + cell, v[tensor_slot(i)]);
-            if (kScalar)
-#pragma unroll
-                for (int i = 0; i < QS; ++i)
-                    store_gout<kTime>(a, i * P + cell,
-                                      scalar_eq(i, a.s_in, a.u_in[0], a.u_in[1], a.u_in[2]));
-        } else {
-            // ghost: keep; outflow: copy the incoming state of the x-1 neighbour
-            int from = cell;
-            if (kind == kOutflow && (x > 0 || (a.periodic & 1))) from = xm + nx * y + nxy * z;
-#pragma unroll
-            for (int i = 0; i < Q; ++i)
-                store_out<T, kTime>(a, fo, i * P + cell, Io<T>::ld(f + i * P + from));
-            if (kScalar)
-#pragma unroll
-                for (int i = 0; i < QS; ++i) store_gout<kTime>(a, i * P + cell, a.g[i * P + from]);
-        }
-        return;
+    // Cell kinds without divergent code paths: every lane issues the same
+    // 27 (+7) loads and stores with its own addresses.  Fluid cells pull
+    // (bounce-back links from the per-cell mask), ghost and outflow cells
+    // load their copy source, solid and inlet cells read their own cell and
+    // discard it; the
+    // collision runs with zero relaxation on non-fluid lanes (an identity
+    // up to rounding), and inlet lanes start from the inlet equilibrium.
+    int kind = kFluid;
+    uint32_t links = 0;
+    int from = cell;
+    if (kFlags) {
+        const uint8_t flag = a.flags[cell];
+        kind = flag & kKindMask;
+        if (flag & kNearWall) links = a.links ? a.links[cell] : bounce_links(a, x, y, z, sx, sy, sz);
+        if (kind == kOutflow && (x > 0 || (a.periodic & 1))) from = xm + nx * y + nxy * z;
     }
+    const bool fluid = kind == kFluid;
+    const bool copies = kind == kGhost || kind == kOutflow;
+    const bool loads = fluid || copies;
 
-    const bool near = kFlags && (flag & kNearWall);
     float v[27];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         int src = sx[kCx[i] + 1] + sy[kCy[i] + 1] + sz[kCz[i] + 1];
         int pl = i;
-        if (kFlags && near) {
-            const bool bb = leaves_box(x, y, z, kCx[i], kCy[i], kCz[i], nx, ny, nz, a.periodic) ||
-                            ((a.flags[src] & kKindMask) == kSolid);
-            if (bb) {   // halfway bounce-back: the cell's own opposite population
+        if (kFlags) {
+            if (links & (1u << i)) {   // halfway bounce-back: own opposite population
                 src = cell;
                 pl = opposite(i);
             }
+            if (!fluid) {   // copy source; solid and inlet lanes read their own cell
+                src = from;
+                pl = i;
+            }
         }
-        v[tensor_slot(i)] = Io<T>::ld(f + pl * P + src);
+        const float hv = Io<T>::ld(f + pl * P + src);   // unconditional: no branch
+        v[tensor_slot(i)] = (!kFlags || loads) ? hv : 0.0f;
     }
+    if (kFlags && kind == kInlet) shifted_equilibrium(v, 1.0f, a.u_in[0], a.u_in[1], a.u_in[2]);
 
     float gv[QS];
     float s = 0.0f;
@@ -192,37 +199,46 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
         for (int i = 0; i < QS; ++i) {
             int src = sx[kSx[i] + 1] + sy[kSy[i] + 1] + sz[kSz[i] + 1];
             int pl = i;
-            if (kFlags && near) {
-                const bool bb = leaves_box(x, y, z, kSx[i], kSy[i], kSz[i], nx, ny, nz, a.periodic) ||
-                                ((a.flags[src] & kKindMask) == kSolid);
-                if (bb) {
+            if (kFlags) {
+                if (links & (1u << i)) {   // D3Q7 direction i is D3Q27 velocity i
                     src = cell;
                     pl = scalar_opposite(i);
                 }
+                if (!fluid) {
+                    src = from;
+                    pl = i;
+                }
             }
-            gv[i] = a.g[pl * P + src];
+            const float gl = a.g[pl * P + src];
+            gv[i] = (!kFlags || loads) ? gl : 0.0f;
         }
         s = (gv[0] + (gv[1] + gv[2])) + ((gv[3] + gv[4]) + (gv[5] + gv[6]));
     }
 
     float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f;
-    if (kForce) {
+    if (kForce && fluid) {
         Fx = a.force[cell];
         Fy = a.force[P + cell];
         Fz = a.force[2 * P + cell];
     }
-    if (kScalar) Fz += a.beta * (s - a.s_ref);
+    if (kScalar && fluid) Fz += a.beta * (s - a.s_ref);
 
-    const CellMacro mc = cm_collide(v, a.r, Fx, Fy, Fz);
+    const CellMacro mc = cm_collide(v, a.r, Fx, Fy, Fz, fluid);
 
 #pragma unroll
     for (int i = 0; i < Q; ++i) store_out<T, kTime>(a, fo, i * P + cell, v[tensor_slot(i)]);
 
     if (kScalar) {
+        const float ux = kind == kInlet ? a.u_in[0] : mc.ux;
+        const float uy = kind == kInlet ? a.u_in[1] : mc.uy;
+        const float uz = kind == kInlet ? a.u_in[2] : mc.uz;
+        const float sc = kind == kInlet ? a.s_in : s;
+        // fluid: BGK; inlet: equilibrium; ghost/outflow: copy; solid: 0
+        const float relax = kind == kFluid ? a.inv_tau_s : (kind == kInlet ? 1.0f : 0.0f);
 #pragma unroll
         for (int i = 0; i < QS; ++i) {
-            const float ge = scalar_eq(i, s, mc.ux, mc.uy, mc.uz);
-            store_gout<kTime>(a, i * P + cell, gv[i] - (gv[i] - ge) * a.inv_tau_s);
+            const float ge = scalar_eq(i, sc, ux, uy, uz);
+            store_gout<kTime>(a, i * P + cell, gv[i] - (gv[i] - ge) * relax);
         }
     }
 }
@@ -237,7 +253,8 @@ __device__ __forceinline__ void cell_coords(int64_t c, int nx, int ny, int& x, i
     z = (int)(c / ((int64_t)nx * ny));
 }
 
-__global__ void k_prepare_flags(uint8_t* flags, int nx, int ny, int nz, int periodic)
+__global__ void k_prepare_flags(uint8_t* flags, uint32_t* links, int nx, int ny, int nz,
+                                int periodic)
 {
     const int64_t N = (int64_t)nx * ny * nz;
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -245,20 +262,22 @@ __global__ void k_prepare_flags(uint8_t* flags, int nx, int ny, int nz, int peri
     int x, y, z;
     cell_coords(c, nx, ny, x, y, z);
     const uint8_t kind = flags[c] & kKindMask;
-    bool near = false;
+    uint32_t m = 0;
     if (kind == kFluid) {
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             if (leaves_box(x, y, z, kCx[i], kCy[i], kCz[i], nx, ny, nz, periodic)) {
-                near = true;
+                m |= 1u << i;
                 continue;
             }
             const int xs = (x - kCx[i] + nx) % nx, ys = (y - kCy[i] + ny) % ny,
                       zs = (z - kCz[i] + nz) % nz;
-            if ((flags[xs + (int64_t)nx * (ys + (int64_t)ny * zs)] & kKindMask) == kSolid) near = true;
+            if ((flags[xs + (int64_t)nx * (ys + (int64_t)ny * zs)] & kKindMask) == kSolid)
+                m |= 1u << i;
         }
     }
-    flags[c] = kind | (near ? kNearWall : 0);
+    flags[c] = kind | (m ? kNearWall : 0);
+    if (links) links[c] = m;
 }
 
 template <typename T>
@@ -621,6 +640,7 @@ int launch_step_interp(const cslbm_level* L, const void* fin, void* fout, const 
     a.g = gin;
     a.go = gout;
     a.flags = L->flags;
+    a.links = L->links;
     a.force = L->force;
     a.nx = L->nx;
     a.ny = L->ny;
@@ -678,7 +698,7 @@ int cslbm_prepare_flags(const cslbm_level* L, hipStream_t stream)
     if (!L->flags) return fail(CSLBM_ERR_ARG, "flags is NULL");
     const int64_t N = cells_of(L);
     hipLaunchKernelGGL(k_prepare_flags, dim3(blocks_for(N, 256)), dim3(256), 0, stream, L->flags,
-                       L->nx, L->ny, L->nz, L->periodic);
+                       L->links, L->nx, L->ny, L->nz, L->periodic);
     return check_launch("k_prepare_flags");
 }
 

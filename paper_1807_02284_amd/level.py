@@ -78,12 +78,14 @@ class Level:
             self.g = torch.zeros(7 * self.plane, dtype=torch.float32, device=self.device)
             self.g_next = torch.zeros_like(self.g)
         self.flags = None
+        self.links = None
         if flags is not None:
             fl = torch.as_tensor(np.asarray(flags, dtype=np.uint8) if not torch.is_tensor(flags)
                                  else flags).to(self.device, torch.uint8).reshape(-1)
             assert fl.numel() == self.n
             self.flags = torch.zeros(self.plane, dtype=torch.uint8, device=self.device)
             self.flags[: self.n] = fl
+            self.links = torch.zeros(self.n, dtype=torch.int32, device=self.device)
         self.force = None
         if force is not None:
             ft = torch.as_tensor(np.asarray(force) if not torch.is_tensor(force) else force)
@@ -109,6 +111,7 @@ class Level:
         self.c.g = _dev_ptr(self.g)
         self.c.g_next = _dev_ptr(self.g_next)
         self.c.flags = _dev_ptr(self.flags)
+        self.c.links = _dev_ptr(self.links)
         self.c.force = _dev_ptr(self.force)
         self.c.p = self.params.to_c()
 
@@ -120,6 +123,7 @@ class Level:
         fl = torch.as_tensor(np.asarray(flags, dtype=np.uint8)).to(self.device).reshape(-1)
         if self.flags is None:
             self.flags = torch.zeros(self.plane, dtype=torch.uint8, device=self.device)
+            self.links = torch.zeros(self.n, dtype=torch.int32, device=self.device)
         self.flags[: self.n] = fl
         self._sync_struct()
         _capi.call("cslbm_prepare_flags", C.byref(self.c), _stream_handle())

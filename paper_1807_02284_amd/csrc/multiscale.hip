@@ -54,17 +54,12 @@ __device__ __forceinline__ int wrap_or_clamp(int i, int n, bool periodic)
     return i < 0 ? 0 : (i >= n ? n - 1 : i);   // lists are validated on the host
 }
 
-template <typename Ts, typename Td>
-__global__ void __launch_bounds__(256) k_exchange(const ExchArgs a)
+// target point of list entry k in source lattice coordinates: base corner
+// and trilinear fractions (geometry in FP64 so coincident nodes resolve)
+__device__ __forceinline__ void target_stencil(const ExchArgs& a, int c, int (&base)[3], float (&t)[3])
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.n_cells) return;
-    const int c = a.cells[k];
     const int x = c % a.dnx, y = (c / a.dnx) % a.dny, z = c / (a.dnx * a.dny);
-    // geometry in FP64 so that coincident nodes resolve exactly
     const double p[3] = {a.dorigin[0] + x * a.ddx, a.dorigin[1] + y * a.ddx, a.dorigin[2] + z * a.ddx};
-    int base[3];
-    float t[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const double q = (p[d] - a.sorigin[d]) / a.sdx;
@@ -72,46 +67,20 @@ __global__ void __launch_bounds__(256) k_exchange(const ExchArgs a)
         base[d] = (int)b;
         t[d] = (float)(q - b);
     }
-    const int n[3] = {a.snx, a.sny, a.snz};
-    int ix[2], iy[2], iz[2];
-#pragma unroll
-    for (int o = 0; o < 2; ++o) {
-        ix[o] = wrap_or_clamp(base[0] + o, n[0], a.speriodic & 1);
-        iy[o] = wrap_or_clamp(base[1] + o, n[1], a.speriodic & 2);
-        iz[o] = wrap_or_clamp(base[2] + o, n[2], a.speriodic & 4);
-    }
-    const Ts* fA = static_cast<const Ts*>(a.fA);
-    const Ts* fB = static_cast<const Ts*>(a.fB);
-    const float w = a.w;
-    float v[27];
-#pragma unroll
-    for (int q = 0; q < 27; ++q) v[q] = 0.0f;
-    float gi[QS] = {0, 0, 0, 0, 0, 0, 0};
-    const bool scalar = a.gA != nullptr && a.go != nullptr;
-#pragma unroll
-    for (int corner = 0; corner < 8; ++corner) {
-        const int ox = corner & 1, oy = (corner >> 1) & 1, oz = (corner >> 2) & 1;
-        const float wt = (ox ? t[0] : 1.0f - t[0]) * (oy ? t[1] : 1.0f - t[1]) *
-                         (oz ? t[2] : 1.0f - t[2]);
-        if (wt == 0.0f) continue;
-        const int64_t sc = ix[ox] + (int64_t)a.snx * (iy[oy] + (int64_t)a.sny * iz[oz]);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const float hA = Io<Ts>::ld(fA + i * a.splane + sc);
-            const float hB = (w != 0.0f) ? Io<Ts>::ld(fB + i * a.splane + sc) : hA;
-            v[tensor_slot(i)] += wt * ((1.0f - w) * hA + w * hB);
-        }
-        if (scalar) {
-#pragma unroll
-            for (int i = 0; i < QS; ++i) {
-                const float gA = a.gA[i * a.splane + sc];
-                const float gB = (w != 0.0f) ? a.gB[i * a.splane + sc] : gA;
-                gi[i] += wt * ((1.0f - w) * gA + w * gB);
-            }
-        }
-    }
+}
 
-    // central-moment frame of the interpolated post-collision state
+__device__ __forceinline__ float corner_weight(const float (&t)[3], int corner)
+{
+    const int ox = corner & 1, oy = (corner >> 1) & 1, oz = (corner >> 2) & 1;
+    return (ox ? t[0] : 1.0f - t[0]) * (oy ? t[1] : 1.0f - t[1]) * (oz ? t[2] : 1.0f - t[2]);
+}
+
+// central-moment mapping of an interpolated post-collision state (in place,
+// tensor order) and the stores of population and scalar outputs
+template <typename Td>
+__device__ __forceinline__ void map_and_store(const ExchArgs& a, int c, float (&v)[27],
+                                              const float (&gi)[QS], bool scalar)
+{
     float dr, jx, jy, jz;
     moments0(v, dr, jx, jy, jz);
     const float inv_rho = 1.0f / (1.0f + dr);
@@ -143,6 +112,62 @@ __global__ void __launch_bounds__(256) k_exchange(const ExchArgs a)
             a.go[i * a.dplane + c] = ge + a.kappa_s * (gi[i] - ge);
         }
     }
+}
+
+// direct gather: each target reads its 8 source corners from global memory
+template <typename Ts, typename Td>
+__device__ __forceinline__ void exchange_direct(const ExchArgs& a, int k)
+{
+    const int c = a.cells[k];
+    int base[3];
+    float t[3];
+    target_stencil(a, c, base, t);
+    const int n[3] = {a.snx, a.sny, a.snz};
+    int ix[2], iy[2], iz[2];
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+        ix[o] = wrap_or_clamp(base[0] + o, n[0], a.speriodic & 1);
+        iy[o] = wrap_or_clamp(base[1] + o, n[1], a.speriodic & 2);
+        iz[o] = wrap_or_clamp(base[2] + o, n[2], a.speriodic & 4);
+    }
+    const Ts* fA = static_cast<const Ts*>(a.fA);
+    const Ts* fB = static_cast<const Ts*>(a.fB);
+    const float w = a.w;
+    float v[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) v[q] = 0.0f;
+    float gi[QS] = {0, 0, 0, 0, 0, 0, 0};
+    const bool scalar = a.gA != nullptr && a.go != nullptr;
+#pragma unroll
+    for (int corner = 0; corner < 8; ++corner) {
+        const int ox = corner & 1, oy = (corner >> 1) & 1, oz = (corner >> 2) & 1;
+        const float wt = corner_weight(t, corner);
+        if (wt == 0.0f) continue;
+        const int64_t sc = ix[ox] + (int64_t)a.snx * (iy[oy] + (int64_t)a.sny * iz[oz]);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const float hA = Io<Ts>::ld(fA + i * a.splane + sc);
+            const float hB = (w != 0.0f) ? Io<Ts>::ld(fB + i * a.splane + sc) : hA;
+            v[tensor_slot(i)] += wt * ((1.0f - w) * hA + w * hB);
+        }
+        if (scalar) {
+#pragma unroll
+            for (int i = 0; i < QS; ++i) {
+                const float gA = a.gA[i * a.splane + sc];
+                const float gB = (w != 0.0f) ? a.gB[i * a.splane + sc] : gA;
+                gi[i] += wt * ((1.0f - w) * gA + w * gB);
+            }
+        }
+    }
+    map_and_store<Td>(a, c, v, gi, scalar);
+}
+
+template <typename Ts, typename Td>
+__global__ void __launch_bounds__(256) k_exchange(const ExchArgs a)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n_cells) return;
+    exchange_direct<Ts, Td>(a, k);
 }
 
 // Lagrange quadratic in time, element by element over all planes

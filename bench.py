@@ -28,16 +28,18 @@ METRIC = "D3Q27 MLUPS + % HBM roofline; FP16-store and adjoint vs FP32 plain ste
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = {"f32": 216, "f16s": 108}   # 27 reads + 27 writes per update
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_traffic.json")
+STEP_KERNEL_SOURCES = ("cslbm.hip", "cm_collide.hpp", "internal.hpp", "lattice.hpp")
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sources that make up the collide-stream kernel (the
+    kernel the counter file describes); other kernels do not change it."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1807_02284_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as fh:
-                h.update(name.encode())
-                h.update(fh.read())
+    for name in STEP_KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 
 #include "../../include/cslbm.h"
 #include "cm_collide.hpp"
@@ -104,6 +105,16 @@ __device__ __forceinline__ void store_gout(const StepArgs& a, int64_t e, float v
     __builtin_nontemporal_store(v, a.go + e);
 }
 
+// Element `idx` of one plane addressed as uniform base + 32-bit byte offset.
+// Used for binary16 planes only: cells are validated below 2^31, so the byte
+// offset idx * 2 always fits in 32 bits.
+template <typename T>
+__device__ __forceinline__ T* plane_at(T* base, int idx)
+{
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return reinterpret_cast<T*>(reinterpret_cast<B*>(base) + (uint32_t)idx * (uint32_t)sizeof(T));
+}
+
 // Bounce-back mask of a near-wall cell computed from the neighbours' kinds
 // (used only when the level has no precomputed links array): bit i is set
 // when the pull source x - c_i is solid or outside a non-periodic face.
@@ -138,6 +149,7 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
     const int64_t P = a.plane;
     const T* __restrict__ f = static_cast<const T*>(a.f);
     T* __restrict__ fo = static_cast<T*>(a.fo);
+    constexpr bool kOff32 = sizeof(T) == 2;
 
     // source coordinates of the pull, indexed by (c + 1): c = -1 pulls from
     // x + 1, c = +1 from x - 1 (periodic wrap; links that leave the box
@@ -187,7 +199,11 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
                 pl = i;
             }
         }
-        const float hv = Io<T>::ld(f + pl * P + src);   // unconditional: no branch
+        // unconditional: no branch.  Without flags the plane base is uniform
+        // and the binary16 kernel addresses it with a 32-bit lane offset
+        // (measured faster there; the FP32 kernel is faster as written).
+        const float hv = (kOff32 && !kFlags) ? Io<T>::ld(plane_at(f + i * P, src))
+                                             : Io<T>::ld(f + pl * P + src);
         v[tensor_slot(i)] = (!kFlags || loads) ? hv : 0.0f;
     }
     if (kFlags && kind == kInlet) shifted_equilibrium(v, 1.0f, a.u_in[0], a.u_in[1], a.u_in[2]);
@@ -226,7 +242,12 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
     const CellMacro mc = cm_collide(v, a.r, Fx, Fy, Fz, fluid);
 
 #pragma unroll
-    for (int i = 0; i < Q; ++i) store_out<T, kTime>(a, fo, i * P + cell, v[tensor_slot(i)]);
+    for (int i = 0; i < Q; ++i) {
+        if (kOff32 && !kTime)
+            Io<T>::st(plane_at(fo + i * P, cell), v[tensor_slot(i)]);
+        else
+            store_out<T, kTime>(a, fo, i * P + cell, v[tensor_slot(i)]);
+    }
 
     if (kScalar) {
         const float ux = kind == kInlet ? a.u_in[0] : mc.ux;

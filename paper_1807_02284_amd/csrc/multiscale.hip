@@ -114,10 +114,17 @@ __device__ __forceinline__ void map_and_store(const ExchArgs& a, int c, float (&
     }
 }
 
-// direct gather: each target reads its 8 source corners from global memory
-template <typename Ts, typename Td>
-__device__ __forceinline__ void exchange_direct(const ExchArgs& a, int k)
+// Direct gather: each target reads its 8 source corners from global memory.
+// kBlend reads both time levels and blends them with w; otherwise the host
+// passes the one level that carries all the weight (w = 0 or w = 1).  Both
+// switches are compile-time so that the 27 (or 54) loads of a corner carry no
+// branch between them and are issued back to back.  Corners of zero weight
+// are still read: their indices are wrapped or clamped into the box.
+template <typename Ts, typename Td, bool kBlend, bool kScalar>
+__global__ void __launch_bounds__(256) k_exchange(const ExchArgs a)
 {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n_cells) return;
     const int c = a.cells[k];
     int base[3];
     float t[3];
@@ -137,37 +144,35 @@ __device__ __forceinline__ void exchange_direct(const ExchArgs& a, int k)
 #pragma unroll
     for (int q = 0; q < 27; ++q) v[q] = 0.0f;
     float gi[QS] = {0, 0, 0, 0, 0, 0, 0};
-    const bool scalar = a.gA != nullptr && a.go != nullptr;
 #pragma unroll
     for (int corner = 0; corner < 8; ++corner) {
         const int ox = corner & 1, oy = (corner >> 1) & 1, oz = (corner >> 2) & 1;
         const float wt = corner_weight(t, corner);
-        if (wt == 0.0f) continue;
         const int64_t sc = ix[ox] + (int64_t)a.snx * (iy[oy] + (int64_t)a.sny * iz[oz]);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const float hA = Io<Ts>::ld(fA + i * a.splane + sc);
-            const float hB = (w != 0.0f) ? Io<Ts>::ld(fB + i * a.splane + sc) : hA;
-            v[tensor_slot(i)] += wt * ((1.0f - w) * hA + w * hB);
+            if (kBlend) {
+                const float hB = Io<Ts>::ld(fB + i * a.splane + sc);
+                v[tensor_slot(i)] += wt * ((1.0f - w) * hA + w * hB);
+            } else {
+                v[tensor_slot(i)] += wt * hA;
+            }
         }
-        if (scalar) {
+        if (kScalar) {
 #pragma unroll
             for (int i = 0; i < QS; ++i) {
                 const float gA = a.gA[i * a.splane + sc];
-                const float gB = (w != 0.0f) ? a.gB[i * a.splane + sc] : gA;
-                gi[i] += wt * ((1.0f - w) * gA + w * gB);
+                if (kBlend) {
+                    const float gB = a.gB[i * a.splane + sc];
+                    gi[i] += wt * ((1.0f - w) * gA + w * gB);
+                } else {
+                    gi[i] += wt * gA;
+                }
             }
         }
     }
-    map_and_store<Td>(a, c, v, gi, scalar);
-}
-
-template <typename Ts, typename Td>
-__global__ void __launch_bounds__(256) k_exchange(const ExchArgs a)
-{
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.n_cells) return;
-    exchange_direct<Ts, Td>(a, k);
+    map_and_store<Td>(a, c, v, gi, kScalar);
 }
 
 // Lagrange quadratic in time, element by element over all planes
@@ -196,6 +201,20 @@ __global__ void __launch_bounds__(256) k_time_interp(const T* s0, const T* s1, c
 // host side
 // ---------------------------------------------------------------------------
 static double shear_rate(const cslbm_level* L) { return 1.0 / (3.0 * L->p.nu + 0.5); }
+
+template <typename Ts, typename Td>
+static void launch_exchange_kernel(const ExchArgs& a, bool blend, bool scalar, dim3 grid,
+                                   dim3 block, hipStream_t st)
+{
+    if (blend && scalar)
+        hipLaunchKernelGGL((k_exchange<Ts, Td, true, true>), grid, block, 0, st, a);
+    else if (blend)
+        hipLaunchKernelGGL((k_exchange<Ts, Td, true, false>), grid, block, 0, st, a);
+    else if (scalar)
+        hipLaunchKernelGGL((k_exchange<Ts, Td, false, true>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((k_exchange<Ts, Td, false, false>), grid, block, 0, st, a);
+}
 
 static int launch_exchange(const cslbm_level* src, const void* fA, const void* fB, const float* gA,
                            const float* gB, double w, const cslbm_level* dst, void* f_out,
@@ -229,16 +248,22 @@ static int launch_exchange(const cslbm_level* src, const void* fA, const void* f
     const double Ss = shear_rate(src), Sd = shear_rate(dst);
     a.kappa = (float)((1.0 - Sd) / (1.0 - Ss) * Ss / (alpha * Sd));
     a.kappa_s = scalar ? (float)((dst->p.tau_s - 1.0) / (alpha * (src->p.tau_s - 1.0))) : 0.0f;
+    // all the weight on one time level: read only that level
+    const bool blend = w > 0.0 && w < 1.0;
+    if (!blend && w >= 1.0) {
+        a.fA = a.fB;
+        a.gA = a.gB;
+    }
     const dim3 grid((n_cells + 255) / 256), block(256);
     const bool s32 = src->storage == CSLBM_F32, d32 = dst->storage == CSLBM_F32;
     if (s32 && d32)
-        hipLaunchKernelGGL((k_exchange<float, float>), grid, block, 0, stream, a);
+        launch_exchange_kernel<float, float>(a, blend, scalar, grid, block, stream);
     else if (s32)
-        hipLaunchKernelGGL((k_exchange<float, _Float16>), grid, block, 0, stream, a);
+        launch_exchange_kernel<float, _Float16>(a, blend, scalar, grid, block, stream);
     else if (d32)
-        hipLaunchKernelGGL((k_exchange<_Float16, float>), grid, block, 0, stream, a);
+        launch_exchange_kernel<_Float16, float>(a, blend, scalar, grid, block, stream);
     else
-        hipLaunchKernelGGL((k_exchange<_Float16, _Float16>), grid, block, 0, stream, a);
+        launch_exchange_kernel<_Float16, _Float16>(a, blend, scalar, grid, block, stream);
     return check_launch("k_exchange");
 }
 

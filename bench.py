@@ -255,7 +255,11 @@ def run_plume(nx: int, ny: int, nz: int, spinup: int, n_ref: int):
     H, boxes = hierarchy.dynamic_hierarchy(lev0, flags, ((2e-3, 0.01), (8e-3, 0.02)), (1.5, 2.0),
                                            solid_fn=sphere)
     alphas = [1.0] + [1.0 / lv.c.dx for lv in H.levels[1:]]
-    subs = [1] + [int(np.floor(a + 1e-12)) + 1 for a in alphas[1:]]
+    # sub-steps per reference step: l = floor(alpha) + 1 (Algorithm 1); at
+    # integer alpha the last one has weight 0 in the time interpolation and
+    # the driver does not compute it, so it is not counted either
+    literal = [1] + [int(np.floor(a + 1e-12)) + 1 for a in alphas[1:]]
+    subs = [1] + [k - 1 if (k - 1) / a == 1.0 else k for k, a in zip(literal[1:], alphas[1:])]
     cells = [lv.n for lv in H.levels]
     lups = sum(c * k for c, k in zip(cells, subs))
     H.step(2)
@@ -273,6 +277,7 @@ def run_plume(nx: int, ny: int, nz: int, spinup: int, n_ref: int):
         "spacing_ratios": alphas,
         "cells_per_scale": cells,
         "substeps_per_scale": subs,
+        "substeps_per_scale_algorithm": literal,
         "boxes_level0_units": [[list(map(int, lo)), list(map(int, hi))] for lo, hi in boxes],
         "coverage_of_reference_volume": [
             float(np.prod([hi[a] - lo[a] + 1 for a in range(3)]) / n0) for lo, hi in boxes],

@@ -114,6 +114,18 @@ __device__ __forceinline__ void map_and_store(const ExchArgs& a, int c, float (&
     }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Give every XCD one contiguous run of the grid (a bijection of block
+// indices) so that neighbouring targets, which share source corners, meet in
+// the same L2 instead of being fetched once per XCD.
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    constexpr int kXcds = 8;
+    const int per = nb / kXcds, rem = nb % kXcds;
+    const int x = b % kXcds, i = b / kXcds;
+    return x * per + (x < rem ? x : rem) + i;
+}
+
 // Direct gather: each target reads its 8 source corners from global memory.
 // kBlend reads both time levels and blends them with w; otherwise the host
 // passes the one level that carries all the weight (w = 0 or w = 1).  Both
@@ -123,7 +135,7 @@ __device__ __forceinline__ void map_and_store(const ExchArgs& a, int c, float (&
 template <typename Ts, typename Td, bool kBlend, bool kScalar>
 __global__ void __launch_bounds__(256) k_exchange(const ExchArgs a)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (k >= a.n_cells) return;
     const int c = a.cells[k];
     int base[3];
@@ -420,16 +432,29 @@ int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t s
             const double L0 = (1.0 - t[1]) * (1.0 - t[2]) / ((t[0] - t[1]) * (t[0] - t[2]));
             const double L1 = (1.0 - t[0]) * (1.0 - t[2]) / ((t[1] - t[0]) * (t[1] - t[2]));
             const double L2 = (1.0 - t[0]) * (1.0 - t[1]) / ((t[2] - t[0]) * (t[2] - t[1]));
+            // At integer alpha the middle node is t = 1 itself: the quadratic
+            // has weights (0, 1, 0) there and the last sub-step does not enter
+            // the result (in floating point too: 0 * a + 1 * b + 0 * c == b).
+            // It is then not computed: the state after sub-step l - 1 is the
+            // interpolated state, and its ghosts are mapped at weight 1 below
+            // just as the skipped sub-step's prior-mapping would have done.
+            const bool node = L2 == 0.0 && L0 == 0.0 && L1 == 1.0;
+            const int last = node ? l - 1 : l;
             void* R = sc.work_f[1];
             float* gR = sc.work_g[1];
-            for (int k = 1; k <= l; ++k) {
+            for (int k = 1; k <= last; ++k) {
                 // prior-mapping of the boundary shell at the sub-step's start time
                 int rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], (k - 1) / alpha, L, cur, gcur,
                                          sc.ghost_cells, sc.n_ghost, stream);
                 if (rc) return rc;
                 if (k < l) {
-                    void* next = bufs[(k - 1) & 1];
-                    float* gnext = gbufs[(k - 1) & 1];
+                    const int slot = (k - 1) & 1;
+                    void* next = bufs[slot];
+                    float* gnext = gbufs[slot];
+                    if (node && k == last) {   // the result goes straight to R
+                        next = R;
+                        gnext = gR;
+                    }
                     rc = launch_step_into(L, cur, next, gcur, gnext, stream);
                     if (rc) return rc;
                     cur = next;

@@ -103,6 +103,23 @@ def check_prior_stencils(parent_kinds, parent_shape, parent_origin, parent_dx, p
             raise ValueError("a ghost cell's prior-mapping stencil touches a non-fluid parent cell")
 
 
+def drop_overwritten_posts(post: dict, n: int) -> dict:
+    """Post-mapping lists {(fine i, coarse j): cells of j} with every cell
+    removed that a later (finer) scale also post-maps into j.  Scales
+    post-map in index order and nothing reads a coarser scale j between two
+    post-mappings into it (prior-mapping reads the parent, which is finer
+    than j), so such a cell keeps only the later value: leaving it out of
+    the earlier list gives the same final state without the duplicate work."""
+    out = {}
+    for j in range(n):
+        later = np.zeros(0, np.int32)
+        for i in range(n - 1, j, -1):
+            cells = np.asarray(post[(i, j)], np.int32)
+            out[(i, j)] = np.setdiff1d(cells, later).astype(np.int32)
+            later = np.union1d(later, cells).astype(np.int32)
+    return out
+
+
 class Hierarchy:
     """Scales 0..n-1 (0 = reference, covering the domain); parents[i] is the
     nearest coarser scale of scale i (default i - 1)."""
@@ -141,13 +158,16 @@ class Hierarchy:
                                        cj.c.dx, self.kinds[i], (lev.nx, lev.ny, lev.nz),
                                        tuple(lev.c.origin), lev.c.dx)
                     self.post[(i, j)] = cells
-                    t = torch.as_tensor(cells, device=dev)
-                    self.lists.append(t)
-                    sc.n_post[j] = cells.size
-                    sc.post_cells[j] = t.data_ptr() if cells.size else None
             self.work.append((work_f, work_g))
             sc.work_f = (C.c_void_p * 2)(*[None if w is None else w.data_ptr() for w in work_f])
             sc.work_g = (C.c_void_p * 2)(*[None if w is None else w.data_ptr() for w in work_g])
+        self.post_full = dict(self.post)
+        self.post = drop_overwritten_posts(self.post_full, n)
+        for (i, j), cells in self.post.items():
+            t = torch.as_tensor(cells, device=dev)
+            self.lists.append(t)
+            self.c_scales[i].n_post[j] = cells.size
+            self.c_scales[i].post_cells[j] = t.data_ptr() if cells.size else None
         self.c = _capi.CslbmHierarchy(n, 0, C.cast(self.c_scales, C.POINTER(_capi.CslbmScale)))
 
     def ghost_cells(self, i: int) -> np.ndarray:

@@ -43,3 +43,70 @@ def test_prior_stencil_check_rejects_ghosts_outside_parent():
     with pytest.raises(ValueError):
         hierarchy.check_prior_stencils(kinds, (n, n, n), (0, 0, 0), 1.0, 0, fine_shape,
                                        (4.5, 1.0, 1.0), 1.0, ghosts)
+
+
+def test_drop_overwritten_posts_keeps_only_the_last_writer():
+    post = {(1, 0): np.array([1, 2, 3, 4]), (2, 0): np.array([3, 4, 5]),
+            (2, 1): np.array([7, 8]), (3, 0): np.array([1, 9]), (3, 1): np.array([8]),
+            (3, 2): np.array([0])}
+    out = hierarchy.drop_overwritten_posts(post, 4)
+    assert out[(1, 0)].tolist() == [2]
+    assert out[(2, 0)].tolist() == [3, 4, 5]
+    assert out[(3, 0)].tolist() == [1, 9]
+    assert out[(2, 1)].tolist() == [7]
+    assert out[(3, 1)].tolist() == [8]
+    assert out[(3, 2)].tolist() == [0]
+    # replaying the writes in scale order leaves the same labels
+    for lists in (post, out):
+        state = {j: np.full(10, -1) for j in range(4)}
+        for i in range(1, 4):
+            for j in range(i):
+                state[j][lists[(i, j)]] = i
+        if lists is post:
+            full = {j: v.copy() for j, v in state.items()}
+    for j in range(4):
+        np.testing.assert_array_equal(state[j], full[j])
+
+
+def _three_scales(n=12):
+    rho = np.ones(n ** 3)
+    u = inputs.smooth_random_field(n, n, n, 0.04, 77, k_max=2)
+    dom = oracle.Domain(n, n, n)
+    f0, _ = oracle.init(dom, rho, u)
+    nu0 = 2e-3
+
+    def box(nx, ny, nz, origin, dx, nu, parent):
+        fl = hierarchy.shell_flags(nx, ny, nz)
+        s = ml.OScale(nx, ny, nz, dx, origin, oracle.Params(nu=nu, g_max=0.05), fl, periodic=0,
+                      parent=parent)
+        return s
+
+    s0 = ml.OScale(n, n, n, 1.0, (0.0, 0.0, 0.0), oracle.Params(nu=nu0, g_max=0.05),
+                   np.zeros(n ** 3, np.uint8), periodic=7, f=f0)
+    s1 = box(13, 12, 12, (2.0, 2.0, 2.0), 1 / 1.5, nu0 * 1.5, 0)
+    s2 = box(12, 10, 10, (3.5, 3.5, 3.5), 0.5, nu0 * 2.0, 1)
+    scales = [s0, s1, s2]
+    for s in scales[1:]:
+        par = scales[s.parent]
+        cells = np.arange(s.n)
+        s.f = np.zeros((27, s.n))
+        oracle.exchange(par.geom(), par.f, par.f, 0.0, s.geom(), cells, s.f)
+    ml.prepare(scales)
+    return scales
+
+
+def test_dropping_overwritten_post_cells_leaves_the_oracle_state_bit_identical():
+    """Three scales (alpha 1.5 and 2, nested): the oracle's Algorithm-1 run
+    with the reduced post-mapping lists equals the run with the full lists
+    bit for bit, after 2 reference steps."""
+    full = _three_scales()
+    red = _three_scales()
+    lists = {(i, j): red[i].post[j] for i in range(1, 3) for j in range(i)}
+    dropped = hierarchy.drop_overwritten_posts(lists, 3)
+    assert dropped[(1, 0)].size < lists[(1, 0)].size
+    for (i, j), cells in dropped.items():
+        red[i].post[j] = cells.astype(np.int64)
+    ml.multiscale_step(full, 2)
+    ml.multiscale_step(red, 2)
+    for a, b in zip(full, red):
+        np.testing.assert_array_equal(a.f, b.f)

@@ -175,7 +175,7 @@ def build_pair(specs, seed, scalar=True):
     H = hierarchy.Hierarchy(levs, [sp.kinds for sp in specs], [sp.parent for sp in specs])
     ml.prepare(oscs)
     for i in range(1, len(specs)):
-        np.testing.assert_array_equal(np.sort(H.post[(i, 0)].astype(np.int64)), oscs[i].post[0])
+        np.testing.assert_array_equal(np.sort(H.post_full[(i, 0)].astype(np.int64)), oscs[i].post[0])
     return H, levs, oscs
 
 
@@ -261,7 +261,7 @@ def test_reduced_plume_three_scales_match_oracle():
     ml.prepare(oscs)
     for i in range(1, 3):
         for j in range(i):
-            np.testing.assert_array_equal(np.sort(H.post[(i, j)].astype(np.int64)), oscs[i].post[j])
+            np.testing.assert_array_equal(np.sort(H.post_full[(i, j)].astype(np.int64)), oscs[i].post[j])
     H.step(12)
     ml.multiscale_step(oscs, 12)
     torch.cuda.synchronize()

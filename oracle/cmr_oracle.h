@@ -19,9 +19,10 @@
  *     0, +x, -x, +y, -y, +z, -z.
  *
  * Parity status: every function here is pinned by the CPU test suite
- * (closed forms, invariants, brute force) except the functions marked
- * "parity unpinned" below, which encode readings of passages the paper
- * leaves open.
+ * (closed forms, invariants, brute force, special cases that reduce to
+ * textbook schemes).  The readings of passages the paper leaves open are
+ * listed in cmr_oracle.c; the multi-scale schedule built on these functions
+ * (multilevel.py) states which of its readings are only loosely pinned.
  */
 #ifndef CMR_ORACLE_H
 #define CMR_ORACLE_H

@@ -68,6 +68,9 @@ extern "C" {
 #define CSLBM_INLET 2    /* Dirichlet: output f^eq(1, u_in), g^eq(s_in, u_in) */
 #define CSLBM_OUTFLOW 3  /* zero gradient: output = input of the x-1 neighbour */
 #define CSLBM_GHOST 4    /* never collided; output = input (scale exchange writes it) */
+#define CSLBM_NEUMANN 5  /* far-field zero gradient (section "Initialization and
+                            boundary treatment"): output = input of the cell one
+                            step inward along every non-periodic face it lies on */
 #define CSLBM_NEAR_WALL 8
 
 /* Relaxation and model parameters (lattice units of the level). */
@@ -249,12 +252,26 @@ typedef struct cslbm_hierarchy {
  *     (k - 1) / alpha_i; the result is interpolated in time by the
  *     quadratic through 0, (l - 1)/alpha_i, l/alpha_i evaluated at 1; the
  *     ghosts are mapped again at weight 1; then the scale is post-mapped
- *     onto post_cells[j] of every coarser scale j < i;
- *   - the interpolated states become the finer scales' level.f (pointer
- *     swap with work_f[1] / work_g[1]).
- * Finer scales need flags with a CSLBM_GHOST shell; every scale must carry
- * the scalar or none.  Errors: CSLBM_ERR_ARG for an inconsistent
- * hierarchy (parents, spacings, buffers, lists, singular relaxation times). */
+ *     onto post_cells[j] of every coarser scale j < i (at integer alpha_i
+ *     the quadratic's weight on sub-step l is exactly 0 and that sub-step
+ *     is not computed; the result is the same);
+ *   - then each far-field scale i (level.dx > scale 0's dx; alpha_i =
+ *     dx_0 / dx_i < 1; section "Temporal alignment and scale mapping" and
+ *     the reversed rules of "Handling multiple scales"), in index order:
+ *     its ghost cells (the whole region it shares with its parent, the
+ *     finer scale it surrounds) are mapped from the parent at t_n; it takes
+ *     one step of dt_i = dt_0 / alpha_i and is interpolated linearly back
+ *     to t_n + dt_0, (1 - alpha_i) f(t_n) + alpha_i f(t_n + dt_i); its
+ *     ghost cells are mapped again at t_n + dt_0; then post_cells[parent]
+ *     (the parent's boundary shell, CSLBM_GHOST cells of the parent) are
+ *     mapped from it.  Its outer faces are normally CSLBM_NEUMANN cells;
+ *   - the interpolated states become the scales' level.f (pointer swap with
+ *     work_f[1] / work_g[1]).
+ * Every scale but scale 0 needs flags with CSLBM_GHOST cells; every scale
+ * must carry the scalar or none; a finer scale's parent is never a far-field
+ * scale and finer scales do not post-map onto far-field scales.  Errors:
+ * CSLBM_ERR_ARG for an inconsistent hierarchy (parents, spacings, buffers,
+ * lists, singular relaxation times). */
 int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t stream);
 
 /* ------------------------------------------------------------------------

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "cmr_oracle.c")
 LIB = os.path.join(HERE, "libcmr_oracle.so")
 
-FLUID, SOLID, INLET, OUTFLOW, GHOST = 0, 1, 2, 3, 4
+FLUID, SOLID, INLET, OUTFLOW, GHOST, NEUMANN = 0, 1, 2, 3, 4, 5
 
 _dp = C.POINTER(C.c_double)
 

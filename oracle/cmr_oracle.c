@@ -413,6 +413,20 @@ static int step_one(const oracle_domain* d, const oracle_params* p,
         }
         return 0;
     }
+    if (kind == ORACLE_NEUMANN) {
+        /* Neumann (zero normal gradient) far-field boundary (section
+         * "Initialization and boundary treatment"): copy the incoming state
+         * of the cell one step inward along each face normal */
+        int xs = x, ys = y, zs = z;
+        if (!(d->periodic & 1) && d->nx > 1) xs = (x == 0) ? 1 : (x == d->nx - 1 ? d->nx - 2 : x);
+        if (!(d->periodic & 2) && d->ny > 1) ys = (y == 0) ? 1 : (y == d->ny - 1 ? d->ny - 2 : y);
+        if (!(d->periodic & 4) && d->nz > 1) zs = (z == 0) ? 1 : (z == d->nz - 1 ? d->nz - 2 : z);
+        const int64_t from = xs + (int64_t)d->nx * (ys + (int64_t)d->ny * zs);
+        for (int i = 0; i < 27; ++i) fo[i * stride] = f[i * N + from];
+        if (g && go)
+            for (int i = 0; i < 7; ++i) go[i * stride] = g[i * N + from];
+        return 0;
+    }
     if (kind == ORACLE_OUTFLOW) {
         /* zero-gradient: copy the incoming state of the x-1 neighbour */
         const int64_t src = source_cell(d, x, y, z, 1, 0, 0);

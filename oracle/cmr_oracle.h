@@ -39,7 +39,10 @@ enum {
     ORACLE_SOLID = 1,   /* halfway bounce-back obstacle; output = rest state w_i */
     ORACLE_INLET = 2,   /* Dirichlet: output = f^eq(1, u_in), g^eq(s_in, u_in) */
     ORACLE_OUTFLOW = 3, /* zero-gradient: output = input of the x-1 neighbour */
-    ORACLE_GHOST = 4    /* written only by the scale exchange; output = input */
+    ORACLE_GHOST = 4,   /* written only by the scale exchange; output = input */
+    ORACLE_NEUMANN = 5  /* far-field zero-gradient on the box faces: output =
+                           input of the neighbour one cell inward along every
+                           non-periodic face the cell lies on */
 };
 
 typedef struct {

@@ -22,6 +22,14 @@ Readings (each also listed in the design doc):
   * post-mapping writes every coarser scale j < i at its FLUID cells whose
     trilinear stencil in scale i consists of FLUID cells of scale i.
 
+Far-field scales (spacing larger than the reference scale, alpha_c < 1)
+follow the reversed rules of section "Handling multiple scales": the region
+they share with their parent is GHOST in their flags and is mapped from the
+parent in full (at t_n before their step and again at t_n + dt_0 after it);
+they take one step and interpolate linearly back to t_n + dt_0; they
+post-map only onto the parent's ghost shell; their own outer faces are
+Neumann cells.  They run after every finer scale.
+
 Pins (CPU tests): a finer scale with the reference spacing on coincident
 points reproduces the single-scale run (integer alpha, mapping = identity);
 uniform flow stays uniform on three nested scales at alpha 1.5 and 2; a
@@ -117,13 +125,28 @@ def post_targets(coarse: OScale, fine: OScale) -> np.ndarray:
     return np.array(out, dtype=np.int64)
 
 
+def is_coarse(scales: list[OScale], i: int) -> bool:
+    """A scale with a larger spacing than the reference scale (far field)."""
+    return i > 0 and scales[i].dx > scales[0].dx
+
+
 def prepare(scales: list[OScale]):
-    """Fill the ghost and post-mapping lists of every finer scale."""
+    """Fill the ghost and post-mapping lists of every scale but the reference.
+
+    A finer scale's ghosts are its one-cell shell; it post-maps onto every
+    coarser scale j < i.  A coarser (far-field) scale is the reverse
+    (section "Handling multiple scales"): its ghosts are the whole region it
+    shares with its parent (the finer scale it surrounds), marked GHOST by
+    the caller, and it post-maps only onto the parent's ghost shell."""
     for i, s in enumerate(scales):
         if i == 0:
             continue
-        s.ghosts = shell_ghosts(s)
-        s.post = {j: post_targets(scales[j], s) for j in range(i)}
+        if is_coarse(scales, i):
+            s.ghosts = np.flatnonzero(s.flags == GHOST).astype(np.int64)
+            s.post = {s.parent: shell_ghosts(scales[s.parent])}
+        else:
+            s.ghosts = shell_ghosts(s)
+            s.post = {j: post_targets(scales[j], s) for j in range(i) if not is_coarse(scales, j)}
 
 
 def multiscale_step(scales: list[OScale], n_ref: int = 1):
@@ -136,6 +159,8 @@ def multiscale_step(scales: list[OScale], n_ref: int = 1):
         B0, gB0 = f1, g1
         states = {0: (A0, B0, gA0, gB0)}
         for i in range(1, len(scales)):
+            if is_coarse(scales, i):
+                continue
             s = scales[i]
             par = scales[s.parent]
             Ap, Bp, gAp, gBp = states[s.parent]
@@ -167,6 +192,29 @@ def multiscale_step(scales: list[OScale], n_ref: int = 1):
                     continue
                 Bj, gBj = states[j][1], states[j][3]
                 exchange(s.geom(), R, R, 0.0, scales[j].geom(), tgt, Bj, gR, gR, gBj)
+        # far-field scales, after every finer scale (section "Temporal
+        # alignment and scale mapping"): the overlap is mapped from the parent
+        # at t_n, one step of dt_c = dt_0 / alpha_c, linear interpolation back
+        # to t_n + dt_0, the overlap mapped again at t_n + dt_0, then the
+        # parent's boundary shell is mapped from this scale
+        for i in range(1, len(scales)):
+            if not is_coarse(scales, i):
+                continue
+            s = scales[i]
+            par = scales[s.parent]
+            Ap, Bp, gAp, gBp = states[s.parent]
+            ac = scales[0].dx / s.dx                     # alpha_c in (0, 1)
+            X0 = s.f.copy()
+            gX0 = None if s.g is None else s.g.copy()
+            exchange(par.geom(), Ap, Bp, 0.0, s.geom(), s.ghosts, X0, gAp, gBp, gX0)
+            X1, gX1 = step(s.domain(), s.params, X0, gX0)
+            R = (1.0 - ac) * X0 + ac * X1
+            gR = None if gX0 is None else (1.0 - ac) * gX0 + ac * gX1
+            exchange(par.geom(), Ap, Bp, 1.0, s.geom(), s.ghosts, R, gAp, gBp, gR)
+            states[i] = (X0, R, gX0, gR)
+            tgt = s.post[s.parent]
+            if tgt.size:
+                exchange(s.geom(), R, R, 0.0, par.geom(), tgt, Bp, gR, gR, gBp)
         for i, s in enumerate(scales):
             s.f = states[i][1]
             s.g = states[i][3]

@@ -115,6 +115,16 @@ __device__ __forceinline__ T* plane_at(T* base, int idx)
     return reinterpret_cast<T*>(reinterpret_cast<B*>(base) + (uint32_t)idx * (uint32_t)sizeof(T));
 }
 
+// Copy source of a Neumann (zero normal gradient) far-field cell: one cell
+// inward along every non-periodic face the cell lies on.
+__device__ __forceinline__ int inward_cell(const StepArgs& a, int x, int y, int z)
+{
+    if (!(a.periodic & 1) && a.nx > 1) x = (x == 0) ? 1 : (x == a.nx - 1 ? a.nx - 2 : x);
+    if (!(a.periodic & 2) && a.ny > 1) y = (y == 0) ? 1 : (y == a.ny - 1 ? a.ny - 2 : y);
+    if (!(a.periodic & 4) && a.nz > 1) z = (z == 0) ? 1 : (z == a.nz - 1 ? a.nz - 2 : z);
+    return x + a.nx * (y + a.ny * z);
+}
+
 // Bounce-back mask of a near-wall cell computed from the neighbours' kinds
 // (used only when the level has no precomputed links array): bit i is set
 // when the pull source x - c_i is solid or outside a non-periodic face.
@@ -166,9 +176,9 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
 
     // Cell kinds without divergent code paths: every lane issues the same
     // 27 (+7) loads and stores with its own addresses.  Fluid cells pull
-    // (bounce-back links from the per-cell mask), ghost and outflow cells
-    // load their copy source, solid and inlet cells read their own cell and
-    // discard it; the
+    // (bounce-back links from the per-cell mask), ghost, outflow and Neumann
+    // cells load their copy source, solid and inlet cells read their own
+    // cell and discard it; the
     // collision runs with zero relaxation on non-fluid lanes (an identity
     // up to rounding), and inlet lanes start from the inlet equilibrium.
     int kind = kFluid;
@@ -179,9 +189,10 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
         kind = flag & kKindMask;
         if (flag & kNearWall) links = a.links ? a.links[cell] : bounce_links(a, x, y, z, sx, sy, sz);
         if (kind == kOutflow && (x > 0 || (a.periodic & 1))) from = xm + nx * y + nxy * z;
+        if (kind == kNeumann) from = inward_cell(a, x, y, z);
     }
     const bool fluid = kind == kFluid;
-    const bool copies = kind == kGhost || kind == kOutflow;
+    const bool copies = kind == kGhost || kind == kOutflow || kind == kNeumann;
     const bool loads = fluid || copies;
 
     float v[27];

@@ -54,6 +54,7 @@ enum : uint8_t {
     kInlet = 2,
     kOutflow = 3,
     kGhost = 4,
+    kNeumann = 5,
 };
 constexpr uint8_t kKindMask = 0x07;
 constexpr uint8_t kNearWall = 0x08;  // set by the library: some pull source is solid

@@ -345,6 +345,9 @@ int cslbm_time_interp(const cslbm_level* L, const void* s0, const void* s1, cons
     return launch_time_interp(L, s0, s1, s2, g0, g1, g2, t, t_eval, out, g_out, stream);
 }
 
+// a scale with a larger spacing than the reference scale (far field)
+static bool far_field(const cslbm_scale* S, int i) { return i > 0 && S[i].level.dx > S[0].level.dx; }
+
 int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t stream)
 {
     if (!H || !H->scales) return fail(CSLBM_ERR_ARG, "hierarchy is NULL");
@@ -373,18 +376,33 @@ int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t s
             continue;
         }
         if (S[i].parent < 0 || S[i].parent >= i)
-            return fail(CSLBM_ERR_ARG, "scale %d: parent %d must be a coarser scale < %d", i,
+            return fail(CSLBM_ERR_ARG, "scale %d: parent %d must be a scale with index < %d", i,
                         S[i].parent, i);
-        if (!(L->dx <= S[S[i].parent].level.dx))
-            return fail(CSLBM_ERR_ARG, "scale %d is not finer than its parent", i);
-        if (!L->flags) return fail(CSLBM_ERR_ARG, "scale %d: finer scales need flags (ghost shell)", i);
+        const cslbm_level* PL = &S[S[i].parent].level;
+        if (far_field(S, i)) {
+            if (!(PL->dx < L->dx))
+                return fail(CSLBM_ERR_ARG, "far-field scale %d is not coarser than its parent", i);
+            for (int j = 0; j < ns; ++j)
+                if (j != S[i].parent && S[i].n_post[j] != 0)
+                    return fail(CSLBM_ERR_ARG,
+                                "far-field scale %d may post-map only onto its parent's shell", i);
+        } else {
+            if (far_field(S, S[i].parent))
+                return fail(CSLBM_ERR_ARG, "scale %d: a finer scale's parent cannot be a far-field scale", i);
+            if (!(L->dx <= PL->dx))
+                return fail(CSLBM_ERR_ARG, "scale %d is not finer than its parent", i);
+            for (int j = 0; j < i; ++j)
+                if (far_field(S, j) && S[i].n_post[j] != 0)
+                    return fail(CSLBM_ERR_ARG, "scale %d may not post-map onto far-field scale %d", i, j);
+        }
+        if (!L->flags) return fail(CSLBM_ERR_ARG, "scale %d: needs flags (ghost cells)", i);
         if (!S[i].work_f[0] || !S[i].work_f[1])
             return fail(CSLBM_ERR_ARG, "scale %d: two work buffers are required", i);
         if (scalar && (!S[i].work_g[0] || !S[i].work_g[1]))
             return fail(CSLBM_ERR_ARG, "scale %d: two scalar work buffers are required", i);
         if (S[i].n_ghost < 0 || (S[i].n_ghost > 0 && !S[i].ghost_cells))
             return fail(CSLBM_ERR_ARG, "scale %d: bad ghost list", i);
-        for (int j = 0; j < i; ++j)
+        for (int j = 0; j < ns; ++j)
             if (S[i].n_post[j] < 0 || (S[i].n_post[j] > 0 && !S[i].post_cells[j]))
                 return fail(CSLBM_ERR_ARG, "scale %d: bad post-mapping list for scale %d", i, j);
     }
@@ -409,6 +427,7 @@ int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t s
         }
         // finer scales, coarse to fine
         for (int i = 1; i < ns; ++i) {
+            if (far_field(S, i)) continue;
             cslbm_scale& sc = S[i];
             cslbm_level* L = &sc.level;
             const cslbm_level* P = &S[sc.parent].level;
@@ -473,6 +492,41 @@ int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t s
                                      sc.post_cells[j], sc.n_post[j], stream);
                 if (rc) return rc;
             }
+        }
+        // far-field scales (spacing larger than the reference scale), after
+        // every finer scale, with the reversed rules of section "Handling
+        // multiple scales": the whole region shared with the parent (GHOST
+        // cells of this scale) is mapped from the parent at t_n, the scale
+        // takes one step of dt_c = dt_0 / alpha_c and is interpolated linearly
+        // back to t_n + dt_0 (fused into the step's store), the shared region
+        // is mapped again at t_n + dt_0, and the parent's boundary shell is
+        // post-mapped from this scale.
+        for (int i = 1; i < ns; ++i) {
+            if (!far_field(S, i)) continue;
+            cslbm_scale& sc = S[i];
+            cslbm_level* L = &sc.level;
+            const cslbm_level* P = &S[sc.parent].level;
+            const int p = sc.parent;
+            const double ac = S[0].level.dx / L->dx;
+            void* X0 = L->f;
+            float* gX0 = L->g;
+            void* R = sc.work_f[1];
+            float* gR = sc.work_g[1];
+            int rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], 0.0, L, X0, gX0, sc.ghost_cells,
+                                     sc.n_ghost, stream);
+            if (rc) return rc;
+            rc = launch_step_interp(L, X0, R, gX0, gR, X0, gX0, 1.0 - ac, 0.0, ac, stream);
+            if (rc) return rc;
+            rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], 1.0, L, R, gR, sc.ghost_cells,
+                                 sc.n_ghost, stream);
+            if (rc) return rc;
+            A[i] = X0;
+            B[i] = R;
+            gA[i] = gX0;
+            gB[i] = gR;
+            rc = launch_exchange(L, R, R, gR, gR, 0.0, P, B[p], gB[p], sc.post_cells[p], sc.n_post[p],
+                                 stream);
+            if (rc) return rc;
         }
         // the interpolated states become the scales' states at the new reference time
         for (int i = 1; i < ns; ++i) {

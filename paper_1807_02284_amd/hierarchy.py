@@ -103,6 +103,35 @@ def check_prior_stencils(parent_kinds, parent_shape, parent_origin, parent_dx, p
             raise ValueError("a ghost cell's prior-mapping stencil touches a non-fluid parent cell")
 
 
+def check_shell_stencils(shell_shape, shell_origin, shell_dx, shell_cells,
+                         src_kinds, src_shape, src_origin, src_dx, src_periodic):
+    """The boundary shell of a scale, post-mapped from a far-field scale
+    around it, must interpolate from cells of that scale that hold a state
+    (not SOLID) inside its box on non-periodic axes."""
+    nx, ny, _ = shell_shape
+    gx, gy, gz = shell_cells % nx, (shell_cells // nx) % ny, shell_cells // (nx * ny)
+    pts = np.stack([shell_origin[0] + gx * shell_dx, shell_origin[1] + gy * shell_dx,
+                    shell_origin[2] + gz * shell_dx])
+    base, t = _stencil(pts, src_origin, src_dx, src_shape)
+    for corner in range(8):
+        o = np.array([corner & 1, (corner >> 1) & 1, (corner >> 2) & 1])
+        wt = np.ones(shell_cells.size)
+        for a in range(3):
+            wt *= t[a] if o[a] else 1.0 - t[a]
+        idx = base + o[:, None]
+        for a in range(3):
+            if src_periodic & (1 << a):
+                idx[a] %= src_shape[a]
+        inside = np.all((idx >= 0) & (idx < np.array(src_shape)[:, None]), axis=0)
+        need = wt != 0.0
+        if np.any(need & ~inside):
+            raise ValueError("a boundary cell's stencil leaves the far-field scale's box")
+        sc = idx[0] + src_shape[0] * (idx[1] + src_shape[1] * idx[2])
+        sc = np.where(inside, sc, 0)
+        if np.any(need & (src_kinds[sc] == _capi.SOLID)):
+            raise ValueError("a boundary cell's stencil touches a solid far-field cell")
+
+
 def drop_overwritten_posts(post: dict, n: int) -> dict:
     """Post-mapping lists {(fine i, coarse j): cells of j} with every cell
     removed that a later (finer) scale also post-maps into j.  Scales
@@ -114,6 +143,8 @@ def drop_overwritten_posts(post: dict, n: int) -> dict:
     for j in range(n):
         later = np.zeros(0, np.int32)
         for i in range(n - 1, j, -1):
+            if (i, j) not in post:
+                continue
             cells = np.asarray(post[(i, j)], np.int32)
             out[(i, j)] = np.setdiff1d(cells, later).astype(np.int32)
             later = np.union1d(later, cells).astype(np.int32)
@@ -121,18 +152,29 @@ def drop_overwritten_posts(post: dict, n: int) -> dict:
 
 
 class Hierarchy:
-    """Scales 0..n-1 (0 = reference, covering the domain); parents[i] is the
-    nearest coarser scale of scale i (default i - 1)."""
+    """Scales 0..n-1 (0 = reference); parents[i] is the nearest coarser scale
+    of a finer scale i (default i - 1).  A scale with a larger spacing than
+    scale 0 is a far-field scale: its parent is the finer scale it surrounds
+    (default 0), its GHOST cells are the region it shares with that parent,
+    and it post-maps onto the parent's GHOST shell."""
 
     def __init__(self, levels: list[Level], kinds: list[np.ndarray], parents=None):
         assert len(levels) == len(kinds) and 1 <= len(levels) <= _capi.MAX_SCALES
         self.levels = levels
         self.kinds = [np.asarray(k, np.uint8) for k in kinds]
-        self.parents = parents or [-1] + list(range(len(levels) - 1))
+        n = len(levels)
+        self.far = [i > 0 and levels[i].c.dx > levels[0].c.dx for i in range(n)]
+        if parents is None:
+            parents, last_fine = [-1], 0
+            for i in range(1, n):
+                parents.append(0 if self.far[i] else last_fine)
+                if not self.far[i]:
+                    last_fine = i
+        self.parents = list(parents)
         self.work = []
         self.lists = []
         self.post = {}
-        n = len(levels)
+        far_post = {}
         self.c_scales = (_capi.CslbmScale * n)()
         dev = levels[0].device
         for i, lev in enumerate(levels):
@@ -152,17 +194,28 @@ class Hierarchy:
                 self.lists.append(g_t)
                 sc.n_ghost = ghosts.size
                 sc.ghost_cells = g_t.data_ptr() if ghosts.size else None
-                for j in range(i):
-                    cj = levels[j]
-                    cells = post_cells(self.kinds[j], (cj.nx, cj.ny, cj.nz), tuple(cj.c.origin),
-                                       cj.c.dx, self.kinds[i], (lev.nx, lev.ny, lev.nz),
-                                       tuple(lev.c.origin), lev.c.dx)
-                    self.post[(i, j)] = cells
+                if self.far[i]:
+                    # reversed rules: post-map onto the parent's boundary shell
+                    pk = self.kinds[self.parents[i]]
+                    shell = np.flatnonzero(pk == GHOST).astype(np.int32)
+                    check_shell_stencils((par.nx, par.ny, par.nz), tuple(par.c.origin), par.c.dx,
+                                         shell, self.kinds[i], (lev.nx, lev.ny, lev.nz),
+                                         tuple(lev.c.origin), lev.c.dx, lev.c.periodic)
+                    far_post[(i, self.parents[i])] = shell
+                else:
+                    for j in range(i):
+                        if self.far[j]:
+                            continue
+                        cj = levels[j]
+                        cells = post_cells(self.kinds[j], (cj.nx, cj.ny, cj.nz), tuple(cj.c.origin),
+                                           cj.c.dx, self.kinds[i], (lev.nx, lev.ny, lev.nz),
+                                           tuple(lev.c.origin), lev.c.dx)
+                        self.post[(i, j)] = cells
             self.work.append((work_f, work_g))
             sc.work_f = (C.c_void_p * 2)(*[None if w is None else w.data_ptr() for w in work_f])
             sc.work_g = (C.c_void_p * 2)(*[None if w is None else w.data_ptr() for w in work_g])
-        self.post_full = dict(self.post)
-        self.post = drop_overwritten_posts(self.post_full, n)
+        self.post_full = {**self.post, **far_post}
+        self.post = {**drop_overwritten_posts(self.post, n), **far_post}
         for (i, j), cells in self.post.items():
             t = torch.as_tensor(cells, device=dev)
             self.lists.append(t)
@@ -252,6 +305,37 @@ def fine_scale(lo, hi, alpha: float, params0: Params, solid_fn=None, *, scalar: 
     p.tau_s = 0.5 + alpha * (params0.tau_s - 0.5)
     lev = Level(*shape, p, storage=storage, scalar=scalar, periodic=0, flags=kinds,
                 origin=origin, dx=dx)
+    return lev, kinds
+
+
+def far_field_scale(ref: Level, ref_kinds: np.ndarray, dx: float, origin, shape, *,
+                    periodic: int = 0, solid_fn=None):
+    """A far-field scale (section "Scale construction": scales coarser than
+    the reference over the far-field domain) of `shape` lattice points at
+    origin + (x, y, z) * dx, dx > 1 in reference units (alpha_c = 1/dx).
+    Cells whose trilinear stencil in the reference scale consists of its
+    FLUID cells are GHOST (the shared region, mapped from the reference);
+    faces on non-periodic axes are NEUMANN; `solid_fn` marks SOLID cells.
+    Parameters: nu = alpha_c nu0, tau_s - 1/2 = alpha_c (tau_s0 - 1/2)."""
+    nx, ny, nz = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    x, y, z = x.reshape(-1), y.reshape(-1), z.reshape(-1)
+    kinds = np.full(x.size, FLUID, np.uint8)
+    if solid_fn is not None:
+        kinds[solid_fn(origin[0] + x * dx, origin[1] + y * dx, origin[2] + z * dx)] = _capi.SOLID
+    probe = np.where(kinds == FLUID, FLUID, _capi.SOLID).astype(np.uint8)
+    shared = post_cells(probe, shape, tuple(origin), dx, np.asarray(ref_kinds, np.uint8),
+                        (ref.nx, ref.ny, ref.nz), tuple(ref.c.origin), ref.c.dx)
+    kinds[shared] = GHOST
+    for a, (c, n) in enumerate(((x, nx), (y, ny), (z, nz))):
+        if not periodic & (1 << a):
+            kinds[((c == 0) | (c == n - 1)) & (kinds != _capi.SOLID)] = _capi.NEUMANN
+    alpha = ref.c.dx / dx
+    p = Params(**{**ref.params.__dict__})
+    p.nu = ref.params.nu * alpha
+    p.tau_s = 0.5 + alpha * (ref.params.tau_s - 0.5)
+    lev = Level(nx, ny, nz, p, storage=ref.storage, scalar=ref.g is not None, periodic=periodic,
+                flags=kinds, origin=tuple(origin), dx=dx)
     return lev, kinds
 
 

@@ -295,6 +295,74 @@ def run_plume(nx: int, ny: int, nz: int, spinup: int, n_ref: int):
     return out
 
 
+def run_far_field(nx: int, ny: int, nz: int, pad: int, spinup: int, n_ref: int):
+    """Open jet with a far field: the plume's reference box (inflow disk on
+    the x = 0 face, solid sphere, FP32 scalar, nu0 = 1e-4, tau_s0 = 0.51)
+    with its walls and outflow plane replaced by a ghost shell, inside a
+    far-field scale of spacing 2 (alpha_c = 0.5) that reaches `pad`
+    reference cells beyond the box on every side and has Neumann faces.
+    `spinup` reference steps, then `n_ref` timed reference steps of the
+    two-scale schedule."""
+    import numpy as np
+    import torch
+    from paper_1807_02284_amd import _capi, hierarchy, inputs
+    from paper_1807_02284_amd.level import Level, Params
+
+    sc = nx / 512.0
+    x, y, z = inputs.grid_coords(nx, ny, nz)
+    kinds = hierarchy.shell_flags(nx, ny, nz)
+    disk = (x == 0) & ((y + 0.5 - ny / 2) ** 2 + (z + 0.5 - nz / 2) ** 2 <= (32 * sc) ** 2)
+    kinds[disk & (y > 0) & (y < ny - 1) & (z > 0) & (z < nz - 1)] = _capi.INLET
+    r = 24.0 * sc
+    centre = (160.0 * sc, ny / 2.0, nz / 2.0)
+
+    def sphere(px, py, pz):
+        return (px + 0.5 - centre[0]) ** 2 + (py + 0.5 - centre[1]) ** 2 + (pz + 0.5 - centre[2]) ** 2 <= r * r
+
+    kinds[sphere(x, y, z)] = _capi.SOLID
+    p0 = Params(nu=1e-4, g_max=0.1, tau_s=0.51, u_in=(0.05, 0.0, 0.0), s_in=1.0)
+    lev0 = Level(nx, ny, nz, p0, scalar=True, periodic=0, flags=kinds)
+    jet = ((y + 0.5 - ny / 2) ** 2 + (z + 0.5 - nz / 2) ** 2 <= (32 * sc) ** 2) & (kinds == 0)
+    u = np.zeros((3, x.size), np.float32)
+    u[0, jet] = 0.05
+    s0 = np.where(jet & (x < 64 * sc), 1.0, 0.0).astype(np.float32)
+    lev0.init_equilibrium(None, u, s0)
+    del x, y, z, u, s0, jet
+    dxc = 2.0
+    shape_c = tuple(int(np.ceil((m - 1 + 2 * pad) / dxc)) + 1 for m in (nx, ny, nz))
+    origin_c = (-float(pad),) * 3
+    far, kinds_c = hierarchy.far_field_scale(lev0, kinds, dxc, origin_c, shape_c, solid_fn=sphere)
+    far.init_equilibrium(None, np.zeros((3, far.n), np.float32), np.zeros(far.n, np.float32))
+    H = hierarchy.Hierarchy([lev0, far], [kinds, kinds_c])
+    H.step(spinup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    H.step(n_ref)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / n_ref
+    # the reference scale alone (flags + scalar), for the share of the exchange
+    ms0 = time_steps(lev0, 20, 2) / 20
+    cells = [lev0.n, far.n]
+    bad = lev0.count_nonfinite() + far.count_nonfinite()
+    out = {
+        "reference_box": [nx, ny, nz],
+        "far_field_shape": list(shape_c),
+        "far_field_spacing": dxc,
+        "far_field_shared_cells": int(np.count_nonzero(kinds_c == _capi.GHOST)),
+        "reference_shell_cells": int(np.count_nonzero(kinds == _capi.GHOST)),
+        "cells_per_scale": cells,
+        "ms_per_reference_step": ms,
+        "mlups_all_scales": sum(cells) / (ms * 1e-3) / 1e6,
+        "reference_scale_step_ms": ms0,
+        "nonfinite": int(bad),
+    }
+    del H, lev0, far
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(n: int, target_s: float = 12.0):
     """The FP64 oracle (as is) on a bounded sample of the workload: a periodic
     n x n x nz_s slab cut from the same seeded turbulence field, one or more
@@ -340,6 +408,8 @@ def main():
                     help="skip the 128^3 differentiable buoyant-smoke variant")
     ap.add_argument("--no-plume", action="store_true",
                     help="skip the 512x256x256 three-scale plume variant")
+    ap.add_argument("--no-far-field", action="store_true",
+                    help="skip the open-jet variant with a far-field scale")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the runs, copy a 1 GiB float32 tensor 3 times (reference "
                          "kernel of known traffic for HBM counter calibration)")
@@ -389,6 +459,13 @@ def main():
               f"{pl['ms_per_reference_step']:.2f} ms/reference step, "
               f"{pl['mlups_all_scales']:.0f} MLUPS over all scales; reference scale alone "
               f"{pl['reference_scale_mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+
+    if not args.no_far_field:
+        ff = run_far_field(512, 256, 256, 128, 100, 40)
+        variants["far_field_open_jet_512x256x256"] = ff
+        print(f"[bench] far field: cells {ff['cells_per_scale']}, {ff['ms_per_reference_step']:.2f} "
+              f"ms/reference step ({ff['reference_scale_step_ms']:.2f} ms reference scale alone)",
+              file=sys.stderr, flush=True)
 
     if args.copy_calibration:
         x = torch.rand(1 << 28, device="cuda")      # 1 GiB

@@ -37,7 +37,8 @@ def build(force: bool = True) -> str:
 class _Params(C.Structure):
     _fields_ = [("nu", C.c_double), ("nu_hi", C.c_double * 4), ("a", C.c_double),
                 ("b", C.c_double), ("g_max", C.c_double), ("adaptive", C.c_int32),
-                ("tau_s", C.c_double), ("beta", C.c_double), ("s_ref", C.c_double)]
+                ("grad_mode", C.c_int32), ("tau_s", C.c_double), ("beta", C.c_double),
+                ("s_ref", C.c_double)]
 
 
 class _Domain(C.Structure):
@@ -64,10 +65,12 @@ class Params:
     tau_s: float = 0.51
     beta: float = 0.0
     s_ref: float = 0.0
+    grad_mode: int = 0          # 0: local strain-rate estimate; 1: |grad u|_F by differences
 
     def c(self) -> _Params:
         return _Params(self.nu, (C.c_double * 4)(*self.nu_hi), self.a, self.b,
-                       self.g_max, int(self.adaptive), self.tau_s, self.beta, self.s_ref)
+                       self.g_max, int(self.adaptive), int(self.grad_mode), self.tau_s, self.beta,
+                       self.s_ref)
 
 
 @dataclass
@@ -125,6 +128,8 @@ def lib():
         L.oracle_step_cells.argtypes = [C.POINTER(_Domain), C.POINTER(_Params), _dp, _dp,
                                         C.POINTER(C.c_int64), C.c_int64, _dp, _dp]
         L.oracle_macro.argtypes = [C.POINTER(_Domain), C.POINTER(_Params), _dp, _dp, _dp, _dp, _dp]
+        L.oracle_grad_field.argtypes = [C.POINTER(_Domain), C.POINTER(_Params), _dp, _dp, _dp]
+        L.oracle_collide_g.argtypes = [_dp, _dp, C.POINTER(_Params), C.c_double, _dp, _dp]
         L.oracle_exchange.argtypes = [C.POINTER(_Scale), _dp, _dp, _dp, _dp, C.c_double,
                                       C.POINTER(_Scale), C.POINTER(C.c_int64), C.c_int64, _dp, _dp]
         L.oracle_time_interp.argtypes = [_dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
@@ -259,6 +264,30 @@ def macro(dom: Domain, params: Params, f, g=None):
     dc, pc = dom.c(), params.c()
     lib().oracle_macro(C.byref(dc), C.byref(pc), _p(f), _p(g), _p(rho), _p(u), _p(s))
     return rho, u, s
+
+
+def grad_field(dom: Domain, params: Params, f, g=None):
+    """|grad u|_F of the read-back velocity of the state (f, g) [N]."""
+    n = dom.n
+    f = _f64(f, 27 * n)
+    g = None if g is None else _f64(g, 7 * n)
+    G = np.zeros(n)
+    dc, pc = dom.c(), params.c()
+    if lib().oracle_grad_field(C.byref(dc), C.byref(pc), _p(f), _p(g), _p(G)) != 0:
+        raise RuntimeError("oracle_grad_field failed")
+    return G
+
+
+def collide_g(f, params: Params, G: float, F=None):
+    """One cell's collision with the adaptive factor's G given."""
+    f = _f64(f, 27)
+    Fv = np.zeros(3) if F is None else _f64(F, 3)
+    out = np.zeros(27)
+    diag = np.zeros(6)
+    pc = params.c()
+    if lib().oracle_collide_g(_p(f), _p(Fv), C.byref(pc), float(G), _p(out), _p(diag)) != 0:
+        raise RuntimeError("oracle_collide_g failed")
+    return out, dict(zip(("rho", "ux", "uy", "uz", "G", "phi"), diag))
 
 
 def _scale_c(nx, ny, nz, periodic, origin, dx, nu, tau_s=0.0) -> _Scale:

@@ -224,8 +224,23 @@ static void scalar_eq(double s, const double u[3], double geq[7])
  *   for i > 8 (appendix), nu^_i' = phi nu_i' (section "Adaptive
  *   relaxation"), plus the body-force source (I - S/2) R.
  * ------------------------------------------------------------------- */
+static int collide_impl(const double f[27], const double F[3], const oracle_params* p,
+                        const double* S_override, double G_given, double out[27], double diag[6]);
+
 int oracle_collide(const double f[27], const double F[3], const oracle_params* p,
                    const double* S_override, double out[27], double diag[6])
+{
+    return collide_impl(f, F, p, S_override, -1.0, out, diag);
+}
+
+int oracle_collide_g(const double f[27], const double F[3], const oracle_params* p, double G,
+                     double out[27], double diag[6])
+{
+    return collide_impl(f, F, p, NULL, G, out, diag);
+}
+
+static int collide_impl(const double f[27], const double F[3], const oracle_params* p,
+                        const double* S_override, double G_given, double out[27], double diag[6])
 {
     const double Fz[3] = {0.0, 0.0, 0.0};
     if (!F) F = Fz;
@@ -263,7 +278,7 @@ int oracle_collide(const double f[27], const double F[3], const oracle_params* p
     const double PP = Pxx * Pxx + Pyy * Pyy + Pzz * Pzz +
                       2.0 * (Pxy * Pxy + Pxz * Pxz + Pyz * Pyz);
     const double scale = 3.0 * S_shear / (2.0 * rho);
-    const double G = sqrt(2.0 * scale * scale * PP);
+    const double G = (G_given >= 0.0) ? G_given : sqrt(2.0 * scale * scale * PP);
     double phi = 1.0;
     if (p->adaptive) {
         const double x = G / p->g_max;
@@ -381,7 +396,7 @@ static void gather(const oracle_domain* d, const double* f, const double* g,
  * collide.  fo[27 * stride] / go[7 * stride] receive the output with
  * element stride `stride`. */
 static int step_one(const oracle_domain* d, const oracle_params* p,
-                    const double* f, const double* g, int64_t cell,
+                    const double* f, const double* g, const double* gfield, int64_t cell,
                     double* fo, double* go, int64_t stride)
 {
     const int64_t N = n_cells(d);
@@ -450,7 +465,8 @@ static int step_one(const oracle_domain* d, const oracle_params* p,
     if (g) F[2] += p->beta * (s - p->s_ref);
 
     double post[27], diag[6];
-    if (oracle_collide(fi, F, p, NULL, post, diag) != 0) return -1;
+    const double Gc = gfield ? gfield[cell] : -1.0;
+    if (collide_impl(fi, F, p, NULL, Gc, post, diag) != 0) return -1;
     for (int i = 0; i < 27; ++i) fo[i * stride] = post[i];
 
     if (g && go) {
@@ -483,15 +499,68 @@ int oracle_init(const oracle_domain* d, const double* rho, const double* u,
     return err ? -1 : 0;
 }
 
+/* |grad u|_F of the read-back velocity field (central differences). */
+int oracle_grad_field(const oracle_domain* d, const oracle_params* p,
+                      const double* f, const double* g, double* G)
+{
+    const int64_t N = n_cells(d);
+    double* rho = (double*)malloc(sizeof(double) * N);
+    double* u = (double*)malloc(sizeof(double) * 3 * N);
+    if (!rho || !u) {
+        free(rho);
+        free(u);
+        return -1;
+    }
+    oracle_macro(d, p, f, g, rho, u, NULL);
+    const int n[3] = {d->nx, d->ny, d->nz};
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < N; ++c) {
+        const int x[3] = {(int)(c % d->nx), (int)((c / d->nx) % d->ny),
+                          (int)(c / ((int64_t)d->nx * d->ny))};
+        double sum = 0.0;
+        for (int a = 0; a < 3; ++a) {          /* derivative direction */
+            int lo[3] = {x[0], x[1], x[2]}, hi[3] = {x[0], x[1], x[2]};
+            double h = 2.0;
+            if (d->periodic & (1 << a)) {
+                lo[a] = (x[a] - 1 + n[a]) % n[a];
+                hi[a] = (x[a] + 1) % n[a];
+            } else {
+                lo[a] = x[a] > 0 ? x[a] - 1 : x[a];
+                hi[a] = x[a] < n[a] - 1 ? x[a] + 1 : x[a];
+                h = (double)(hi[a] - lo[a]);
+            }
+            const int64_t cl = lo[0] + (int64_t)d->nx * (lo[1] + (int64_t)d->ny * lo[2]);
+            const int64_t ch = hi[0] + (int64_t)d->nx * (hi[1] + (int64_t)d->ny * hi[2]);
+            for (int b = 0; b < 3; ++b) {      /* velocity component */
+                const double dv = (h > 0.0) ? (u[b * N + ch] - u[b * N + cl]) / h : 0.0;
+                sum += dv * dv;
+            }
+        }
+        G[c] = sqrt(sum);
+    }
+    free(rho);
+    free(u);
+    return 0;
+}
+
 int oracle_step(const oracle_domain* d, const oracle_params* p,
                 const double* f, const double* g, double* f_out, double* g_out)
 {
     const int64_t N = n_cells(d);
+    double* gfield = NULL;
+    if (p->grad_mode == 1) {
+        gfield = (double*)malloc(sizeof(double) * N);
+        if (!gfield || oracle_grad_field(d, p, f, g, gfield) != 0) {
+            free(gfield);
+            return -1;
+        }
+    }
     int err = 0;
 #pragma omp parallel for schedule(dynamic, 64) reduction(| : err)
     for (int64_t c = 0; c < N; ++c) {
-        if (step_one(d, p, f, g, c, f_out + c, g_out ? g_out + c : NULL, N) != 0) err |= 1;
+        if (step_one(d, p, f, g, gfield, c, f_out + c, g_out ? g_out + c : NULL, N) != 0) err |= 1;
     }
+    free(gfield);
     return err ? -1 : 0;
 }
 
@@ -500,6 +569,14 @@ int oracle_step_cells(const oracle_domain* d, const oracle_params* p,
                       const int64_t* cells, int64_t n, double* f_out, double* g_out)
 {
     const int64_t N = n_cells(d);
+    double* gfield = NULL;
+    if (p->grad_mode == 1) {
+        gfield = (double*)malloc(sizeof(double) * N);
+        if (!gfield || oracle_grad_field(d, p, f, g, gfield) != 0) {
+            free(gfield);
+            return -1;
+        }
+    }
     int err = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(| : err)
     for (int64_t k = 0; k < n; ++k) {
@@ -507,9 +584,10 @@ int oracle_step_cells(const oracle_domain* d, const oracle_params* p,
             err |= 1;
             continue;
         }
-        if (step_one(d, p, f, g, cells[k], f_out + k, g_out ? g_out + k : NULL, n) != 0)
+        if (step_one(d, p, f, g, gfield, cells[k], f_out + k, g_out ? g_out + k : NULL, n) != 0)
             err |= 1;
     }
+    free(gfield);
     return err ? -1 : 0;
 }
 

@@ -51,6 +51,10 @@ typedef struct {
     double a, b;      /* adaptive relaxation model parameters */
     double g_max;     /* gradient normalisation of the adaptive relaxation */
     int32_t adaptive; /* 0: phi = 1; 1: phi = a*min(G/g_max,1) + b */
+    int32_t grad_mode; /* G of the adaptive factor: 0 = local strain-rate
+                          magnitude sqrt(2 S^:S^) from the non-equilibrium
+                          stress; 1 = |grad u|_F of the stored velocity field
+                          by central differences (one step lagged) */
     double tau_s;     /* D3Q7 scalar BGK relaxation time */
     double beta;      /* buoyancy coefficient, F_z += beta*(s - s_ref) */
     double s_ref;
@@ -87,6 +91,17 @@ int oracle_init(const oracle_domain* d, const double* rho, const double* u,
                 const double* s, double* f, double* g);
 
 /* One step for every cell.  g / g_out may be NULL (no scalar). */
+/* oracle_collide with the gradient magnitude G of the adaptive factor
+ * given (G >= 0) instead of estimated from the cell's own stress (G < 0). */
+int oracle_collide_g(const double f[27], const double F[3], const oracle_params* p, double G,
+                     double out[27], double diag[6]);
+
+/* |grad u|_F at every cell of the velocity read back from the stored state
+ * (f, g): central differences, periodic wrap on periodic axes, one-sided
+ * differences at non-periodic faces.  G[N]. */
+int oracle_grad_field(const oracle_domain* d, const oracle_params* p,
+                      const double* f, const double* g, double* G);
+
 int oracle_step(const oracle_domain* d, const oracle_params* p,
                 const double* f, const double* g, double* f_out, double* g_out);
 

@@ -295,6 +295,46 @@ def run_plume(nx: int, ny: int, nz: int, spinup: int, n_ref: int):
     return out
 
 
+def run_gradient_mode(n: int, steps: int, compare_steps: int):
+    """The 256^3 turbulence workload with the adaptive factor driven by the
+    finite-difference |grad u|_F of the stored velocity (grad_mode 1, one
+    step lagged; +24 B/LUP for the velocity field) instead of the local
+    strain-rate estimate: MLUPS, and after `compare_steps` steps from the
+    same start the velocity-field and kinetic-energy differences between
+    the two modes."""
+    import numpy as np
+    import torch
+    from paper_1807_02284_amd import inputs
+    from paper_1807_02284_amd.level import Level, Params
+
+    rho, u = inputs.turbulence(n, 2, 32, 0.04, seed=1807)
+    fields = {}
+    out = {}
+    for mode in (1, 0):
+        lev = Level(n, n, n, Params(nu=1e-5, g_max=0.1, adaptive=True, grad_mode=mode))
+        lev.init_equilibrium(rho, u)
+        if mode == 1:
+            ms = time_steps(lev, steps, 10)
+            out["ms_per_step"] = ms / steps
+            out["mlups"] = n ** 3 * steps / (ms * 1e-3) / 1e6
+            out["achieved_gbs"] = n ** 3 * 240 / (ms / steps * 1e-3) / 1e9
+            lev.init_equilibrium(rho, u)
+        lev.step(compare_steps)
+        _, ug, _ = lev.read_macro()
+        torch.cuda.synchronize()
+        fields[mode] = ug.double()
+        del lev
+        torch.cuda.empty_cache()
+    d = fields[1] - fields[0]
+    out["bytes_per_lup"] = 240
+    out["compare_steps"] = compare_steps
+    out["velocity_rel_l2_fd_vs_local"] = float(torch.linalg.norm(d) / torch.linalg.norm(fields[0]))
+    e1, e0 = float((fields[1] ** 2).sum()), float((fields[0] ** 2).sum())
+    out["kinetic_energy_ratio_fd_vs_local"] = e1 / e0
+    out["kinetic_energy_decay_local"] = e0 / float(np.sum(u.astype(np.float64) ** 2))
+    return out
+
+
 def run_far_field(nx: int, ny: int, nz: int, pad: int, spinup: int, n_ref: int):
     """Open jet with a far field: the plume's reference box (inflow disk on
     the x = 0 face, solid sphere, FP32 scalar, nu0 = 1e-4, tau_s0 = 0.51)
@@ -408,6 +448,8 @@ def main():
                     help="skip the 128^3 differentiable buoyant-smoke variant")
     ap.add_argument("--no-plume", action="store_true",
                     help="skip the 512x256x256 three-scale plume variant")
+    ap.add_argument("--no-gradient-mode", action="store_true",
+                    help="skip the finite-difference gradient-mode variant")
     ap.add_argument("--no-far-field", action="store_true",
                     help="skip the open-jet variant with a far-field scale")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -459,6 +501,13 @@ def main():
               f"{pl['ms_per_reference_step']:.2f} ms/reference step, "
               f"{pl['mlups_all_scales']:.0f} MLUPS over all scales; reference scale alone "
               f"{pl['reference_scale_mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+
+    if not args.no_gradient_mode:
+        gm = run_gradient_mode(args.n, 200, 500)
+        variants["gradient_mode_fd_256"] = gm
+        print(f"[bench] gradient mode: {gm['mlups']:.0f} MLUPS; after {gm['compare_steps']} steps "
+              f"velocity rel L2 vs local mode {gm['velocity_rel_l2_fd_vs_local']:.2e}, energy ratio "
+              f"{gm['kinetic_energy_ratio_fd_vs_local']:.5f}", file=sys.stderr, flush=True)
 
     if not args.no_far_field:
         ff = run_far_field(512, 256, 256, 128, 100, 40)

@@ -82,6 +82,12 @@ typedef struct cslbm_params {
                          G clamped to g_max (paper: a = -4, b = 5) */
     double g_max;     /* gradient normalisation, > 0 */
     int32_t adaptive; /* 0: the factor is 1 (fixed nu'_i) */
+    int32_t grad_mode; /* G of the adaptive factor: 0 = local strain-rate
+                          magnitude sqrt(2 S^:S^) from the cell's own
+                          non-equilibrium stress (eq. pi_1); 1 = |grad u|_F
+                          of the stored velocity field by central differences
+                          (one step lagged; needs vel/vel_next, fully
+                          periodic levels without flags, cslbm_step only) */
     double tau_s;     /* scalar BGK relaxation time (> 1/2) */
     double beta;      /* buoyancy: F_z += beta (s - s_ref) */
     double s_ref;
@@ -109,6 +115,11 @@ typedef struct cslbm_level {
                                  x - c_i is solid or outside a non-periodic
                                  face), or NULL (computed per step instead) */
     const float* force;       /* [3][plane] body force field theta, or NULL */
+    float* vel;               /* [3][nx*ny*nz] velocity read back from the
+                                 current state (grad_mode 1), or NULL; written
+                                 by cslbm_init_equilibrium and
+                                 cslbm_set_populations, advanced by cslbm_step */
+    float* vel_next;          /* [3][nx*ny*nz] next velocity (grad_mode 1) */
     double origin[3];         /* physical position of cell (0,0,0) */
     double dx;                /* physical spacing of this scale */
     cslbm_params p;

@@ -28,6 +28,7 @@ class CslbmParams(C.Structure):
         ("b", C.c_double),
         ("g_max", C.c_double),
         ("adaptive", C.c_int32),
+        ("grad_mode", C.c_int32),
         ("tau_s", C.c_double),
         ("beta", C.c_double),
         ("s_ref", C.c_double),
@@ -52,6 +53,8 @@ class CslbmLevel(C.Structure):
         ("flags", _vp),
         ("links", _vp),
         ("force", _vp),
+        ("vel", _vp),
+        ("vel_next", _vp),
         ("origin", C.c_double * 3),
         ("dx", C.c_double),
         ("p", CslbmParams),

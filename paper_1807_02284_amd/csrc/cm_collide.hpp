@@ -174,9 +174,10 @@ struct CellMacro {
 // F is the body force (zero when absent): u = (j + F/2)/rho and the
 // order-one central moments receive +F (source (I - S/2) R with S_1..3 = 0).
 // active == false relaxes nothing (the transform pair is then an identity up
-// to rounding); kernels use it for lanes of non-fluid cells.
+// to rounding); kernels use it for lanes of non-fluid cells.  g_given >= 0
+// replaces the cell's own estimate of the gradient magnitude G.
 __host__ __device__ __forceinline__ CellMacro cm_collide(float (&v)[27], const Rates& r, float Fx, float Fy,
-                                               float Fz, bool active = true)
+                                               float Fz, bool active = true, float g_given = -1.0f)
 {
     float dr, jx, jy, jz;
     moments0(v, dr, jx, jy, jz);
@@ -202,7 +203,7 @@ __host__ __device__ __forceinline__ CellMacro cm_collide(float (&v)[27], const R
 
     // adaptive relaxation: G = sqrt(2 S^:S^), S^ = -(3 S / (2 rho)) Pi_dev
     const float pp = pxx * pxx + pyy * pyy + pzz * pzz + 2.0f * (nxy * nxy + nxz * nxz + nyz * nyz);
-    const float G = 1.5f * r.S * inv_rho * sqrtf(2.0f * pp);
+    const float G = g_given >= 0.0f ? g_given : 1.5f * r.S * inv_rho * sqrtf(2.0f * pp);
     float phi = 1.0f;
     if (r.adaptive) phi = r.a * fminf(G * r.inv_gmax, 1.0f) + r.b;
     float om[4];

@@ -67,6 +67,11 @@ struct StepArgs {
     const void* t0;
     const float* gt0;
     float l0, l1, l2;
+    // finite-difference gradient mode: stored velocity [3][N] of the input
+    // state and of the output state
+    const float* vel;
+    float* vel_out;
+    int64_t ncells;
 };
 
 // D3Q7 equilibrium g^eq_i = w_i s (1 + 4 c_i.u)  (cs^2 = 1/4)
@@ -146,7 +151,7 @@ __device__ __forceinline__ uint32_t bounce_links(const StepArgs& a, int x, int y
 // ---------------------------------------------------------------------------
 // K: fused pull-stream + collide
 // ---------------------------------------------------------------------------
-template <typename T, bool kFlags, bool kForce, bool kScalar, bool kTime>
+template <typename T, bool kFlags, bool kForce, bool kScalar, bool kTime, bool kGradFD>
 __global__ void __launch_bounds__(256) k_step(const StepArgs a)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -250,7 +255,33 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
     }
     if (kScalar && fluid) Fz += a.beta * (s - a.s_ref);
 
-    const CellMacro mc = cm_collide(v, a.r, Fx, Fy, Fz, fluid);
+    // gradient mode: |grad u|_F of the stored velocity field by central
+    // differences (the level is fully periodic: kGradFD excludes flags)
+    float g_given = -1.0f;
+    if (kGradFD) {
+        const int64_t Nc = a.ncells;
+        const int cxm = xm + sy[1] + sz[1], cxp = xp + sy[1] + sz[1];
+        const int cym = x + sy[2] + sz[1], cyp = x + sy[0] + sz[1];
+        const int czm = x + sy[1] + sz[2], czp = x + sy[1] + sz[0];
+        float sum = 0.0f;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const float* U = a.vel + b * Nc;
+            const float dx = 0.5f * (U[cxp] - U[cxm]);
+            const float dy = 0.5f * (U[cyp] - U[cym]);
+            const float dz = 0.5f * (U[czp] - U[czm]);
+            sum += dx * dx + dy * dy + dz * dz;
+        }
+        g_given = sqrtf(sum);
+    }
+    const CellMacro mc = cm_collide(v, a.r, Fx, Fy, Fz, fluid, g_given);
+    if (kGradFD) {
+        // velocity of the new state as read back from it: (j~ - F/2)/rho
+        // equals the collision velocity (j + F/2)/rho since j~ = j + F
+        a.vel_out[cell] = mc.ux;
+        a.vel_out[a.ncells + cell] = mc.uy;
+        a.vel_out[2 * a.ncells + cell] = mc.uz;
+    }
 
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -580,7 +611,27 @@ int validate_params(const cslbm_level* L)
     }
     if (L->g && !(p.tau_s > 0.5))
         return fail(CSLBM_ERR_ARG, "scalar relaxation time tau_s = %g must exceed 1/2", p.tau_s);
+    if (p.grad_mode != 0 && p.grad_mode != 1)
+        return fail(CSLBM_ERR_ARG, "grad_mode = %d must be 0 or 1", p.grad_mode);
     return CSLBM_OK;
+}
+
+static inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+// After the state of a gradient-mode level was written: its velocity field.
+static int refresh_velocity(const cslbm_level* L, hipStream_t stream)
+{
+    if (L->p.grad_mode != 1 || !L->vel) return CSLBM_OK;
+    const int64_t N = cells_of(L);
+    const dim3 grid(blocks_for(N, 256)), block(256);
+    const float beta = (float)L->p.beta, sref = (float)L->p.s_ref;
+    if (L->storage == CSLBM_F32)
+        hipLaunchKernelGGL(k_macro<float>, grid, block, 0, stream, (const float*)L->f, L->g, L->force,
+                           N, L->plane, beta, sref, nullptr, L->vel, nullptr);
+    else
+        hipLaunchKernelGGL(k_macro<_Float16>, grid, block, 0, stream, (const _Float16*)L->f, L->g,
+                           L->force, N, L->plane, beta, sref, nullptr, L->vel, nullptr);
+    return check_launch("k_macro");
 }
 
 Rates make_rates(const cslbm_params& p)
@@ -613,12 +664,26 @@ dim3 step_block(int nx)
     return dim3(best, 256 / best, 1);
 }
 
-template <typename T, bool kFlags, bool kForce, bool kScalar, bool kTime = false>
+template <typename T, bool kFlags, bool kForce, bool kScalar, bool kTime = false,
+          bool kGradFD = false>
 static void launch_step(const StepArgs& a, hipStream_t st)
 {
     const dim3 block = step_block(a.nx);
     const dim3 grid((a.nx + block.x - 1) / block.x, (a.ny + block.y - 1) / block.y, a.nz);
-    hipLaunchKernelGGL((k_step<T, kFlags, kForce, kScalar, kTime>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((k_step<T, kFlags, kForce, kScalar, kTime, kGradFD>), grid, block, 0, st, a);
+}
+
+// gradient-mode variants: fully periodic levels without flags
+template <typename T>
+static void dispatch_step_grad(const StepArgs& a, bool force, bool scalar, hipStream_t st)
+{
+    const int key = (force ? 2 : 0) | (scalar ? 1 : 0);
+    switch (key) {
+        case 0: launch_step<T, false, false, false, false, true>(a, st); break;
+        case 1: launch_step<T, false, false, true, false, true>(a, st); break;
+        case 2: launch_step<T, false, true, false, false, true>(a, st); break;
+        default: launch_step<T, false, true, true, false, true>(a, st); break;
+    }
 }
 
 // time-interpolating variants exist for flagged levels only (finer scales)
@@ -649,24 +714,44 @@ static void dispatch_step(const StepArgs& a, bool flags, bool force, bool scalar
     }
 }
 
-static inline unsigned blocks_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
-
 int launch_step_into(const cslbm_level* L, const void* fin, void* fout, const float* gin,
                      float* gout, hipStream_t stream)
 {
     return launch_step_interp(L, fin, fout, gin, gout, nullptr, nullptr, 0.0, 0.0, 1.0, stream);
 }
 
-int launch_step_interp(const cslbm_level* L, const void* fin, void* fout, const float* gin,
-                       float* gout, const void* t0, const float* gt0, double l0, double l1,
-                       double l2, hipStream_t stream)
+static StepArgs step_args(const cslbm_level* L, const void* fin, void* fout, const float* gin,
+                          float* gout);
+
+// One step in the finite-difference gradient mode (grad_mode 1): the
+// adaptive factor takes |grad u|_F of vel (the input state's velocity) and
+// the new state's velocity goes to vel_out.
+static int launch_step_grad(const cslbm_level* L, const void* fin, void* fout, const float* gin,
+                            float* gout, const float* vel, float* vel_out, hipStream_t stream)
+{
+    StepArgs a = step_args(L, fin, fout, gin, gout);
+    a.vel = vel;
+    a.vel_out = vel_out;
+    a.ncells = cells_of(L);
+    if (L->storage == CSLBM_F32)
+        dispatch_step_grad<float>(a, L->force != nullptr, gin != nullptr, stream);
+    else
+        dispatch_step_grad<_Float16>(a, L->force != nullptr, gin != nullptr, stream);
+    return check_launch("k_step");
+}
+
+static StepArgs step_args(const cslbm_level* L, const void* fin, void* fout, const float* gin,
+                          float* gout)
 {
     StepArgs a;
-    a.t0 = t0;
-    a.gt0 = gt0;
-    a.l0 = (float)l0;
-    a.l1 = (float)l1;
-    a.l2 = (float)l2;
+    a.t0 = nullptr;
+    a.gt0 = nullptr;
+    a.l0 = 0.0f;
+    a.l1 = 0.0f;
+    a.l2 = 1.0f;
+    a.vel = nullptr;
+    a.vel_out = nullptr;
+    a.ncells = 0;
     a.f = fin;
     a.fo = fout;
     a.g = gin;
@@ -685,6 +770,22 @@ int launch_step_interp(const cslbm_level* L, const void* fin, void* fout, const 
     a.inv_tau_s = gin ? (float)(1.0 / L->p.tau_s) : 0.0f;
     for (int k = 0; k < 3; ++k) a.u_in[k] = (float)L->p.u_in[k];
     a.s_in = (float)L->p.s_in;
+    return a;
+}
+
+int launch_step_interp(const cslbm_level* L, const void* fin, void* fout, const float* gin,
+                       float* gout, const void* t0, const float* gt0, double l0, double l1,
+                       double l2, hipStream_t stream)
+{
+    if (L->p.grad_mode != 0)
+        return fail(CSLBM_ERR_UNSUPPORTED,
+                    "the finite-difference gradient mode runs through cslbm_step only");
+    StepArgs a = step_args(L, fin, fout, gin, gout);
+    a.t0 = t0;
+    a.gt0 = gt0;
+    a.l0 = (float)l0;
+    a.l1 = (float)l1;
+    a.l2 = (float)l2;
     const bool has_flags = L->flags != nullptr;
     const bool has_force = L->force != nullptr;
     const bool has_scalar = gin != nullptr;
@@ -748,7 +849,8 @@ int cslbm_init_equilibrium(cslbm_level* L, const float* rho, const float* u, con
     else
         hipLaunchKernelGGL(k_init_eq<_Float16>, grid, block, 0, stream, (_Float16*)L->f, L->g, N,
                            L->plane, rho, u, s);
-    return check_launch("k_init_eq");
+    rc = check_launch("k_init_eq");
+    return rc ? rc : refresh_velocity(L, stream);
 }
 
 int cslbm_set_populations(cslbm_level* L, const float* f, const float* g, int32_t shifted,
@@ -765,7 +867,8 @@ int cslbm_set_populations(cslbm_level* L, const float* f, const float* g, int32_
     else
         hipLaunchKernelGGL(k_set_pop<_Float16>, grid, block, 0, stream, (_Float16*)L->f, L->g, N,
                            L->plane, f, g, shifted);
-    return check_launch("k_set_pop");
+    rc = check_launch("k_set_pop");
+    return rc ? rc : refresh_velocity(L, stream);
 }
 
 int cslbm_get_populations(const cslbm_level* L, float* f, float* g, int32_t shifted,
@@ -795,10 +898,20 @@ int cslbm_step(cslbm_level* L, int32_t n_steps, hipStream_t stream)
     if (!L->f_next) return fail(CSLBM_ERR_ARG, "f_next is NULL");
     if (L->f == L->f_next) return fail(CSLBM_ERR_ARG, "f and f_next alias");
     if (L->g && L->g == L->g_next) return fail(CSLBM_ERR_ARG, "g and g_next alias");
+    const bool grad = L->p.grad_mode == 1;
+    if (grad) {
+        if (L->flags)
+            return fail(CSLBM_ERR_UNSUPPORTED,
+                        "the finite-difference gradient mode needs a fully periodic level without flags");
+        if (!L->vel || !L->vel_next || L->vel == L->vel_next)
+            return fail(CSLBM_ERR_ARG, "grad_mode 1 needs distinct vel and vel_next buffers");
+    }
 
     for (int n = 0; n < n_steps; ++n) {
-        rc = launch_step_into(L, L->f, L->f_next, L->g, L->g_next, stream);
+        rc = grad ? launch_step_grad(L, L->f, L->f_next, L->g, L->g_next, L->vel, L->vel_next, stream)
+                  : launch_step_into(L, L->f, L->f_next, L->g, L->g_next, stream);
         if (rc) return rc;
+        if (grad) std::swap(L->vel, L->vel_next);
         void* t = L->f;
         L->f = L->f_next;
         L->f_next = t;

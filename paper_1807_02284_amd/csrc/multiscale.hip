@@ -364,6 +364,8 @@ int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t s
         rc = validate_params(L);
         if (rc) return fail(rc, "scale %d: %s", i, cslbm_last_error());
         if (!L->f_next || L->f == L->f_next) return fail(CSLBM_ERR_ARG, "scale %d: bad f_next", i);
+        if (L->p.grad_mode != 0)
+            return fail(CSLBM_ERR_UNSUPPORTED, "scale %d: the gradient mode is single-level only", i);
         if ((L->g != nullptr) != scalar)
             return fail(CSLBM_ERR_ARG, "scale %d: every scale or none must carry the scalar", i);
         if (!(L->dx > 0.0)) return fail(CSLBM_ERR_ARG, "scale %d: dx must be positive", i);

@@ -32,11 +32,12 @@ class Params:
     s_ref: float = 0.0
     u_in: tuple = (0.0, 0.0, 0.0)
     s_in: float = 0.0
+    grad_mode: int = 0     # 0: local strain-rate estimate; 1: |grad u|_F by differences
 
     def to_c(self) -> _capi.CslbmParams:
         return _capi.CslbmParams(
             self.nu, (C.c_double * 4)(*self.nu_hi), self.a, self.b, self.g_max,
-            int(self.adaptive), self.tau_s, self.beta, self.s_ref,
+            int(self.adaptive), int(self.grad_mode), self.tau_s, self.beta, self.s_ref,
             (C.c_double * 3)(*self.u_in), self.s_in)
 
 
@@ -93,6 +94,10 @@ class Level:
             self.force = torch.zeros(3, self.plane, dtype=torch.float32, device=self.device)
             self.force[:, : self.n] = ft
             self.force = self.force.reshape(-1)
+        self.vel = self.vel_next = None
+        if self.params.grad_mode == 1:
+            self.vel = torch.zeros(3 * self.n, dtype=torch.float32, device=self.device)
+            self.vel_next = torch.zeros_like(self.vel)
         self.c = _capi.CslbmLevel()
         self.c.nx, self.c.ny, self.c.nz = self.nx, self.ny, self.nz
         self.c.storage = storage
@@ -113,11 +118,20 @@ class Level:
         self.c.flags = _dev_ptr(self.flags)
         self.c.links = _dev_ptr(self.links)
         self.c.force = _dev_ptr(self.force)
+        self.c.vel = _dev_ptr(self.vel)
+        self.c.vel_next = _dev_ptr(self.vel_next)
         self.c.p = self.params.to_c()
 
     def set_params(self, params: Params):
         self.params = params
         self.c.p = params.to_c()
+        if params.grad_mode == 1 and self.vel is None:
+            # the velocity of the current state, as the gradient mode needs it
+            self.vel = torch.zeros(3 * self.n, dtype=torch.float32, device=self.device)
+            self.vel_next = torch.zeros_like(self.vel)
+            self._sync_struct()
+            _capi.call("cslbm_read_macro", C.byref(self.c), None, _dev_ptr(self.vel), None,
+                       _stream_handle())
 
     def set_flags(self, flags):
         fl = torch.as_tensor(np.asarray(flags, dtype=np.uint8)).to(self.device).reshape(-1)
@@ -167,6 +181,8 @@ class Level:
             self.f, self.f_next = self.f_next, self.f
             if self.g is not None:
                 self.g, self.g_next = self.g_next, self.g
+            if self.vel is not None:
+                self.vel, self.vel_next = self.vel_next, self.vel
         assert self.c.f == self.f.data_ptr()
 
     def read_macro(self, stream=None):

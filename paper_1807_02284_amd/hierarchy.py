@@ -13,6 +13,7 @@ import math
 
 import numpy as np
 import torch
+from scipy import ndimage
 
 from . import _capi
 from .level import Level, Params, _stream_handle
@@ -379,3 +380,140 @@ def dynamic_hierarchy(lev0: Level, kinds0: np.ndarray, thresholds, alphas, *, ma
         hi_lim = [hi[a] - nest for a in range(3)]
     torch.cuda.synchronize()
     return Hierarchy(levels, kinds), boxes
+
+
+# ---------------------------------------------------------------------------
+# static scale construction (section "Scale construction", static scales)
+# ---------------------------------------------------------------------------
+def object_distance(kinds: np.ndarray, shape, periodic: int = 0, faces: bool = True) -> np.ndarray:
+    """Distance (reference cells) from every cell to the nearest SOLID cell or
+    non-periodic box face, by an exact Euclidean distance transform.  With
+    faces=False only objects count: SOLID cells on the box faces (walls)
+    and the faces themselves are ignored."""
+    nx, ny, nz = shape
+    solid = np.asarray(kinds).reshape(nz, ny, nx) == _capi.SOLID
+    if not faces:
+        solid = solid.copy()
+        solid[:, :, 0] = solid[:, :, -1] = False
+        solid[:, 0, :] = solid[:, -1, :] = False
+        solid[0, :, :] = solid[-1, :, :] = False
+        if not solid.any():
+            return np.full(nx * ny * nz, np.inf)
+        periodic = 7
+    free = ~solid
+    pad = [(0 if periodic & (1 << a) else 1) for a in (2, 1, 0)]
+    if any(pad):
+        free = np.pad(free, [(p, p) for p in pad], constant_values=False)
+    d = ndimage.distance_transform_edt(free)
+    sl = tuple(slice(p, d.shape[i] - p) for i, p in enumerate(pad))
+    return d[sl].reshape(-1)
+
+
+def wake_shadow(kinds: np.ndarray, shape, inlet_center, inlet_radius: float, *,
+                samples: int = 16, coarsen: int = 8) -> np.ndarray:
+    """Soft shadow of the objects lit by the inlet disk on the x = 0 face (an
+    area light): per cell, the fraction of `samples` points of the disk
+    whose straight segment to the cell passes through a SOLID cell that is
+    not on a box face.  1 in the umbra, between 0 and 1 in the penumbra.
+    Computed on a grid coarsened by `coarsen` and sampled back."""
+    nx, ny, nz = shape
+    k = np.asarray(kinds).reshape(nz, ny, nx)
+    obj = k == _capi.SOLID
+    obj[:, :, 0] = obj[:, :, -1] = False
+    obj[:, 0, :] = obj[:, -1, :] = False
+    obj[0, :, :] = obj[-1, :, :] = False
+    c = coarsen
+    cz, cy, cx = -(-nz // c), -(-ny // c), -(-nx // c)
+    occ = np.zeros((cz, cy, cx), bool)
+    zz, yy, xx = np.nonzero(obj)
+    occ[zz // c, yy // c, xx // c] = True
+    # disk samples: a golden-angle spiral over the disk
+    j = np.arange(samples) + 0.5
+    rad = inlet_radius * np.sqrt(j / samples)
+    ang = j * np.pi * (3.0 - np.sqrt(5.0))
+    qy, qz = inlet_center[0] + rad * np.cos(ang), inlet_center[1] + rad * np.sin(ang)
+    gz, gy, gx = np.meshgrid((np.arange(cz) + 0.5) * c, (np.arange(cy) + 0.5) * c,
+                             (np.arange(cx) + 0.5) * c, indexing="ij")
+    px, py, pz = gx.reshape(-1), gy.reshape(-1), gz.reshape(-1)
+    hit = np.zeros(px.size)
+    n_march = 2 * cx
+    for s in range(samples):
+        blocked = np.zeros(px.size, bool)
+        for t in (np.arange(n_march) + 0.5) / n_march:
+            x = t * px
+            y = qy[s] + t * (py - qy[s])
+            z = qz[s] + t * (pz - qz[s])
+            ix = np.clip((x // c).astype(np.int64), 0, cx - 1)
+            iy = np.clip((y // c).astype(np.int64), 0, cy - 1)
+            iz = np.clip((z // c).astype(np.int64), 0, cz - 1)
+            blocked |= occ[iz, iy, ix]
+        hit += blocked
+    frac = (hit / samples).reshape(cz, cy, cx)
+    z, y, x = np.meshgrid(np.arange(nz) // c, np.arange(ny) // c, np.arange(nx) // c, indexing="ij")
+    return frac[z, y, x].reshape(-1)
+
+
+def static_levels(kinds: np.ndarray, shape, n_scales: int, d_max: float, *, periodic: int = 0,
+                  faces: bool = True, inlet_center=None, inlet_radius: float = 0.0,
+                  shadow_samples: int = 16, shadow_coarsen: int = 8) -> np.ndarray:
+    """Scale index per cell (0 = the reference scale, n_scales - 1 = the
+    finest): the distance to objects (and box faces unless faces=False),
+    normalised by d_max and lowered in the objects' wake (soft shadow of
+    the inlet), quantised into n_scales levels.  SOLID cells get level 0."""
+    ind = np.clip(object_distance(kinds, shape, periodic, faces) / d_max, 0.0, 1.0)
+    if inlet_center is not None and inlet_radius > 0.0:
+        ind = np.minimum(ind, 1.0 - wake_shadow(kinds, shape, inlet_center, inlet_radius,
+                                                samples=shadow_samples, coarsen=shadow_coarsen))
+    lev = np.floor((1.0 - ind) * n_scales).astype(np.int64)
+    lev = np.clip(lev, 0, n_scales - 1)
+    lev[np.asarray(kinds) == _capi.SOLID] = 0
+    return lev
+
+
+def static_boxes(levels: np.ndarray, shape, n_scales: int, *, dilate: int = 2, margin: int = 3,
+                 nest: int = 2):
+    """Nested boxes (inclusive reference-cell bounds) of the cells at or
+    above each level 1..n_scales-1; a level whose region is empty or
+    degenerate ends the list."""
+    nx, ny, nz = shape
+    lv = levels.reshape(nz, ny, nx)
+    lo_lim = [margin] * 3
+    hi_lim = [shape[a] - 1 - margin for a in range(3)]
+    boxes = []
+    for k in range(1, n_scales):
+        zs, ys, xs = np.nonzero(lv >= k)
+        if xs.size == 0:
+            break
+        lo = [max(xs.min() - dilate, lo_lim[0]), max(ys.min() - dilate, lo_lim[1]),
+              max(zs.min() - dilate, lo_lim[2])]
+        hi = [min(xs.max() + dilate, hi_lim[0]), min(ys.max() + dilate, hi_lim[1]),
+              min(zs.max() + dilate, hi_lim[2])]
+        if any(h - l < 3 for l, h in zip(lo, hi)):
+            break
+        boxes.append((lo, hi))
+        lo_lim = [lo[a] + nest for a in range(3)]
+        hi_lim = [hi[a] - nest for a in range(3)]
+    return boxes
+
+
+def static_hierarchy(lev0: Level, kinds0: np.ndarray, n_scales: int, dx_min: float, d_max: float,
+                     *, faces: bool = True, inlet_center=None, inlet_radius: float = 0.0,
+                     solid_fn=None, stream=None, **kw):
+    """Scales set by the domain geometry: levels from `static_levels`, boxes
+    from `static_boxes`, spacings interpolated linearly from 1 (the
+    reference) to dx_min (the finest), each scale filled from its parent.
+    Returns (Hierarchy, boxes, spacings)."""
+    shape = (lev0.nx, lev0.ny, lev0.nz)
+    lv = static_levels(kinds0, shape, n_scales, d_max, periodic=lev0.c.periodic, faces=faces,
+                       inlet_center=inlet_center, inlet_radius=inlet_radius)
+    boxes = static_boxes(lv, shape, n_scales, **kw)
+    spacings = [1.0 + (dx_min - 1.0) * k / (n_scales - 1) for k in range(1, n_scales)]
+    levels, kinds = [lev0], [np.asarray(kinds0, np.uint8)]
+    for (lo, hi), dx in zip(boxes, spacings):
+        lev, k = fine_scale(lo, hi, 1.0 / dx, lev0.params, solid_fn, scalar=lev0.g is not None,
+                            storage=lev0.storage)
+        fill_from_parent(levels[-1], lev, stream)
+        levels.append(lev)
+        kinds.append(k)
+    torch.cuda.synchronize()
+    return Hierarchy(levels, kinds), boxes, spacings[:len(boxes)]

@@ -21,10 +21,11 @@ def oparams_grad(p: Params) -> oracle.Params:
     return op
 
 
-@pytest.mark.parametrize("g_max", [0.002, 0.05])
+@pytest.mark.parametrize("g_max", [0.022, 0.1])
 def test_gradient_mode_ten_steps_match_oracle(g_max):
-    """Smooth seeded start with per-cell noise; g_max 0.002 puts part of the
-    box on the clamp, 0.05 none of it."""
+    """Smooth seeded start with per-cell noise (|grad u| from 0.004 to 0.042,
+    median 0.022): g_max 0.022 puts about half of the box on the clamp, 0.1
+    none of it."""
     nx, ny, nz = 40, 18, 11
     n = nx * ny * nz
     p = Params(nu=2e-3, g_max=g_max, grad_mode=1)
@@ -36,8 +37,10 @@ def test_gradient_mode_ten_steps_match_oracle(g_max):
     lev = Level(nx, ny, nz, p)
     lev.set_populations(f0 - W[:, None], shifted=True)
     G = oracle.grad_field(dom, oparams_grad(p), f0)
-    if g_max < 0.01:
-        assert np.mean(G > g_max) > 0.1 and np.mean(G < g_max) > 0.1
+    if g_max < 0.05:
+        assert np.mean(G > g_max) > 0.3 and np.mean(G < g_max) > 0.3
+    else:
+        assert np.all(G < g_max)
     lev.step(10)
     ref, _ = oracle.step(dom, oparams_grad(p), f0, n_steps=10)
     got, _ = gpu_f64(lev)

@@ -154,6 +154,17 @@ int cslbm_init_equilibrium(cslbm_level* L, const float* rho, const float* u, con
 int cslbm_set_populations(cslbm_level* L, const float* f, const float* g, int32_t shifted,
                           hipStream_t stream);
 
+/* Copy the state (f, and g when both carry the scalar) of the listed cells
+ * of src to the listed cells of dst: dst cell dst_cells[k] receives src cell
+ * src_cells[k] (device int32 lists of n_cells entries, each inside its
+ * level; dst_cells distinct).  Both levels must use one storage format.
+ * Used when a dynamic region is rebuilt (section "Scale construction",
+ * dynamic scales): cells in both the old and the new box of a scale keep
+ * their state.  Errors: CSLBM_ERR_UNSUPPORTED for mixed storage,
+ * CSLBM_ERR_ARG for bad lists, aliasing states or a scalar on one side. */
+int cslbm_copy_cells(const cslbm_level* src, const int32_t* src_cells, cslbm_level* dst,
+                     const int32_t* dst_cells, int32_t n_cells, hipStream_t stream);
+
 /* Copy L->f out to a dense [27][N] float array (physical f_i, or f_i - w_i
  * when shifted != 0), and L->g to g when both are non-NULL. */
 int cslbm_get_populations(const cslbm_level* L, float* f, float* g, int32_t shifted,

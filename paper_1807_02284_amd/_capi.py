@@ -96,6 +96,8 @@ _SIGNATURES = {
     "cslbm_init_equilibrium": (C.c_int, [C.POINTER(CslbmLevel), _vp, _vp, _vp, _vp]),
     "cslbm_set_populations": (C.c_int, [C.POINTER(CslbmLevel), _vp, _vp, C.c_int32, _vp]),
     "cslbm_get_populations": (C.c_int, [C.POINTER(CslbmLevel), _vp, _vp, C.c_int32, _vp]),
+    "cslbm_copy_cells": (C.c_int, [C.POINTER(CslbmLevel), _vp, C.POINTER(CslbmLevel), _vp,
+                                   C.c_int32, _vp]),
     "cslbm_step": (C.c_int, [C.POINTER(CslbmLevel), C.c_int32, _vp]),
     "cslbm_read_macro": (C.c_int, [C.POINTER(CslbmLevel), _vp, _vp, _vp, _vp]),
     "cslbm_vorticity": (C.c_int, [C.POINTER(CslbmLevel), _vp, _vp, _vp]),

@@ -378,6 +378,23 @@ __global__ void k_set_pop(T* f, float* g, int64_t N, int64_t P, const float* src
         for (int i = 0; i < QS; ++i) g[i * P + c] = gsrc[i * N + c];
 }
 
+// Population copy between two levels of one storage type, cell list to
+// cell list (the kept part of a rebuilt region).  One thread per cell.
+template <typename T>
+__global__ void __launch_bounds__(256) k_copy_cells(const T* f, const float* g, int64_t P, T* fo,
+                                                    float* go, int64_t Po, const int32_t* src,
+                                                    const int32_t* dst, int n)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t a = src[k], b = dst[k];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) fo[i * Po + b] = f[i * P + a];
+    if (g)
+#pragma unroll
+        for (int i = 0; i < QS; ++i) go[i * Po + b] = g[i * P + a];
+}
+
 template <typename T>
 __global__ void k_get_pop(const T* f, const float* g, int64_t N, int64_t P, float* dst, float* gdst,
                           int shifted)
@@ -886,6 +903,33 @@ int cslbm_get_populations(const cslbm_level* L, float* f, float* g, int32_t shif
         hipLaunchKernelGGL(k_get_pop<_Float16>, grid, block, 0, stream, (const _Float16*)L->f, L->g,
                            N, L->plane, f, g, shifted);
     return check_launch("k_get_pop");
+}
+
+int cslbm_copy_cells(const cslbm_level* src, const int32_t* src_cells, cslbm_level* dst,
+                     const int32_t* dst_cells, int32_t n_cells, hipStream_t stream)
+{
+    int rc = validate_shape(src);
+    if (rc) return rc;
+    rc = validate_shape(dst);
+    if (rc) return rc;
+    if (src->storage != dst->storage)
+        return fail(CSLBM_ERR_UNSUPPORTED, "copying between storage formats is not supported");
+    if (n_cells < 0 || (n_cells > 0 && (!src_cells || !dst_cells)))
+        return fail(CSLBM_ERR_ARG, "bad cell lists");
+    if ((src->g != nullptr) != (dst->g != nullptr))
+        return fail(CSLBM_ERR_ARG, "both levels or neither must carry the scalar");
+    if (src->f == dst->f) return fail(CSLBM_ERR_ARG, "source and destination states alias");
+    if (n_cells == 0) return CSLBM_OK;
+    const dim3 grid(blocks_for(n_cells, 256)), block(256);
+    if (src->storage == CSLBM_F32)
+        hipLaunchKernelGGL(k_copy_cells<float>, grid, block, 0, stream, (const float*)src->f, src->g,
+                           src->plane, (float*)dst->f, dst->g, dst->plane, src_cells, dst_cells,
+                           n_cells);
+    else
+        hipLaunchKernelGGL(k_copy_cells<_Float16>, grid, block, 0, stream, (const _Float16*)src->f,
+                           src->g, src->plane, (_Float16*)dst->f, dst->g, dst->plane, src_cells,
+                           dst_cells, n_cells);
+    return check_launch("k_copy_cells");
 }
 
 int cslbm_step(cslbm_level* L, int32_t n_steps, hipStream_t stream)

@@ -352,13 +352,51 @@ def fill_from_parent(parent: Level, lev: Level, stream=None):
                lev.g.data_ptr() if g_ok else None, cells.data_ptr(), lev.n, _stream_handle(stream))
 
 
+def kept_cells(old: Level, old_kinds: np.ndarray, new: Level, new_kinds: np.ndarray):
+    """(old cells, new cells) of the FLUID cells two boxes of one scale share:
+    both boxes lie on the global lattice of spacing dx (origins i0 dx), so a
+    cell is the same lattice point in both when its global index matches."""
+    dx = new.c.dx
+    o_old = [int(round(old.c.origin[a] / dx)) for a in range(3)]
+    o_new = [int(round(new.c.origin[a] / dx)) for a in range(3)]
+    shp_old, shp_new = (old.nx, old.ny, old.nz), (new.nx, new.ny, new.nz)
+    lo = [max(o_old[a], o_new[a]) for a in range(3)]
+    hi = [min(o_old[a] + shp_old[a], o_new[a] + shp_new[a]) for a in range(3)]
+    if any(h <= l for l, h in zip(lo, hi)):
+        return np.zeros(0, np.int32), np.zeros(0, np.int32)
+    gz, gy, gx = np.meshgrid(np.arange(lo[2], hi[2]), np.arange(lo[1], hi[1]),
+                             np.arange(lo[0], hi[0]), indexing="ij")
+    gx, gy, gz = gx.reshape(-1), gy.reshape(-1), gz.reshape(-1)
+    c_old = (gx - o_old[0]) + shp_old[0] * ((gy - o_old[1]) + shp_old[1] * (gz - o_old[2]))
+    c_new = (gx - o_new[0]) + shp_new[0] * ((gy - o_new[1]) + shp_new[1] * (gz - o_new[2]))
+    keep = (old_kinds[c_old] == FLUID) & (new_kinds[c_new] == FLUID)
+    return c_old[keep].astype(np.int32), c_new[keep].astype(np.int32)
+
+
+def copy_cells(src: Level, src_cells: np.ndarray, dst: Level, dst_cells: np.ndarray, stream=None):
+    a = torch.as_tensor(np.asarray(src_cells, np.int32), device=dst.device)
+    b = torch.as_tensor(np.asarray(dst_cells, np.int32), device=dst.device)
+    src._sync_struct()
+    dst._sync_struct()
+    _capi.call("cslbm_copy_cells", C.byref(src.c), a.data_ptr(), C.byref(dst.c), b.data_ptr(),
+               int(a.numel()), _stream_handle(stream))
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+
+
 def dynamic_hierarchy(lev0: Level, kinds0: np.ndarray, thresholds, alphas, *, margin: int = 3,
-                      dilate: int = 2, nest: int = 2, solid_fn=None, stream=None):
+                      dilate: int = 2, nest: int = 2, solid_fn=None, stream=None, previous=None):
     """Scales set by thresholds: scale k covers the bounding box of the cells
     with |curl u| > thresholds[k-1][0] and |u| > thresholds[k-1][1]
     (dilated), kept `margin` cells from the domain faces and `nest` cells
     inside its parent; spacing 1/alphas[k-1].  Returns (Hierarchy, boxes);
-    scales whose region is empty are left out."""
+    scales whose region is empty are left out.
+
+    With `previous` (a Hierarchy built by this function on the same
+    reference scale) the regions are rebuilt, as the dynamic construction
+    repeats every 40 iterations: every cell of a new scale first takes the
+    full prior-mapping from its (new) parent, then the FLUID cells the old
+    and the new box of that scale share keep their old state; cells that
+    leave a region are dropped with the old levels."""
     om, sp = lev0.vorticity(stream)
     omega, speed = om.cpu().numpy(), sp.cpu().numpy()
     shape = (lev0.nx, lev0.ny, lev0.nz)
@@ -373,6 +411,11 @@ def dynamic_hierarchy(lev0: Level, kinds0: np.ndarray, thresholds, alphas, *, ma
         lev, k = fine_scale(lo, hi, alpha, lev0.params, solid_fn, scalar=lev0.g is not None,
                             storage=lev0.storage)
         fill_from_parent(levels[-1], lev, stream)
+        i = len(levels)
+        if previous is not None and i < len(previous.levels) and \
+                abs(previous.levels[i].c.dx - lev.c.dx) < 1e-12:
+            src, dst = kept_cells(previous.levels[i], previous.kinds[i], lev, k)
+            copy_cells(previous.levels[i], src, lev, dst, stream)
         levels.append(lev)
         kinds.append(k)
         boxes.append((lo, hi))

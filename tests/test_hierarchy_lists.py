@@ -110,3 +110,30 @@ def test_dropping_overwritten_post_cells_leaves_the_oracle_state_bit_identical()
     ml.multiscale_step(red, 2)
     for a, b in zip(full, red):
         np.testing.assert_array_equal(a.f, b.f)
+
+
+def test_kept_cells_pair_the_same_lattice_points_of_two_boxes():
+    from types import SimpleNamespace
+
+    dx = 1 / 1.5
+
+    def box(i0, shape):
+        c = SimpleNamespace(dx=dx, origin=tuple(i * dx for i in i0))
+        kinds = hierarchy.shell_flags(*shape)
+        return SimpleNamespace(c=c, nx=shape[0], ny=shape[1], nz=shape[2]), kinds
+
+    old, ko = box((10, 4, 7), (12, 9, 8))
+    new, kn = box((14, 2, 9), (11, 10, 9))
+    src, dst = hierarchy.kept_cells(old, ko, new, kn)
+    assert src.size > 0
+    # brute force over the new box
+    pairs = set()
+    for c in np.flatnonzero(kn == hierarchy.FLUID):
+        x, y, z = c % 11, (c // 11) % 10, c // 110
+        g = (x + 14, y + 2, z + 9)
+        lx, ly, lz = g[0] - 10, g[1] - 4, g[2] - 7
+        if 0 <= lx < 12 and 0 <= ly < 9 and 0 <= lz < 8:
+            co = lx + 12 * (ly + 9 * lz)
+            if ko[co] == hierarchy.FLUID:
+                pairs.add((co, c))
+    assert pairs == set(zip(src.tolist(), dst.tolist()))

@@ -270,6 +270,15 @@ def run_plume(nx: int, ny: int, nz: int, spinup: int, n_ref: int):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / n_ref
+    # the dynamic construction repeats every 40 reference steps: rebuild the
+    # regions from the current flow (new cells mapped from the parent,
+    # shared cells kept), timed on its own (host construction + GPU fill)
+    t0 = time.perf_counter()
+    H, boxes2 = hierarchy.dynamic_hierarchy(lev0, flags, ((2e-3, 0.01), (8e-3, 0.02)), (1.5, 2.0),
+                                            solid_fn=sphere, previous=H)
+    rebuild_s = time.perf_counter() - t0
+    H.step(2)
+    torch.cuda.synchronize()
     bad = sum(lv.count_nonfinite() for lv in H.levels)
     out = {
         "reference_box": [nx, ny, nz],
@@ -282,6 +291,10 @@ def run_plume(nx: int, ny: int, nz: int, spinup: int, n_ref: int):
         "coverage_of_reference_volume": [
             float(np.prod([hi[a] - lo[a] + 1 for a in range(3)]) / n0) for lo, hi in boxes],
         "ms_per_reference_step": ms,
+        "region_rebuild_s": rebuild_s,
+        "boxes_after_rebuild_level0_units": [[list(map(int, lo)), list(map(int, hi))]
+                                             for lo, hi in boxes2],
+        "ms_per_reference_step_with_rebuild_every_40": ms + rebuild_s * 1e3 / n_ref,
         "lattice_updates_per_reference_step": lups,
         "mlups_all_scales": lups / (ms * 1e-3) / 1e6,
         "reference_scale_step_ms": ms0 / spinup,
@@ -394,6 +407,10 @@ def run_far_field(nx: int, ny: int, nz: int, pad: int, spinup: int, n_ref: int):
         "reference_shell_cells": int(np.count_nonzero(kinds == _capi.GHOST)),
         "cells_per_scale": cells,
         "ms_per_reference_step": ms,
+        "region_rebuild_s": rebuild_s,
+        "boxes_after_rebuild_level0_units": [[list(map(int, lo)), list(map(int, hi))]
+                                             for lo, hi in boxes2],
+        "ms_per_reference_step_with_rebuild_every_40": ms + rebuild_s * 1e3 / n_ref,
         "mlups_all_scales": sum(cells) / (ms * 1e-3) / 1e6,
         "reference_scale_step_ms": ms0,
         "nonfinite": int(bad),

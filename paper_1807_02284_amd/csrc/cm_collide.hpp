@@ -166,6 +166,18 @@ __host__ __device__ __forceinline__ void moments0(const float (&v)[27], float& d
     jz = sz[2] - sz[0];
 }
 
+// Reciprocal: the hardware v_rcp_f32 on the device (about 1 ulp; measured
+// faster than the correctly rounded division in the binary16 kernel, same
+// in the FP32 one), the plain division on the host.
+__host__ __device__ __forceinline__ float rcp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+
 struct CellMacro {
     float rho, ux, uy, uz, G, phi;
 };
@@ -182,7 +194,7 @@ __host__ __device__ __forceinline__ CellMacro cm_collide(float (&v)[27], const R
     float dr, jx, jy, jz;
     moments0(v, dr, jx, jy, jz);
     const float rho = 1.0f + dr;
-    const float inv_rho = 1.0f / rho;
+    const float inv_rho = rcp(rho);
     const float ux = (jx + 0.5f * Fx) * inv_rho;
     const float uy = (jy + 0.5f * Fy) * inv_rho;
     const float uz = (jz + 0.5f * Fz) * inv_rho;
@@ -208,7 +220,7 @@ __host__ __device__ __forceinline__ CellMacro cm_collide(float (&v)[27], const R
     if (r.adaptive) phi = r.a * fminf(G * r.inv_gmax, 1.0f) + r.b;
     float om[4];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) om[g] = active ? 1.0f - 1.0f / (phi * r.nu3[g] + 0.5f) : 1.0f;
+    for (int g = 0; g < 4; ++g) om[g] = active ? 1.0f - rcp(phi * r.nu3[g] + 0.5f) : 1.0f;
     const float om_s = active ? 1.0f - r.S : 1.0f;
 
     // relax: dk* = D + (1 - S)(dk - D); conserved moments unchanged, +F

@@ -39,6 +39,14 @@ def _stencil(points: np.ndarray, origin, dx, n):
     return base, q - base
 
 
+def _axis_stencil(lo: int, hi: int, c_origin: float, c_dx: float, f_origin: float, f_dx: float):
+    """Trilinear stencil along one axis for coarse indices lo..hi: base fine
+    index and fraction (the stencil is separable per axis)."""
+    q = (c_origin + np.arange(lo, hi + 1) * c_dx - f_origin) / f_dx
+    b = np.floor(q)
+    return b.astype(np.int64), q - b
+
+
 def post_cells(coarse_kinds: np.ndarray, coarse_shape, coarse_origin, coarse_dx,
                fine_kinds: np.ndarray, fine_shape, fine_origin, fine_dx) -> np.ndarray:
     """Cells of the coarse scale whose position has a trilinear stencil (the
@@ -51,29 +59,27 @@ def post_cells(coarse_kinds: np.ndarray, coarse_shape, coarse_origin, coarse_dx,
           for a in range(3)]
     if any(h < l for l, h in zip(lo, hi)):
         return np.zeros(0, np.int32)
-    zz, yy, xx = np.meshgrid(np.arange(lo[2], hi[2] + 1), np.arange(lo[1], hi[1] + 1),
-                             np.arange(lo[0], hi[0] + 1), indexing="ij")
-    xx, yy, zz = xx.reshape(-1), yy.reshape(-1), zz.reshape(-1)
-    cells = xx + cnx * (yy + cny * zz)
-    keep = coarse_kinds[cells] == FLUID
-    cells, xx, yy, zz = cells[keep], xx[keep], yy[keep], zz[keep]
-    pts = np.stack([coarse_origin[0] + xx * coarse_dx, coarse_origin[1] + yy * coarse_dx,
-                    coarse_origin[2] + zz * coarse_dx])
-    base, t = _stencil(pts, fine_origin, fine_dx, fine_shape)
-    ok = np.ones(cells.size, bool)
+    ax = [_axis_stencil(lo[a], hi[a], coarse_origin[a], coarse_dx, fine_origin[a], fine_dx)
+          for a in range(3)]
+    ck = np.asarray(coarse_kinds).reshape(cnz, cny, cnx)
+    ok = ck[lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1] == FLUID
+    fk = np.asarray(fine_kinds).reshape(fnz, fny, fnx) == FLUID
+    fn = (fnx, fny, fnz)
     for corner in range(8):
-        o = np.array([corner & 1, (corner >> 1) & 1, (corner >> 2) & 1])
-        wt = np.ones(cells.size)
+        o = (corner & 1, (corner >> 1) & 1, (corner >> 2) & 1)
+        idx, inside, need = [], [], []
         for a in range(3):
-            wt *= t[a] if o[a] else 1.0 - t[a]
-        idx = base + o[:, None]
-        inside = ((idx[0] >= 0) & (idx[0] < fnx) & (idx[1] >= 0) & (idx[1] < fny) &
-                  (idx[2] >= 0) & (idx[2] < fnz))
-        fc = np.clip(idx[0], 0, fnx - 1) + fnx * (np.clip(idx[1], 0, fny - 1) +
-                                                  fny * np.clip(idx[2], 0, fnz - 1))
-        good = inside & (fine_kinds[fc] == FLUID)
-        ok &= good | (wt == 0.0)
-    return cells[ok].astype(np.int32)
+            b, t = ax[a]
+            i = b + o[a]
+            idx.append(np.clip(i, 0, fn[a] - 1))
+            inside.append((i >= 0) & (i < fn[a]))
+            need.append(np.ones(b.size, bool) if o[a] == 0 else t != 0.0)   # weight != 0
+        good = fk[np.ix_(idx[2], idx[1], idx[0])]
+        good &= inside[2][:, None, None] & inside[1][None, :, None] & inside[0][None, None, :]
+        needed = need[2][:, None, None] & need[1][None, :, None] & need[0][None, None, :]
+        ok &= good | ~needed
+    zz, yy, xx = np.nonzero(ok)
+    return ((xx + lo[0]) + cnx * ((yy + lo[1]) + cny * (zz + lo[2]))).astype(np.int32)
 
 
 def check_prior_stencils(parent_kinds, parent_shape, parent_origin, parent_dx, parent_periodic,
@@ -142,13 +148,15 @@ def drop_overwritten_posts(post: dict, n: int) -> dict:
     the earlier list gives the same final state without the duplicate work."""
     out = {}
     for j in range(n):
-        later = np.zeros(0, np.int32)
-        for i in range(n - 1, j, -1):
-            if (i, j) not in post:
-                continue
+        keys = [i for i in range(n - 1, j, -1) if (i, j) in post]
+        if not keys:
+            continue
+        size = 1 + max(int(np.max(post[(i, j)])) if len(post[(i, j)]) else 0 for i in keys)
+        later = np.zeros(size, bool)
+        for i in keys:
             cells = np.asarray(post[(i, j)], np.int32)
-            out[(i, j)] = np.setdiff1d(cells, later).astype(np.int32)
-            later = np.union1d(later, cells).astype(np.int32)
+            out[(i, j)] = cells[~later[cells]]
+            later[cells] = True
     return out
 
 
@@ -291,16 +299,21 @@ def fine_scale(lo, hi, alpha: float, params0: Params, solid_fn=None, *, scalar: 
     nxp = -(-inner_shape[0] // row_align) * row_align
     shape = (nxp, inner_shape[1], inner_shape[2])
     origin = tuple(i0[a] * dx for a in range(3))
-    z, y, x = np.meshgrid(np.arange(shape[2]), np.arange(shape[1]), np.arange(shape[0]),
-                          indexing="ij")
-    x, y, z = x.reshape(-1), y.reshape(-1), z.reshape(-1)
-    inner = np.zeros(x.size, np.uint8)
+    # per-axis coordinates broadcast over the box (solid_fn is elementwise)
+    k3 = np.zeros((shape[2], shape[1], shape[0]), np.uint8)
     if solid_fn is not None:
-        inner[solid_fn(origin[0] + x * dx, origin[1] + y * dx, origin[2] + z * dx)] = _capi.SOLID
+        px = origin[0] + np.arange(shape[0]) * dx
+        py = origin[1] + np.arange(shape[1]) * dx
+        pz = origin[2] + np.arange(shape[2]) * dx
+        solid = np.broadcast_to(solid_fn(px[None, None, :], py[None, :, None], pz[:, None, None]),
+                                k3.shape)
+        k3[solid] = _capi.SOLID
     nx0 = inner_shape[0]
-    kinds = np.where((x == 0) | (x == nx0 - 1) | (y == 0) | (y == shape[1] - 1) | (z == 0) |
-                     (z == shape[2] - 1), GHOST, inner).astype(np.uint8)
-    kinds[x >= nx0] = _capi.SOLID
+    k3[:, :, 0] = k3[:, :, nx0 - 1] = GHOST
+    k3[:, 0, :] = k3[:, -1, :] = GHOST
+    k3[0, :, :] = k3[-1, :, :] = GHOST
+    k3[:, :, nx0:] = _capi.SOLID
+    kinds = k3.reshape(-1)
     p = Params(**{**params0.__dict__})
     p.nu = params0.nu * alpha
     p.tau_s = 0.5 + alpha * (params0.tau_s - 0.5)
@@ -364,11 +377,14 @@ def kept_cells(old: Level, old_kinds: np.ndarray, new: Level, new_kinds: np.ndar
     hi = [min(o_old[a] + shp_old[a], o_new[a] + shp_new[a]) for a in range(3)]
     if any(h <= l for l, h in zip(lo, hi)):
         return np.zeros(0, np.int32), np.zeros(0, np.int32)
-    gz, gy, gx = np.meshgrid(np.arange(lo[2], hi[2]), np.arange(lo[1], hi[1]),
-                             np.arange(lo[0], hi[0]), indexing="ij")
-    gx, gy, gz = gx.reshape(-1), gy.reshape(-1), gz.reshape(-1)
-    c_old = (gx - o_old[0]) + shp_old[0] * ((gy - o_old[1]) + shp_old[1] * (gz - o_old[2]))
-    c_new = (gx - o_new[0]) + shp_new[0] * ((gy - o_new[1]) + shp_new[1] * (gz - o_new[2]))
+    gx, gy, gz = (np.arange(lo[a], hi[a]) for a in range(3))
+
+    def cells(o, shp):
+        return ((gx - o[0])[None, None, :] +
+                shp[0] * ((gy - o[1])[None, :, None] + shp[1] * (gz - o[2])[:, None, None]))
+
+    c_old = cells(o_old, shp_old).reshape(-1)
+    c_new = cells(o_new, shp_new).reshape(-1)
     keep = (old_kinds[c_old] == FLUID) & (new_kinds[c_new] == FLUID)
     return c_old[keep].astype(np.int32), c_new[keep].astype(np.int32)
 

@@ -271,11 +271,14 @@ def region_box(omega: np.ndarray, speed: np.ndarray, shape, thresholds, dilate: 
     and clipped to [lo_limit, hi_limit]; None when no cell passes."""
     nx, ny, nz = shape
     w = ((np.asarray(omega) > thresholds[0]) & (np.asarray(speed) > thresholds[1])).reshape(nz, ny, nx)
-    if not w.any():
+    # the bounding box from the three projections of the mask
+    xs = np.flatnonzero(w.any(axis=(0, 1)))
+    if xs.size == 0:
         return None
-    zs, ys, xs = np.nonzero(w)
-    lo = [xs.min() - dilate, ys.min() - dilate, zs.min() - dilate]
-    hi = [xs.max() + dilate, ys.max() + dilate, zs.max() + dilate]
+    ys = np.flatnonzero(w.any(axis=(0, 2)))
+    zs = np.flatnonzero(w.any(axis=(1, 2)))
+    lo = [int(xs[0]) - dilate, int(ys[0]) - dilate, int(zs[0]) - dilate]
+    hi = [int(xs[-1]) + dilate, int(ys[-1]) + dilate, int(zs[-1]) + dilate]
     lo = [max(lo[a], lo_limit[a]) for a in range(3)]
     hi = [min(hi[a], hi_limit[a]) for a in range(3)]
     if any(h - l < 3 for l, h in zip(lo, hi)):

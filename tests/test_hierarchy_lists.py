@@ -137,3 +137,25 @@ def test_kept_cells_pair_the_same_lattice_points_of_two_boxes():
             if ko[co] == hierarchy.FLUID:
                 pairs.add((co, c))
     assert pairs == set(zip(src.tolist(), dst.tolist()))
+
+
+def test_region_box_is_the_dilated_clipped_bounding_box_of_both_thresholds():
+    rng = np.random.default_rng(5)
+    shape = (30, 20, 16)
+    n = int(np.prod(shape))
+    x, y, z = inputs.grid_coords(*shape)
+    om = rng.random(n) * 1e-3
+    sp = rng.random(n) * 1e-2
+    blob = (np.abs(x - 17) < 5) & (np.abs(y - 9) < 4) & (np.abs(z - 6) < 3)
+    om[blob] += 0.01
+    sp[blob] += 0.05
+    sp[(x == 20) & (y == 10) & (z == 7)] = 0.0          # fails the speed threshold
+    om[(x == 3) & (y == 3) & (z == 3)] = 1.0            # passes vorticity, not speed
+    box = hierarchy.region_box(om, sp, shape, (5e-3, 2e-2), 2, [2, 2, 2], [27, 17, 13])
+    sel = (om > 5e-3) & (sp > 2e-2)
+    lo = [max(x[sel].min() - 2, 2), max(y[sel].min() - 2, 2), max(z[sel].min() - 2, 2)]
+    hi = [min(x[sel].max() + 2, 27), min(y[sel].max() + 2, 17), min(z[sel].max() + 2, 13)]
+    assert box == (lo, hi)
+    assert hierarchy.region_box(om, sp, shape, (1.0, 1.0), 2, [2, 2, 2], [27, 17, 13]) is None
+    # a region thinner than 3 cells after clipping is dropped
+    assert hierarchy.region_box(om, sp, shape, (5e-3, 2e-2), 0, [2, 2, 2], [27, 17, 6]) is None

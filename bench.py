@@ -210,7 +210,7 @@ def run_adjoint(n: int, steps: int, every: int):
         "adjoint_achieved_gbs": cells * 444 / (adj_ms * 1e-3) / 1e9,
         "plain_step_achieved_gbs": cells * 284 / (step_ms * 1e-3) / 1e9,
         "bytes_per_lup": {"plain_step_scalar_force": 284, "adjoint": 444},
-        "loss": float(loss),
+        "loss": float(loss.detach()),
         "grad_theta_norm": float(theta.grad.norm()),
     }
     del lev
@@ -407,10 +407,6 @@ def run_far_field(nx: int, ny: int, nz: int, pad: int, spinup: int, n_ref: int):
         "reference_shell_cells": int(np.count_nonzero(kinds == _capi.GHOST)),
         "cells_per_scale": cells,
         "ms_per_reference_step": ms,
-        "region_rebuild_s": rebuild_s,
-        "boxes_after_rebuild_level0_units": [[list(map(int, lo)), list(map(int, hi))]
-                                             for lo, hi in boxes2],
-        "ms_per_reference_step_with_rebuild_every_40": ms + rebuild_s * 1e3 / n_ref,
         "mlups_all_scales": sum(cells) / (ms * 1e-3) / 1e6,
         "reference_scale_step_ms": ms0,
         "nonfinite": int(bad),

@@ -120,7 +120,11 @@ __device__ __forceinline__ void map_and_store(const ExchArgs& a, int c, float (&
 // switches are compile-time so that the 27 (or 54) loads of a corner carry no
 // branch between them and are issued back to back.  Corners of zero weight
 // are still read (at an index inside the box), without a branch.
-template <typename Ts, typename Td, bool kBlend, bool kScalar>
+// kNode: every target lies on a source lattice point (the host checked that
+// the target spacing is an integer multiple of the source spacing and the
+// origins differ by whole source cells), so the interpolation is the value
+// at that point: one corner of weight 1 instead of eight.
+template <typename Ts, typename Td, bool kBlend, bool kScalar, bool kNode>
 __global__ void __launch_bounds__(256) k_exchange(const ExchArgs a)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -129,6 +133,13 @@ __global__ void __launch_bounds__(256) k_exchange(const ExchArgs a)
     int base[3];
     float t[3];
     target_stencil(a, c, base, t);
+    if (kNode) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (t[d] >= 0.5f) ++base[d];   // nearest point (fractions are 0 up to rounding)
+            t[d] = 0.0f;
+        }
+    }
     const int n[3] = {a.snx, a.sny, a.snz};
     int ix[2], iy[2], iz[2];
 #pragma unroll
@@ -151,8 +162,9 @@ __global__ void __launch_bounds__(256) k_exchange(const ExchArgs a)
 #pragma unroll
     for (int q = 0; q < 27; ++q) v[q] = 0.0f;
     float gi[QS] = {0, 0, 0, 0, 0, 0, 0};
+    constexpr int kCorners = kNode ? 1 : 8;
 #pragma unroll
-    for (int corner = 0; corner < 8; ++corner) {
+    for (int corner = 0; corner < kCorners; ++corner) {
         const int ox = corner & 1, oy = (corner >> 1) & 1, oz = (corner >> 2) & 1;
         const float wt = corner_weight(t, corner);
         const int64_t sc = ix[ox] + (int64_t)a.snx * (iy[oy] + (int64_t)a.sny * iz[oz]);
@@ -210,17 +222,35 @@ __global__ void __launch_bounds__(256) k_time_interp(const T* s0, const T* s1, c
 static double shear_rate(const cslbm_level* L) { return 1.0 / (3.0 * L->p.nu + 0.5); }
 
 template <typename Ts, typename Td>
-static void launch_exchange_kernel(const ExchArgs& a, bool blend, bool scalar, dim3 grid,
-                                   dim3 block, hipStream_t st)
+static void launch_exchange_kernel(const ExchArgs& a, bool blend, bool scalar, bool node,
+                                   dim3 grid, dim3 block, hipStream_t st)
 {
-    if (blend && scalar)
-        hipLaunchKernelGGL((k_exchange<Ts, Td, true, true>), grid, block, 0, st, a);
+    if (node && !blend) {
+        if (scalar)
+            hipLaunchKernelGGL((k_exchange<Ts, Td, false, true, true>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_exchange<Ts, Td, false, false, true>), grid, block, 0, st, a);
+    } else if (blend && scalar)
+        hipLaunchKernelGGL((k_exchange<Ts, Td, true, true, false>), grid, block, 0, st, a);
     else if (blend)
-        hipLaunchKernelGGL((k_exchange<Ts, Td, true, false>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_exchange<Ts, Td, true, false, false>), grid, block, 0, st, a);
     else if (scalar)
-        hipLaunchKernelGGL((k_exchange<Ts, Td, false, true>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_exchange<Ts, Td, false, true, false>), grid, block, 0, st, a);
     else
-        hipLaunchKernelGGL((k_exchange<Ts, Td, false, false>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_exchange<Ts, Td, false, false, false>), grid, block, 0, st, a);
+}
+
+// Every target point of dst is a lattice point of src: the spacing ratio is
+// a whole number and the origins differ by whole source cells.
+static bool nodes_coincide(const cslbm_level* src, const cslbm_level* dst)
+{
+    const double r = dst->dx / src->dx;
+    if (!(r >= 1.0 - 1e-9) || std::fabs(r - std::nearbyint(r)) > 1e-9) return false;
+    for (int d = 0; d < 3; ++d) {
+        const double o = (dst->origin[d] - src->origin[d]) / src->dx;
+        if (std::fabs(o - std::nearbyint(o)) > 1e-9) return false;
+    }
+    return true;
 }
 
 static int launch_exchange(const cslbm_level* src, const void* fA, const void* fB, const float* gA,
@@ -261,16 +291,17 @@ static int launch_exchange(const cslbm_level* src, const void* fA, const void* f
         a.fA = a.fB;
         a.gA = a.gB;
     }
+    const bool node = nodes_coincide(src, dst);
     const dim3 grid((n_cells + 255) / 256), block(256);
     const bool s32 = src->storage == CSLBM_F32, d32 = dst->storage == CSLBM_F32;
     if (s32 && d32)
-        launch_exchange_kernel<float, float>(a, blend, scalar, grid, block, stream);
+        launch_exchange_kernel<float, float>(a, blend, scalar, node, grid, block, stream);
     else if (s32)
-        launch_exchange_kernel<float, _Float16>(a, blend, scalar, grid, block, stream);
+        launch_exchange_kernel<float, _Float16>(a, blend, scalar, node, grid, block, stream);
     else if (d32)
-        launch_exchange_kernel<_Float16, float>(a, blend, scalar, grid, block, stream);
+        launch_exchange_kernel<_Float16, float>(a, blend, scalar, node, grid, block, stream);
     else
-        launch_exchange_kernel<_Float16, _Float16>(a, blend, scalar, grid, block, stream);
+        launch_exchange_kernel<_Float16, _Float16>(a, blend, scalar, node, grid, block, stream);
     return check_launch("k_exchange");
 }
 

@@ -10,7 +10,7 @@ import torch
 import oracle
 from oracle import multilevel as ml
 from paper_1807_02284_amd import _capi, hierarchy, inputs
-from paper_1807_02284_amd.level import F32, Level, Params
+from paper_1807_02284_amd.level import F16S, F32, Level, Params
 
 pytestmark = pytest.mark.gpu
 
@@ -293,3 +293,69 @@ def test_vorticity_matches_central_differences():
         wz = d(U[1], 2) - d(U[0], 1)
         ref = np.sqrt(wx ** 2 + wy ** 2 + wz ** 2).reshape(-1)
         np.testing.assert_allclose(om, ref, rtol=0, atol=1e-6)
+
+
+def _exchange_gpu(lev_src, lev_dst, cells, w=0.0, lev_b=None):
+    import ctypes as C
+    cells_t = torch.as_tensor(np.asarray(cells, np.int32), device="cuda")
+    lev_src._sync_struct()
+    lev_dst._sync_struct()
+    fb = None if lev_b is None else lev_b.f.data_ptr()
+    gb = None if lev_b is None else lev_b.g.data_ptr()
+    _capi.call("cslbm_exchange", C.byref(lev_src.c), lev_src.f.data_ptr(), fb,
+               lev_src.g.data_ptr(), gb, float(w), C.byref(lev_dst.c), lev_dst.f.data_ptr(),
+               lev_dst.g.data_ptr(), cells_t.data_ptr(), int(cells_t.numel()),
+               torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+
+
+def test_exchange_on_coincident_lattices_matches_oracle():
+    """Fine (spacing 1/2) to coarse with the origins on whole fine cells:
+    every target is a fine lattice point (the one-corner path)."""
+    n = 20
+    coarse = Spec((n, n, n), (0.0, 0.0, 0.0), 1.0, 2e-3, np.zeros(n ** 3, np.uint8), periodic=7)
+    fshape = (22, 20, 18)
+    fine = Spec(fshape, (4.5, 5.0, 3.5), 0.5, 2e-3, hierarchy.shell_flags(*fshape))
+    levC, oC = start_both(coarse, 6)
+    levF, oF = start_both(fine, 7)
+    cells = hierarchy.post_cells(coarse.kinds, coarse.shape, coarse.origin, 1.0, fine.kinds,
+                                 fine.shape, fine.origin, fine.dx)
+    assert cells.size > 100
+    _exchange_gpu(levF, levC, cells)
+    fo, go = oC.f.copy(), oC.g.copy()
+    oracle.exchange(geom(fine), oF.f, oF.f, 0.0, geom(coarse), cells.astype(np.int64), fo, oF.g,
+                    oF.g, go)
+    assert rel_err(gpu_pop(levC), fo) <= 1e-6
+    assert np.max(np.abs(gpu_g(levC) - go)) <= 2e-7
+
+
+@pytest.mark.parametrize("s_store,d_store", [(F16S, F16S), (F32, F16S), (F16S, F32)])
+def test_exchange_with_binary16_storage_matches_oracle(s_store, d_store):
+    """Source and destination in binary16 storage: the oracle takes the
+    stored (rounded) source state; the result is within the rounding of its
+    own storage."""
+    n = 20
+    src = Spec((n, n, n), (0.0, 0.0, 0.0), 1.0, 2e-3, np.zeros(n ** 3, np.uint8), periodic=7)
+    dshape = (15, 13, 12)
+    dst = Spec(dshape, (3.3, 2.6, 7.1), 1 / 1.5, 2e-3, hierarchy.shell_flags(*dshape))
+    rho, u, s = smooth_state(src, 8)
+    levS = Level(*src.shape, src.params(), storage=s_store, scalar=True, periodic=7)
+    levS.init_equilibrium(rho, u, s)
+    levD = Level(*dst.shape, dst.params(), storage=d_store, scalar=True, periodic=0,
+                 flags=dst.kinds, origin=dst.origin, dx=dst.dx)
+    cells = np.arange(dst.n, dtype=np.int32)
+    _exchange_gpu(levS, levD, cells)
+    hS, gS = levS.get_populations(shifted=True)
+    fS = hS.double().cpu().numpy() + W[:, None]
+    fo = np.zeros((27, dst.n))
+    go = np.zeros((7, dst.n))
+    oracle.exchange(geom(src), fS, fS, 0.0, geom(dst), cells.astype(np.int64), fo,
+                    gS.double().cpu().numpy(), gS.double().cpu().numpy(), go)
+    hD, gD = levD.get_populations(shifted=True)
+    got = hD.double().cpu().numpy() + W[:, None]
+    if d_store == F32:
+        assert rel_err(got, fo) <= 1e-6
+    else:
+        scale = np.abs(fo - W[:, None]).max(axis=0, keepdims=True)
+        assert np.all(np.abs(got - fo) <= 2.0 * 2.0 ** -11 * scale + 2.0 ** -24 + 1e-7 * np.abs(fo))
+    assert np.max(np.abs(gD.double().cpu().numpy() - go)) <= 2e-7

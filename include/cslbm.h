@@ -73,6 +73,9 @@ extern "C" {
                             step inward along every non-periodic face it lies on */
 #define CSLBM_NEAR_WALL 8
 
+/* floats in cslbm_level.gmax_buf */
+#define CSLBM_GMAX_BUF 1025
+
 /* Relaxation and model parameters (lattice units of the level). */
 typedef struct cslbm_params {
     double nu;        /* shear viscosity: S4..S8 = 1/(3 nu + 1/2) (eq. viscosity) */
@@ -88,6 +91,11 @@ typedef struct cslbm_params {
                           of the stored velocity field by central differences
                           (one step lagged; needs vel/vel_next, fully
                           periodic levels without flags, cslbm_step only) */
+    int32_t gmax_running; /* grad_mode 1 only: 0 = g_max is the constant
+                          above; 1 = g_max is the maximum of the gradient
+                          field of the step (section "Adaptive relaxation":
+                          the maximum gradient magnitude for normalisation),
+                          reduced before every step into gmax_buf */
     double tau_s;     /* scalar BGK relaxation time (> 1/2) */
     double beta;      /* buoyancy: F_z += beta (s - s_ref) */
     double s_ref;
@@ -120,6 +128,9 @@ typedef struct cslbm_level {
                                  by cslbm_init_equilibrium and
                                  cslbm_set_populations, advanced by cslbm_step */
     float* vel_next;          /* [3][nx*ny*nz] next velocity (grad_mode 1) */
+    float* gmax_buf;          /* [CSLBM_GMAX_BUF] work space of the running
+                                 maximum (gmax_running 1): block maxima, then
+                                 the field maximum in the last element */
     double origin[3];         /* physical position of cell (0,0,0) */
     double dx;                /* physical spacing of this scale */
     cslbm_params p;

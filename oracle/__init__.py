@@ -66,6 +66,7 @@ class Params:
     beta: float = 0.0
     s_ref: float = 0.0
     grad_mode: int = 0          # 0: local strain-rate estimate; 1: |grad u|_F by differences
+    gmax_running: bool = False  # grad_mode 1: g_max of each step = max of its gradient field
 
     def c(self) -> _Params:
         return _Params(self.nu, (C.c_double * 4)(*self.nu_hi), self.a, self.b,
@@ -218,6 +219,11 @@ def step(dom: Domain, params: Params, f, g=None, n_steps: int = 1):
     go = None if g is None else np.empty_like(g)
     dc, pc = dom.c(), params.c()
     for _ in range(n_steps):
+        if params.gmax_running and params.grad_mode == 1:
+            # section "Adaptive relaxation": g_max normalises by the maximum
+            # gradient magnitude, here the maximum of this step's field
+            gm = float(np.max(grad_field(dom, params, f, g)))
+            pc.g_max = gm if gm > 0.0 else 1.0
         if lib().oracle_step(C.byref(dc), C.byref(pc), _p(f), _p(g), _p(fo), _p(go)) != 0:
             raise RuntimeError("oracle_step failed")
         f, fo = fo, f

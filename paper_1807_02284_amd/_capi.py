@@ -16,6 +16,7 @@ OK = 0
 ERR_ARG, ERR_SHAPE, ERR_UNSUPPORTED, ERR_HIP, ERR_NONFINITE = -1, -2, -3, -4, -5
 F32, F16S = 0, 1
 FLUID, SOLID, INLET, OUTFLOW, GHOST, NEUMANN, NEAR_WALL = 0, 1, 2, 3, 4, 5, 8
+GMAX_BUF = 1025
 
 _vp = C.c_void_p
 
@@ -29,6 +30,7 @@ class CslbmParams(C.Structure):
         ("g_max", C.c_double),
         ("adaptive", C.c_int32),
         ("grad_mode", C.c_int32),
+        ("gmax_running", C.c_int32),
         ("tau_s", C.c_double),
         ("beta", C.c_double),
         ("s_ref", C.c_double),
@@ -55,6 +57,7 @@ class CslbmLevel(C.Structure):
         ("force", _vp),
         ("vel", _vp),
         ("vel_next", _vp),
+        ("gmax_buf", _vp),
         ("origin", C.c_double * 3),
         ("dx", C.c_double),
         ("p", CslbmParams),

@@ -72,7 +72,34 @@ struct StepArgs {
     const float* vel;
     float* vel_out;
     int64_t ncells;
+    const float* gmax;    // running maximum of the gradient field, or null
 };
+
+// |grad u|_F at cell (x, y, z) of a stored velocity field [3][N] by central
+// differences with periodic wrap (the one formula of the gradient mode:
+// the step and the field maximum both use it, so they agree bit for bit).
+__device__ __forceinline__ float grad_fd(const float* vel, int64_t Nc, int x, int y, int z, int nx,
+                                         int ny, int nz)
+{
+    const int nxy = nx * ny;
+    const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
+    const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
+    const int zm = (z == 0) ? nz - 1 : z - 1, zp = (z == nz - 1) ? 0 : z + 1;
+    const int row = nx * y + nxy * z;
+    const int cxm = xm + row, cxp = xp + row;
+    const int cym = x + nx * ym + nxy * z, cyp = x + nx * yp + nxy * z;
+    const int czm = x + nx * y + nxy * zm, czp = x + nx * y + nxy * zp;
+    float sum = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const float* U = vel + b * Nc;
+        const float dx = 0.5f * (U[cxp] - U[cxm]);
+        const float dy = 0.5f * (U[cyp] - U[cym]);
+        const float dz = 0.5f * (U[czp] - U[czm]);
+        sum += dx * dx + dy * dy + dz * dz;
+    }
+    return sqrtf(sum);
+}
 
 // D3Q7 equilibrium g^eq_i = w_i s (1 + 4 c_i.u)  (cs^2 = 1/4)
 __device__ __forceinline__ float scalar_eq(int i, float s, float ux, float uy, float uz)
@@ -258,23 +285,15 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
     // gradient mode: |grad u|_F of the stored velocity field by central
     // differences (the level is fully periodic: kGradFD excludes flags)
     float g_given = -1.0f;
+    Rates rates = a.r;
     if (kGradFD) {
-        const int64_t Nc = a.ncells;
-        const int cxm = xm + sy[1] + sz[1], cxp = xp + sy[1] + sz[1];
-        const int cym = x + sy[2] + sz[1], cyp = x + sy[0] + sz[1];
-        const int czm = x + sy[1] + sz[2], czp = x + sy[1] + sz[0];
-        float sum = 0.0f;
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            const float* U = a.vel + b * Nc;
-            const float dx = 0.5f * (U[cxp] - U[cxm]);
-            const float dy = 0.5f * (U[cyp] - U[cym]);
-            const float dz = 0.5f * (U[czp] - U[czm]);
-            sum += dx * dx + dy * dy + dz * dz;
+        g_given = grad_fd(a.vel, a.ncells, x, y, z, nx, ny, nz);
+        if (a.gmax) {   // running maximum: normalise by the field's largest gradient
+            const float gm = *a.gmax;
+            rates.inv_gmax = gm > 0.0f ? 1.0f / gm : 0.0f;
         }
-        g_given = sqrtf(sum);
     }
-    const CellMacro mc = cm_collide(v, a.r, Fx, Fy, Fz, fluid, g_given);
+    const CellMacro mc = cm_collide(v, rates, Fx, Fy, Fz, fluid, g_given);
     if (kGradFD) {
         // velocity of the new state as read back from it: (j~ - F/2)/rho
         // equals the collision velocity (j + F/2)/rho since j~ = j + F
@@ -314,6 +333,44 @@ __device__ __forceinline__ void cell_coords(int64_t c, int nx, int ny, int& x, i
     x = (int)(c % nx);
     y = (int)((c / nx) % ny);
     z = (int)(c / ((int64_t)nx * ny));
+}
+
+// Field maximum of the gradient-mode G: block maxima over a grid-stride
+// loop (every thread of a block takes part), then one block reduces them.
+constexpr int kGmaxBlocks = CSLBM_GMAX_BUF - 1;
+
+__global__ void __launch_bounds__(256) k_grad_max_partials(const float* vel, int nx, int ny, int nz,
+                                                           float* partial)
+{
+    __shared__ float red[256];
+    const int64_t N = (int64_t)nx * ny * nz;
+    float m = 0.0f;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < N;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(c % nx), y = (int)((c / nx) % ny), z = (int)(c / ((int64_t)nx * ny));
+        m = fmaxf(m, grad_fd(vel, N, x, y, z, nx, ny, nz));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_grad_max_final(float* buf)
+{
+    __shared__ float red[256];
+    float m = 0.0f;
+    for (int i = threadIdx.x; i < kGmaxBlocks; i += blockDim.x) m = fmaxf(m, buf[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) buf[kGmaxBlocks] = red[0];
 }
 
 __global__ void k_prepare_flags(uint8_t* flags, uint32_t* links, int nx, int ny, int nz,
@@ -630,6 +687,8 @@ int validate_params(const cslbm_level* L)
         return fail(CSLBM_ERR_ARG, "scalar relaxation time tau_s = %g must exceed 1/2", p.tau_s);
     if (p.grad_mode != 0 && p.grad_mode != 1)
         return fail(CSLBM_ERR_ARG, "grad_mode = %d must be 0 or 1", p.grad_mode);
+    if (p.gmax_running && p.grad_mode != 1)
+        return fail(CSLBM_ERR_ARG, "gmax_running needs grad_mode 1");
     return CSLBM_OK;
 }
 
@@ -750,6 +809,12 @@ static int launch_step_grad(const cslbm_level* L, const void* fin, void* fout, c
     a.vel = vel;
     a.vel_out = vel_out;
     a.ncells = cells_of(L);
+    if (L->p.gmax_running) {
+        hipLaunchKernelGGL(k_grad_max_partials, dim3(kGmaxBlocks), dim3(256), 0, stream, vel, L->nx,
+                           L->ny, L->nz, L->gmax_buf);
+        hipLaunchKernelGGL(k_grad_max_final, dim3(1), dim3(256), 0, stream, L->gmax_buf);
+        a.gmax = L->gmax_buf + kGmaxBlocks;
+    }
     if (L->storage == CSLBM_F32)
         dispatch_step_grad<float>(a, L->force != nullptr, gin != nullptr, stream);
     else
@@ -769,6 +834,7 @@ static StepArgs step_args(const cslbm_level* L, const void* fin, void* fout, con
     a.vel = nullptr;
     a.vel_out = nullptr;
     a.ncells = 0;
+    a.gmax = nullptr;
     a.f = fin;
     a.fo = fout;
     a.g = gin;
@@ -949,6 +1015,8 @@ int cslbm_step(cslbm_level* L, int32_t n_steps, hipStream_t stream)
                         "the finite-difference gradient mode needs a fully periodic level without flags");
         if (!L->vel || !L->vel_next || L->vel == L->vel_next)
             return fail(CSLBM_ERR_ARG, "grad_mode 1 needs distinct vel and vel_next buffers");
+        if (L->p.gmax_running && !L->gmax_buf)
+            return fail(CSLBM_ERR_ARG, "gmax_running needs gmax_buf");
     }
 
     for (int n = 0; n < n_steps; ++n) {

@@ -33,12 +33,13 @@ class Params:
     u_in: tuple = (0.0, 0.0, 0.0)
     s_in: float = 0.0
     grad_mode: int = 0     # 0: local strain-rate estimate; 1: |grad u|_F by differences
+    gmax_running: bool = False   # grad_mode 1: g_max = the field's maximum gradient
 
     def to_c(self) -> _capi.CslbmParams:
         return _capi.CslbmParams(
             self.nu, (C.c_double * 4)(*self.nu_hi), self.a, self.b, self.g_max,
-            int(self.adaptive), int(self.grad_mode), self.tau_s, self.beta, self.s_ref,
-            (C.c_double * 3)(*self.u_in), self.s_in)
+            int(self.adaptive), int(self.grad_mode), int(self.gmax_running), self.tau_s,
+            self.beta, self.s_ref, (C.c_double * 3)(*self.u_in), self.s_in)
 
 
 def _stream_handle(stream=None) -> int:
@@ -94,10 +95,11 @@ class Level:
             self.force = torch.zeros(3, self.plane, dtype=torch.float32, device=self.device)
             self.force[:, : self.n] = ft
             self.force = self.force.reshape(-1)
-        self.vel = self.vel_next = None
+        self.vel = self.vel_next = self.gmax_buf = None
         if self.params.grad_mode == 1:
             self.vel = torch.zeros(3 * self.n, dtype=torch.float32, device=self.device)
             self.vel_next = torch.zeros_like(self.vel)
+            self.gmax_buf = torch.zeros(_capi.GMAX_BUF, dtype=torch.float32, device=self.device)
         self.c = _capi.CslbmLevel()
         self.c.nx, self.c.ny, self.c.nz = self.nx, self.ny, self.nz
         self.c.storage = storage
@@ -120,6 +122,7 @@ class Level:
         self.c.force = _dev_ptr(self.force)
         self.c.vel = _dev_ptr(self.vel)
         self.c.vel_next = _dev_ptr(self.vel_next)
+        self.c.gmax_buf = _dev_ptr(self.gmax_buf)
         self.c.p = self.params.to_c()
 
     def set_params(self, params: Params):
@@ -129,6 +132,7 @@ class Level:
             # the velocity of the current state, as the gradient mode needs it
             self.vel = torch.zeros(3 * self.n, dtype=torch.float32, device=self.device)
             self.vel_next = torch.zeros_like(self.vel)
+            self.gmax_buf = torch.zeros(_capi.GMAX_BUF, dtype=torch.float32, device=self.device)
             self._sync_struct()
             _capi.call("cslbm_read_macro", C.byref(self.c), None, _dev_ptr(self.vel), None,
                        _stream_handle())

@@ -90,3 +90,27 @@ def test_gradient_modes_agree_on_uniform_flow():
     a, _ = oracle.step(dom, oracle.Params(nu=0.01, grad_mode=0), f, n_steps=3)
     b, _ = oracle.step(dom, oracle.Params(nu=0.01, grad_mode=1), f, n_steps=3)
     np.testing.assert_allclose(a, b, rtol=0, atol=1e-15)
+
+
+def test_running_maximum_normalises_by_the_fields_largest_gradient():
+    """With gmax_running the step equals the step with g_max set to the
+    maximum of the gradient field, so no cell is clamped and the cell with
+    the largest gradient gets the smallest factor a + b."""
+    nx, ny, nz = 9, 8, 6
+    n = nx * ny * nz
+    u = inputs.smooth_random_field(nx, ny, nz, 0.05, 15, k_max=2)
+    dom = oracle.Domain(nx, ny, nz)
+    f, _ = oracle.init(dom, np.ones(n), u)
+    p = oracle.Params(nu=0.005, g_max=1e-9, grad_mode=1, gmax_running=True)
+    G = oracle.grad_field(dom, p, f)
+    fixed = oracle.Params(**{**p.__dict__, "gmax_running": False, "g_max": float(G.max())})
+    a, _ = oracle.step(dom, p, f)
+    b, _ = oracle.step(dom, fixed, f)
+    np.testing.assert_array_equal(a, b)
+    # the tiny constant g_max would clamp every cell instead
+    c, _ = oracle.step(dom, oracle.Params(**{**p.__dict__, "gmax_running": False}), f)
+    assert np.max(np.abs(c - a)) > 1e-9
+    fs, _ = oracle.stream(dom, f)
+    k = int(np.argmax(G))
+    _, diag = oracle.collide_g(fs[:, k], fixed, G[k])
+    assert diag["phi"] == pytest.approx(fixed.a + fixed.b)

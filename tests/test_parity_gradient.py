@@ -106,3 +106,25 @@ def test_gradient_mode_rejects_flagged_levels_and_other_paths():
     lam = torch.zeros(27 * lev2.plane, device="cuda")
     with pytest.raises(_capi.CslbmError):
         lev2.adjoint_step(lev2.f, None, lam, None, torch.zeros_like(lam), None, None)
+
+
+def test_gradient_mode_running_maximum_matches_oracle():
+    """g_max of every step = the maximum of that step's gradient field
+    (reduced on the GPU before the step)."""
+    nx, ny, nz = 40, 18, 11
+    n = nx * ny * nz
+    p = Params(nu=2e-3, g_max=0.05, grad_mode=1, gmax_running=True)
+    rho, u = start_fields(nx, ny, nz, 81, u_amp=0.05)
+    dom = oracle.Domain(nx, ny, nz)
+    f0, _ = oracle.init(dom, rho, u)
+    lev = Level(nx, ny, nz, p)
+    lev.set_populations(f0 - W[:, None], shifted=True)
+    lev.step(10)
+    op = oparams_grad(p)
+    op.gmax_running = True
+    f9, _ = oracle.step(dom, op, f0, n_steps=9)
+    gmax9 = float(oracle.grad_field(dom, op, f9).max())
+    ref, _ = oracle.step(dom, op, f9, n_steps=1)
+    got, _ = gpu_f64(lev)
+    assert rel_err(got, ref) <= 5e-6
+    assert float(lev.gmax_buf[-1]) == pytest.approx(gmax9, rel=1e-5)

@@ -50,36 +50,50 @@ def _axis_stencil(lo: int, hi: int, c_origin: float, c_dx: float, f_origin: floa
 def post_cells(coarse_kinds: np.ndarray, coarse_shape, coarse_origin, coarse_dx,
                fine_kinds: np.ndarray, fine_shape, fine_origin, fine_dx) -> np.ndarray:
     """Cells of the coarse scale whose position has a trilinear stencil (the
-    corners with non-zero weight) made of FLUID cells inside the fine box."""
+    corners with non-zero weight) made of FLUID cells inside the fine box.
+
+    The stencil is separable: along each axis a coarse index uses the fine
+    index b and, when its fraction is not 0, b + 1.  Staying inside the box
+    is a product of per-axis conditions; the non-FLUID fine cells (ghost
+    shell, padding, solids) then rule out the coarse cells that use them,
+    found through per-axis inverse maps (at most two coarse indices per
+    fine index per axis)."""
     cnx, cny, cnz = coarse_shape
     fnx, fny, fnz = fine_shape
+    fn = (fnx, fny, fnz)
     lo = [max(0, math.floor((fine_origin[a] - coarse_origin[a]) / coarse_dx) - 1) for a in range(3)]
     hi = [min(coarse_shape[a] - 1,
               math.ceil((fine_origin[a] + (fine_shape[a] - 1) * fine_dx - coarse_origin[a]) / coarse_dx) + 1)
           for a in range(3)]
     if any(h < l for l, h in zip(lo, hi)):
         return np.zeros(0, np.int32)
-    ax = [_axis_stencil(lo[a], hi[a], coarse_origin[a], coarse_dx, fine_origin[a], fine_dx)
-          for a in range(3)]
+    inside, inv = [], []
+    for a in range(3):
+        b, t = _axis_stencil(lo[a], hi[a], coarse_origin[a], coarse_dx, fine_origin[a], fine_dx)
+        up = t != 0.0                                   # b + 1 has non-zero weight
+        inside.append((b >= 0) & (b < fn[a]) & (~up | (b + 1 < fn[a])))
+        # inverse map: fine index -> up to two coarse (candidate-box) indices
+        m = np.full((fn[a] + 1, 2), -1, np.int64)
+        idx = np.arange(b.size)
+        for f_idx, sel, slot in ((b, np.ones(b.size, bool), 0), (b + 1, up, 1)):
+            ok = sel & (f_idx >= 0) & (f_idx < fn[a])
+            m[f_idx[ok], slot] = idx[ok]
+        inv.append(m)
     ck = np.asarray(coarse_kinds).reshape(cnz, cny, cnx)
     ok = ck[lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1] == FLUID
-    fk = np.asarray(fine_kinds).reshape(fnz, fny, fnx) == FLUID
-    fn = (fnx, fny, fnz)
-    for corner in range(8):
-        o = (corner & 1, (corner >> 1) & 1, (corner >> 2) & 1)
-        idx, inside, need = [], [], []
-        for a in range(3):
-            b, t = ax[a]
-            i = b + o[a]
-            idx.append(np.clip(i, 0, fn[a] - 1))
-            inside.append((i >= 0) & (i < fn[a]))
-            need.append(np.ones(b.size, bool) if o[a] == 0 else t != 0.0)   # weight != 0
-        good = fk[np.ix_(idx[2], idx[1], idx[0])]
-        good &= inside[2][:, None, None] & inside[1][None, :, None] & inside[0][None, None, :]
-        needed = need[2][:, None, None] & need[1][None, :, None] & need[0][None, None, :]
-        ok &= good | ~needed
-    zz, yy, xx = np.nonzero(ok)
-    return ((xx + lo[0]) + cnx * ((yy + lo[1]) + cny * (zz + lo[2]))).astype(np.int32)
+    ok &= inside[2][:, None, None] & inside[1][None, :, None] & inside[0][None, None, :]
+    # coarse cells that use a non-FLUID fine cell
+    bz, by, bx = np.nonzero(np.asarray(fine_kinds).reshape(fnz, fny, fnx) != FLUID)
+    for sz in range(2):
+        for sy in range(2):
+            for sx in range(2):
+                iz, iy, ix = inv[2][bz, sz], inv[1][by, sy], inv[0][bx, sx]
+                hit = (iz >= 0) & (iy >= 0) & (ix >= 0)
+                ok[iz[hit], iy[hit], ix[hit]] = False
+    flat = (np.arange(lo[0], hi[0] + 1, dtype=np.int32)[None, None, :] +
+            np.int32(cnx) * (np.arange(lo[1], hi[1] + 1, dtype=np.int32)[None, :, None] +
+                             np.int32(cny) * np.arange(lo[2], hi[2] + 1, dtype=np.int32)[:, None, None]))
+    return flat[ok]
 
 
 def check_prior_stencils(parent_kinds, parent_shape, parent_origin, parent_dx, parent_periodic,

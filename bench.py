@@ -338,6 +338,15 @@ def run_gradient_mode(n: int, steps: int, compare_steps: int):
         fields[mode] = ug.double()
         del lev
         torch.cuda.empty_cache()
+    # the running-maximum option: the field maximum is reduced before each step
+    lev = Level(n, n, n, Params(nu=1e-5, g_max=0.1, adaptive=True, grad_mode=1, gmax_running=True))
+    lev.init_equilibrium(rho, u)
+    ms = time_steps(lev, steps, 10)
+    out["running_max_ms_per_step"] = ms / steps
+    out["running_max_mlups"] = n ** 3 * steps / (ms * 1e-3) / 1e6
+    out["running_max_last_gmax"] = float(lev.gmax_buf[-1])
+    del lev
+    torch.cuda.empty_cache()
     d = fields[1] - fields[0]
     out["bytes_per_lup"] = 240
     out["compare_steps"] = compare_steps

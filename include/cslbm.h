@@ -129,8 +129,10 @@ typedef struct cslbm_level {
                                  cslbm_set_populations, advanced by cslbm_step */
     float* vel_next;          /* [3][nx*ny*nz] next velocity (grad_mode 1) */
     float* gmax_buf;          /* [CSLBM_GMAX_BUF] work space of the running
-                                 maximum (gmax_running 1): block maxima, then
-                                 the field maximum in the last element */
+                                 maximum (gmax_running 1): CSLBM_GMAX_BUF - 1
+                                 partial slots, zeroed by the caller once and
+                                 left zeroed by every step, then the field
+                                 maximum of the last step in the last element */
     double origin[3];         /* physical position of cell (0,0,0) */
     double dx;                /* physical spacing of this scale */
     cslbm_params p;

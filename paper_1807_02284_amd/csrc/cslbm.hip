@@ -335,35 +335,45 @@ __device__ __forceinline__ void cell_coords(int64_t c, int nx, int ny, int& x, i
     z = (int)(c / ((int64_t)nx * ny));
 }
 
-// Field maximum of the gradient-mode G: block maxima over a grid-stride
-// loop (every thread of a block takes part), then one block reduces them.
+// Field maximum of the gradient-mode G.  One thread per cell in the step's
+// launch shape; every block reduces its maximum in LDS (out-of-box threads
+// take part with 0) and folds it into one of the partial slots with an
+// atomic maximum on the bit pattern (G >= 0, so the order of float bit
+// patterns is the order of the values and the result does not depend on
+// the order of the atomics).  The final pass reduces the slots, stores the
+// maximum and clears the slots for the next step.
 constexpr int kGmaxBlocks = CSLBM_GMAX_BUF - 1;
 
 __global__ void __launch_bounds__(256) k_grad_max_partials(const float* vel, int nx, int ny, int nz,
-                                                           float* partial)
+                                                           unsigned int* slots)
 {
     __shared__ float red[256];
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
     const int64_t N = (int64_t)nx * ny * nz;
-    float m = 0.0f;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < N;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        const int x = (int)(c % nx), y = (int)((c / nx) % ny), z = (int)(c / ((int64_t)nx * ny));
-        m = fmaxf(m, grad_fd(vel, N, x, y, z, nx, ny, nz));
-    }
-    red[threadIdx.x] = m;
+    red[tid] = (x < nx && y < ny) ? grad_fd(vel, N, x, y, z, nx, ny, nz) : 0.0f;
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] = fmaxf(red[tid], red[tid + s]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+    if (tid == 0) {
+        const unsigned int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+        atomicMax(slots + (b % kGmaxBlocks), __float_as_uint(red[0]));
+    }
 }
 
 __global__ void __launch_bounds__(256) k_grad_max_final(float* buf)
 {
     __shared__ float red[256];
+    unsigned int* slots = reinterpret_cast<unsigned int*>(buf);
     float m = 0.0f;
-    for (int i = threadIdx.x; i < kGmaxBlocks; i += blockDim.x) m = fmaxf(m, buf[i]);
+    for (int i = threadIdx.x; i < kGmaxBlocks; i += blockDim.x) {
+        m = fmaxf(m, __uint_as_float(slots[i]));
+        slots[i] = 0u;
+    }
     red[threadIdx.x] = m;
     __syncthreads();
     for (int s = blockDim.x / 2; s > 0; s >>= 1) {
@@ -810,8 +820,10 @@ static int launch_step_grad(const cslbm_level* L, const void* fin, void* fout, c
     a.vel_out = vel_out;
     a.ncells = cells_of(L);
     if (L->p.gmax_running) {
-        hipLaunchKernelGGL(k_grad_max_partials, dim3(kGmaxBlocks), dim3(256), 0, stream, vel, L->nx,
-                           L->ny, L->nz, L->gmax_buf);
+        const dim3 block = step_block(L->nx);
+        const dim3 grid((L->nx + block.x - 1) / block.x, (L->ny + block.y - 1) / block.y, L->nz);
+        hipLaunchKernelGGL(k_grad_max_partials, grid, block, 0, stream, vel, L->nx, L->ny, L->nz,
+                           reinterpret_cast<unsigned int*>(L->gmax_buf));
         hipLaunchKernelGGL(k_grad_max_final, dim3(1), dim3(256), 0, stream, L->gmax_buf);
         a.gmax = L->gmax_buf + kGmaxBlocks;
     }

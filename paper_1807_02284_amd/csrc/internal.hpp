@@ -52,6 +52,13 @@ dim3 step_block(int nx);
 int launch_step_into(const cslbm_level* L, const void* fin, void* fout, const float* gin,
                      float* gout, hipStream_t stream);
 
+// One step in the finite-difference gradient mode (grad_mode 1): the
+// adaptive factor takes |grad u|_F of vel, the input state's velocity, and
+// the new state's velocity goes to vel_out.  With gmax_running the field
+// maximum of that gradient is reduced into L->gmax_buf first.
+int launch_step_grad(const cslbm_level* L, const void* fin, void* fout, const float* gin,
+                     float* gout, const float* vel, float* vel_out, hipStream_t stream);
+
 // The same step with its output replaced by the quadratic time interpolation
 // l0 * t0 + l1 * fin + l2 * step(fin) at every cell (and likewise for g);
 // L must have flags.

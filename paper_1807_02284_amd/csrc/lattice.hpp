@@ -59,6 +59,23 @@ enum : uint8_t {
 constexpr uint8_t kKindMask = 0x07;
 constexpr uint8_t kNearWall = 0x08;  // set by the library: some pull source is solid
 
+// D3Q7 equilibrium g^eq_i = w_i s (1 + 4 c_i.u)  (cs^2 = 1/4)
+__device__ __forceinline__ float scalar_eq(int i, float s, float ux, float uy, float uz)
+{
+    return kSw[i] * s * (1.0f + 4.0f * (kSx[i] * ux + kSy[i] * uy + kSz[i] * uz));
+}
+
+__device__ __forceinline__ bool leaves_box(int x, int y, int z, int cx, int cy, int cz, int nx,
+                                           int ny, int nz, int periodic)
+{
+    // the pull source x - c lies outside a non-periodic face
+    const bool ox = !(periodic & 1) && ((cx == 1 && x == 0) || (cx == -1 && x == nx - 1));
+    const bool oy = !(periodic & 2) && ((cy == 1 && y == 0) || (cy == -1 && y == ny - 1));
+    const bool oz = !(periodic & 4) && ((cz == 1 && z == 0) || (cz == -1 && z == nz - 1));
+    return ox || oy || oz;
+}
+
+
 static_assert(tensor_slot(0) == 13, "rest velocity sits in the middle of the cube");
 static_assert(tensor_slot(13) == 2 + 3 * 1 + 9 * 0, "erratum: velocity 13 is (1,0,-1)");
 

@@ -71,8 +71,14 @@ def time_steps(lev, steps: int, warmup: int):
     return start.elapsed_time(end)   # ms
 
 
+def kinetic_energy(lev) -> float:
+    """E = sum over cells of rho |u|^2 / 2 of the stored state (FP64 sum)."""
+    rho, u, _ = lev.read_macro()
+    return float(0.5 * (rho.double() * (u.double() ** 2).sum(0)).sum())
+
+
 def run_gpu(n: int, storage: str, steps: int, warmup: int):
-    import numpy as np  # noqa: F401
+    import numpy as np
     import torch
     from paper_1807_02284_amd import inputs
     from paper_1807_02284_amd.level import F16S, F32, Level, Params
@@ -82,8 +88,10 @@ def run_gpu(n: int, storage: str, steps: int, warmup: int):
     lev = Level(n, n, n, p, storage=F32 if storage == "f32" else F16S)
     lev.init_equilibrium(rho, u)
     c0 = lev.conserved()
+    e0 = kinetic_energy(lev)
     ms = time_steps(lev, steps, warmup)
     c1 = lev.conserved()
+    e1 = kinetic_energy(lev)
     bad = lev.count_nonfinite()
     cells = n ** 3
     ms_step = ms / steps
@@ -96,6 +104,8 @@ def run_gpu(n: int, storage: str, steps: int, warmup: int):
         "achieved_gbs": achieved,
         "bytes_per_launch": bytes_launch,
         "mass_drift_rel": abs(c1[0] - c0[0]) / c0[0],
+        "momentum_drift_abs": float(np.max(np.abs(c1[1:4] - c0[1:4]))),
+        "kinetic_energy_ratio": e1 / e0,
         "nonfinite": bad,
     }
     del lev
@@ -585,6 +595,8 @@ def main():
             "algorithmic_bytes_per_launch": main_run["bytes_per_launch"],
         },
         "checks": {"mass_drift_rel": main_run["mass_drift_rel"],
+                   "momentum_drift_abs": main_run["momentum_drift_abs"],
+                   "kinetic_energy_ratio_after_warmup_and_steps": main_run["kinetic_energy_ratio"],
                    "nonfinite": main_run["nonfinite"]},
         "variants": variants,
         "source_hash": kernel_source_hash(),

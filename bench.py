@@ -280,6 +280,27 @@ def run_plume(nx: int, ny: int, nz: int, spinup: int, n_ref: int):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / n_ref
+    # adjoint of one reference step (forward recompute into the workspace,
+    # then the reverse schedule) from the current states, arbitrary adjoints
+    ws = torch.empty(H.adjoint_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    f_in = [lv.f.clone() for lv in H.levels]
+    g_in = [lv.g.clone() for lv in H.levels]
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    lam = [1e-3 * torch.randn(27 * lv.plane, device="cuda", generator=gen) for lv in H.levels]
+    mu = [1e-3 * torch.randn(7 * lv.plane, device="cuda", generator=gen) for lv in H.levels]
+    H.adjoint_step(f_in, g_in, lam, mu, ws)
+    torch.cuda.synchronize()
+    n_adj = 3
+    e0.record()
+    for _ in range(n_adj):
+        H.adjoint_step(f_in, g_in, lam, mu, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    adj_ms = e0.elapsed_time(e1) / n_adj
+    adj_finite = bool(all(torch.isfinite(x).all() for x in lam + mu))
+    ws_gb = ws.numel() / 1e9
+    del ws, f_in, g_in, lam, mu
+    torch.cuda.empty_cache()
     # the dynamic construction repeats every 40 reference steps: rebuild the
     # regions from the current flow (new cells mapped from the parent,
     # shared cells kept), timed on its own (host construction + GPU fill)
@@ -307,6 +328,10 @@ def run_plume(nx: int, ny: int, nz: int, spinup: int, n_ref: int):
         "ms_per_reference_step_with_rebuild_every_40": ms + rebuild_s * 1e3 / n_ref,
         "lattice_updates_per_reference_step": lups,
         "mlups_all_scales": lups / (ms * 1e-3) / 1e6,
+        "adjoint_ms_per_reference_step": adj_ms,
+        "adjoint_vs_forward_reference_step": adj_ms / ms,
+        "adjoint_workspace_gb": ws_gb,
+        "adjoint_finite": adj_finite,
         "reference_scale_step_ms": ms0 / spinup,
         "reference_scale_mlups": n0 / (ms0 / spinup * 1e-3) / 1e6,
         "reference_scale_achieved_gbs": n0 * 273 / (ms0 / spinup * 1e-3) / 1e9,

@@ -326,12 +326,57 @@ int cslbm_step_store(const cslbm_level* L, int32_t n_steps, void* const* f_state
  * forward step read, lam_next = dL/df(n+1) [27][plane] and mu_next =
  * dL/dg(n+1) [7][plane], writes lam = dL/df(n) and mu = dL/dg(n) and adds
  * dL/dtheta to dtheta [3][plane] (may be NULL).  Adjoints are FP32 and refer
- * to the physical populations (a shift by w_i does not change them).  Only
- * fully periodic levels without flags are supported (CSLBM_ERR_UNSUPPORTED
- * otherwise).  Non-smooth points of the adaptive factor take the derivative
- * of the branch they are on. */
+ * to the physical populations (a shift by w_i does not change them).  A
+ * level without flags must be fully periodic (CSLBM_ERR_UNSUPPORTED
+ * otherwise).  With flags: solid and inlet outputs do not depend on the
+ * state; ghost, outflow and Neumann cells copy their source cell (identity
+ * Jacobian); lam and mu are overwritten everywhere (zero where no output
+ * depends on an element).  Non-smooth points of the adaptive factor take the
+ * derivative of the branch they are on. */
 int cslbm_adjoint_step(const cslbm_level* L, const float* lam_next, const float* mu_next,
                        float* lam, float* mu, float* dtheta, hipStream_t stream);
+
+/* Adjoint of cslbm_exchange (sections "Spatial scale mapping" and
+ * "Temporal alignment and scale mapping"): with the forward arguments (src,
+ * fA, fB, gA, gB, w, dst, cells), lam_d [27][dst plane] (mu_d [7][..]) holds
+ * dL/d(destination after the exchange); the listed cells' entries are routed
+ * to the source states and then set to 0 (the exchange overwrote them):
+ * lam_a += (1 - w) J^T lam_d and lam_b += w J^T lam_d (J the trilinear
+ * interpolation followed by the central-moment rescaling of the target
+ * state), likewise mu_a / mu_b.  A time level of weight 0 is not read or
+ * touched and may be NULL.  FP32 source states only (CSLBM_ERR_UNSUPPORTED);
+ * targets sharing source corners are summed with atomic adds. */
+int cslbm_exchange_adjoint(const cslbm_level* src, const void* fA, const void* fB, const float* gA,
+                           const float* gB, double w, const cslbm_level* dst, float* lam_d,
+                           float* mu_d, float* lam_a, float* lam_b, float* mu_a, float* mu_b,
+                           const int32_t* cells, int32_t n_cells, hipStream_t stream);
+
+/* Workspace bytes that cslbm_multiscale_adjoint_step needs for H (the input
+ * of every sub-step, the interpolated states and adjoint temporaries of all
+ * scales), or -1 if H is not supported (message in cslbm_last_error). */
+int64_t cslbm_multiscale_adjoint_bytes(const cslbm_hierarchy* H);
+
+/* Adjoint of one reference step of cslbm_multiscale_step (Algorithm 1:
+ * reference step, prior-mapping of each finer scale's ghost shell at the
+ * sub-step times, sub-steps with the quadratic time interpolation, ghost
+ * remap at weight 1, post-mapping into every coarser scale).
+ *   f_in[i], g_in[i]  DEVICE states of scale i at t_n (HOST arrays of
+ *                     n_scales pointers; g_in NULL without scalar); read only
+ *   lam[i], mu[i]     in: dL/d(state of scale i at t_n + dt_0) [27|7][plane];
+ *                     out: dL/d(state of scale i at t_n)
+ *   workspace         DEVICE, at least cslbm_multiscale_adjoint_bytes(H)
+ * The forward step is recomputed from f_in into the workspace (the level
+ * structs' own f / f_next / work buffers are not touched), the flags, lists,
+ * force and parameters of H are used as in the forward step.  Supported:
+ * FP32 storage, finer scales only (no far-field scale), every finer scale's
+ * parent is the next coarser one (scale i's parent is i - 1); the force
+ * field is held fixed (no dL/dtheta).  Target adjoints of the exchanges are
+ * propagated with atomic adds, so the result is not bit-reproducible.
+ * Errors: CSLBM_ERR_UNSUPPORTED outside that scope, CSLBM_ERR_ARG for NULL
+ * buffers or a short workspace, and the checks of cslbm_multiscale_step. */
+int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f_in,
+                                  const float* const* g_in, float* const* lam, float* const* mu,
+                                  void* workspace, int64_t workspace_bytes, hipStream_t stream);
 
 /* sizeof(cslbm_params) and sizeof(cslbm_level) as compiled into the
  * library (HOST pointers), so that bindings can verify their struct layout

@@ -114,6 +114,13 @@ _SIGNATURES = {
     "cslbm_step_store": (C.c_int, [C.POINTER(CslbmLevel), C.c_int32, C.POINTER(_vp),
                                    C.POINTER(_vp), _vp]),
     "cslbm_adjoint_step": (C.c_int, [C.POINTER(CslbmLevel), _vp, _vp, _vp, _vp, _vp, _vp]),
+    "cslbm_exchange_adjoint": (C.c_int, [C.POINTER(CslbmLevel), _vp, _vp, _vp, _vp, C.c_double,
+                                         C.POINTER(CslbmLevel), _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                         C.c_int32, _vp]),
+    "cslbm_multiscale_adjoint_bytes": (C.c_int64, [C.POINTER(CslbmHierarchy)]),
+    "cslbm_multiscale_adjoint_step": (C.c_int, [C.POINTER(CslbmHierarchy), C.POINTER(_vp),
+                                                C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp),
+                                                _vp, C.c_int64, _vp]),
     "cslbm_abi_sizes": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "cslbm_last_error": (C.c_char_p, []),
 }

@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcslbm.so")
-SOURCES = ["cslbm.hip", "step.hip", "multiscale.hip", "adjoint.hip"]
+SOURCES = ["cslbm.hip", "step.hip", "multiscale.hip", "adjoint.hip", "adjoint_ms.hip"]
 ARCH = os.environ.get("CSLBM_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are disabled for all device code.

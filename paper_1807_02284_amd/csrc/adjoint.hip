@@ -9,6 +9,16 @@
 // plane i).  On a periodic lattice the pull is a permutation, so every
 // (plane, cell) of lam(n) is written by exactly one thread and no atomics are
 // needed.  dL/dtheta(x) is accumulated by the thread that owns cell x.
+//
+// Levels with cell kinds: a fluid cell pulls (x - c_i, i), or its own
+// opposite population (x, opp(i)) across a bounce-back link; no two fluid
+// cells pull the same element, so the fluid pass still writes without
+// atomics, into an adjoint cleared first (elements no fluid cell pulls have
+// adjoint zero).  Solid and inlet outputs do not depend on the state.  Ghost,
+// outflow and Neumann cells copy a source cell (their own, the x - 1
+// neighbour, the inward neighbour) through a collision with zero relaxation,
+// the identity: a second pass adds their output adjoints to the source
+// elements with atomic adds, since a fluid cell may pull the same element.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -16,6 +26,7 @@
 #include "../../include/cslbm.h"
 #include "cm_adjoint.hpp"
 #include "cm_collide.hpp"
+#include "exchange.hpp"
 #include "internal.hpp"
 #include "lattice.hpp"
 
@@ -30,12 +41,32 @@ struct AdjArgs {
     float* lam0;          // dL/df(n)
     float* mu0;           // dL/dg(n)
     float* dtheta;        // [3][plane] accumulated, or null
-    int nx, ny, nz;
+    const uint8_t* flags;    // cell kinds or null (fully periodic level)
+    const uint32_t* links;   // bounce-back masks of near-wall cells or null
+    int nx, ny, nz, periodic;
     int64_t plane;
     AdjointParams ap;
 };
 
-template <typename T, bool kScalar>
+// Bounce-back mask of a near-wall cell from its neighbours' kinds (bit i:
+// the pull source x - c_i is solid or outside a non-periodic face), as the
+// forward step computes it when the level has no links array.
+__device__ __forceinline__ uint32_t adj_links(const AdjArgs& a, int x, int y, int z,
+                                              const int (&sx)[3], const int (&sy)[3],
+                                              const int (&sz)[3])
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int src = sx[kCx[i] + 1] + sy[kCy[i] + 1] + sz[kCz[i] + 1];
+        if (leaves_box(x, y, z, kCx[i], kCy[i], kCz[i], a.nx, a.ny, a.nz, a.periodic) ||
+            (a.flags[src] & kKindMask) == kSolid)
+            m |= 1u << i;
+    }
+    return m;
+}
+
+template <typename T, bool kScalar, bool kFlags>
 __global__ void __launch_bounds__(256) k_adjoint(const AdjArgs a)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -52,20 +83,47 @@ __global__ void __launch_bounds__(256) k_adjoint(const AdjArgs a)
     const int sy[3] = {yp * nx, y * nx, ym * nx};
     const int sz[3] = {zp * nxy, z * nxy, zm * nxy};
     const T* f = static_cast<const T*>(a.f);
+    uint32_t links = 0;
+    if (kFlags) {
+        const uint8_t flag = a.flags[cell];
+        if ((flag & kKindMask) != kFluid) return;   // the copy pass handles copying kinds
+        if (flag & kNearWall) links = a.links ? a.links[cell] : adj_links(a, x, y, z, sx, sy, sz);
+    }
+    // pull source of velocity i: (plane, cell) as in the forward step
+    auto source = [&](int i, int& pl) {
+        pl = i;
+        int src = sx[kCx[i] + 1] + sy[kCy[i] + 1] + sz[kCz[i] + 1];
+        if (kFlags && (links & (1u << i))) {
+            src = cell;
+            pl = opposite(i);
+        }
+        return src;
+    };
+    auto scalar_source = [&](int i, int& pl) {
+        pl = i;
+        int src = sx[kSx[i] + 1] + sy[kSy[i] + 1] + sz[kSz[i] + 1];
+        if (kFlags && (links & (1u << i))) {   // D3Q7 direction i is D3Q27 velocity i
+            src = cell;
+            pl = scalar_opposite(i);
+        }
+        return src;
+    };
 
     float h[27], lam[27];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const int src = sx[kCx[i] + 1] + sy[kCy[i] + 1] + sz[kCz[i] + 1];
-        h[tensor_slot(i)] = Io<T>::ld(f + i * P + src);
+        int pl;
+        const int src = source(i, pl);
+        h[tensor_slot(i)] = Io<T>::ld(f + pl * P + src);
         lam[tensor_slot(i)] = a.lam1[i * P + cell];
     }
     float gv[QS] = {0, 0, 0, 0, 0, 0, 0}, mu[QS] = {0, 0, 0, 0, 0, 0, 0};
     if (kScalar) {
 #pragma unroll
         for (int i = 0; i < QS; ++i) {
-            const int src = sx[kSx[i] + 1] + sy[kSy[i] + 1] + sz[kSz[i] + 1];
-            gv[i] = a.g[i * P + src];
+            int pl;
+            const int src = scalar_source(i, pl);
+            gv[i] = a.g[pl * P + src];
             mu[i] = a.mu1[i * P + cell];
         }
     }
@@ -79,14 +137,16 @@ __global__ void __launch_bounds__(256) k_adjoint(const AdjArgs a)
     cm_collide_adjoint<kScalar>(h, gv, th, a.ap, lam, mu, hb, gb, thb);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const int src = sx[kCx[i] + 1] + sy[kCy[i] + 1] + sz[kCz[i] + 1];
-        __builtin_nontemporal_store(hb[tensor_slot(i)], a.lam0 + i * P + src);
+        int pl;
+        const int src = source(i, pl);
+        __builtin_nontemporal_store(hb[tensor_slot(i)], a.lam0 + pl * P + src);
     }
     if (kScalar) {
 #pragma unroll
         for (int i = 0; i < QS; ++i) {
-            const int src = sx[kSx[i] + 1] + sy[kSy[i] + 1] + sz[kSz[i] + 1];
-            a.mu0[i * P + src] = gb[i];
+            int pl;
+            const int src = scalar_source(i, pl);
+            a.mu0[pl * P + src] = gb[i];
         }
     }
     if (a.dtheta) {
@@ -96,15 +156,97 @@ __global__ void __launch_bounds__(256) k_adjoint(const AdjArgs a)
     }
 }
 
+// Second pass on levels with cell kinds: ghost, outflow and Neumann cells
+// copy their source cell's state (identity Jacobian), so their output
+// adjoints are added to the source elements.
+__global__ void __launch_bounds__(256) k_adjoint_copies(const AdjArgs a, bool scalar)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= a.nx || y >= a.ny) return;
+    const int nx = a.nx, ny = a.ny, nxy = nx * ny;
+    const int cell = x + nx * y + nxy * z;
+    const int kind = a.flags[cell] & kKindMask;
+    int from;
+    if (kind == kGhost) {
+        from = cell;
+    } else if (kind == kOutflow) {
+        from = (x > 0 || (a.periodic & 1)) ? ((x == 0 ? nx - 1 : x - 1) + nx * y + nxy * z) : cell;
+    } else if (kind == kNeumann) {
+        int xi = x, yi = y, zi = z;
+        if (!(a.periodic & 1) && nx > 1) xi = (x == 0) ? 1 : (x == nx - 1 ? nx - 2 : x);
+        if (!(a.periodic & 2) && ny > 1) yi = (y == 0) ? 1 : (y == ny - 1 ? ny - 2 : y);
+        if (!(a.periodic & 4) && a.nz > 1) zi = (z == 0) ? 1 : (z == a.nz - 1 ? a.nz - 2 : z);
+        from = xi + nx * (yi + ny * zi);
+    } else {
+        return;
+    }
+    const int64_t P = a.plane;
+    for (int i = 0; i < Q; ++i) atomicAdd(a.lam0 + i * P + from, a.lam1[i * P + cell]);
+    if (scalar)
+        for (int i = 0; i < QS; ++i) atomicAdd(a.mu0 + i * P + from, a.mu1[i * P + cell]);
+}
+
+__global__ void __launch_bounds__(256) k_fill_zero(float* p, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
 template <typename T>
 static void launch_adjoint(const AdjArgs& a, bool scalar, hipStream_t st)
 {
     const dim3 block = step_block(a.nx);
     const dim3 grid((a.nx + block.x - 1) / block.x, (a.ny + block.y - 1) / block.y, a.nz);
+    if (a.flags) {
+        const int64_t nf = (int64_t)Q * a.plane, ng = (int64_t)QS * a.plane;
+        hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st, a.lam0, nf);
+        if (scalar)
+            hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st, a.mu0, ng);
+        if (scalar)
+            hipLaunchKernelGGL((k_adjoint<T, true, true>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_adjoint<T, false, true>), grid, block, 0, st, a);
+        hipLaunchKernelGGL(k_adjoint_copies, grid, block, 0, st, a, scalar);
+        return;
+    }
     if (scalar)
-        hipLaunchKernelGGL((k_adjoint<T, true>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_adjoint<T, true, false>), grid, block, 0, st, a);
     else
-        hipLaunchKernelGGL((k_adjoint<T, false>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_adjoint<T, false, false>), grid, block, 0, st, a);
+}
+
+int launch_adjoint_into(const cslbm_level* L, const void* fin, const float* gin,
+                        const float* lam_next, const float* mu_next, float* lam, float* mu,
+                        float* dtheta, hipStream_t stream)
+{
+    const bool scalar = gin != nullptr;
+    AdjArgs a;
+    a.f = fin;
+    a.g = gin;
+    a.theta = L->force;
+    a.lam1 = lam_next;
+    a.mu1 = scalar ? mu_next : nullptr;
+    a.lam0 = lam;
+    a.mu0 = scalar ? mu : nullptr;
+    a.dtheta = dtheta;
+    a.flags = L->flags;
+    a.links = L->links;
+    a.nx = L->nx;
+    a.ny = L->ny;
+    a.nz = L->nz;
+    a.periodic = L->periodic & 7;
+    a.plane = L->plane;
+    a.ap.r = make_rates(L->p);
+    a.ap.beta = (float)L->p.beta;
+    a.ap.s_ref = (float)L->p.s_ref;
+    a.ap.inv_tau_s = scalar ? (float)(1.0 / L->p.tau_s) : 0.0f;
+    if (L->storage == CSLBM_F32)
+        launch_adjoint<float>(a, scalar, stream);
+    else
+        launch_adjoint<_Float16>(a, scalar, stream);
+    return check_launch("k_adjoint");
 }
 
 }  // namespace cslbm
@@ -120,9 +262,9 @@ int cslbm_adjoint_step(const cslbm_level* L, const float* lam_next, const float*
     if (rc) return rc;
     rc = validate_params(L);
     if (rc) return rc;
-    if ((L->periodic & 7) != 7 || L->flags)
+    if ((L->periodic & 7) != 7 && !L->flags)
         return fail(CSLBM_ERR_UNSUPPORTED,
-                    "the adjoint step supports fully periodic levels without cell flags");
+                    "the adjoint step of a level without cell flags needs a fully periodic box");
     if (L->p.grad_mode != 0)
         return fail(CSLBM_ERR_UNSUPPORTED,
                     "the adjoint step differentiates the local gradient estimate (grad_mode 0)");
@@ -131,28 +273,7 @@ int cslbm_adjoint_step(const cslbm_level* L, const float* lam_next, const float*
     const bool scalar = L->g != nullptr;
     if (scalar && (!mu_next || !mu || mu == mu_next))
         return fail(CSLBM_ERR_ARG, "a level with a scalar needs distinct mu and mu_next");
-    AdjArgs a;
-    a.f = L->f;
-    a.g = L->g;
-    a.theta = L->force;
-    a.lam1 = lam_next;
-    a.mu1 = scalar ? mu_next : nullptr;
-    a.lam0 = lam;
-    a.mu0 = scalar ? mu : nullptr;
-    a.dtheta = dtheta;
-    a.nx = L->nx;
-    a.ny = L->ny;
-    a.nz = L->nz;
-    a.plane = L->plane;
-    a.ap.r = make_rates(L->p);
-    a.ap.beta = (float)L->p.beta;
-    a.ap.s_ref = (float)L->p.s_ref;
-    a.ap.inv_tau_s = scalar ? (float)(1.0 / L->p.tau_s) : 0.0f;
-    if (L->storage == CSLBM_F32)
-        launch_adjoint<float>(a, scalar, stream);
-    else
-        launch_adjoint<_Float16>(a, scalar, stream);
-    return check_launch("k_adjoint");
+    return launch_adjoint_into(L, L->f, L->g, lam_next, mu_next, lam, mu, dtheta, stream);
 }
 
 int cslbm_step_store(const cslbm_level* L, int32_t n_steps, void* const* f_states,

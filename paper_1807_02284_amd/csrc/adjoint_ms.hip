@@ -1,0 +1,599 @@
+// adjoint_ms.hip -- reverse mode of one reference step of Algorithm 1 over a
+// chain of finer scales (gfx950): the adjoints of the exchange (prior- and
+// post-mapping, section "Handling multiple scales"), of the quadratic time
+// interpolation fused into the last sub-step (section "Temporal alignment and
+// scale mapping") and of every collide-stream step, in the reverse order of
+// the forward schedule.
+//
+// The forward step is recomputed from the scales' states at t_n into a
+// caller-provided workspace (the input of every sub-step and the
+// interpolated result), then walked backwards.  Post-mapped values are never
+// read again within a reference step when every scale's parent is the next
+// coarser scale, so the recompute leaves them out and the adjoint of a
+// post-mapping only routes the target cells' adjoint to the fine state and
+// clears it there.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "../../include/cslbm.h"
+#include "cm_adjoint.hpp"
+#include "cm_collide.hpp"
+#include "exchange.hpp"
+#include "internal.hpp"
+#include "lattice.hpp"
+
+namespace cslbm {
+
+// Vector-Jacobian product of the exchange's cell map: the interpolated
+// post-collision state v (tensor order) and scalar gi go to
+//   out = K(u)^-1 (k with its second-order non-equilibrium rescaled by kappa,
+//                  the trace kept),  k = K(u) v, u = j / (1 + dr),
+//   g_out = g^eq(s, u) + kappa_s (gi - g^eq(s, u)),  s = sum gi.
+// Given lam = dL/d(out) and mu = dL/d(g_out), returns vb = dL/dv and
+// gb = dL/dgi.
+template <bool kScalar>
+__device__ __forceinline__ void exchange_map_adjoint(const float (&v)[27], const float (&gi)[7],
+                                                     float kap, float kap_s,
+                                                     const float (&lam)[27], const float (&mu)[7],
+                                                     float (&vb)[27], float (&gb)[7])
+{
+    float dr, jx, jy, jz;
+    moments0(v, dr, jx, jy, jz);
+    const float ir = 1.0f / (1.0f + dr);
+    const float ux = jx * ir, uy = jy * ir, uz = jz * ir;
+
+    // forward: mapped moments w
+    float w[27];
+    {
+        float d[27];
+#pragma unroll
+        for (int q = 0; q < 27; ++q) w[q] = v[q];
+        to_moments(w, ux, uy, uz);
+        deviation_equilibrium(d, dr, ux, uy, uz);
+        w[kslot(1, 1, 0)] = d[kslot(1, 1, 0)] + kap * (w[kslot(1, 1, 0)] - d[kslot(1, 1, 0)]);
+        w[kslot(1, 0, 1)] = d[kslot(1, 0, 1)] + kap * (w[kslot(1, 0, 1)] - d[kslot(1, 0, 1)]);
+        w[kslot(0, 1, 1)] = d[kslot(0, 1, 1)] + kap * (w[kslot(0, 1, 1)] - d[kslot(0, 1, 1)]);
+        const float nxx = w[kslot(2, 0, 0)] - d[kslot(2, 0, 0)];
+        const float nyy = w[kslot(0, 2, 0)] - d[kslot(0, 2, 0)];
+        const float nzz = w[kslot(0, 0, 2)] - d[kslot(0, 0, 2)];
+        const float tr = (nxx + nyy + nzz) * (1.0f / 3.0f);
+        w[kslot(2, 0, 0)] = d[kslot(2, 0, 0)] + kap * (nxx - tr) + tr;
+        w[kslot(0, 2, 0)] = d[kslot(0, 2, 0)] + kap * (nyy - tr) + tr;
+        w[kslot(0, 0, 2)] = d[kslot(0, 0, 2)] + kap * (nzz - tr) + tr;
+    }
+
+    float uxb = 0.0f, uyb = 0.0f, uzb = 0.0f;
+    // scalar: g_out = (1 - kap_s) g^eq(s, u) + kap_s gi
+    if (kScalar) {
+        const float s = (gi[0] + (gi[1] + gi[2])) + ((gi[3] + gi[4]) + (gi[5] + gi[6]));
+        float sb = 0.0f;
+#pragma unroll
+        for (int i = 0; i < QS; ++i) {
+            const float me = (1.0f - kap_s) * mu[i];
+            const float cu = kSx[i] * ux + kSy[i] * uy + kSz[i] * uz;
+            sb += me * kSw[i] * (1.0f + 4.0f * cu);
+            const float su = me * kSw[i] * s * 4.0f;
+            uxb += su * kSx[i];
+            uyb += su * kSy[i];
+            uzb += su * kSz[i];
+        }
+#pragma unroll
+        for (int i = 0; i < QS; ++i) gb[i] = kap_s * mu[i] + sb;
+    } else {
+#pragma unroll
+        for (int i = 0; i < QS; ++i) gb[i] = 0.0f;
+    }
+
+    // inverse sweeps: out = Ix(Iy(Iz(w)))
+    float bar[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) bar[q] = lam[q];
+    {
+        float t[27];
+#pragma unroll
+        for (int q = 0; q < 27; ++q) t[q] = w[q];
+        sweep_inv<9, 1, 3>(t, uz);
+        sweep_inv<3, 1, 9>(t, uy);
+        sweep_inv_rev<1, 3, 9>(t, bar, ux, uxb);
+#pragma unroll
+        for (int q = 0; q < 27; ++q) t[q] = w[q];
+        sweep_inv<9, 1, 3>(t, uz);
+        sweep_inv_rev<3, 1, 9>(t, bar, uy, uyb);
+        sweep_inv_rev<9, 1, 3>(w, bar, uz, uzb);
+    }
+    // bar = dL/dw; the map: off-diagonal w = d + kap (k - d); diagonal
+    // w_a = d_a + kap n_a + (1 - kap) tr with n_a = k_a - d_a, tr = mean n
+    float kb[27], db[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) {
+        kb[q] = bar[q];
+        db[q] = 0.0f;
+    }
+#define CSLBM_OFFDIAG(m, n, p)                              \
+    kb[kslot(m, n, p)] = kap * bar[kslot(m, n, p)];         \
+    db[kslot(m, n, p)] = (1.0f - kap) * bar[kslot(m, n, p)];
+    CSLBM_OFFDIAG(1, 1, 0)
+    CSLBM_OFFDIAG(1, 0, 1)
+    CSLBM_OFFDIAG(0, 1, 1)
+#undef CSLBM_OFFDIAG
+    {
+        const float bxx = bar[kslot(2, 0, 0)], byy = bar[kslot(0, 2, 0)], bzz = bar[kslot(0, 0, 2)];
+        const float m3 = (1.0f - kap) * (bxx + byy + bzz) * (1.0f / 3.0f);
+        const float nxb = kap * bxx + m3, nyb = kap * byy + m3, nzb = kap * bzz + m3;
+        kb[kslot(2, 0, 0)] = nxb;
+        kb[kslot(0, 2, 0)] = nyb;
+        kb[kslot(0, 0, 2)] = nzb;
+        db[kslot(2, 0, 0)] = bxx - nxb;
+        db[kslot(0, 2, 0)] = byy - nyb;
+        db[kslot(0, 0, 2)] = bzz - nzb;
+    }
+    float drb = 0.0f;
+    deviation_equilibrium_rev(db, dr, ux, uy, uz, drb, uxb, uyb, uzb);
+
+    // forward sweeps: k = Fz(Fy(Fx(v)))
+    {
+        float t[27];
+#pragma unroll
+        for (int q = 0; q < 27; ++q) t[q] = v[q];
+        sweep_fwd<1, 3, 9>(t, ux);
+        sweep_fwd<3, 1, 9>(t, uy);
+        sweep_fwd_rev<9, 1, 3>(t, kb, uz, uzb);
+#pragma unroll
+        for (int q = 0; q < 27; ++q) t[q] = v[q];
+        sweep_fwd<1, 3, 9>(t, ux);
+        sweep_fwd_rev<3, 1, 9>(t, kb, uy, uyb);
+        sweep_fwd_rev<1, 3, 9>(v, kb, ux, uxb);
+    }
+    // u = j ir, dr = sum v, j = sum c v
+    const float jxb = uxb * ir, jyb = uyb * ir, jzb = uzb * ir;
+    drb += -(uxb * jx + uyb * jy + uzb * jz) * ir * ir;
+#pragma unroll
+    for (int t = 0; t < 27; ++t) {
+        const int cx = t % 3 - 1, cy = (t / 3) % 3 - 1, cz = t / 9 - 1;
+        vb[t] = kb[t] + drb + cx * jxb + cy * jyb + cz * jzb;
+    }
+}
+
+struct ExchAdjArgs {
+    ExchArgs e;           // forward exchange (FP32 source states fA, fB)
+    float* lam_d;         // dL/d(destination) [27][dplane]: read at the targets, then cleared
+    float* mu_d;          // [7][dplane] or null
+    float* lam_a;         // dL/d(fA) [27][splane], accumulated
+    float* lam_b;         // dL/d(fB), accumulated
+    float* mu_a;
+    float* mu_b;
+    float ca, cb;         // time weights of fA and fB: 1 - w and w (0: not touched)
+};
+
+// Adjoint of one exchange launch: one thread per listed target recomputes
+// the target's interpolated source state, applies the map's vector-Jacobian
+// product to the target's adjoint, clears that adjoint (the forward
+// overwrote the target) and adds the trilinear- and time-weighted result to
+// the source adjoints of its corners with atomic adds (neighbouring targets
+// share corners).
+template <bool kScalar, bool kNode>
+__global__ void __launch_bounds__(256) k_exchange_adjoint(const ExchAdjArgs a)
+{
+    const ExchArgs& e = a.e;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= e.n_cells) return;
+    const int c = e.cells[k];
+    int base[3];
+    float t[3];
+    target_stencil(e, c, base, t);
+    if (kNode) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (t[d] >= 0.5f) ++base[d];
+            t[d] = 0.0f;
+        }
+    }
+    const int n[3] = {e.snx, e.sny, e.snz};
+    int ix[2], iy[2], iz[2];
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+        ix[o] = wrap_or_clamp(base[0] + o, n[0], e.speriodic & 1);
+        iy[o] = wrap_or_clamp(base[1] + o, n[1], e.speriodic & 2);
+        iz[o] = wrap_or_clamp(base[2] + o, n[2], e.speriodic & 4);
+    }
+    const float* fA = static_cast<const float*>(e.fA);
+    const float* fB = static_cast<const float*>(e.fB);
+    const float w = e.w;
+    const bool blend = a.ca != 0.0f && a.cb != 0.0f;
+    constexpr int kCorners = kNode ? 1 : 8;
+
+    float v[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) v[q] = 0.0f;
+    float gi[QS] = {0, 0, 0, 0, 0, 0, 0};
+    for (int corner = 0; corner < kCorners; ++corner) {
+        const float wt = corner_weight(t, corner);
+        const int64_t sc = ix[corner & 1] + (int64_t)e.snx * (iy[(corner >> 1) & 1] +
+                                                              (int64_t)e.sny * iz[(corner >> 2) & 1]);
+        for (int i = 0; i < Q; ++i) {
+            const float hA = fA[i * e.splane + sc], hB = fB[i * e.splane + sc];
+            v[tensor_slot(i)] += wt * (blend ? (1.0f - w) * hA + w * hB : (a.cb != 0.0f ? hB : hA));
+        }
+        if (kScalar)
+            for (int i = 0; i < QS; ++i) {
+                const float gA = e.gA[i * e.splane + sc], gB = e.gB[i * e.splane + sc];
+                gi[i] += wt * (blend ? (1.0f - w) * gA + w * gB : (a.cb != 0.0f ? gB : gA));
+            }
+    }
+    float lam[27], mu[QS] = {0, 0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < Q; ++i) {
+        lam[tensor_slot(i)] = a.lam_d[i * e.dplane + c];
+        a.lam_d[i * e.dplane + c] = 0.0f;
+    }
+    if (kScalar)
+        for (int i = 0; i < QS; ++i) {
+            mu[i] = a.mu_d[i * e.dplane + c];
+            a.mu_d[i * e.dplane + c] = 0.0f;
+        }
+    float vb[27], gb[QS];
+    exchange_map_adjoint<kScalar>(v, gi, e.kappa, e.kappa_s, lam, mu, vb, gb);
+    for (int corner = 0; corner < kCorners; ++corner) {
+        const float wt = corner_weight(t, corner);
+        if (wt == 0.0f) continue;
+        const int64_t sc = ix[corner & 1] + (int64_t)e.snx * (iy[(corner >> 1) & 1] +
+                                                              (int64_t)e.sny * iz[(corner >> 2) & 1]);
+        for (int i = 0; i < Q; ++i) {
+            const float b = wt * vb[tensor_slot(i)];
+            if (a.ca != 0.0f) atomicAdd(a.lam_a + i * e.splane + sc, a.ca * b);
+            if (a.cb != 0.0f) atomicAdd(a.lam_b + i * e.splane + sc, a.cb * b);
+        }
+        if (kScalar)
+            for (int i = 0; i < QS; ++i) {
+                const float b = wt * gb[i];
+                if (a.ca != 0.0f) atomicAdd(a.mu_a + i * e.splane + sc, a.ca * b);
+                if (a.cb != 0.0f) atomicAdd(a.mu_b + i * e.splane + sc, a.cb * b);
+            }
+    }
+}
+
+// y = alpha x + beta y over n elements
+__global__ void __launch_bounds__(256) k_axpby(const float* x, float* y, int64_t n, float alpha,
+                                               float beta)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) y[i] = alpha * x[i] + beta * y[i];
+}
+
+__global__ void __launch_bounds__(256) k_zero(float* p, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+static unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// adjoint of launch_exchange(src, fA, fB, w, dst, ..., cells): the
+// destination adjoint lam_d (mu_d) at the cells goes to the source adjoints
+static int launch_exchange_adjoint(const cslbm_level* src, const void* fA, const void* fB,
+                                   const float* gA, const float* gB, double w,
+                                   const cslbm_level* dst, float* lam_d, float* mu_d,
+                                   float* lam_a, float* lam_b, float* mu_a, float* mu_b,
+                                   const int32_t* cells, int32_t n_cells, hipStream_t stream)
+{
+    if (n_cells == 0) return CSLBM_OK;
+    const bool scalar = gA != nullptr && mu_d != nullptr;
+    ExchAdjArgs a;
+    a.e = exchange_args(src, fA, fB, scalar ? gA : nullptr, scalar ? gB : nullptr, w, dst, nullptr,
+                        scalar ? mu_d : nullptr, cells, n_cells);
+    a.lam_d = lam_d;
+    a.mu_d = scalar ? mu_d : nullptr;
+    a.lam_a = lam_a;
+    a.lam_b = lam_b;
+    a.mu_a = mu_a;
+    a.mu_b = mu_b;
+    a.ca = w >= 1.0 ? 0.0f : (float)(1.0 - w);
+    a.cb = w <= 0.0 ? 0.0f : (float)w;
+    const bool node = nodes_coincide(src, dst);
+    const dim3 grid(grid_for(n_cells)), block(256);
+    if (scalar) {
+        if (node)
+            hipLaunchKernelGGL((k_exchange_adjoint<true, true>), grid, block, 0, stream, a);
+        else
+            hipLaunchKernelGGL((k_exchange_adjoint<true, false>), grid, block, 0, stream, a);
+    } else {
+        if (node)
+            hipLaunchKernelGGL((k_exchange_adjoint<false, true>), grid, block, 0, stream, a);
+        else
+            hipLaunchKernelGGL((k_exchange_adjoint<false, false>), grid, block, 0, stream, a);
+    }
+    return check_launch("k_exchange_adjoint");
+}
+
+// Sub-step schedule of a finer scale (Algorithm 1 with the quadratic time
+// interpolation through 0, (l-1)/alpha, l/alpha evaluated at 1).
+struct SubSteps {
+    double alpha, l0, l1, l2;
+    int l, last;
+    bool node;   // integer alpha: the last sub-step has weight 0 and is skipped
+};
+
+static SubSteps sub_steps(const cslbm_scale* S, int i)
+{
+    SubSteps s;
+    s.alpha = S[0].level.dx / S[i].level.dx;
+    s.l = (int)std::floor(s.alpha + 1e-12) + 1;
+    const double t0 = 0.0, t1 = (s.l - 1) / s.alpha, t2 = s.l / s.alpha;
+    s.l0 = (1.0 - t1) * (1.0 - t2) / ((t0 - t1) * (t0 - t2));
+    s.l1 = (1.0 - t0) * (1.0 - t2) / ((t1 - t0) * (t1 - t2));
+    s.l2 = (1.0 - t0) * (1.0 - t1) / ((t2 - t0) * (t2 - t1));
+    s.node = s.l2 == 0.0 && s.l0 == 0.0 && s.l1 == 1.0;
+    s.last = s.node ? s.l - 1 : s.l;
+    return s;
+}
+
+// A population state (27 planes) with its scalar (7 planes) in the workspace.
+struct Buf {
+    float* f;
+    float* g;
+};
+
+struct Layout {
+    int64_t bytes;
+    Buf B0;                          // reference scale after its step
+    Buf cur[CSLBM_MAX_SCALES][8];    // inputs of the sub-steps 1..last (index k - 1)
+    Buf R[CSLBM_MAX_SCALES];         // interpolated state of a finer scale
+    Buf lamA[CSLBM_MAX_SCALES];      // adjoint of each scale's state after its first prior-map
+    Buf t1[CSLBM_MAX_SCALES], t2[CSLBM_MAX_SCALES];   // adjoint temporaries
+};
+
+static int64_t buf_bytes(const cslbm_level* L, bool scalar)
+{
+    const int64_t b = ((int64_t)Q + (scalar ? QS : 0)) * L->plane * 4;
+    return (b + 255) / 256 * 256;
+}
+
+// Workspace layout; with base == nullptr only the size is computed.
+static Layout layout(const cslbm_hierarchy* H, char* base)
+{
+    Layout o;
+    std::memset(&o, 0, sizeof o);
+    const cslbm_scale* S = H->scales;
+    const bool scalar = S[0].level.g != nullptr;
+    int64_t off = 0;
+    auto take = [&](const cslbm_level* L) {
+        Buf b;
+        b.f = base ? reinterpret_cast<float*>(base + off) : nullptr;
+        b.g = (base && scalar) ? b.f + (int64_t)Q * L->plane : nullptr;
+        off += buf_bytes(L, scalar);
+        return b;
+    };
+    o.B0 = take(&S[0].level);
+    o.lamA[0] = take(&S[0].level);
+    o.t1[0] = take(&S[0].level);
+    for (int i = 1; i < H->n_scales; ++i) {
+        const SubSteps ss = sub_steps(S, i);
+        for (int k = 0; k < ss.last; ++k) o.cur[i][k] = take(&S[i].level);
+        o.R[i] = take(&S[i].level);
+        o.lamA[i] = take(&S[i].level);
+        o.t1[i] = take(&S[i].level);
+        o.t2[i] = take(&S[i].level);
+    }
+    o.bytes = off;
+    return o;
+}
+
+static int validate_adjoint_hierarchy(const cslbm_hierarchy* H)
+{
+    int rc = validate_hierarchy(H);
+    if (rc) return rc;
+    const cslbm_scale* S = H->scales;
+    for (int i = 0; i < H->n_scales; ++i) {
+        const cslbm_level* L = &S[i].level;
+        if (L->storage != CSLBM_F32)
+            return fail(CSLBM_ERR_UNSUPPORTED, "scale %d: the multi-scale adjoint needs FP32 storage", i);
+        if (i > 0 && L->dx > S[0].level.dx)
+            return fail(CSLBM_ERR_UNSUPPORTED, "scale %d: far-field scales are not differentiated", i);
+        if (i > 0 && S[i].parent != i - 1)
+            return fail(CSLBM_ERR_UNSUPPORTED,
+                        "scale %d: the multi-scale adjoint needs a chain (parent of scale i is i - 1)", i);
+        if (!L->flags && (L->periodic & 7) != 7)
+            return fail(CSLBM_ERR_UNSUPPORTED, "scale %d: a level without flags must be periodic", i);
+        if (i > 0 && sub_steps(S, i).last > 8)
+            return fail(CSLBM_ERR_UNSUPPORTED, "scale %d: more than 8 sub-steps", i);
+    }
+    return CSLBM_OK;
+}
+
+static void axpby(const float* x, float* y, int64_t n, float alpha, float beta, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(256), 0, st, x, y, n, alpha, beta);
+}
+
+}  // namespace cslbm
+
+using namespace cslbm;
+
+extern "C" {
+
+int cslbm_exchange_adjoint(const cslbm_level* src, const void* fA, const void* fB, const float* gA,
+                           const float* gB, double w, const cslbm_level* dst, float* lam_d,
+                           float* mu_d, float* lam_a, float* lam_b, float* mu_a, float* mu_b,
+                           const int32_t* cells, int32_t n_cells, hipStream_t stream)
+{
+    int rc = validate_shape(src);
+    if (rc) return rc;
+    rc = validate_shape(dst);
+    if (rc) return rc;
+    if (src->storage != CSLBM_F32)
+        return fail(CSLBM_ERR_UNSUPPORTED, "the exchange adjoint reads FP32 source states");
+    if (!(src->dx > 0.0) || !(dst->dx > 0.0)) return fail(CSLBM_ERR_ARG, "scale spacings must be positive");
+    if (std::fabs(1.0 - shear_rate(src)) < 1e-9)
+        return fail(CSLBM_ERR_ARG, "source relaxation time is 1: the mapping is singular");
+    if (!(w >= 0.0 && w <= 1.0)) return fail(CSLBM_ERR_ARG, "time weight %g outside [0, 1]", w);
+    if (n_cells < 0 || (n_cells > 0 && !cells)) return fail(CSLBM_ERR_ARG, "bad cell list");
+    if (!fA || !lam_d) return fail(CSLBM_ERR_ARG, "source state or destination adjoint is NULL");
+    if ((w < 1.0 && !lam_a) || (w > 0.0 && (!fB || !lam_b)))
+        return fail(CSLBM_ERR_ARG, "a time level with nonzero weight needs its state and adjoint");
+    const bool scalar = gA && mu_d;
+    if (scalar && ((w < 1.0 && !mu_a) || (w > 0.0 && (!gB || !mu_b))))
+        return fail(CSLBM_ERR_ARG, "scalar adjoint buffers are NULL");
+    if (lam_d == lam_a || lam_d == lam_b) return fail(CSLBM_ERR_ARG, "destination and source adjoints alias");
+    return launch_exchange_adjoint(src, fA, fB ? fB : fA, scalar ? gA : nullptr,
+                                   scalar ? (gB ? gB : gA) : nullptr, w, dst, lam_d,
+                                   scalar ? mu_d : nullptr, lam_a, lam_b, mu_a, mu_b, cells, n_cells,
+                                   stream);
+}
+
+int64_t cslbm_multiscale_adjoint_bytes(const cslbm_hierarchy* H)
+{
+    if (validate_adjoint_hierarchy(H)) return -1;
+    return layout(H, nullptr).bytes;
+}
+
+int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f_in,
+                                  const float* const* g_in, float* const* lam, float* const* mu,
+                                  void* workspace, int64_t workspace_bytes, hipStream_t stream)
+{
+    int rc = validate_adjoint_hierarchy(H);
+    if (rc) return rc;
+    const int ns = H->n_scales;
+    const cslbm_scale* S = H->scales;
+    const bool scalar = S[0].level.g != nullptr;
+    if (!f_in || !lam) return fail(CSLBM_ERR_ARG, "state or adjoint arrays are NULL");
+    if (scalar && (!g_in || !mu)) return fail(CSLBM_ERR_ARG, "scalar state or adjoint arrays are NULL");
+    for (int i = 0; i < ns; ++i) {
+        if (!f_in[i] || !lam[i]) return fail(CSLBM_ERR_ARG, "scale %d: NULL state or adjoint", i);
+        if (scalar && (!g_in[i] || !mu[i]))
+            return fail(CSLBM_ERR_ARG, "scale %d: NULL scalar state or adjoint", i);
+    }
+    const Layout need = layout(H, nullptr);
+    if (!workspace || workspace_bytes < need.bytes)
+        return fail(CSLBM_ERR_ARG, "workspace of %lld bytes, %lld needed", (long long)workspace_bytes,
+                    (long long)need.bytes);
+    const Layout W = layout(H, static_cast<char*>(workspace));
+    auto nelem = [&](int i) { return ((int64_t)Q + (scalar ? QS : 0)) * S[i].level.plane; };
+
+    // ---- forward recompute of the reference step from the states at t_n ----
+    const void* A[CSLBM_MAX_SCALES];
+    const void* B[CSLBM_MAX_SCALES];
+    const float* gA[CSLBM_MAX_SCALES];
+    const float* gB[CSLBM_MAX_SCALES];
+    {
+        const cslbm_level* L = &S[0].level;
+        rc = launch_step_into(L, f_in[0], W.B0.f, scalar ? g_in[0] : nullptr, W.B0.g, stream);
+        if (rc) return rc;
+        A[0] = f_in[0];
+        gA[0] = scalar ? g_in[0] : nullptr;
+        B[0] = W.B0.f;
+        gB[0] = W.B0.g;
+    }
+    for (int i = 1; i < ns; ++i) {
+        const cslbm_scale& sc = S[i];
+        const cslbm_level* L = &sc.level;
+        const cslbm_level* P = &S[i - 1].level;
+        const int p = i - 1;
+        const SubSteps ss = sub_steps(S, i);
+        const int64_t fb = (int64_t)Q * L->plane * 4, gbytes = (int64_t)QS * L->plane * 4;
+        CSLBM_HIP_TRY(hipMemcpyAsync(W.cur[i][0].f, f_in[i], fb, hipMemcpyDeviceToDevice, stream));
+        if (scalar)
+            CSLBM_HIP_TRY(hipMemcpyAsync(W.cur[i][0].g, g_in[i], gbytes, hipMemcpyDeviceToDevice, stream));
+        for (int k = 1; k <= ss.last; ++k) {
+            const Buf& cur = W.cur[i][k - 1];
+            rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], (k - 1) / ss.alpha, L, cur.f, cur.g,
+                                 sc.ghost_cells, sc.n_ghost, stream);
+            if (rc) return rc;
+            if (k < ss.l) {
+                const Buf& out = (ss.node && k == ss.last) ? W.R[i] : W.cur[i][k];
+                rc = launch_step_into(L, cur.f, out.f, cur.g, out.g, stream);
+            } else {
+                rc = launch_step_interp(L, cur.f, W.R[i].f, cur.g, W.R[i].g, W.cur[i][0].f,
+                                        W.cur[i][0].g, ss.l0, ss.l1, ss.l2, stream);
+            }
+            if (rc) return rc;
+        }
+        rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], 1.0, L, W.R[i].f, W.R[i].g, sc.ghost_cells,
+                             sc.n_ghost, stream);
+        if (rc) return rc;
+        A[i] = W.cur[i][0].f;
+        gA[i] = W.cur[i][0].g;
+        B[i] = W.R[i].f;
+        gB[i] = W.R[i].g;
+    }
+
+    // ---- reverse ----
+    for (int i = 0; i < ns; ++i)
+        hipLaunchKernelGGL(k_zero, dim3(grid_for(nelem(i))), dim3(256), 0, stream, W.lamA[i].f, nelem(i));
+    for (int i = ns - 1; i >= 1; --i) {
+        const cslbm_scale& sc = S[i];
+        const cslbm_level* L = &sc.level;
+        const cslbm_level* P = &S[i - 1].level;
+        const int p = i - 1;
+        const SubSteps ss = sub_steps(S, i);
+        float* lamR = lam[i];
+        float* muR = scalar ? mu[i] : nullptr;
+        // post-mappings into the coarser scales (forward order j = 0 .. i - 1)
+        for (int j = i - 1; j >= 0; --j) {
+            rc = launch_exchange_adjoint(L, W.R[i].f, W.R[i].f, W.R[i].g, W.R[i].g, 0.0, &S[j].level,
+                                         lam[j], scalar ? mu[j] : nullptr, lamR, nullptr, muR,
+                                         nullptr, sc.post_cells[j], sc.n_post[j], stream);
+            if (rc) return rc;
+        }
+        // ghost shell of the interpolated state, mapped at weight 1
+        rc = launch_exchange_adjoint(P, A[p], B[p], gA[p], gB[p], 1.0, L, lamR, muR, W.lamA[p].f,
+                                     lam[p], W.lamA[p].g, scalar ? mu[p] : nullptr, sc.ghost_cells,
+                                     sc.n_ghost, stream);
+        if (rc) return rc;
+        // last sub-step: R = l0 cur_1 + l1 cur_l + l2 step(cur_l), or R = step(cur_last)
+        Buf lc = W.t1[i], spare = W.t2[i];
+        const Buf& in_last = W.cur[i][ss.last - 1];
+        rc = launch_adjoint_into(L, in_last.f, in_last.g, lamR, muR, lc.f, lc.g, nullptr, stream);
+        if (rc) return rc;
+        if (!ss.node) {
+            const int64_t nf = (int64_t)Q * L->plane, ngs = (int64_t)QS * L->plane;
+            axpby(lamR, lc.f, nf, (float)ss.l1, (float)ss.l2, stream);
+            axpby(lamR, W.lamA[i].f, nf, (float)ss.l0, 1.0f, stream);
+            if (scalar) {
+                axpby(muR, lc.g, ngs, (float)ss.l1, (float)ss.l2, stream);
+                axpby(muR, W.lamA[i].g, ngs, (float)ss.l0, 1.0f, stream);
+            }
+        }
+        // lc = adjoint of the input of sub-step k (after its prior-map)
+        for (int k = ss.last; k >= 1; --k) {
+            if (k == 1) {
+                // the first input is also read by the interpolation and by the
+                // next finer scale's prior-maps: their adjoints are in lamA[i]
+                axpby(W.lamA[i].f, lc.f, nelem(i), 1.0f, 1.0f, stream);
+            }
+            rc = launch_exchange_adjoint(P, A[p], B[p], gA[p], gB[p], (k - 1) / ss.alpha, L, lc.f,
+                                         lc.g, W.lamA[p].f, lam[p], W.lamA[p].g,
+                                         scalar ? mu[p] : nullptr, sc.ghost_cells, sc.n_ghost, stream);
+            if (rc) return rc;
+            if (k == 1) break;
+            const Buf& in = W.cur[i][k - 2];
+            rc = launch_adjoint_into(L, in.f, in.g, lc.f, lc.g, spare.f, spare.g, nullptr, stream);
+            if (rc) return rc;
+            const Buf tmp = lc;
+            lc = spare;
+            spare = tmp;
+        }
+        // lc = dL/d(state of scale i at t_n)
+        CSLBM_HIP_TRY(hipMemcpyAsync(lam[i], lc.f, (int64_t)Q * L->plane * 4, hipMemcpyDeviceToDevice,
+                                     stream));
+        if (scalar)
+            CSLBM_HIP_TRY(hipMemcpyAsync(mu[i], lc.g, (int64_t)QS * L->plane * 4,
+                                         hipMemcpyDeviceToDevice, stream));
+    }
+    {
+        const cslbm_level* L = &S[0].level;
+        rc = launch_adjoint_into(L, f_in[0], scalar ? g_in[0] : nullptr, lam[0],
+                                 scalar ? mu[0] : nullptr, W.t1[0].f, W.t1[0].g, nullptr, stream);
+        if (rc) return rc;
+        const int64_t nf = (int64_t)Q * L->plane, ngs = (int64_t)QS * L->plane;
+        axpby(W.t1[0].f, W.lamA[0].f, nf, 1.0f, 1.0f, stream);
+        CSLBM_HIP_TRY(hipMemcpyAsync(lam[0], W.lamA[0].f, nf * 4, hipMemcpyDeviceToDevice, stream));
+        if (scalar) {
+            axpby(W.t1[0].g, W.lamA[0].g, ngs, 1.0f, 1.0f, stream);
+            CSLBM_HIP_TRY(hipMemcpyAsync(mu[0], W.lamA[0].g, ngs * 4, hipMemcpyDeviceToDevice, stream));
+        }
+    }
+    return check_launch("cslbm_multiscale_adjoint_step");
+}
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+// exchange.hpp -- arguments and stencil geometry of the cross-scale
+// exchange (section "Spatial scale mapping"), shared by the exchange kernels
+// and their adjoints.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "../../include/cslbm.h"
+
+namespace cslbm {
+
+struct ExchArgs {
+    const void* fA;
+    const void* fB;
+    const float* gA;
+    const float* gB;
+    int snx, sny, snz, speriodic;
+    int64_t splane;
+    double sorigin[3], sdx;
+    void* fo;
+    float* go;
+    int dnx, dny;
+    int64_t dplane;
+    double dorigin[3], ddx;
+    const int32_t* cells;
+    int n_cells;
+    float w;
+    float kappa;     // stress rescaling
+    float kappa_s;   // scalar non-equilibrium rescaling
+};
+
+__device__ __forceinline__ int wrap_or_clamp(int i, int n, bool periodic)
+{
+    if (periodic) {
+        i %= n;
+        return i < 0 ? i + n : i;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);   // lists are validated on the host
+}
+
+// target point of list entry k in source lattice coordinates: base corner
+// and trilinear fractions (geometry in FP64 so coincident nodes resolve)
+__device__ __forceinline__ void target_stencil(const ExchArgs& a, int c, int (&base)[3], float (&t)[3])
+{
+    const int x = c % a.dnx, y = (c / a.dnx) % a.dny, z = c / (a.dnx * a.dny);
+    const double p[3] = {a.dorigin[0] + x * a.ddx, a.dorigin[1] + y * a.ddx, a.dorigin[2] + z * a.ddx};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double q = (p[d] - a.sorigin[d]) / a.sdx;
+        const double b = floor(q);
+        base[d] = (int)b;
+        t[d] = (float)(q - b);
+    }
+}
+
+__device__ __forceinline__ float corner_weight(const float (&t)[3], int corner)
+{
+    const int ox = corner & 1, oy = (corner >> 1) & 1, oz = (corner >> 2) & 1;
+    return (ox ? t[0] : 1.0f - t[0]) * (oy ? t[1] : 1.0f - t[1]) * (oz ? t[2] : 1.0f - t[2]);
+}
+
+inline double shear_rate(const cslbm_level* L) { return 1.0 / (3.0 * L->p.nu + 0.5); }
+
+// Every target lies on a source lattice point: the target spacing is a whole
+// multiple of the source spacing and the origins are whole source cells apart.
+inline bool nodes_coincide(const cslbm_level* src, const cslbm_level* dst)
+{
+    const double r = dst->dx / src->dx;
+    if (!(r >= 1.0 - 1e-9) || std::fabs(r - std::nearbyint(r)) > 1e-9) return false;
+    for (int d = 0; d < 3; ++d) {
+        const double o = (dst->origin[d] - src->origin[d]) / src->dx;
+        if (std::fabs(o - std::nearbyint(o)) > 1e-9) return false;
+    }
+    return true;
+}
+
+// Kernel arguments of one exchange from src (states fA, fB blended with
+// weight w) to the listed cells of dst (outputs f_out, g_out).
+inline ExchArgs exchange_args(const cslbm_level* src, const void* fA, const void* fB,
+                              const float* gA, const float* gB, double w, const cslbm_level* dst,
+                              void* f_out, float* g_out, const int32_t* cells, int32_t n_cells)
+{
+    ExchArgs a;
+    a.fA = fA;
+    a.fB = fB ? fB : fA;
+    const bool scalar = gA && g_out;
+    a.gA = scalar ? gA : nullptr;
+    a.gB = scalar ? (gB ? gB : gA) : nullptr;
+    a.snx = src->nx;
+    a.sny = src->ny;
+    a.snz = src->nz;
+    a.speriodic = src->periodic & 7;
+    a.splane = src->plane;
+    std::memcpy(a.sorigin, src->origin, sizeof a.sorigin);
+    a.sdx = src->dx;
+    a.fo = f_out;
+    a.go = scalar ? g_out : nullptr;
+    a.dnx = dst->nx;
+    a.dny = dst->ny;
+    a.dplane = dst->plane;
+    std::memcpy(a.dorigin, dst->origin, sizeof a.dorigin);
+    a.ddx = dst->dx;
+    a.cells = cells;
+    a.n_cells = n_cells;
+    a.w = (float)w;
+    const double alpha = src->dx / dst->dx;
+    const double Ss = shear_rate(src), Sd = shear_rate(dst);
+    a.kappa = (float)((1.0 - Sd) / (1.0 - Ss) * Ss / (alpha * Sd));
+    a.kappa_s = scalar ? (float)((dst->p.tau_s - 1.0) / (alpha * (src->p.tau_s - 1.0))) : 0.0f;
+    return a;
+}
+
+// One exchange launch (validated arguments); defined with the kernels.
+int launch_exchange(const cslbm_level* src, const void* fA, const void* fB, const float* gA,
+                    const float* gB, double w, const cslbm_level* dst, void* f_out, float* g_out,
+                    const int32_t* cells, int32_t n_cells, hipStream_t stream);
+
+// Adjoint of one collide-stream step of level L from the input state
+// (fin, gin): lam = dL/d(input) from lam_next = dL/d(output) (likewise mu for
+// the scalar), dtheta accumulated when not null.  Arguments validated.
+int launch_adjoint_into(const cslbm_level* L, const void* fin, const float* gin,
+                        const float* lam_next, const float* mu_next, float* lam, float* mu,
+                        float* dtheta, hipStream_t stream);
+
+// Checks of a hierarchy (scale kinds, parents, lists, buffers) shared by the
+// multi-scale step and its adjoint; 0 or an error code with the message set.
+int validate_hierarchy(const cslbm_hierarchy* H);
+
+}  // namespace cslbm

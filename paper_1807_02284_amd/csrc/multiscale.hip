@@ -20,60 +20,11 @@
 
 #include "../../include/cslbm.h"
 #include "cm_collide.hpp"
+#include "exchange.hpp"
 #include "internal.hpp"
 #include "lattice.hpp"
 
 namespace cslbm {
-
-struct ExchArgs {
-    const void* fA;
-    const void* fB;
-    const float* gA;
-    const float* gB;
-    int snx, sny, snz, speriodic;
-    int64_t splane;
-    double sorigin[3], sdx;
-    void* fo;
-    float* go;
-    int dnx, dny;
-    int64_t dplane;
-    double dorigin[3], ddx;
-    const int32_t* cells;
-    int n_cells;
-    float w;
-    float kappa;     // stress rescaling
-    float kappa_s;   // scalar non-equilibrium rescaling
-};
-
-__device__ __forceinline__ int wrap_or_clamp(int i, int n, bool periodic)
-{
-    if (periodic) {
-        i %= n;
-        return i < 0 ? i + n : i;
-    }
-    return i < 0 ? 0 : (i >= n ? n - 1 : i);   // lists are validated on the host
-}
-
-// target point of list entry k in source lattice coordinates: base corner
-// and trilinear fractions (geometry in FP64 so coincident nodes resolve)
-__device__ __forceinline__ void target_stencil(const ExchArgs& a, int c, int (&base)[3], float (&t)[3])
-{
-    const int x = c % a.dnx, y = (c / a.dnx) % a.dny, z = c / (a.dnx * a.dny);
-    const double p[3] = {a.dorigin[0] + x * a.ddx, a.dorigin[1] + y * a.ddx, a.dorigin[2] + z * a.ddx};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const double q = (p[d] - a.sorigin[d]) / a.sdx;
-        const double b = floor(q);
-        base[d] = (int)b;
-        t[d] = (float)(q - b);
-    }
-}
-
-__device__ __forceinline__ float corner_weight(const float (&t)[3], int corner)
-{
-    const int ox = corner & 1, oy = (corner >> 1) & 1, oz = (corner >> 2) & 1;
-    return (ox ? t[0] : 1.0f - t[0]) * (oy ? t[1] : 1.0f - t[1]) * (oz ? t[2] : 1.0f - t[2]);
-}
 
 // central-moment mapping of an interpolated post-collision state (in place,
 // tensor order) and the stores of population and scalar outputs
@@ -219,7 +170,6 @@ __global__ void __launch_bounds__(256) k_time_interp(const T* s0, const T* s1, c
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-static double shear_rate(const cslbm_level* L) { return 1.0 / (3.0 * L->p.nu + 0.5); }
 
 template <typename Ts, typename Td>
 static void launch_exchange_kernel(const ExchArgs& a, bool blend, bool scalar, bool node,
@@ -242,49 +192,14 @@ static void launch_exchange_kernel(const ExchArgs& a, bool blend, bool scalar, b
 
 // Every target point of dst is a lattice point of src: the spacing ratio is
 // a whole number and the origins differ by whole source cells.
-static bool nodes_coincide(const cslbm_level* src, const cslbm_level* dst)
-{
-    const double r = dst->dx / src->dx;
-    if (!(r >= 1.0 - 1e-9) || std::fabs(r - std::nearbyint(r)) > 1e-9) return false;
-    for (int d = 0; d < 3; ++d) {
-        const double o = (dst->origin[d] - src->origin[d]) / src->dx;
-        if (std::fabs(o - std::nearbyint(o)) > 1e-9) return false;
-    }
-    return true;
-}
 
-static int launch_exchange(const cslbm_level* src, const void* fA, const void* fB, const float* gA,
-                           const float* gB, double w, const cslbm_level* dst, void* f_out,
-                           float* g_out, const int32_t* cells, int32_t n_cells, hipStream_t stream)
+int launch_exchange(const cslbm_level* src, const void* fA, const void* fB, const float* gA,
+                    const float* gB, double w, const cslbm_level* dst, void* f_out, float* g_out,
+                    const int32_t* cells, int32_t n_cells, hipStream_t stream)
 {
     if (n_cells == 0) return CSLBM_OK;
-    ExchArgs a;
-    a.fA = fA;
-    a.fB = fB ? fB : fA;
-    const bool scalar = gA && g_out;
-    a.gA = scalar ? gA : nullptr;
-    a.gB = scalar ? (gB ? gB : gA) : nullptr;
-    a.snx = src->nx;
-    a.sny = src->ny;
-    a.snz = src->nz;
-    a.speriodic = src->periodic & 7;
-    a.splane = src->plane;
-    std::memcpy(a.sorigin, src->origin, sizeof a.sorigin);
-    a.sdx = src->dx;
-    a.fo = f_out;
-    a.go = scalar ? g_out : nullptr;
-    a.dnx = dst->nx;
-    a.dny = dst->ny;
-    a.dplane = dst->plane;
-    std::memcpy(a.dorigin, dst->origin, sizeof a.dorigin);
-    a.ddx = dst->dx;
-    a.cells = cells;
-    a.n_cells = n_cells;
-    a.w = (float)w;
-    const double alpha = src->dx / dst->dx;
-    const double Ss = shear_rate(src), Sd = shear_rate(dst);
-    a.kappa = (float)((1.0 - Sd) / (1.0 - Ss) * Ss / (alpha * Sd));
-    a.kappa_s = scalar ? (float)((dst->p.tau_s - 1.0) / (alpha * (src->p.tau_s - 1.0))) : 0.0f;
+    ExchArgs a = exchange_args(src, fA, fB, gA, gB, w, dst, f_out, g_out, cells, n_cells);
+    const bool scalar = a.gA != nullptr;
     // all the weight on one time level: read only that level
     const bool blend = w > 0.0 && w < 1.0;
     if (!blend && w >= 1.0) {
@@ -344,52 +259,20 @@ static int validate_exchange_pair(const cslbm_level* src, const cslbm_level* dst
     return CSLBM_OK;
 }
 
-}  // namespace cslbm
-
-using namespace cslbm;
-
-extern "C" {
-
-int cslbm_exchange(const cslbm_level* src, const void* fA, const void* fB, const float* gA,
-                   const float* gB, double w, const cslbm_level* dst, void* f_out, float* g_out,
-                   const int32_t* cells, int32_t n_cells, hipStream_t stream)
-{
-    int rc = validate_exchange_pair(src, dst);
-    if (rc) return rc;
-    if (!fA || !f_out) return fail(CSLBM_ERR_ARG, "source or destination populations are NULL");
-    if (n_cells < 0 || (n_cells > 0 && !cells)) return fail(CSLBM_ERR_ARG, "bad cell list");
-    if (!(w >= 0.0 && w <= 1.0)) return fail(CSLBM_ERR_ARG, "time weight %g outside [0, 1]", w);
-    if (g_out && gA && std::fabs(src->p.tau_s - 1.0) < 1e-9)
-        return fail(CSLBM_ERR_ARG, "source scalar relaxation time is 1 (singular mapping)");
-    return launch_exchange(src, fA, fB, gA, gB, w, dst, f_out, g_out, cells, n_cells, stream);
-}
-
-int cslbm_time_interp(const cslbm_level* L, const void* s0, const void* s1, const void* s2,
-                      const float* g0, const float* g1, const float* g2, const double t[3],
-                      double t_eval, void* out, float* g_out, hipStream_t stream)
-{
-    int rc = validate_shape(L);
-    if (rc) return rc;
-    if (!s0 || !s1 || !s2 || !out || !t) return fail(CSLBM_ERR_ARG, "NULL state or times");
-    if (t[0] == t[1] || t[0] == t[2] || t[1] == t[2])
-        return fail(CSLBM_ERR_ARG, "interpolation times must be distinct");
-    return launch_time_interp(L, s0, s1, s2, g0, g1, g2, t, t_eval, out, g_out, stream);
-}
-
 // a scale with a larger spacing than the reference scale (far field)
 static bool far_field(const cslbm_scale* S, int i) { return i > 0 && S[i].level.dx > S[0].level.dx; }
 
-int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t stream)
+// Checks of a hierarchy shared by the multi-scale step and its adjoint.
+int validate_hierarchy(const cslbm_hierarchy* H)
 {
     if (!H || !H->scales) return fail(CSLBM_ERR_ARG, "hierarchy is NULL");
     const int ns = H->n_scales;
     if (ns < 1 || ns > CSLBM_MAX_SCALES)
         return fail(CSLBM_ERR_ARG, "n_scales = %d outside [1, %d]", ns, CSLBM_MAX_SCALES);
-    if (n_ref_steps < 0) return fail(CSLBM_ERR_ARG, "n_ref_steps is negative");
-    cslbm_scale* S = H->scales;
+    const cslbm_scale* S = H->scales;
     const bool scalar = S[0].level.g != nullptr;
     for (int i = 0; i < ns; ++i) {
-        cslbm_level* L = &S[i].level;
+        const cslbm_level* L = &S[i].level;
         int rc = validate_shape(L);
         if (rc) return fail(rc, "scale %d: %s", i, cslbm_last_error());
         rc = validate_params(L);
@@ -440,6 +323,49 @@ int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t s
                 return fail(CSLBM_ERR_ARG, "scale %d: bad post-mapping list for scale %d", i, j);
     }
 
+    return CSLBM_OK;
+}
+
+}  // namespace cslbm
+
+using namespace cslbm;
+
+extern "C" {
+
+int cslbm_exchange(const cslbm_level* src, const void* fA, const void* fB, const float* gA,
+                   const float* gB, double w, const cslbm_level* dst, void* f_out, float* g_out,
+                   const int32_t* cells, int32_t n_cells, hipStream_t stream)
+{
+    int rc = validate_exchange_pair(src, dst);
+    if (rc) return rc;
+    if (!fA || !f_out) return fail(CSLBM_ERR_ARG, "source or destination populations are NULL");
+    if (n_cells < 0 || (n_cells > 0 && !cells)) return fail(CSLBM_ERR_ARG, "bad cell list");
+    if (!(w >= 0.0 && w <= 1.0)) return fail(CSLBM_ERR_ARG, "time weight %g outside [0, 1]", w);
+    if (g_out && gA && std::fabs(src->p.tau_s - 1.0) < 1e-9)
+        return fail(CSLBM_ERR_ARG, "source scalar relaxation time is 1 (singular mapping)");
+    return launch_exchange(src, fA, fB, gA, gB, w, dst, f_out, g_out, cells, n_cells, stream);
+}
+
+int cslbm_time_interp(const cslbm_level* L, const void* s0, const void* s1, const void* s2,
+                      const float* g0, const float* g1, const float* g2, const double t[3],
+                      double t_eval, void* out, float* g_out, hipStream_t stream)
+{
+    int rc = validate_shape(L);
+    if (rc) return rc;
+    if (!s0 || !s1 || !s2 || !out || !t) return fail(CSLBM_ERR_ARG, "NULL state or times");
+    if (t[0] == t[1] || t[0] == t[2] || t[1] == t[2])
+        return fail(CSLBM_ERR_ARG, "interpolation times must be distinct");
+    return launch_time_interp(L, s0, s1, s2, g0, g1, g2, t, t_eval, out, g_out, stream);
+}
+
+
+int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t stream)
+{
+    int vrc = validate_hierarchy(H);
+    if (vrc) return vrc;
+    if (n_ref_steps < 0) return fail(CSLBM_ERR_ARG, "n_ref_steps is negative");
+    const int ns = H->n_scales;
+    cslbm_scale* S = H->scales;
     // states of each scale at t_n (A) and t_n + dt_0 (B) within one reference step
     const void* A[CSLBM_MAX_SCALES];
     void* B[CSLBM_MAX_SCALES];

@@ -274,6 +274,37 @@ class Hierarchy:
             lev._sync_struct()
 
 
+    def _sync_scales(self):
+        for i, lev in enumerate(self.levels):
+            lev._sync_struct()
+            self.c_scales[i].level = lev.c
+
+    def adjoint_workspace_bytes(self) -> int:
+        """Workspace bytes of adjoint_step (raises if the hierarchy is outside
+        the adjoint's scope)."""
+        self._sync_scales()
+        lib = _capi.load()
+        n = lib.cslbm_multiscale_adjoint_bytes(C.byref(self.c))
+        if n < 0:
+            raise _capi.CslbmError(_capi.ERR_UNSUPPORTED, "cslbm_multiscale_adjoint_bytes",
+                                   lib.cslbm_last_error().decode())
+        return int(n)
+
+    def adjoint_step(self, f_in, g_in, lam, mu, workspace: torch.Tensor, stream=None):
+        """Adjoint of one reference step (cslbm_multiscale_adjoint_step).
+        f_in[i] / g_in[i]: scale i's state at t_n ([27][plane] / [7][plane]
+        buffers); lam[i] / mu[i]: in dL/d(state at t_n + dt_0), out dL/d(state
+        at t_n), overwritten in place."""
+        self._sync_scales()
+        n = len(self.levels)
+        scalar = self.levels[0].g is not None
+        vp = C.c_void_p * n
+        ptrs = lambda ts: vp(*[t.data_ptr() for t in ts])  # noqa: E731
+        _capi.call("cslbm_multiscale_adjoint_step", C.byref(self.c), ptrs(f_in),
+                   ptrs(g_in) if scalar else None, ptrs(lam), ptrs(mu) if scalar else None,
+                   workspace.data_ptr(), workspace.numel(), _stream_handle(stream))
+
+
 # ---------------------------------------------------------------------------
 # dynamic scale construction (section "Scale construction", dynamic scales)
 # ---------------------------------------------------------------------------

@@ -8,6 +8,12 @@ initial populations come from the hand-written adjoint step of libcslbm
 forward pass and each segment is recomputed with ``cslbm_step_store`` in the
 backward pass.  Tensors are dense: theta [3][N], h0 [27][N] shifted
 populations f - w, g0 [7][N].
+
+``MultiscaleRollout`` does the same for the reference steps of a hierarchy
+(Algorithm 1 over a chain of finer scales): ``forward(n_ref)`` keeps every
+``every``-th set of scale states, ``backward`` recomputes each segment one
+reference step at a time and applies ``cslbm_multiscale_adjoint_step`` in
+reverse, giving dL/d(initial state) of every scale from dL/d(final state).
 """
 from __future__ import annotations
 
@@ -68,3 +74,62 @@ class _Rollout(torch.autograd.Function):
 def rollout(lev: Level, theta: torch.Tensor, h0: torch.Tensor, g0: torch.Tensor, n_steps: int,
             every: int = 20) -> torch.Tensor:
     return _Rollout.apply(theta, h0, g0, lev, int(n_steps), int(every))
+
+
+class MultiscaleRollout:
+    """Checkpointed reference steps of a hierarchy and their adjoint."""
+
+    def __init__(self, H, every: int = 10):
+        self.H = H
+        self.every = max(1, int(every))
+        self.checkpoints = []
+        self.workspace = torch.empty(H.adjoint_workspace_bytes(), dtype=torch.uint8,
+                                     device=H.levels[0].device)
+
+    def _states(self):
+        return ([lev.f.clone() for lev in self.H.levels],
+                [None if lev.g is None else lev.g.clone() for lev in self.H.levels])
+
+    def _restore(self, fs, gs):
+        for lev, f, g in zip(self.H.levels, fs, gs):
+            lev.f.copy_(f)
+            if g is not None:
+                lev.g.copy_(g)
+
+    def forward(self, n_ref: int):
+        """n_ref reference steps from the scales' current states."""
+        self.checkpoints = []
+        done = 0
+        while done < n_ref:
+            k = min(self.every, n_ref - done)
+            self.checkpoints.append((k, *self._states()))
+            self.H.step(k)
+            done += k
+        self.final = self._states()
+
+    def backward(self, lam_f, lam_g=None):
+        """lam_f[i]: dL/d(final populations of scale i), dense [27][N_i]
+        (lam_g[i]: [7][N_i] with a scalar).  Returns the adjoints of the
+        initial states in the same form.  The scales are left in their final
+        forward state."""
+        H = self.H
+        scalar = H.levels[0].g is not None
+        lam, mu = [], []
+        for i, lev in enumerate(H.levels):
+            lam.append(_dense_to_plane(lev, lam_f[i], 27).reshape(-1))
+            mu.append(_dense_to_plane(lev, lam_g[i], 7).reshape(-1) if scalar else None)
+        for k, fs, gs in reversed(self.checkpoints):
+            states = [(fs, gs)]
+            if k > 1:
+                self._restore(fs, gs)
+                for _ in range(k - 1):
+                    H.step(1)
+                    states.append(self._states())
+            for f_n, g_n in reversed(states):
+                H.adjoint_step(f_n, g_n if scalar else None, lam, mu if scalar else None,
+                               self.workspace)
+        self._restore(*self.final)
+        out_f = [l.reshape(27, lev.plane)[:, : lev.n].clone() for l, lev in zip(lam, H.levels)]
+        out_g = ([m.reshape(7, lev.plane)[:, : lev.n].clone() for m, lev in zip(mu, H.levels)]
+                 if scalar else None)
+        return out_f, out_g

@@ -108,8 +108,8 @@ def test_adjoint_and_step_store_argument_checks(lib):
     assert adj(C.byref(L), None, None, 0x5000, None, None, None) == _capi.ERR_ARG
     assert adj(C.byref(L), 0x5000, None, 0x5000, None, None, None) == _capi.ERR_ARG
     assert "alias" in err(lib)
-    flagged = make_level(flags=0x9000)
-    assert adj(C.byref(flagged), 0x5000, None, 0x6000, None, None, None) == _capi.ERR_UNSUPPORTED
+    open_box = make_level(periodic=3)                # no flags: only fully periodic boxes
+    assert adj(C.byref(open_box), 0x5000, None, 0x6000, None, None, None) < 0
     grad = make_level(p_grad_mode=1)
     assert adj(C.byref(grad), 0x5000, None, 0x6000, None, None, None) == _capi.ERR_UNSUPPORTED
     scalar = make_level(g=0x3000, g_next=0x4000, p_tau_s=0.6)
@@ -129,3 +129,31 @@ def test_gradient_mode_argument_checks(lib):
     assert "vel" in err(lib)
     flagged = make_level(p_grad_mode=1, flags=0x9000, vel=0xB000, vel_next=0xC000)
     assert lib.cslbm_step(C.byref(flagged), 1, None) == _capi.ERR_UNSUPPORTED
+
+
+def test_multiscale_adjoint_argument_checks(lib):
+    ab, adj = lib.cslbm_multiscale_adjoint_bytes, lib.cslbm_multiscale_adjoint_step
+    L0 = make_level(dx=1.0)
+    L1 = make_level(dx=0.5, flags=0x9000, periodic=0)
+    L2 = make_level(dx=0.25, flags=0x9100, periodic=0)
+    H, keep = hierarchy_of([L0, L1, L2], [-1, 0, 1])
+    n = ab(C.byref(H))
+    assert n > 0
+    ptrs = (C.c_void_p * 3)(0x1000, 0x2000, 0x3000)
+    assert adj(C.byref(H), ptrs, None, ptrs, None, None, n, None) == _capi.ERR_ARG
+    assert "workspace" in err(lib)
+    assert adj(C.byref(H), ptrs, None, ptrs, None, 0xF000, n - 1, None) == _capi.ERR_ARG
+    assert adj(C.byref(H), None, None, ptrs, None, 0xF000, n, None) == _capi.ERR_ARG
+    # not a chain
+    H, keep = hierarchy_of([L0, L1, L2], [-1, 0, 0])
+    assert ab(C.byref(H)) == -1
+    assert "chain" in err(lib)
+    assert adj(C.byref(H), ptrs, None, ptrs, None, 0xF000, n, None) == _capi.ERR_UNSUPPORTED
+    # binary16 storage
+    H, keep = hierarchy_of([L0, make_level(dx=0.5, flags=0x9000, periodic=0, storage=_capi.F16S)],
+                           [-1, 0])
+    assert ab(C.byref(H)) == -1
+    assert "FP32" in err(lib)
+    # a far-field scale
+    H, keep = hierarchy_of([L0, make_level(dx=2.0, flags=0x9000, periodic=0)], [-1, 0])
+    assert ab(C.byref(H)) == -1

@@ -45,13 +45,15 @@ class Spec:
         self.tau_s = 0.5 + self.alpha * (tau_s0 - 0.5)
         self.kinds, self.periodic, self.parent = kinds, periodic, parent
         self.u_in, self.s_in = u_in, s_in
+        self.adaptive = True
 
     @property
     def n(self):
         return int(np.prod(self.shape))
 
     def params(self):
-        return Params(nu=self.nu, g_max=0.05, tau_s=self.tau_s, u_in=self.u_in, s_in=self.s_in)
+        return Params(nu=self.nu, g_max=0.05, tau_s=self.tau_s, u_in=self.u_in, s_in=self.s_in,
+                      adaptive=self.adaptive)
 
     def level(self, scalar):
         flags = None if (self.periodic == 7 and np.all(self.kinds == 0)) else self.kinds
@@ -61,7 +63,8 @@ class Spec:
     def oscale(self):
         p = self.params()
         return ml.OScale(*self.shape, self.dx, self.origin,
-                         oracle.Params(nu=p.nu, g_max=p.g_max, tau_s=p.tau_s), self.kinds,
+                         oracle.Params(nu=p.nu, g_max=p.g_max, tau_s=p.tau_s, adaptive=p.adaptive),
+                         self.kinds,
                          periodic=self.periodic, parent=self.parent, u_in=self.u_in, s_in=self.s_in)
 
     def positions(self):

@@ -344,12 +344,24 @@ int cslbm_adjoint_step(const cslbm_level* L, const float* lam_next, const float*
  * lam_a += (1 - w) J^T lam_d and lam_b += w J^T lam_d (J the trilinear
  * interpolation followed by the central-moment rescaling of the target
  * state), likewise mu_a / mu_b.  A time level of weight 0 is not read or
- * touched and may be NULL.  FP32 source states only (CSLBM_ERR_UNSUPPORTED);
- * targets sharing source corners are summed with atomic adds. */
+ * touched and may be NULL.  FP32 source states only (CSLBM_ERR_UNSUPPORTED).
+ * workspace NULL: targets sharing source corners are summed with atomic adds
+ * (summation order not reproducible).  workspace DEVICE of at least
+ * cslbm_exchange_adjoint_bytes(src, dst, n_cells) bytes (caller-owned,
+ * contents overwritten): the gather form, where each source cell sums its
+ * targets' contributions itself (reproducible; targets whose stencil wraps
+ * or is clamped at the source faces still use atomic adds). */
 int cslbm_exchange_adjoint(const cslbm_level* src, const void* fA, const void* fB, const float* gA,
                            const float* gB, double w, const cslbm_level* dst, float* lam_d,
                            float* mu_d, float* lam_a, float* lam_b, float* mu_a, float* mu_b,
-                           const int32_t* cells, int32_t n_cells, hipStream_t stream);
+                           const int32_t* cells, int32_t n_cells, void* workspace,
+                           int64_t workspace_bytes, hipStream_t stream);
+
+/* Workspace bytes of the gather form of cslbm_exchange_adjoint for n_cells
+ * targets (a [34][n_cells] FP32 buffer, an int32 index map of the
+ * destination box and a byte flag per source cell); -1 for NULL levels or a
+ * negative count. */
+int64_t cslbm_exchange_adjoint_bytes(const cslbm_level* src, const cslbm_level* dst, int32_t n_cells);
 
 /* Workspace bytes that cslbm_multiscale_adjoint_step needs for H (the input
  * of every sub-step, the interpolated states and adjoint temporaries of all
@@ -361,7 +373,11 @@ int64_t cslbm_multiscale_adjoint_bytes(const cslbm_hierarchy* H);
  * sub-step times, sub-steps with the quadratic time interpolation, ghost
  * remap at weight 1, post-mapping into every coarser scale).
  *   f_in[i], g_in[i]  DEVICE states of scale i at t_n (HOST arrays of
- *                     n_scales pointers; g_in NULL without scalar); read only
+ *                     n_scales pointers; g_in NULL without scalar).  The
+ *                     GHOST cells of the finer scales' states are rewritten
+ *                     with their prior-mapped values, as the forward step
+ *                     does (their old values never enter the step); all
+ *                     other elements are read only
  *   lam[i], mu[i]     in: dL/d(state of scale i at t_n + dt_0) [27|7][plane];
  *                     out: dL/d(state of scale i at t_n)
  *   workspace         DEVICE, at least cslbm_multiscale_adjoint_bytes(H)
@@ -370,8 +386,9 @@ int64_t cslbm_multiscale_adjoint_bytes(const cslbm_hierarchy* H);
  * force and parameters of H are used as in the forward step.  Supported:
  * FP32 storage, finer scales only (no far-field scale), every finer scale's
  * parent is the next coarser one (scale i's parent is i - 1); the force
- * field is held fixed (no dL/dtheta).  Target adjoints of the exchanges are
- * propagated with atomic adds, so the result is not bit-reproducible.
+ * field is held fixed (no dL/dtheta).  The exchange adjoints use the gather
+ * form of cslbm_exchange_adjoint in the workspace (reproducible except for
+ * targets whose stencil wraps at a periodic face).
  * Errors: CSLBM_ERR_UNSUPPORTED outside that scope, CSLBM_ERR_ARG for NULL
  * buffers or a short workspace, and the checks of cslbm_multiscale_step. */
 int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f_in,

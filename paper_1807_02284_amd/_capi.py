@@ -116,7 +116,9 @@ _SIGNATURES = {
     "cslbm_adjoint_step": (C.c_int, [C.POINTER(CslbmLevel), _vp, _vp, _vp, _vp, _vp, _vp]),
     "cslbm_exchange_adjoint": (C.c_int, [C.POINTER(CslbmLevel), _vp, _vp, _vp, _vp, C.c_double,
                                          C.POINTER(CslbmLevel), _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                                         C.c_int32, _vp]),
+                                         C.c_int32, _vp, C.c_int64, _vp]),
+    "cslbm_exchange_adjoint_bytes": (C.c_int64, [C.POINTER(CslbmLevel), C.POINTER(CslbmLevel),
+                                                 C.c_int32]),
     "cslbm_multiscale_adjoint_bytes": (C.c_int64, [C.POINTER(CslbmHierarchy)]),
     "cslbm_multiscale_adjoint_step": (C.c_int, [C.POINTER(CslbmHierarchy), C.POINTER(_vp),
                                                 C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp),

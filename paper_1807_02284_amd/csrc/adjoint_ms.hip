@@ -14,6 +14,7 @@
 // clears it there.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -253,12 +254,303 @@ __global__ void __launch_bounds__(256) k_exchange_adjoint(const ExchAdjArgs a)
     }
 }
 
+// Gather form of the exchange adjoint, without atomics.  Pass A (one thread
+// per target): the target's vector-Jacobian product goes to column k of a
+// [34][n] buffer, the target's cell to a dense index map of the destination
+// box and its source corners are flagged; targets whose stencil wraps or is
+// clamped at the source box's faces are scattered with atomics instead.  Pass
+// B (one thread per flagged source cell): the cell sums weight times column
+// over the targets whose stencil holds it, found through the index map, and
+// adds the sum to its own adjoint entries (one writer per entry).  Pass C
+// resets the index map; pass B resets the flags.
+struct GatherWs {
+    float* vb;          // [34][n_cells] per-target products
+    int32_t* map;       // [dst cells]: list index of a gathered target, -1 otherwise
+    uint8_t* touched;   // [src cells]: 1 for a source corner of a gathered target
+};
+
+// Stencil of list entry k (forward arithmetic): corner indices after wrap or
+// clamp, trilinear fractions, and whether the stencil lies inside the source
+// box without wrapping or clamping.
+template <bool kNode>
+__device__ __forceinline__ bool target_corners(const ExchArgs& e, int c, int (&ix)[2], int (&iy)[2],
+                                               int (&iz)[2], float (&t)[3])
+{
+    int base[3];
+    target_stencil(e, c, base, t);
+    if (kNode) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            if (t[d] >= 0.5f) ++base[d];
+            t[d] = 0.0f;
+        }
+    }
+    const int n[3] = {e.snx, e.sny, e.snz};
+    bool interior = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        interior = interior && base[d] >= 0 && base[d] + (kNode ? 0 : 1) <= n[d] - 1;
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+        ix[o] = wrap_or_clamp(base[0] + o, n[0], e.speriodic & 1);
+        iy[o] = wrap_or_clamp(base[1] + o, n[1], e.speriodic & 2);
+        iz[o] = wrap_or_clamp(base[2] + o, n[2], e.speriodic & 4);
+    }
+    return interior;
+}
+
+// Pass A1: the interpolated source state of every target into column k of
+// the buffer; index map and corner flags for the gathered targets.
+template <bool kScalar, bool kNode, bool kBlend>
+__global__ void __launch_bounds__(256) k_exadj_interp(const ExchAdjArgs a, const GatherWs g)
+{
+    const ExchArgs& e = a.e;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= e.n_cells) return;
+    const int c = e.cells[k];
+    int ix[2], iy[2], iz[2];
+    float t[3];
+    const bool interior = target_corners<kNode>(e, c, ix, iy, iz, t);
+    // without blending the host passes the time level that carries the weight
+    const float* fA = static_cast<const float*>(kBlend || a.cb == 0.0f ? e.fA : e.fB);
+    const float* fB = static_cast<const float*>(e.fB);
+    const float* gA = kBlend || a.cb == 0.0f ? e.gA : e.gB;
+    const float* gB = e.gB;
+    const float w = e.w;
+    constexpr int kCorners = kNode ? 1 : 8;
+    float v[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) v[q] = 0.0f;
+    float gi[QS] = {0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int corner = 0; corner < kCorners; ++corner) {
+        const float wt = corner_weight(t, corner);
+        const int64_t sc = ix[corner & 1] + (int64_t)e.snx * (iy[(corner >> 1) & 1] +
+                                                              (int64_t)e.sny * iz[(corner >> 2) & 1]);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const float hA = fA[i * e.splane + sc];
+            if (kBlend) {
+                const float hB = fB[i * e.splane + sc];
+                v[i] += wt * ((1.0f - w) * hA + w * hB);
+            } else {
+                v[i] += wt * hA;
+            }
+        }
+        if (kScalar)
+#pragma unroll
+            for (int i = 0; i < QS; ++i) {
+                const float g0 = gA[i * e.splane + sc];
+                if (kBlend) {
+                    const float g1 = gB[i * e.splane + sc];
+                    gi[i] += wt * ((1.0f - w) * g0 + w * g1);
+                } else {
+                    gi[i] += wt * g0;
+                }
+            }
+    }
+    const int64_t n_t = e.n_cells;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) g.vb[i * n_t + k] = v[i];
+    if (kScalar)
+#pragma unroll
+        for (int i = 0; i < QS; ++i) g.vb[(Q + i) * n_t + k] = gi[i];
+    if (interior) {
+        g.map[c] = k;
+#pragma unroll
+        for (int corner = 0; corner < kCorners; ++corner)
+            g.touched[ix[corner & 1] + (int64_t)e.snx * (iy[(corner >> 1) & 1] +
+                                                         (int64_t)e.sny * iz[(corner >> 2) & 1])] = 1;
+    }
+}
+
+// Pass A2: the map's vector-Jacobian product of every target, from its
+// interpolated state (column k) and the target's adjoint (then cleared);
+// the result replaces column k, or is scattered with atomics for a target
+// outside the gather (stencil wrapped or clamped).
+template <bool kScalar, bool kNode>
+__global__ void __launch_bounds__(256) k_exadj_vjp(const ExchAdjArgs a, const GatherWs g)
+{
+    const ExchArgs& e = a.e;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= e.n_cells) return;
+    const int c = e.cells[k];
+    const int64_t n_t = e.n_cells;
+    float v[27], gi[QS] = {0, 0, 0, 0, 0, 0, 0};
+    float lam[27], mu[QS] = {0, 0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < Q; ++i) {
+        v[tensor_slot(i)] = g.vb[i * n_t + k];
+        lam[tensor_slot(i)] = a.lam_d[i * e.dplane + c];
+        a.lam_d[i * e.dplane + c] = 0.0f;
+    }
+    if (kScalar)
+        for (int i = 0; i < QS; ++i) {
+            gi[i] = g.vb[(Q + i) * n_t + k];
+            mu[i] = a.mu_d[i * e.dplane + c];
+            a.mu_d[i * e.dplane + c] = 0.0f;
+        }
+    float vb[27], gb[QS];
+    exchange_map_adjoint<kScalar>(v, gi, e.kappa, e.kappa_s, lam, mu, vb, gb);
+    if (g.map[c] == k) {
+        for (int i = 0; i < Q; ++i) g.vb[i * n_t + k] = vb[tensor_slot(i)];
+        if (kScalar)
+            for (int i = 0; i < QS; ++i) g.vb[(Q + i) * n_t + k] = gb[i];
+        return;
+    }
+    int ix[2], iy[2], iz[2];
+    float t[3];
+    target_corners<kNode>(e, c, ix, iy, iz, t);
+    constexpr int kCorners = kNode ? 1 : 8;
+    for (int corner = 0; corner < kCorners; ++corner) {
+        const float wt = corner_weight(t, corner);
+        if (wt == 0.0f) continue;
+        const int64_t sc = ix[corner & 1] + (int64_t)e.snx * (iy[(corner >> 1) & 1] +
+                                                              (int64_t)e.sny * iz[(corner >> 2) & 1]);
+        for (int i = 0; i < Q; ++i) {
+            const float b = wt * vb[tensor_slot(i)];
+            if (a.ca != 0.0f) atomicAdd(a.lam_a + i * e.splane + sc, a.ca * b);
+            if (a.cb != 0.0f) atomicAdd(a.lam_b + i * e.splane + sc, a.cb * b);
+        }
+        if (kScalar)
+            for (int i = 0; i < QS; ++i) {
+                const float b = wt * gb[i];
+                if (a.ca != 0.0f) atomicAdd(a.mu_a + i * e.splane + sc, a.ca * b);
+                if (a.cb != 0.0f) atomicAdd(a.mu_b + i * e.splane + sc, a.cb * b);
+            }
+    }
+}
+
+// Weight of source index s on one axis for destination index j, with the
+// forward stencil's arithmetic (target_stencil, then corner_weight's factor).
+template <bool kNode>
+__device__ __forceinline__ float axis_weight(double dorigin, double ddx, double sorigin, double sdx,
+                                             int j, int s)
+{
+    const double p = dorigin + j * ddx;
+    const double q = (p - sorigin) / sdx;
+    const double b = floor(q);
+    int base = (int)b;
+    float t = (float)(q - b);
+    if (kNode) {
+        if (t >= 0.5f) ++base;
+        return base == s ? 1.0f : 0.0f;
+    }
+    if (base == s) return 1.0f - t;
+    if (base + 1 == s) return t;
+    return 0.0f;
+}
+
+constexpr int kMaxCand = 8;   // destination candidates per axis (host checks the spacing ratio)
+constexpr int kList = 8;      // targets collected before their columns are summed
+
+// sum += weight * column for the collected (k, weight) pairs
+template <bool kScalar>
+__device__ __forceinline__ void sum_columns(const GatherWs& g, int64_t n_t, const int (&kk)[kList],
+                                            const float (&ww)[kList], int nk, float (&acc)[27],
+                                            float (&gacc)[QS])
+{
+#pragma unroll
+    for (int e = 0; e < kList; ++e) {
+        if (e >= nk) break;
+        for (int i = 0; i < Q; ++i) acc[i] += ww[e] * g.vb[i * n_t + kk[e]];
+        if (kScalar)
+            for (int i = 0; i < QS; ++i) gacc[i] += ww[e] * g.vb[(Q + i) * n_t + kk[e]];
+    }
+}
+
+template <bool kScalar, bool kNode>
+__global__ void __launch_bounds__(256) k_exadj_sources(const ExchAdjArgs a, const GatherWs g)
+{
+    const ExchArgs& e = a.e;
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t n_src = (int64_t)e.snx * e.sny * e.snz;
+    if (s >= n_src || !g.touched[s]) return;
+    g.touched[s] = 0;
+    const int sxyz[3] = {(int)(s % e.snx), (int)((s / e.snx) % e.sny), (int)(s / ((int64_t)e.snx * e.sny))};
+    const int nd[3] = {e.dnx, e.dny, e.dnz};
+    // per axis: destination indices whose stencil can hold source index s,
+    // q(j) in [s - 1, s + 1), with one index of margin each side
+    int lo[3], hi[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double jl = ((sxyz[d] - 1) * e.sdx + e.sorigin[d] - e.dorigin[d]) / e.ddx;
+        lo[d] = max(0, (int)floor(jl) - 1);
+        hi[d] = min(nd[d] - 1, (int)floor(jl) - 2 + kMaxCand);
+    }
+    const int64_t n_t = e.n_cells;
+    float acc[27];
+#pragma unroll
+    for (int q = 0; q < 27; ++q) acc[q] = 0.0f;
+    float gacc[QS] = {0, 0, 0, 0, 0, 0, 0};
+    // the targets found are collected first and their columns summed in
+    // batches: the lanes of a wave then load together instead of inside a
+    // loop nest whose taken branches differ from lane to lane
+    int kk[kList];
+    float ww[kList];
+    int nk = 0;
+    for (int jz = lo[2]; jz <= hi[2]; ++jz) {
+        const float wz = axis_weight<kNode>(e.dorigin[2], e.ddx, e.sorigin[2], e.sdx, jz, sxyz[2]);
+        if (wz == 0.0f) continue;
+        for (int jy = lo[1]; jy <= hi[1]; ++jy) {
+            const float wy = axis_weight<kNode>(e.dorigin[1], e.ddx, e.sorigin[1], e.sdx, jy, sxyz[1]);
+            if (wy == 0.0f) continue;
+            for (int jx = lo[0]; jx <= hi[0]; ++jx) {
+                const float wx = axis_weight<kNode>(e.dorigin[0], e.ddx, e.sorigin[0], e.sdx, jx, sxyz[0]);
+                if (wx == 0.0f) continue;
+                const int k = g.map[jx + e.dnx * (jy + e.dny * jz)];
+                if (k < 0) continue;
+                const float wt = (wx * wy) * wz;
+#pragma unroll
+                for (int m = 0; m < kList; ++m)
+                    if (m == nk) {
+                        kk[m] = k;
+                        ww[m] = wt;
+                    }
+                if (++nk == kList) {
+                    sum_columns<kScalar>(g, n_t, kk, ww, nk, acc, gacc);
+                    nk = 0;
+                }
+            }
+        }
+    }
+    sum_columns<kScalar>(g, n_t, kk, ww, nk, acc, gacc);
+    for (int i = 0; i < Q; ++i) {
+        if (a.ca != 0.0f) a.lam_a[i * e.splane + s] += a.ca * acc[i];
+        if (a.cb != 0.0f) a.lam_b[i * e.splane + s] += a.cb * acc[i];
+    }
+    if (kScalar)
+        for (int i = 0; i < QS; ++i) {
+            if (a.ca != 0.0f) a.mu_a[i * e.splane + s] += a.ca * gacc[i];
+            if (a.cb != 0.0f) a.mu_b[i * e.splane + s] += a.cb * gacc[i];
+        }
+}
+
+__global__ void __launch_bounds__(256) k_exadj_reset(int32_t* map, const int32_t* cells, int n)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) map[cells[k]] = -1;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fill_value(T* p, int64_t n, T value)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = value;
+}
+
 // y = alpha x + beta y over n elements
 __global__ void __launch_bounds__(256) k_axpby(const float* x, float* y, int64_t n, float alpha,
                                                float beta)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) y[i] = alpha * x[i] + beta * y[i];
+}
+
+// z = x + y over n elements
+__global__ void __launch_bounds__(256) k_sum(const float* x, const float* y, float* z, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) z[i] = x[i] + y[i];
 }
 
 __global__ void __launch_bounds__(256) k_zero(float* p, int64_t n)
@@ -275,7 +567,8 @@ static int launch_exchange_adjoint(const cslbm_level* src, const void* fA, const
                                    const float* gA, const float* gB, double w,
                                    const cslbm_level* dst, float* lam_d, float* mu_d,
                                    float* lam_a, float* lam_b, float* mu_a, float* mu_b,
-                                   const int32_t* cells, int32_t n_cells, hipStream_t stream)
+                                   const int32_t* cells, int32_t n_cells, const GatherWs* gw,
+                                   hipStream_t stream)
 {
     if (n_cells == 0) return CSLBM_OK;
     const bool scalar = gA != nullptr && mu_d != nullptr;
@@ -292,6 +585,32 @@ static int launch_exchange_adjoint(const cslbm_level* src, const void* fA, const
     a.cb = w <= 0.0 ? 0.0f : (float)w;
     const bool node = nodes_coincide(src, dst);
     const dim3 grid(grid_for(n_cells)), block(256);
+    // The candidate window of the gather pass spans q(j) in [s - 1, s + 1)
+    // plus one index each side: 2 src->dx / dst->dx + 4 indices at most.
+    if (gw && 2.0 * src->dx / dst->dx + 4.0 <= (double)kMaxCand) {
+        const GatherWs g = *gw;
+        const dim3 sgrid(grid_for((int64_t)src->nx * src->ny * src->nz));
+        const bool blend = a.ca != 0.0f && a.cb != 0.0f;
+#define CSLBM_GATHER(S_, N_)                                                                   \
+        if (blend)                                                                             \
+            hipLaunchKernelGGL((k_exadj_interp<S_, N_, true>), grid, block, 0, stream, a, g);  \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_exadj_interp<S_, N_, false>), grid, block, 0, stream, a, g); \
+        hipLaunchKernelGGL((k_exadj_vjp<S_, N_>), grid, block, 0, stream, a, g);              \
+        hipLaunchKernelGGL((k_exadj_sources<S_, N_>), sgrid, block, 0, stream, a, g);
+        if (scalar && node) {
+            CSLBM_GATHER(true, true)
+        } else if (scalar) {
+            CSLBM_GATHER(true, false)
+        } else if (node) {
+            CSLBM_GATHER(false, true)
+        } else {
+            CSLBM_GATHER(false, false)
+        }
+#undef CSLBM_GATHER
+        hipLaunchKernelGGL(k_exadj_reset, grid, block, 0, stream, g.map, cells, n_cells);
+        return check_launch("k_exchange_adjoint (gather)");
+    }
     if (scalar) {
         if (node)
             hipLaunchKernelGGL((k_exchange_adjoint<true, true>), grid, block, 0, stream, a);
@@ -337,11 +656,29 @@ struct Buf {
 struct Layout {
     int64_t bytes;
     Buf B0;                          // reference scale after its step
-    Buf cur[CSLBM_MAX_SCALES][8];    // inputs of the sub-steps 1..last (index k - 1)
+    Buf cur[CSLBM_MAX_SCALES][8];    // inputs of the sub-steps 2..last (index k - 1)
     Buf R[CSLBM_MAX_SCALES];         // interpolated state of a finer scale
     Buf lamA[CSLBM_MAX_SCALES];      // adjoint of each scale's state after its first prior-map
     Buf t1[CSLBM_MAX_SCALES], t2[CSLBM_MAX_SCALES];   // adjoint temporaries
+    GatherWs gather;                 // gather form of the exchange adjoints
+    int64_t max_cells;               // largest scale (index map and flags)
 };
+
+static int64_t gather_bytes(int64_t n_targets, int64_t dst_cells, int64_t src_cells)
+{
+    auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+    return up((int64_t)(Q + QS) * n_targets * 4) + up(dst_cells * 4) + up(src_cells);
+}
+
+static GatherWs gather_at(char* base, int64_t n_targets, int64_t dst_cells)
+{
+    auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+    GatherWs g;
+    g.vb = reinterpret_cast<float*>(base);
+    g.map = reinterpret_cast<int32_t*>(base + up((int64_t)(Q + QS) * n_targets * 4));
+    g.touched = reinterpret_cast<uint8_t*>(base + up((int64_t)(Q + QS) * n_targets * 4) + up(dst_cells * 4));
+    return g;
+}
 
 static int64_t buf_bytes(const cslbm_level* L, bool scalar)
 {
@@ -369,12 +706,23 @@ static Layout layout(const cslbm_hierarchy* H, char* base)
     o.t1[0] = take(&S[0].level);
     for (int i = 1; i < H->n_scales; ++i) {
         const SubSteps ss = sub_steps(S, i);
-        for (int k = 0; k < ss.last; ++k) o.cur[i][k] = take(&S[i].level);
+        for (int k = 1; k < ss.last; ++k) o.cur[i][k] = take(&S[i].level);   // k = 0: f_in[i]
         o.R[i] = take(&S[i].level);
         o.lamA[i] = take(&S[i].level);
         o.t1[i] = take(&S[i].level);
         o.t2[i] = take(&S[i].level);
     }
+    int64_t max_targets = 0, max_cells = 0;
+    for (int i = 0; i < H->n_scales; ++i) {
+        const cslbm_level* L = &S[i].level;
+        max_cells = std::max<int64_t>(max_cells, (int64_t)L->nx * L->ny * L->nz);
+        if (i == 0) continue;
+        max_targets = std::max<int64_t>(max_targets, S[i].n_ghost);
+        for (int j = 0; j < i; ++j) max_targets = std::max<int64_t>(max_targets, S[i].n_post[j]);
+    }
+    o.max_cells = max_cells;
+    o.gather = base ? gather_at(base + off, max_targets, max_cells) : GatherWs{nullptr, nullptr, nullptr};
+    off += gather_bytes(max_targets, max_cells, max_cells);
     o.bytes = off;
     return o;
 }
@@ -412,10 +760,18 @@ using namespace cslbm;
 
 extern "C" {
 
+int64_t cslbm_exchange_adjoint_bytes(const cslbm_level* src, const cslbm_level* dst, int32_t n_cells)
+{
+    if (!src || !dst || n_cells < 0) return -1;
+    return gather_bytes(n_cells, (int64_t)dst->nx * dst->ny * dst->nz,
+                        (int64_t)src->nx * src->ny * src->nz);
+}
+
 int cslbm_exchange_adjoint(const cslbm_level* src, const void* fA, const void* fB, const float* gA,
                            const float* gB, double w, const cslbm_level* dst, float* lam_d,
                            float* mu_d, float* lam_a, float* lam_b, float* mu_a, float* mu_b,
-                           const int32_t* cells, int32_t n_cells, hipStream_t stream)
+                           const int32_t* cells, int32_t n_cells, void* workspace,
+                           int64_t workspace_bytes, hipStream_t stream)
 {
     int rc = validate_shape(src);
     if (rc) return rc;
@@ -435,10 +791,24 @@ int cslbm_exchange_adjoint(const cslbm_level* src, const void* fA, const void* f
     if (scalar && ((w < 1.0 && !mu_a) || (w > 0.0 && (!gB || !mu_b))))
         return fail(CSLBM_ERR_ARG, "scalar adjoint buffers are NULL");
     if (lam_d == lam_a || lam_d == lam_b) return fail(CSLBM_ERR_ARG, "destination and source adjoints alias");
+    if (w > 0.0 && w < 1.0 && lam_a == lam_b)
+        return fail(CSLBM_ERR_ARG, "the two time levels' adjoints alias");
+    GatherWs g{nullptr, nullptr, nullptr};
+    if (workspace) {
+        const int64_t need = cslbm_exchange_adjoint_bytes(src, dst, n_cells);
+        if (workspace_bytes < need)
+            return fail(CSLBM_ERR_ARG, "workspace of %lld bytes, %lld needed", (long long)workspace_bytes,
+                        (long long)need);
+        const int64_t nd = (int64_t)dst->nx * dst->ny * dst->nz, ns = (int64_t)src->nx * src->ny * src->nz;
+        g = gather_at(static_cast<char*>(workspace), n_cells, nd);
+        hipLaunchKernelGGL(k_fill_value<int32_t>, dim3(grid_for(nd)), dim3(256), 0, stream, g.map, nd, -1);
+        hipLaunchKernelGGL(k_fill_value<uint8_t>, dim3(grid_for(ns)), dim3(256), 0, stream, g.touched, ns,
+                           (uint8_t)0);
+    }
     return launch_exchange_adjoint(src, fA, fB ? fB : fA, scalar ? gA : nullptr,
                                    scalar ? (gB ? gB : gA) : nullptr, w, dst, lam_d,
                                    scalar ? mu_d : nullptr, lam_a, lam_b, mu_a, mu_b, cells, n_cells,
-                                   stream);
+                                   workspace ? &g : nullptr, stream);
 }
 
 int64_t cslbm_multiscale_adjoint_bytes(const cslbm_hierarchy* H)
@@ -467,7 +837,7 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
     if (!workspace || workspace_bytes < need.bytes)
         return fail(CSLBM_ERR_ARG, "workspace of %lld bytes, %lld needed", (long long)workspace_bytes,
                     (long long)need.bytes);
-    const Layout W = layout(H, static_cast<char*>(workspace));
+    Layout W = layout(H, static_cast<char*>(workspace));
     auto nelem = [&](int i) { return ((int64_t)Q + (scalar ? QS : 0)) * S[i].level.plane; };
 
     // ---- forward recompute of the reference step from the states at t_n ----
@@ -490,10 +860,10 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
         const cslbm_level* P = &S[i - 1].level;
         const int p = i - 1;
         const SubSteps ss = sub_steps(S, i);
-        const int64_t fb = (int64_t)Q * L->plane * 4, gbytes = (int64_t)QS * L->plane * 4;
-        CSLBM_HIP_TRY(hipMemcpyAsync(W.cur[i][0].f, f_in[i], fb, hipMemcpyDeviceToDevice, stream));
-        if (scalar)
-            CSLBM_HIP_TRY(hipMemcpyAsync(W.cur[i][0].g, g_in[i], gbytes, hipMemcpyDeviceToDevice, stream));
+        // the first sub-step's input is the caller's state itself: its prior-
+        // mapping rewrites only the GHOST cells, whose old values never enter
+        W.cur[i][0] = Buf{static_cast<float*>(const_cast<void*>(f_in[i])),
+                          scalar ? const_cast<float*>(g_in[i]) : nullptr};
         for (int k = 1; k <= ss.last; ++k) {
             const Buf& cur = W.cur[i][k - 1];
             rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], (k - 1) / ss.alpha, L, cur.f, cur.g,
@@ -518,6 +888,11 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
     }
 
     // ---- reverse ----
+    hipLaunchKernelGGL(k_fill_value<int32_t>, dim3(grid_for(W.max_cells)), dim3(256), 0, stream,
+                       W.gather.map, W.max_cells, -1);
+    hipLaunchKernelGGL(k_fill_value<uint8_t>, dim3(grid_for(W.max_cells)), dim3(256), 0, stream,
+                       W.gather.touched, W.max_cells, (uint8_t)0);
+    const GatherWs* gw = &W.gather;
     for (int i = 0; i < ns; ++i)
         hipLaunchKernelGGL(k_zero, dim3(grid_for(nelem(i))), dim3(256), 0, stream, W.lamA[i].f, nelem(i));
     for (int i = ns - 1; i >= 1; --i) {
@@ -532,21 +907,21 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
         for (int j = i - 1; j >= 0; --j) {
             rc = launch_exchange_adjoint(L, W.R[i].f, W.R[i].f, W.R[i].g, W.R[i].g, 0.0, &S[j].level,
                                          lam[j], scalar ? mu[j] : nullptr, lamR, nullptr, muR,
-                                         nullptr, sc.post_cells[j], sc.n_post[j], stream);
+                                         nullptr, sc.post_cells[j], sc.n_post[j], gw, stream);
             if (rc) return rc;
         }
         // ghost shell of the interpolated state, mapped at weight 1
         rc = launch_exchange_adjoint(P, A[p], B[p], gA[p], gB[p], 1.0, L, lamR, muR, W.lamA[p].f,
                                      lam[p], W.lamA[p].g, scalar ? mu[p] : nullptr, sc.ghost_cells,
-                                     sc.n_ghost, stream);
+                                     sc.n_ghost, gw, stream);
         if (rc) return rc;
         // last sub-step: R = l0 cur_1 + l1 cur_l + l2 step(cur_l), or R = step(cur_last)
-        Buf lc = W.t1[i], spare = W.t2[i];
+        const int64_t nf = (int64_t)Q * L->plane, ngs = (int64_t)QS * L->plane;
+        Buf lc = W.t1[i];
         const Buf& in_last = W.cur[i][ss.last - 1];
         rc = launch_adjoint_into(L, in_last.f, in_last.g, lamR, muR, lc.f, lc.g, nullptr, stream);
         if (rc) return rc;
         if (!ss.node) {
-            const int64_t nf = (int64_t)Q * L->plane, ngs = (int64_t)QS * L->plane;
             axpby(lamR, lc.f, nf, (float)ss.l1, (float)ss.l2, stream);
             axpby(lamR, W.lamA[i].f, nf, (float)ss.l0, 1.0f, stream);
             if (scalar) {
@@ -554,31 +929,34 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
                 axpby(muR, W.lamA[i].g, ngs, (float)ss.l0, 1.0f, stream);
             }
         }
-        // lc = adjoint of the input of sub-step k (after its prior-map)
+        // lam[i] is free from here on.  lc = adjoint of the input of sub-step
+        // k (after its prior-map); the step adjoints below alternate between
+        // lam[i] and t2 so that the last one writes lam[i].
+        const Buf out_final{lamR, muR};
         for (int k = ss.last; k >= 1; --k) {
             if (k == 1) {
                 // the first input is also read by the interpolation and by the
                 // next finer scale's prior-maps: their adjoints are in lamA[i]
-                axpby(W.lamA[i].f, lc.f, nelem(i), 1.0f, 1.0f, stream);
+                axpby(W.lamA[i].f, lc.f, nf, 1.0f, 1.0f, stream);
+                if (scalar) axpby(W.lamA[i].g, lc.g, ngs, 1.0f, 1.0f, stream);
             }
             rc = launch_exchange_adjoint(P, A[p], B[p], gA[p], gB[p], (k - 1) / ss.alpha, L, lc.f,
                                          lc.g, W.lamA[p].f, lam[p], W.lamA[p].g,
-                                         scalar ? mu[p] : nullptr, sc.ghost_cells, sc.n_ghost, stream);
+                                         scalar ? mu[p] : nullptr, sc.ghost_cells, sc.n_ghost, gw,
+                                         stream);
             if (rc) return rc;
             if (k == 1) break;
+            const Buf out = ((k - 2) % 2 == 0) ? out_final : W.t2[i];
             const Buf& in = W.cur[i][k - 2];
-            rc = launch_adjoint_into(L, in.f, in.g, lc.f, lc.g, spare.f, spare.g, nullptr, stream);
+            rc = launch_adjoint_into(L, in.f, in.g, lc.f, lc.g, out.f, out.g, nullptr, stream);
             if (rc) return rc;
-            const Buf tmp = lc;
-            lc = spare;
-            spare = tmp;
+            lc = out;
         }
-        // lc = dL/d(state of scale i at t_n)
-        CSLBM_HIP_TRY(hipMemcpyAsync(lam[i], lc.f, (int64_t)Q * L->plane * 4, hipMemcpyDeviceToDevice,
-                                     stream));
-        if (scalar)
-            CSLBM_HIP_TRY(hipMemcpyAsync(mu[i], lc.g, (int64_t)QS * L->plane * 4,
-                                         hipMemcpyDeviceToDevice, stream));
+        // lc = dL/d(state of scale i at t_n); only a single sub-step leaves it in t1
+        if (lc.f != lamR) {
+            CSLBM_HIP_TRY(hipMemcpyAsync(lamR, lc.f, nf * 4, hipMemcpyDeviceToDevice, stream));
+            if (scalar) CSLBM_HIP_TRY(hipMemcpyAsync(muR, lc.g, ngs * 4, hipMemcpyDeviceToDevice, stream));
+        }
     }
     {
         const cslbm_level* L = &S[0].level;
@@ -586,12 +964,10 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
                                  scalar ? mu[0] : nullptr, W.t1[0].f, W.t1[0].g, nullptr, stream);
         if (rc) return rc;
         const int64_t nf = (int64_t)Q * L->plane, ngs = (int64_t)QS * L->plane;
-        axpby(W.t1[0].f, W.lamA[0].f, nf, 1.0f, 1.0f, stream);
-        CSLBM_HIP_TRY(hipMemcpyAsync(lam[0], W.lamA[0].f, nf * 4, hipMemcpyDeviceToDevice, stream));
-        if (scalar) {
-            axpby(W.t1[0].g, W.lamA[0].g, ngs, 1.0f, 1.0f, stream);
-            CSLBM_HIP_TRY(hipMemcpyAsync(mu[0], W.lamA[0].g, ngs * 4, hipMemcpyDeviceToDevice, stream));
-        }
+        hipLaunchKernelGGL(k_sum, dim3(grid_for(nf)), dim3(256), 0, stream, W.t1[0].f, W.lamA[0].f, lam[0], nf);
+        if (scalar)
+            hipLaunchKernelGGL(k_sum, dim3(grid_for(ngs)), dim3(256), 0, stream, W.t1[0].g, W.lamA[0].g,
+                               mu[0], ngs);
     }
     return check_launch("cslbm_multiscale_adjoint_step");
 }

@@ -22,7 +22,7 @@ struct ExchArgs {
     double sorigin[3], sdx;
     void* fo;
     float* go;
-    int dnx, dny;
+    int dnx, dny, dnz;
     int64_t dplane;
     double dorigin[3], ddx;
     const int32_t* cells;
@@ -100,6 +100,7 @@ inline ExchArgs exchange_args(const cslbm_level* src, const void* fA, const void
     a.go = scalar ? g_out : nullptr;
     a.dnx = dst->nx;
     a.dny = dst->ny;
+    a.dnz = dst->nz;
     a.dplane = dst->plane;
     std::memcpy(a.dorigin, dst->origin, sizeof a.dorigin);
     a.ddx = dst->dx;

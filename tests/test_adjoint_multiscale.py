@@ -97,24 +97,32 @@ def test_flagged_step_adjoint_matches_fp64_finite_differences(kind):
         assert ad == pytest.approx(fd, rel=1e-3), (seed, ad, fd)
 
 
-def _exchange_adjoint_gpu(lev_src, lev_dst, cells, w, fA, fB, gA, gB, lam_d, mu_d):
+def _exchange_adjoint_gpu(lev_src, lev_dst, cells, w, fA, fB, gA, gB, lam_d, mu_d, gather=False):
     import ctypes as C
     cells_t = torch.as_tensor(np.asarray(cells, np.int32), device="cuda")
     lev_src._sync_struct()
     lev_dst._sync_struct()
     lam_a, lam_b = torch.zeros_like(fA), torch.zeros_like(fA)
     mu_a, mu_b = torch.zeros_like(gA), torch.zeros_like(gA)
+    ws, nbytes = None, 0
+    if gather:
+        lib = _capi.load()
+        nbytes = lib.cslbm_exchange_adjoint_bytes(C.byref(lev_src.c), C.byref(lev_dst.c),
+                                                  int(cells_t.numel()))
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     _capi.call("cslbm_exchange_adjoint", C.byref(lev_src.c), fA.data_ptr(), fB.data_ptr(),
                gA.data_ptr(), gB.data_ptr(), float(w), C.byref(lev_dst.c), lam_d.data_ptr(),
                mu_d.data_ptr(), lam_a.data_ptr(), lam_b.data_ptr(), mu_a.data_ptr(),
                mu_b.data_ptr(), cells_t.data_ptr(), int(cells_t.numel()),
+               None if ws is None else ws.data_ptr(), int(nbytes),
                torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
     return lam_a, lam_b, mu_a, mu_b
 
 
+@pytest.mark.parametrize("gather", [False, True])
 @pytest.mark.parametrize("case", ["prior_blend", "post", "post_node"])
-def test_exchange_adjoint_matches_fp64_finite_differences(case):
+def test_exchange_adjoint_matches_fp64_finite_differences(case, gather):
     n = 20
     nu0 = 2e-3
     coarse = Spec((n, n, n), (0.0, 0.0, 0.0), 1.0, nu0, np.zeros(n ** 3, np.uint8), periodic=7)
@@ -147,7 +155,7 @@ def test_exchange_adjoint_matches_fp64_finite_differences(case):
         return t.reshape(-1)
 
     lam_d, mu_d = plane(Tf, 27, dst), plane(Tg, 7, dst)
-    la, lb, ma, mb = _exchange_adjoint_gpu(src, dst, cells, w, fA, fB, gA, gB, lam_d, mu_d)
+    la, lb, ma, mb = _exchange_adjoint_gpu(src, dst, cells, w, fA, fB, gA, gB, lam_d, mu_d, gather)
     # the targets' adjoints are cleared, the others kept
     ld = lam_d.reshape(27, dst.plane)[:, : dst.n].cpu().numpy()
     assert np.all(ld[:, cells] == 0.0)
@@ -179,6 +187,53 @@ def test_exchange_adjoint_matches_fp64_finite_differences(case):
         fd = (L(dA, dB, dgA, dgB) - L(-dA, -dB, -dgA, -dgB)) / 2.0
         ad = float(np.sum(gla * dA) + np.sum(glb * dB) + np.sum(gma * dgA) + np.sum(gmb * dgB))
         assert ad == pytest.approx(fd, rel=1e-4), (seed, ad, fd)
+
+
+@pytest.mark.parametrize("case", ["prior_blend", "post", "post_node", "wrapping"])
+def test_exchange_adjoint_gather_equals_atomic_scatter(case):
+    """The gather form and the atomic scatter sum the same contributions
+    (different order); "wrapping" puts targets whose stencil wraps around a
+    periodic source box next to interior ones."""
+    n = 20
+    nu0 = 2e-3
+    coarse = Spec((n, n, n), (0.0, 0.0, 0.0), 1.0, nu0, np.zeros(n ** 3, np.uint8), periodic=7)
+    if case == "post_node":
+        fshape = (22, 20, 18)
+        fine = Spec(fshape, (4.5, 5.0, 3.5), 0.5, nu0, hierarchy.shell_flags(*fshape))
+    elif case == "wrapping":
+        fshape = (12, 10, 9)
+        fine = Spec(fshape, (14.2, 3.3, 5.1), 1 / 1.5, nu0, hierarchy.shell_flags(*fshape))
+    else:
+        fshape = (19, 19, 17)
+        fine = Spec(fshape, (5.3, 5.4, 5.6), 1 / 1.5, nu0, hierarchy.shell_flags(*fshape))
+    levC, _ = start_both(coarse, 6)
+    levC2, _ = start_both(coarse, 8)
+    levF, _ = start_both(fine, 7)
+    if case in ("prior_blend", "wrapping"):
+        src, dst, w = levC, levF, 0.37
+        cells = np.arange(fine.n) if case == "wrapping" else np.flatnonzero(fine.kinds == _capi.GHOST)
+        fA, fB, gA, gB = levC.f, levC2.f, levC.g, levC2.g
+    else:
+        src, dst, w = levF, levC, 0.0
+        cells = hierarchy.post_cells(coarse.kinds, coarse.shape, coarse.origin, 1.0, fine.kinds,
+                                     fine.shape, fine.origin, fine.dx)
+        fA, fB, gA, gB = levF.f, levF.f, levF.g, levF.g
+    rng = np.random.default_rng(4)
+    out = []
+    for gather in (False, True):
+        lam_d = torch.zeros(27, dst.plane, device="cuda")
+        lam_d[:, : dst.n] = torch.as_tensor(rng.standard_normal((27, dst.n)) if not out else Tf,
+                                            dtype=torch.float32, device="cuda")
+        if not out:
+            Tf = lam_d[:, : dst.n].cpu().numpy().astype(np.float64)
+        mu_d = torch.zeros(7, dst.plane, device="cuda")
+        mu_d[:, : dst.n] = 0.5
+        res = _exchange_adjoint_gpu(src, dst, cells, w, fA, fB, gA, gB, lam_d.reshape(-1),
+                                    mu_d.reshape(-1), gather)
+        out.append([r.cpu().numpy() for r in res])
+    for a, b in zip(*out):
+        scale = max(np.max(np.abs(a)), 1e-30)
+        assert np.max(np.abs(a - b)) <= 1e-5 * scale
 
 
 def chain_specs(nu0=2e-3, adaptive=True):

@@ -133,10 +133,31 @@ typedef struct cslbm_level {
                                  partial slots, zeroed by the caller once and
                                  left zeroed by every step, then the field
                                  maximum of the last step in the last element */
+    const int32_t* brick_table;  /* sparse brick storage, or NULL for a dense
+                                 box: [nz/8][ny/8][nx/8] index of each 8x8x8
+                                 brick of the box among the stored bricks, -1
+                                 for a brick that is not stored */
+    const int32_t* brick_origin; /* [n_bricks][3] brick coordinates (x, y, z,
+                                 in bricks) of the stored bricks */
+    int32_t n_bricks;         /* stored bricks (brick levels); cells are then
+                                 stored brick after brick, 512 per brick in
+                                 x-fastest order: index 512 b + lx + 8 ly + 64 lz,
+                                 and every per-cell array (flags, links,
+                                 states, lists) uses that order */
+    int32_t reserved1;
     double origin[3];         /* physical position of cell (0,0,0) */
     double dx;                /* physical spacing of this scale */
     cslbm_params p;
 } cslbm_level;
+
+/* Brick levels (brick_table set; build addition for thin dynamic regions):
+ * nx, ny, nz multiples of 8, no periodic axis, flags required, and every
+ * FLUID cell's 26 neighbours stored (a GHOST or SOLID layer separates the
+ * fluid from the bricks that are not stored).  Supported by the step (no
+ * force field, grad_mode 0), the exchange on either side, the multi-scale
+ * step and every per-cell call; not by cslbm_vorticity, the adjoints or the
+ * gradient mode (CSLBM_ERR_UNSUPPORTED).  The plane stride of a brick level
+ * is that of n_bricks * 512 cells: cslbm_plane_stride(512 * n_bricks, 1, 1). */
 
 /* Recommended plane stride for a level: nx*ny*nz rounded up and padded so
  * that the 27 planes do not start at identical offsets modulo large powers

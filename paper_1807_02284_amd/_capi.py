@@ -58,6 +58,10 @@ class CslbmLevel(C.Structure):
         ("vel", _vp),
         ("vel_next", _vp),
         ("gmax_buf", _vp),
+        ("brick_table", _vp),
+        ("brick_origin", _vp),
+        ("n_bricks", C.c_int32),
+        ("reserved1", C.c_int32),
         ("origin", C.c_double * 3),
         ("dx", C.c_double),
         ("p", CslbmParams),

@@ -736,6 +736,8 @@ static int validate_adjoint_hierarchy(const cslbm_hierarchy* H)
         const cslbm_level* L = &S[i].level;
         if (L->storage != CSLBM_F32)
             return fail(CSLBM_ERR_UNSUPPORTED, "scale %d: the multi-scale adjoint needs FP32 storage", i);
+        if (L->brick_table)
+            return fail(CSLBM_ERR_UNSUPPORTED, "scale %d: brick levels are not differentiated", i);
         if (i > 0 && L->dx > S[0].level.dx)
             return fail(CSLBM_ERR_UNSUPPORTED, "scale %d: far-field scales are not differentiated", i);
         if (i > 0 && S[i].parent != i - 1)
@@ -779,6 +781,8 @@ int cslbm_exchange_adjoint(const cslbm_level* src, const void* fA, const void* f
     if (rc) return rc;
     if (src->storage != CSLBM_F32)
         return fail(CSLBM_ERR_UNSUPPORTED, "the exchange adjoint reads FP32 source states");
+    if (src->brick_table || dst->brick_table)
+        return fail(CSLBM_ERR_UNSUPPORTED, "the exchange adjoint of brick levels");
     if (!(src->dx > 0.0) || !(dst->dx > 0.0)) return fail(CSLBM_ERR_ARG, "scale spacings must be positive");
     if (std::fabs(1.0 - shear_rate(src)) < 1e-9)
         return fail(CSLBM_ERR_ARG, "source relaxation time is 1: the mapping is singular");

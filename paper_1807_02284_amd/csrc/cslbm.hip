@@ -14,6 +14,7 @@
 
 #include "../../include/cslbm.h"
 #include "cm_collide.hpp"
+#include "brick.hpp"
 #include "internal.hpp"
 #include "lattice.hpp"
 
@@ -53,13 +54,15 @@ __device__ __forceinline__ void cell_coords(int64_t c, int nx, int ny, int& x, i
 }
 
 __global__ void k_prepare_flags(uint8_t* flags, uint32_t* links, int nx, int ny, int nz,
-                                int periodic)
+                                int periodic, int64_t N, const BrickMap bm)
 {
-    const int64_t N = (int64_t)nx * ny * nz;
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= N) return;
     int x, y, z;
-    cell_coords(c, nx, ny, x, y, z);
+    if (bm.table)
+        brick_xyz(bm, (int)c, x, y, z);
+    else
+        cell_coords(c, nx, ny, x, y, z);
     const uint8_t kind = flags[c] & kKindMask;
     uint32_t m = 0;
     if (kind == kFluid) {
@@ -69,10 +72,22 @@ __global__ void k_prepare_flags(uint8_t* flags, uint32_t* links, int nx, int ny,
                 m |= 1u << i;
                 continue;
             }
-            const int xs = (x - kCx[i] + nx) % nx, ys = (y - kCy[i] + ny) % ny,
-                      zs = (z - kCz[i] + nz) % nz;
-            if ((flags[xs + (int64_t)nx * (ys + (int64_t)ny * zs)] & kKindMask) == kSolid)
-                m |= 1u << i;
+            int64_t src;
+            if (bm.table) {
+                // a source that is not stored counts as solid (a valid brick
+                // level never lets a fluid cell pull from one)
+                const int s = brick_neighbour(bm, (int)c, x, y, z, kCx[i], kCy[i], kCz[i]);
+                if (s < 0) {
+                    m |= 1u << i;
+                    continue;
+                }
+                src = s;
+            } else {
+                const int xs = (x - kCx[i] + nx) % nx, ys = (y - kCy[i] + ny) % ny,
+                          zs = (z - kCz[i] + nz) % nz;
+                src = xs + (int64_t)nx * (ys + (int64_t)ny * zs);
+            }
+            if ((flags[src] & kKindMask) == kSolid) m |= 1u << i;
         }
     }
     flags[c] = kind | (m ? kNearWall : 0);
@@ -319,7 +334,21 @@ __global__ void k_count_nonfinite(const T* f, const float* g, int64_t N, int64_t
 // ---------------------------------------------------------------------------
 // host side: validation and launches
 // ---------------------------------------------------------------------------
-int64_t cells_of(const cslbm_level* L) { return (int64_t)L->nx * L->ny * L->nz; }
+int64_t cells_of(const cslbm_level* L)
+{
+    return L->brick_table ? (int64_t)L->n_bricks * kBrickCells : (int64_t)L->nx * L->ny * L->nz;
+}
+
+BrickMap brick_map(const cslbm_level* L)
+{
+    BrickMap m;
+    m.table = L->brick_table;
+    m.origin = L->brick_origin;
+    m.bnx = L->nx / kBrickEdge;
+    m.bny = L->ny / kBrickEdge;
+    m.bnz = L->nz / kBrickEdge;
+    return m;
+}
 
 int validate_shape(const cslbm_level* L)
 {
@@ -343,6 +372,18 @@ int validate_shape(const cslbm_level* L)
     if ((L->periodic & 7) != 7 && !L->flags)
         return fail(CSLBM_ERR_ARG, "a non-periodic axis needs a flags array (periodic = %d)",
                     L->periodic);
+    if (L->brick_table) {
+        if (L->nx % kBrickEdge || L->ny % kBrickEdge || L->nz % kBrickEdge)
+            return fail(CSLBM_ERR_SHAPE, "a brick level's box %d x %d x %d must be a multiple of 8",
+                        L->nx, L->ny, L->nz);
+        const int64_t nb = (int64_t)(L->nx / 8) * (L->ny / 8) * (L->nz / 8);
+        if (L->n_bricks < 1 || L->n_bricks > nb)
+            return fail(CSLBM_ERR_ARG, "n_bricks = %d outside [1, %lld]", L->n_bricks, (long long)nb);
+        if (!L->brick_origin) return fail(CSLBM_ERR_ARG, "brick_origin is NULL");
+        if (!L->flags) return fail(CSLBM_ERR_ARG, "a brick level needs flags");
+        if (L->periodic & 7) return fail(CSLBM_ERR_UNSUPPORTED, "a brick level has no periodic axis");
+        if (L->force) return fail(CSLBM_ERR_UNSUPPORTED, "a brick level has no force field");
+    }
     return CSLBM_OK;
 }
 
@@ -437,7 +478,7 @@ int cslbm_prepare_flags(const cslbm_level* L, hipStream_t stream)
     if (!L->flags) return fail(CSLBM_ERR_ARG, "flags is NULL");
     const int64_t N = cells_of(L);
     hipLaunchKernelGGL(k_prepare_flags, dim3(blocks_for(N, 256)), dim3(256), 0, stream, L->flags,
-                       L->links, L->nx, L->ny, L->nz, L->periodic);
+                       L->links, L->nx, L->ny, L->nz, L->periodic, N, brick_map(L));
     return check_launch("k_prepare_flags");
 }
 
@@ -578,6 +619,7 @@ int cslbm_vorticity(const cslbm_level* L, float* omega, float* speed, hipStream_
 {
     int rc = validate_shape(L);
     if (rc) return rc;
+    if (L->brick_table) return fail(CSLBM_ERR_UNSUPPORTED, "vorticity of a brick level");
     if (!omega) return fail(CSLBM_ERR_ARG, "omega is NULL");
     const int64_t N = cells_of(L);
     float* u = nullptr;

@@ -9,6 +9,7 @@
 #include <cstring>
 
 #include "../../include/cslbm.h"
+#include "brick.hpp"
 
 namespace cslbm {
 
@@ -23,6 +24,7 @@ struct ExchArgs {
     void* fo;
     float* go;
     int dnx, dny, dnz;
+    BrickMap sb, db;      // brick storage of source and destination (table null: dense)
     int64_t dplane;
     double dorigin[3], ddx;
     const int32_t* cells;
@@ -45,7 +47,14 @@ __device__ __forceinline__ int wrap_or_clamp(int i, int n, bool periodic)
 // and trilinear fractions (geometry in FP64 so coincident nodes resolve)
 __device__ __forceinline__ void target_stencil(const ExchArgs& a, int c, int (&base)[3], float (&t)[3])
 {
-    const int x = c % a.dnx, y = (c / a.dnx) % a.dny, z = c / (a.dnx * a.dny);
+    int x, y, z;
+    if (a.db.table) {
+        brick_xyz(a.db, c, x, y, z);
+    } else {
+        x = c % a.dnx;
+        y = (c / a.dnx) % a.dny;
+        z = c / (a.dnx * a.dny);
+    }
     const double p[3] = {a.dorigin[0] + x * a.ddx, a.dorigin[1] + y * a.ddx, a.dorigin[2] + z * a.ddx};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -54,6 +63,18 @@ __device__ __forceinline__ void target_stencil(const ExchArgs& a, int c, int (&b
         base[d] = (int)b;
         t[d] = (float)(q - b);
     }
+}
+
+// storage index of source corner (ix, iy, iz) (inside the source box); a
+// corner in a brick that is not stored reads cell 0 (validated lists never
+// put weight on one)
+__device__ __forceinline__ int64_t source_cell(const ExchArgs& a, int ix, int iy, int iz)
+{
+    if (a.sb.table) {
+        const int s = brick_cell(a.sb, ix, iy, iz);
+        return s < 0 ? 0 : s;
+    }
+    return ix + (int64_t)a.snx * (iy + (int64_t)a.sny * iz);
 }
 
 __device__ __forceinline__ float corner_weight(const float (&t)[3], int corner)
@@ -104,6 +125,8 @@ inline ExchArgs exchange_args(const cslbm_level* src, const void* fA, const void
     a.dplane = dst->plane;
     std::memcpy(a.dorigin, dst->origin, sizeof a.dorigin);
     a.ddx = dst->dx;
+    a.sb = brick_map(src);
+    a.db = brick_map(dst);
     a.cells = cells;
     a.n_cells = n_cells;
     a.w = (float)w;

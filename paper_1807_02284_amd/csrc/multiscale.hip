@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(256) k_exchange(const ExchArgs a)
     for (int corner = 0; corner < kCorners; ++corner) {
         const int ox = corner & 1, oy = (corner >> 1) & 1, oz = (corner >> 2) & 1;
         const float wt = corner_weight(t, corner);
-        const int64_t sc = ix[ox] + (int64_t)a.snx * (iy[oy] + (int64_t)a.sny * iz[oz]);
+        const int64_t sc = source_cell(a, ix[ox], iy[oy], iz[oz]);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const float hA = Io<Ts>::ld(fA + i * a.splane + sc);

@@ -10,6 +10,7 @@
 #include <type_traits>
 
 #include "../../include/cslbm.h"
+#include "brick.hpp"
 #include "cm_collide.hpp"
 #include "internal.hpp"
 #include "lattice.hpp"
@@ -44,6 +45,7 @@ struct StepArgs {
     float* vel_out;
     int64_t ncells;
     const float* gmax;    // running maximum of the gradient field, or null
+    BrickMap bricks;      // sparse brick storage (table null: dense box)
 };
 
 // |grad u|_F at cell (x, y, z) of a stored velocity field [3][N] by central
@@ -130,19 +132,50 @@ __device__ __forceinline__ uint32_t bounce_links(const StepArgs& a, int x, int y
     return m;
 }
 
+// Brick levels: pull source of velocity i for the cell at storage index c
+// (own index when that cell is not stored; a valid brick level gives no
+// fluid cell such a source), and the bounce-back mask from the neighbours'
+// kinds (a source that is not stored counts as a wall).
+__device__ __forceinline__ int brick_source(const StepArgs& a, int c, int x, int y, int z, int cx,
+                                            int cy, int cz)
+{
+    const int s = brick_neighbour(a.bricks, c, x, y, z, cx, cy, cz);
+    return s < 0 ? c : s;
+}
+
+__device__ __forceinline__ uint32_t bounce_links_brick(const StepArgs& a, int c, int x, int y, int z)
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int s = brick_neighbour(a.bricks, c, x, y, z, kCx[i], kCy[i], kCz[i]);
+        if (s < 0 || (a.flags[s] & kKindMask) == kSolid) m |= 1u << i;
+    }
+    return m;
+}
+
 // ---------------------------------------------------------------------------
 // K: fused pull-stream + collide
 // ---------------------------------------------------------------------------
-template <typename T, bool kFlags, bool kForce, bool kScalar, bool kTime, bool kGradFD>
+template <typename T, bool kFlags, bool kForce, bool kScalar, bool kTime, bool kGradFD,
+          bool kBrick = false>
 __global__ void __launch_bounds__(256) k_step(const StepArgs a)
 {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= a.nx || y >= a.ny) return;
+    // dense box: (x, y, z) from the 3-D grid; brick level: two blocks per
+    // stored brick, each 256 cells of it in storage order
+    int x, y, z, cell;
+    if (kBrick) {
+        cell = ((blockIdx.x >> 1) << 9) + threadIdx.x + ((blockIdx.x & 1) << 8);
+        brick_xyz(a.bricks, cell, x, y, z);
+    } else {
+        x = blockIdx.x * blockDim.x + threadIdx.x;
+        y = blockIdx.y * blockDim.y + threadIdx.y;
+        z = blockIdx.z;
+        if (x >= a.nx || y >= a.ny) return;
+        cell = x + a.nx * y + a.nx * a.ny * z;
+    }
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int nxy = nx * ny;
-    const int cell = x + nx * y + nxy * z;
     const int64_t P = a.plane;
     const T* __restrict__ f = static_cast<const T*>(a.f);
     T* __restrict__ fo = static_cast<T*>(a.fo);
@@ -174,9 +207,22 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
     if (kFlags) {
         const uint8_t flag = a.flags[cell];
         kind = flag & kKindMask;
-        if (flag & kNearWall) links = a.links ? a.links[cell] : bounce_links(a, x, y, z, sx, sy, sz);
-        if (kind == kOutflow && (x > 0 || (a.periodic & 1))) from = xm + nx * y + nxy * z;
-        if (kind == kNeumann) from = inward_cell(a, x, y, z);
+        if (kBrick) {
+            if (flag & kNearWall) links = a.links ? a.links[cell] : bounce_links_brick(a, cell, x, y, z);
+            if (kind == kOutflow) from = brick_source(a, cell, x, y, z, 1, 0, 0);
+            if (kind == kNeumann) {
+                int xi = x, yi = y, zi = z;   // no periodic axis on a brick level
+                if (nx > 1) xi = (x == 0) ? 1 : (x == nx - 1 ? nx - 2 : x);
+                if (ny > 1) yi = (y == 0) ? 1 : (y == ny - 1 ? ny - 2 : y);
+                if (nz > 1) zi = (z == 0) ? 1 : (z == nz - 1 ? nz - 2 : z);
+                const int s = brick_cell(a.bricks, xi, yi, zi);
+                from = s < 0 ? cell : s;
+            }
+        } else {
+            if (flag & kNearWall) links = a.links ? a.links[cell] : bounce_links(a, x, y, z, sx, sy, sz);
+            if (kind == kOutflow && (x > 0 || (a.periodic & 1))) from = xm + nx * y + nxy * z;
+            if (kind == kNeumann) from = inward_cell(a, x, y, z);
+        }
     }
     const bool fluid = kind == kFluid;
     const bool copies = kind == kGhost || kind == kOutflow || kind == kNeumann;
@@ -185,7 +231,8 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
     float v[27];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        int src = sx[kCx[i] + 1] + sy[kCy[i] + 1] + sz[kCz[i] + 1];
+        int src = kBrick ? brick_source(a, cell, x, y, z, kCx[i], kCy[i], kCz[i])
+                         : sx[kCx[i] + 1] + sy[kCy[i] + 1] + sz[kCz[i] + 1];
         int pl = i;
         if (kFlags) {
             if (links & (1u << i)) {   // halfway bounce-back: own opposite population
@@ -211,7 +258,8 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
     if (kScalar) {
 #pragma unroll
         for (int i = 0; i < QS; ++i) {
-            int src = sx[kSx[i] + 1] + sy[kSy[i] + 1] + sz[kSz[i] + 1];
+            int src = kBrick ? brick_source(a, cell, x, y, z, kSx[i], kSy[i], kSz[i])
+                             : sx[kSx[i] + 1] + sy[kSy[i] + 1] + sz[kSz[i] + 1];
             int pl = i;
             if (kFlags) {
                 if (links & (1u << i)) {   // D3Q7 direction i is D3Q27 velocity i
@@ -351,6 +399,21 @@ static void launch_step(const StepArgs& a, hipStream_t st)
     hipLaunchKernelGGL((k_step<T, kFlags, kForce, kScalar, kTime, kGradFD>), grid, block, 0, st, a);
 }
 
+// brick levels: flags, no force field, two 256-thread blocks per stored brick
+template <typename T>
+static void launch_step_brick(const StepArgs& a, bool scalar, bool time, int n_bricks, hipStream_t st)
+{
+    const dim3 grid(2u * (unsigned)n_bricks), block(256);
+    if (scalar && time)
+        hipLaunchKernelGGL((k_step<T, true, false, true, true, false, true>), grid, block, 0, st, a);
+    else if (scalar)
+        hipLaunchKernelGGL((k_step<T, true, false, true, false, false, true>), grid, block, 0, st, a);
+    else if (time)
+        hipLaunchKernelGGL((k_step<T, true, false, false, true, false, true>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((k_step<T, true, false, false, false, false, true>), grid, block, 0, st, a);
+}
+
 // gradient-mode variants: fully periodic levels without flags
 template <typename T>
 static void dispatch_step_grad(const StepArgs& a, bool force, bool scalar, hipStream_t st)
@@ -429,6 +492,7 @@ static StepArgs step_args(const cslbm_level* L, const void* fin, void* fout, con
     a.inv_tau_s = gin ? (float)(1.0 / L->p.tau_s) : 0.0f;
     for (int k = 0; k < 3; ++k) a.u_in[k] = (float)L->p.u_in[k];
     a.s_in = (float)L->p.s_in;
+    a.bricks = brick_map(L);
     return a;
 }
 
@@ -476,6 +540,13 @@ int launch_step_interp(const cslbm_level* L, const void* fin, void* fout, const 
     const bool time = t0 != nullptr;
     if (time && !has_flags)
         return fail(CSLBM_ERR_UNSUPPORTED, "time-interpolating steps need a flagged level");
+    if (L->brick_table) {   // validated: flags, no force field
+        if (L->storage == CSLBM_F32)
+            launch_step_brick<float>(a, has_scalar, time, L->n_bricks, stream);
+        else
+            launch_step_brick<_Float16>(a, has_scalar, time, L->n_bricks, stream);
+        return check_launch("k_step (bricks)");
+    }
     if (L->storage == CSLBM_F32)
         dispatch_step<float>(a, has_flags, has_force, has_scalar, time, stream);
     else

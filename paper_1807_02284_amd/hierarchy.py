@@ -174,12 +174,23 @@ def drop_overwritten_posts(post: dict, n: int) -> dict:
     return out
 
 
+def _storage_list(lev: Level, box_cells: np.ndarray) -> np.ndarray:
+    """A cell list over a level's box in the level's storage order (int32);
+    every listed cell of a brick level must be stored."""
+    idx = lev.storage_of(np.asarray(box_cells, np.int64))
+    if np.any(idx < 0):
+        raise ValueError("a listed cell lies in a brick that is not stored")
+    return idx.astype(np.int32)
+
+
 class Hierarchy:
     """Scales 0..n-1 (0 = reference); parents[i] is the nearest coarser scale
     of a finer scale i (default i - 1).  A scale with a larger spacing than
     scale 0 is a far-field scale: its parent is the finer scale it surrounds
     (default 0), its GHOST cells are the region it shares with that parent,
-    and it post-maps onto the parent's GHOST shell."""
+    and it post-maps onto the parent's GHOST shell.  ``kinds`` are over each
+    level's box (for a brick level: SOLID outside the stored bricks); the
+    cell lists sent to the library are in each level's storage order."""
 
     def __init__(self, levels: list[Level], kinds: list[np.ndarray], parents=None):
         assert len(levels) == len(kinds) and 1 <= len(levels) <= _capi.MAX_SCALES
@@ -213,7 +224,7 @@ class Hierarchy:
                 check_prior_stencils(self.kinds[self.parents[i]], (par.nx, par.ny, par.nz),
                                      tuple(par.c.origin), par.c.dx, par.c.periodic,
                                      (lev.nx, lev.ny, lev.nz), tuple(lev.c.origin), lev.c.dx, ghosts)
-                g_t = torch.as_tensor(ghosts, device=dev)
+                g_t = torch.as_tensor(_storage_list(lev, ghosts), device=dev)
                 self.lists.append(g_t)
                 sc.n_ghost = ghosts.size
                 sc.ghost_cells = g_t.data_ptr() if ghosts.size else None
@@ -240,7 +251,7 @@ class Hierarchy:
         self.post_full = {**self.post, **far_post}
         self.post = {**drop_overwritten_posts(self.post, n), **far_post}
         for (i, j), cells in self.post.items():
-            t = torch.as_tensor(cells, device=dev)
+            t = torch.as_tensor(_storage_list(levels[j], cells), device=dev)
             self.lists.append(t)
             self.c_scales[i].n_post[j] = cells.size
             self.c_scales[i].post_cells[j] = t.data_ptr() if cells.size else None
@@ -367,6 +378,64 @@ def fine_scale(lo, hi, alpha: float, params0: Params, solid_fn=None, *, scalar: 
     p.tau_s = 0.5 + alpha * (params0.tau_s - 0.5)
     lev = Level(*shape, p, storage=storage, scalar=scalar, periodic=0, flags=kinds,
                 origin=origin, dx=dx)
+    return lev, kinds
+
+
+def brick_kinds(region: np.ndarray, solid: np.ndarray | None = None):
+    """Stored bricks and cell kinds of a brick-stored scale.  ``region``
+    (bool [nz][ny][nx], sizes multiples of 8) marks the cells the scale must
+    cover; a brick is stored when it holds a region cell.  Stored cells with a
+    neighbour (26-neighbourhood) outside the stored bricks or outside the box
+    are GHOST (the scale's boundary, written by prior-mapping), the other
+    stored cells FLUID, or SOLID where ``solid`` is set; cells outside the
+    stored bricks are SOLID (never pulled: the ghost layer lies between).
+    Returns (bricks [nz/8][ny/8][nx/8], kinds over the box)."""
+    region = np.asarray(region, bool)
+    nz, ny, nx = region.shape
+    if nx % 8 or ny % 8 or nz % 8:
+        raise ValueError(f"box {nx}x{ny}x{nz} is not a multiple of 8")
+    bricks = region.reshape(nz // 8, 8, ny // 8, 8, nx // 8, 8).any(axis=(1, 3, 5))
+    stored = bricks.repeat(8, 0).repeat(8, 1).repeat(8, 2)
+    pad = np.pad(stored, 1, constant_values=False)
+    inner = stored.copy()
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                inner &= pad[1 + dz:1 + dz + nz, 1 + dy:1 + dy + ny, 1 + dx:1 + dx + nx]
+    kinds = np.full(stored.shape, _capi.SOLID, np.uint8)
+    kinds[stored] = GHOST
+    kinds[inner] = FLUID
+    if solid is not None:
+        kinds[inner & np.asarray(solid, bool).reshape(stored.shape)] = _capi.SOLID
+    return bricks, kinds.reshape(-1)
+
+
+def brick_scale(lo, hi, alpha: float, params0: Params, region_fn, solid_fn=None, *, scalar: bool,
+                storage: int):
+    """A finer scale like ``fine_scale`` whose box (sizes rounded up to
+    multiples of 8) is stored in 8x8x8 bricks: only the bricks that hold
+    cells where ``region_fn(px, py, pz)`` (physical coordinates, elementwise)
+    is true, plus the ghost layer of ``brick_kinds``.  Returns (level, kinds
+    over the box)."""
+    dx = 1.0 / alpha
+    i0 = [math.ceil(lo[a] * alpha - 1e-9) for a in range(3)]
+    i1 = [math.floor(hi[a] * alpha + 1e-9) for a in range(3)]
+    shape = tuple(-(-(i1[a] - i0[a] + 1) // 8) * 8 for a in range(3))
+    origin = tuple(i0[a] * dx for a in range(3))
+    px = origin[0] + np.arange(shape[0]) * dx
+    py = origin[1] + np.arange(shape[1]) * dx
+    pz = origin[2] + np.arange(shape[2]) * dx
+    full = (shape[2], shape[1], shape[0])
+    region = np.broadcast_to(region_fn(px[None, None, :], py[None, :, None], pz[:, None, None]), full)
+    solid = None
+    if solid_fn is not None:
+        solid = np.broadcast_to(solid_fn(px[None, None, :], py[None, :, None], pz[:, None, None]), full)
+    bricks, kinds = brick_kinds(region, solid)
+    p = Params(**{**params0.__dict__})
+    p.nu = params0.nu * alpha
+    p.tau_s = 0.5 + alpha * (params0.tau_s - 0.5)
+    lev = Level(*shape, p, storage=storage, scalar=scalar, periodic=0, flags=kinds, origin=origin,
+                dx=dx, bricks=bricks)
     return lev, kinds
 
 

@@ -54,21 +54,65 @@ def _dev_ptr(t: torch.Tensor | None):
     return t.data_ptr()
 
 
+def brick_layout(mask: np.ndarray, nx: int, ny: int, nz: int):
+    """Storage layout of the stored bricks ``mask`` (bool [nz/8][ny/8][nx/8])
+    of an nx*ny*nz box: the brick table (index of each brick among the
+    stored ones, -1 for the others, x fastest), the stored bricks'
+    coordinates [n_bricks * 3] and, for every storage index (512 per brick,
+    x fastest inside the brick), the cell's index in the box."""
+    mask = np.asarray(mask, bool)
+    bnx, bny, bnz = nx // 8, ny // 8, nz // 8
+    if (nx % 8 or ny % 8 or nz % 8) or mask.shape != (bnz, bny, bnx):
+        raise ValueError(f"brick mask {mask.shape} does not tile the box {nx}x{ny}x{nz} with 8x8x8 bricks")
+    ids = np.flatnonzero(mask.reshape(-1))
+    if ids.size == 0:
+        raise ValueError("no stored brick")
+    table = np.full(mask.size, -1, np.int32)
+    table[ids] = np.arange(ids.size, dtype=np.int32)
+    bx, by, bz = ids % bnx, (ids // bnx) % bny, ids // (bnx * bny)
+    origin = np.stack([bx, by, bz], axis=1).astype(np.int32).reshape(-1)
+    l = np.arange(512)
+    lx, ly, lz = l % 8, (l // 8) % 8, l // 64
+    X = (bx[:, None] * 8 + lx[None, :]).reshape(-1)
+    Y = (by[:, None] * 8 + ly[None, :]).reshape(-1)
+    Z = (bz[:, None] * 8 + lz[None, :]).reshape(-1)
+    return table, origin, (X + nx * (Y + ny * Z)).astype(np.int64)
+
+
 class Level:
-    """One uniform D3Q27 level of nx*ny*nz cells on the current CUDA device."""
+    """One uniform D3Q27 level of nx*ny*nz cells on the current CUDA device.
+
+    With ``bricks`` (a boolean mask over the 8x8x8 bricks of the box, shape
+    (nz/8, ny/8, nx/8)) only the marked bricks are stored: ``n`` is then the
+    number of stored cells, every per-cell array of the level (states, flags,
+    inputs and outputs of the calls) is in storage order, and ``flags`` /
+    ``force`` may be given over the whole box (they are gathered).
+    ``dense_index`` maps storage order to box order."""
 
     def __init__(self, nx: int, ny: int, nz: int, params: Params | None = None, *,
                  storage: int = F32, scalar: bool = False, periodic: int = 7,
                  flags: np.ndarray | torch.Tensor | None = None,
                  force: np.ndarray | torch.Tensor | None = None,
-                 origin=(0.0, 0.0, 0.0), dx: float = 1.0, device=None):
+                 origin=(0.0, 0.0, 0.0), dx: float = 1.0, device=None, bricks=None):
         lib = _capi.load()
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
-        self.n = self.nx * self.ny * self.nz
+        self.n_box = self.nx * self.ny * self.nz
+        self.n = self.n_box
         self.params = params or Params()
         self.storage = storage
         self.device = torch.device(device) if device is not None else torch.device("cuda")
-        plane = lib.cslbm_plane_stride(self.nx, self.ny, self.nz)
+        self.brick_table = self.brick_origin = None
+        self.n_bricks = 0
+        self.dense_index = None
+        if bricks is not None:
+            self._init_bricks(np.asarray(bricks, dtype=bool))
+            periodic = 0
+            if flags is not None and np.asarray(flags).size == self.n_box:
+                flags = np.asarray(flags, dtype=np.uint8).reshape(-1)[self.dense_index]
+            if force is not None:
+                raise ValueError("brick levels take no force field")
+        plane = lib.cslbm_plane_stride(self.nx, self.ny, self.nz) if bricks is None else \
+            lib.cslbm_plane_stride(self.n, 1, 1)
         if plane < 0:
             raise _capi.CslbmError(plane, "cslbm_plane_stride", lib.cslbm_last_error().decode())
         self.plane = int(plane)
@@ -111,6 +155,28 @@ class Level:
         if self.flags is not None:
             _capi.call("cslbm_prepare_flags", C.byref(self.c), _stream_handle())
 
+    def _init_bricks(self, mask: np.ndarray):
+        table, origin, self.dense_index = brick_layout(mask, self.nx, self.ny, self.nz)
+        self.n_bricks = origin.size // 3
+        self.n = self.n_bricks * 512
+        self.brick_table = torch.as_tensor(table, device=self.device)
+        self.brick_origin = torch.as_tensor(origin, device=self.device)
+
+    def storage_of(self, dense: np.ndarray) -> np.ndarray:
+        """Storage indices of box cells (box order for a dense level; -1 for
+        cells of a brick level that are not stored)."""
+        dense = np.asarray(dense, dtype=np.int64)
+        if self.dense_index is None:
+            return dense
+        inv = np.full(self.n_box, -1, np.int64)
+        inv[self.dense_index] = np.arange(self.n)
+        return inv[dense]
+
+    def to_storage(self, box_values: np.ndarray) -> np.ndarray:
+        """Per-cell values over the box ([..., n_box]) in storage order."""
+        v = np.asarray(box_values)
+        return v if self.dense_index is None else v[..., self.dense_index]
+
     # -- struct <-> tensors ------------------------------------------------
     def _sync_struct(self):
         self.c.f = _dev_ptr(self.f)
@@ -123,6 +189,9 @@ class Level:
         self.c.vel = _dev_ptr(self.vel)
         self.c.vel_next = _dev_ptr(self.vel_next)
         self.c.gmax_buf = _dev_ptr(self.gmax_buf)
+        self.c.brick_table = _dev_ptr(self.brick_table)
+        self.c.brick_origin = _dev_ptr(self.brick_origin)
+        self.c.n_bricks = self.n_bricks
         self.c.p = self.params.to_c()
 
     def set_params(self, params: Params):
@@ -138,7 +207,10 @@ class Level:
                        _stream_handle())
 
     def set_flags(self, flags):
-        fl = torch.as_tensor(np.asarray(flags, dtype=np.uint8)).to(self.device).reshape(-1)
+        flags = np.asarray(flags, dtype=np.uint8).reshape(-1)
+        if self.dense_index is not None and flags.size == self.n_box:
+            flags = flags[self.dense_index]
+        fl = torch.as_tensor(flags).to(self.device).reshape(-1)
         if self.flags is None:
             self.flags = torch.zeros(self.plane, dtype=torch.uint8, device=self.device)
             self.links = torch.zeros(self.n, dtype=torch.int32, device=self.device)

@@ -1,0 +1,85 @@
+"""Host logic of sparse brick storage: the storage layout (brick table,
+brick coordinates, storage -> box index map), the ghost layer that
+``brick_kinds`` puts between the fluid and the bricks that are not stored,
+and the C ABI's checks of brick levels (no GPU needed)."""
+import ctypes as C
+
+import numpy as np
+
+from paper_1807_02284_amd import _capi, hierarchy
+from paper_1807_02284_amd.level import brick_layout
+from test_capi_abi import make_level
+
+
+def test_brick_layout_is_a_bijection_onto_the_stored_bricks():
+    nx, ny, nz = 24, 16, 32
+    rng = np.random.default_rng(2)
+    mask = rng.random((nz // 8, ny // 8, nx // 8)) < 0.6
+    table, origin, dense = brick_layout(mask, nx, ny, nz)
+    nb = int(mask.sum())
+    assert origin.size == 3 * nb and dense.size == 512 * nb
+    assert np.unique(dense).size == dense.size
+    # every storage index lies in its own brick, x fastest inside the brick
+    x, y, z = dense % nx, (dense // nx) % ny, dense // (nx * ny)
+    b = np.arange(dense.size) // 512
+    o = origin.reshape(-1, 3)
+    assert np.array_equal(x // 8, o[b, 0]) and np.array_equal(y // 8, o[b, 1])
+    assert np.array_equal(z // 8, o[b, 2])
+    l = np.arange(dense.size) % 512
+    assert np.array_equal(x % 8 + 8 * (y % 8) + 64 * (z % 8), l)
+    # the table points each stored brick at its index, the others at -1
+    bricks = (x // 8) + (nx // 8) * ((y // 8) + (ny // 8) * (z // 8))
+    assert np.array_equal(table[bricks], b)
+    assert np.all(table[~mask.reshape(-1)] == -1)
+
+
+def test_brick_kinds_keep_every_fluid_neighbourhood_stored():
+    shape = (32, 24, 16)
+    nx, ny, nz = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    region = (x - 15.5) ** 2 + (y - 11.0) ** 2 + (z - 7.0) ** 2 <= 7.5 ** 2
+    solid = (x - 15.5) ** 2 + (y - 11.0) ** 2 + (z - 7.0) ** 2 <= 2.0 ** 2
+    bricks, kinds = hierarchy.brick_kinds(region, solid)
+    assert np.array_equal(bricks, region.reshape(2, 8, 3, 8, 4, 8).any(axis=(1, 3, 5)))
+    k = kinds.reshape(nz, ny, nx)
+    stored = bricks.repeat(8, 0).repeat(8, 1).repeat(8, 2)
+    assert np.all(k[~stored] == _capi.SOLID)
+    assert np.all(k[region & ~solid & stored] != _capi.SOLID)   # the region is covered
+    fl = np.argwhere(k == _capi.FLUID)
+    assert fl.size
+    for d in np.array(np.meshgrid([-1, 0, 1], [-1, 0, 1], [-1, 0, 1])).reshape(3, -1).T:
+        nb = fl + d
+        assert np.all((nb >= 0).all(axis=1) & (nb < [nz, ny, nx]).all(axis=1))
+        assert np.all(stored[nb[:, 0], nb[:, 1], nb[:, 2]])
+    # a GHOST cell is a stored cell with a neighbour outside the stored bricks or the box
+    gh = np.argwhere(k == _capi.GHOST)
+    pad = np.pad(stored, 1, constant_values=False)
+    outside = np.zeros(len(gh), bool)
+    for d in np.array(np.meshgrid([-1, 0, 1], [-1, 0, 1], [-1, 0, 1])).reshape(3, -1).T:
+        q = gh + d + 1
+        outside |= ~pad[q[:, 0], q[:, 1], q[:, 2]]
+    assert np.all(outside)
+
+
+def test_brick_level_argument_checks():
+    lib = _capi.load()
+    L = make_level(nx=16, ny=16, nz=16, periodic=0, flags=0x9000, brick_table=0xA000,
+                   brick_origin=0xB000, n_bricks=3)
+    L.plane = 4096
+    assert lib.cslbm_step(C.byref(make_level(nx=12, ny=16, nz=16, periodic=0, flags=0x9000,
+                                             brick_table=0xA000, brick_origin=0xB000, n_bricks=1)),
+                          1, None) == _capi.ERR_SHAPE
+    assert lib.cslbm_step(C.byref(make_level(nx=16, ny=16, nz=16, periodic=0, flags=0x9000,
+                                             brick_table=0xA000, brick_origin=0xB000, n_bricks=9, plane=8192)),
+                          1, None) == _capi.ERR_ARG
+    periodic = make_level(nx=16, ny=16, nz=16, periodic=1, flags=0x9000, brick_table=0xA000,
+                          brick_origin=0xB000, n_bricks=3, plane=8192)
+    assert lib.cslbm_step(C.byref(periodic), 1, None) == _capi.ERR_UNSUPPORTED
+    forced = make_level(nx=16, ny=16, nz=16, periodic=0, flags=0x9000, brick_table=0xA000,
+                        brick_origin=0xB000, n_bricks=3, force=0xC000, plane=8192)
+    assert lib.cslbm_step(C.byref(forced), 1, None) == _capi.ERR_UNSUPPORTED
+    no_flags = make_level(nx=16, ny=16, nz=16, periodic=0, brick_table=0xA000,
+                          brick_origin=0xB000, n_bricks=3, plane=8192)
+    assert lib.cslbm_step(C.byref(no_flags), 1, None) < 0
+    vort = lib.cslbm_vorticity
+    assert vort(C.byref(L), 0xD000, None, None) == _capi.ERR_UNSUPPORTED

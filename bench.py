@@ -311,9 +311,29 @@ def run_plume(nx: int, ny: int, nz: int, spinup: int, n_ref: int):
     H.step(2)
     torch.cuda.synchronize()
     bad = sum(lv.count_nonfinite() for lv in H.levels)
+    n_scales = len(H.levels)
+    del H
+    torch.cuda.empty_cache()
+    # the same thresholds with the finer scales stored in 8x8x8 bricks of
+    # their regions instead of the regions' bounding boxes
+    Hb, _ = hierarchy.dynamic_hierarchy(lev0, flags, ((2e-3, 0.01), (8e-3, 0.02)), (1.5, 2.0),
+                                        solid_fn=sphere, bricks=True)
+    cells_b = [lv.n for lv in Hb.levels]
+    subs_b = subs[: len(cells_b)]
+    Hb.step(2)
+    torch.cuda.synchronize()
+    e0.record()
+    Hb.step(n_ref)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1) / n_ref
+    bad_b = sum(lv.count_nonfinite() for lv in Hb.levels)
+    lups_b = sum(c * k for c, k in zip(cells_b, subs_b))
+    del Hb
+    torch.cuda.empty_cache()
     out = {
         "reference_box": [nx, ny, nz],
-        "scales": len(H.levels),
+        "scales": n_scales,
         "spacing_ratios": alphas,
         "cells_per_scale": cells,
         "substeps_per_scale": subs,
@@ -337,8 +357,12 @@ def run_plume(nx: int, ny: int, nz: int, spinup: int, n_ref: int):
         "reference_scale_achieved_gbs": n0 * 273 / (ms0 / spinup * 1e-3) / 1e9,
         "bytes_per_lup_collide_stream": 273,
         "nonfinite": bad,
+        "bricks": {"cells_per_scale": cells_b, "ms_per_reference_step": ms_b,
+                   "lattice_updates_per_reference_step": lups_b,
+                   "mlups_all_scales": lups_b / (ms_b * 1e-3) / 1e6,
+                   "speedup_vs_boxes": ms / ms_b, "nonfinite": bad_b},
     }
-    del H, lev0
+    del lev0
     torch.cuda.empty_cache()
     return out
 

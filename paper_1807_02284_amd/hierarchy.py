@@ -410,13 +410,12 @@ def brick_kinds(region: np.ndarray, solid: np.ndarray | None = None):
     return bricks, kinds.reshape(-1)
 
 
-def brick_scale(lo, hi, alpha: float, params0: Params, region_fn, solid_fn=None, *, scalar: bool,
-                storage: int):
-    """A finer scale like ``fine_scale`` whose box (sizes rounded up to
-    multiples of 8) is stored in 8x8x8 bricks: only the bricks that hold
-    cells where ``region_fn(px, py, pz)`` (physical coordinates, elementwise)
-    is true, plus the ghost layer of ``brick_kinds``.  Returns (level, kinds
-    over the box)."""
+def brick_scale_layout(lo, hi, alpha: float, region_fn, solid_fn=None):
+    """Box, stored bricks and kinds of a brick-stored finer scale covering
+    the level-0 box [lo, hi] at spacing 1/alpha (box sizes rounded up to
+    multiples of 8): the bricks that hold cells where ``region_fn(px, py,
+    pz)`` (physical coordinates, elementwise) is true, with the ghost layer
+    of ``brick_kinds``.  Returns (shape, origin, dx, bricks, kinds)."""
     dx = 1.0 / alpha
     i0 = [math.ceil(lo[a] * alpha - 1e-9) for a in range(3)]
     i1 = [math.floor(hi[a] * alpha + 1e-9) for a in range(3)]
@@ -431,6 +430,14 @@ def brick_scale(lo, hi, alpha: float, params0: Params, region_fn, solid_fn=None,
     if solid_fn is not None:
         solid = np.broadcast_to(solid_fn(px[None, None, :], py[None, :, None], pz[:, None, None]), full)
     bricks, kinds = brick_kinds(region, solid)
+    return shape, origin, dx, bricks, kinds
+
+
+def brick_scale(lo, hi, alpha: float, params0: Params, region_fn, solid_fn=None, *, scalar: bool,
+                storage: int):
+    """A finer scale like ``fine_scale`` stored in 8x8x8 bricks (see
+    ``brick_scale_layout``).  Returns (level, kinds over the box)."""
+    shape, origin, dx, bricks, kinds = brick_scale_layout(lo, hi, alpha, region_fn, solid_fn)
     p = Params(**{**params0.__dict__})
     p.nu = params0.nu * alpha
     p.tau_s = 0.5 + alpha * (params0.tau_s - 0.5)
@@ -516,8 +523,66 @@ def copy_cells(src: Level, src_cells: np.ndarray, dst: Level, dst_cells: np.ndar
     torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
 
 
+def brick_regions(omega, speed, kinds0, shape, thresholds, alphas, *, margin: int = 3,
+                  dilate: int = 2, nest: int = 2):
+    """Regions (bool [nz][ny][nx] over the reference scale) of brick-stored
+    finer scales: the cells kept by each scale's thresholds, dilated; every
+    interior object (SOLID cells off the box faces) that a region touches is
+    added whole with a layer of fluid around it, thick enough to survive the
+    shrinking of the deeper scales; then the region is cut to its parent's
+    region shrunk by `nest` plus one brick of the scale (the reference: the
+    box less `margin`), so that the scale's stored bricks and ghost layer lie
+    on its parent's fluid.  Stops at the first empty region."""
+    nx, ny, nz = shape
+    solid = np.asarray(kinds0).reshape(nz, ny, nx) == _capi.SOLID
+    solid[:, :, [0, -1]] = False
+    solid[:, [0, -1], :] = False
+    solid[[0, -1], :, :] = False
+    labels, _ = ndimage.label(solid)
+    cube = np.ones((3, 3, 3), bool)   # distances in the max norm: bricks and stencils are cubes
+    shrink = [nest + math.ceil(8 / a) for a in alphas]
+    allowed = np.zeros((nz, ny, nx), bool)
+    allowed[margin:nz - margin, margin:ny - margin, margin:nx - margin] = True
+    regions = []
+    for k, thr in enumerate(thresholds):
+        keep = ((np.asarray(omega) > thr[0]) & (np.asarray(speed) > thr[1])).reshape(nz, ny, nx)
+        if not keep.any():
+            break
+        if dilate > 0:
+            keep = ndimage.binary_dilation(keep, structure=cube, iterations=dilate)
+        touched = np.unique(labels[ndimage.binary_dilation(keep, structure=cube) & (labels > 0)])
+        if touched.size:
+            objects = np.isin(labels, touched)
+            keep |= ndimage.binary_dilation(objects, structure=cube,
+                                            iterations=nest + 1 + sum(shrink[k + 1:]))
+        region = keep & ndimage.binary_erosion(allowed, structure=cube, iterations=shrink[k])
+        if not region.any():
+            break
+        regions.append(region)
+        allowed = region
+    return regions
+
+
+def region_box_fn(region: np.ndarray):
+    """Bounding box (level-0 units, inclusive) of a region over the reference
+    scale and its indicator at physical points (nearest reference cell)."""
+    nz, ny, nx = region.shape
+    zs, ys, xs = (np.flatnonzero(region.any(axis=ax)) for ax in ((1, 2), (0, 2), (0, 1)))
+    lo = [int(xs[0]), int(ys[0]), int(zs[0])]
+    hi = [int(xs[-1]), int(ys[-1]), int(zs[-1])]
+
+    def region_fn(px, py, pz):
+        ix = np.clip(np.rint(px).astype(np.int64), 0, nx - 1)
+        iy = np.clip(np.rint(py).astype(np.int64), 0, ny - 1)
+        iz = np.clip(np.rint(pz).astype(np.int64), 0, nz - 1)
+        return region[iz, iy, ix]
+
+    return lo, hi, region_fn
+
+
 def dynamic_hierarchy(lev0: Level, kinds0: np.ndarray, thresholds, alphas, *, margin: int = 3,
-                      dilate: int = 2, nest: int = 2, solid_fn=None, stream=None, previous=None):
+                      dilate: int = 2, nest: int = 2, solid_fn=None, stream=None, previous=None,
+                      bricks: bool = False):
     """Scales set by thresholds: scale k covers the bounding box of the cells
     with |curl u| > thresholds[k-1][0] and |u| > thresholds[k-1][1]
     (dilated), kept `margin` cells from the domain faces and `nest` cells
@@ -529,26 +594,43 @@ def dynamic_hierarchy(lev0: Level, kinds0: np.ndarray, thresholds, alphas, *, ma
     repeats every 40 iterations: every cell of a new scale first takes the
     full prior-mapping from its (new) parent, then the FLUID cells the old
     and the new box of that scale share keep their old state; cells that
-    leave a region are dropped with the old levels."""
+    leave a region are dropped with the old levels.
+
+    With `bricks` each finer scale stores only the 8x8x8 bricks holding its
+    region (the cells kept by the thresholds, dilated, inside its parent's
+    region shrunk by `nest` plus one brick of the scale, so that its stored
+    bricks and their ghost layer lie on the parent's fluid), instead of the
+    region's bounding box."""
     om, sp = lev0.vorticity(stream)
     omega, speed = om.cpu().numpy(), sp.cpu().numpy()
     shape = (lev0.nx, lev0.ny, lev0.nz)
     lo_lim = [margin] * 3
     hi_lim = [shape[a] - 1 - margin for a in range(3)]
     levels, kinds, boxes = [lev0], [np.asarray(kinds0, np.uint8)], []
-    for thr, alpha in zip(thresholds, alphas):
-        box = region_box(omega, speed, shape, thr, dilate, lo_lim, hi_lim)
-        if box is None:
-            break
-        lo, hi = box
-        lev, k = fine_scale(lo, hi, alpha, lev0.params, solid_fn, scalar=lev0.g is not None,
-                            storage=lev0.storage)
+    regions = brick_regions(omega, speed, kinds0, shape, thresholds, alphas, margin=margin,
+                            dilate=dilate, nest=nest) if bricks else None
+    for k_scale, (thr, alpha) in enumerate(zip(thresholds, alphas)):
+        if bricks:
+            if k_scale >= len(regions):
+                break
+            lo, hi, region_fn = region_box_fn(regions[k_scale])
+            lev, k = brick_scale(lo, hi, alpha, lev0.params, region_fn, solid_fn,
+                                 scalar=lev0.g is not None, storage=lev0.storage)
+        else:
+            box = region_box(omega, speed, shape, thr, dilate, lo_lim, hi_lim)
+            if box is None:
+                break
+            lo, hi = box
+            lev, k = fine_scale(lo, hi, alpha, lev0.params, solid_fn, scalar=lev0.g is not None,
+                                storage=lev0.storage)
         fill_from_parent(levels[-1], lev, stream)
         i = len(levels)
         if previous is not None and i < len(previous.levels) and \
                 abs(previous.levels[i].c.dx - lev.c.dx) < 1e-12:
             src, dst = kept_cells(previous.levels[i], previous.kinds[i], lev, k)
-            copy_cells(previous.levels[i], src, lev, dst, stream)
+            # box indices to storage order (FLUID cells of a brick level are stored)
+            copy_cells(previous.levels[i], _storage_list(previous.levels[i], src), lev,
+                       _storage_list(lev, dst), stream)
         levels.append(lev)
         kinds.append(k)
         boxes.append((lo, hi))

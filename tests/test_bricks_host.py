@@ -83,3 +83,48 @@ def test_brick_level_argument_checks():
     assert lib.cslbm_step(C.byref(no_flags), 1, None) < 0
     vort = lib.cslbm_vorticity
     assert vort(C.byref(L), 0xD000, None, None) == _capi.ERR_UNSUPPORTED
+
+
+def _plume_like_field(shape, centre, radius, jet_r):
+    """A smooth stand-in for the plume's |curl u| and |u|: a jet shear layer
+    along x and a wake cone behind a sphere."""
+    nx, ny, nz = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r = np.sqrt((y + 0.5 - ny / 2) ** 2 + (z + 0.5 - nz / 2) ** 2)
+    speed = 0.05 * np.exp(-np.maximum(r - jet_r, 0.0) ** 2 / 8.0)
+    omega = 0.012 * np.exp(-(r - jet_r) ** 2 / 6.0)
+    d = np.sqrt((x - centre[0]) ** 2 + (y - centre[1]) ** 2 + (z - centre[2]) ** 2)
+    wake = (x > centre[0]) & (r < radius + 0.3 * (x - centre[0]))
+    omega = np.where(wake | (d < radius + 3), np.maximum(omega, 0.01), omega)
+    return omega.reshape(-1), speed.reshape(-1)
+
+
+def test_brick_regions_of_a_plume_like_flow_nest_on_fluid():
+    """The brick construction of the plume benchmark at 128x64x64: every
+    scale's ghost stencils lie on its parent's FLUID cells (the sphere is
+    taken into the regions whole), and the bricks store fewer cells than
+    the regions' bounding boxes."""
+    shape = (128, 64, 64)
+    nx, ny, nz = shape
+    from paper_1807_02284_amd import inputs
+    centre, radius = (40.0, 32.0, 32.0), 6.0
+    kinds0 = inputs.plume_flags(nx, ny, nz, sphere_center=centre, sphere_radius=radius)
+    omega, speed = _plume_like_field(shape, centre, radius, 8.0)
+
+    def sphere(px, py, pz):
+        return (px + 0.5 - centre[0]) ** 2 + (py + 0.5 - centre[1]) ** 2 + (pz + 0.5 - centre[2]) ** 2 \
+            <= radius ** 2
+
+    alphas = (1.5, 2.0)
+    regions = hierarchy.brick_regions(omega, speed, kinds0, shape, ((2e-3, 0.01), (8e-3, 0.02)),
+                                      alphas)
+    assert len(regions) == 2
+    parent = (kinds0, shape, (0.0, 0.0, 0.0), 1.0)
+    for region, alpha in zip(regions, alphas):
+        lo, hi, fn = hierarchy.region_box_fn(region)
+        shp, origin, dx, bricks, kinds = hierarchy.brick_scale_layout(lo, hi, alpha, fn, sphere)
+        ghosts = np.flatnonzero(kinds == hierarchy.GHOST)
+        hierarchy.check_prior_stencils(parent[0], parent[1], parent[2], parent[3], 0, shp, origin,
+                                       dx, ghosts)
+        assert bricks.sum() * 512 < np.prod(shp)
+        parent = (kinds, shp, origin, dx)

@@ -28,7 +28,7 @@ METRIC = "D3Q27 MLUPS + % HBM roofline; FP16-store and adjoint vs FP32 plain ste
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = {"f32": 216, "f16s": 108}   # 27 reads + 27 writes per update
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_traffic.json")
-STEP_KERNEL_SOURCES = ("step.hip", "cm_collide.hpp", "internal.hpp", "lattice.hpp")
+STEP_KERNEL_SOURCES = ("step.hip", "brick.hpp", "cm_collide.hpp", "internal.hpp", "lattice.hpp")
 
 
 def kernel_source_hash() -> str:

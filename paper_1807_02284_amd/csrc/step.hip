@@ -132,24 +132,30 @@ __device__ __forceinline__ uint32_t bounce_links(const StepArgs& a, int x, int y
     return m;
 }
 
-// Brick levels: pull source of velocity i for the cell at storage index c
-// (own index when that cell is not stored; a valid brick level gives no
-// fluid cell such a source), and the bounce-back mask from the neighbours'
-// kinds (a source that is not stored counts as a wall).
-__device__ __forceinline__ int brick_source(const StepArgs& a, int c, int x, int y, int z, int cx,
-                                            int cy, int cz)
+// Brick levels: the block's brick and its 26 neighbours (index -1: not
+// stored or outside the box) are read once into LDS; the pull source of
+// velocity i of the cell at brick-local (lx, ly, lz) is then the
+// neighbouring brick's cell at (lx - cx, ly - cy, lz - cz) mod 8, or the
+// cell itself when that brick is not stored (a valid brick level gives no
+// fluid cell such a source).
+__device__ __forceinline__ int brick_source(const int* nbr, int c, int cx, int cy, int cz)
 {
-    const int s = brick_neighbour(a.bricks, c, x, y, z, cx, cy, cz);
-    return s < 0 ? c : s;
+    const int lx = (c & 7) - cx, ly = ((c >> 3) & 7) - cy, lz = ((c >> 6) & 7) - cz;
+    const int k = (lx < 0 ? 0 : (lx > 7 ? 2 : 1)) + 3 * (ly < 0 ? 0 : (ly > 7 ? 2 : 1)) +
+                  9 * (lz < 0 ? 0 : (lz > 7 ? 2 : 1));
+    const int b = nbr[k];
+    return b < 0 ? c : (b << 9) + (lx & 7) + ((ly & 7) << 3) + ((lz & 7) << 6);
 }
 
-__device__ __forceinline__ uint32_t bounce_links_brick(const StepArgs& a, int c, int x, int y, int z)
+// bounce-back mask from the neighbours' kinds (a source that is not stored
+// counts as a wall)
+__device__ __forceinline__ uint32_t bounce_links_brick(const StepArgs& a, const int* nbr, int c)
 {
     uint32_t m = 0;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-        const int s = brick_neighbour(a.bricks, c, x, y, z, kCx[i], kCy[i], kCz[i]);
-        if (s < 0 || (a.flags[s] & kKindMask) == kSolid) m |= 1u << i;
+        const int s = brick_source(nbr, c, kCx[i], kCy[i], kCz[i]);
+        if (s == c || (a.flags[s] & kKindMask) == kSolid) m |= 1u << i;
     }
     return m;
 }
@@ -164,9 +170,21 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
     // dense box: (x, y, z) from the 3-D grid; brick level: two blocks per
     // stored brick, each 256 cells of it in storage order
     int x, y, z, cell;
+    __shared__ int nbr[kBrick ? 27 : 1];
     if (kBrick) {
-        cell = ((blockIdx.x >> 1) << 9) + threadIdx.x + ((blockIdx.x & 1) << 8);
+        const int b = blockIdx.x >> 1;
+        cell = (b << 9) + threadIdx.x + ((blockIdx.x & 1) << 8);
         brick_xyz(a.bricks, cell, x, y, z);
+        if (threadIdx.x < 27) {
+            const int t = threadIdx.x;
+            const int bx = a.bricks.origin[3 * b] + t % 3 - 1;
+            const int by = a.bricks.origin[3 * b + 1] + (t / 3) % 3 - 1;
+            const int bz = a.bricks.origin[3 * b + 2] + t / 9 - 1;
+            const bool in = bx >= 0 && by >= 0 && bz >= 0 && bx < a.bricks.bnx && by < a.bricks.bny &&
+                            bz < a.bricks.bnz;
+            nbr[t] = in ? a.bricks.table[bx + a.bricks.bnx * (by + a.bricks.bny * bz)] : -1;
+        }
+        __syncthreads();
     } else {
         x = blockIdx.x * blockDim.x + threadIdx.x;
         y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -208,8 +226,8 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
         const uint8_t flag = a.flags[cell];
         kind = flag & kKindMask;
         if (kBrick) {
-            if (flag & kNearWall) links = a.links ? a.links[cell] : bounce_links_brick(a, cell, x, y, z);
-            if (kind == kOutflow) from = brick_source(a, cell, x, y, z, 1, 0, 0);
+            if (flag & kNearWall) links = a.links ? a.links[cell] : bounce_links_brick(a, nbr, cell);
+            if (kind == kOutflow) from = brick_source(nbr, cell, 1, 0, 0);
             if (kind == kNeumann) {
                 int xi = x, yi = y, zi = z;   // no periodic axis on a brick level
                 if (nx > 1) xi = (x == 0) ? 1 : (x == nx - 1 ? nx - 2 : x);
@@ -231,7 +249,7 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
     float v[27];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        int src = kBrick ? brick_source(a, cell, x, y, z, kCx[i], kCy[i], kCz[i])
+        int src = kBrick ? brick_source(nbr, cell, kCx[i], kCy[i], kCz[i])
                          : sx[kCx[i] + 1] + sy[kCy[i] + 1] + sz[kCz[i] + 1];
         int pl = i;
         if (kFlags) {
@@ -258,7 +276,7 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
     if (kScalar) {
 #pragma unroll
         for (int i = 0; i < QS; ++i) {
-            int src = kBrick ? brick_source(a, cell, x, y, z, kSx[i], kSy[i], kSz[i])
+            int src = kBrick ? brick_source(nbr, cell, kSx[i], kSy[i], kSz[i])
                              : sx[kSx[i] + 1] + sy[kSy[i] + 1] + sz[kSz[i] + 1];
             int pl = i;
             if (kFlags) {

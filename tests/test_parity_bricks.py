@@ -87,29 +87,40 @@ def _spec_with(shape, origin, dx, nu0, kinds, parent):
     return Spec(shape, origin, dx, nu0, kinds, parent=parent)
 
 
-@pytest.mark.parametrize("n_scales", [2, 3])
-def test_hierarchy_with_a_brick_scale_matches_oracle(n_scales):
+@pytest.mark.parametrize("n_scales,brick2", [(2, False), (3, False), (3, True)])
+def test_hierarchy_with_a_brick_scale_matches_oracle(n_scales, brick2):
     """Reference 32^3 periodic (dense); scale 1 brick-stored over a ball at
-    spacing 2/3; with three scales, scale 2 is a dense box at spacing 1/2
-    inside scale 1's fluid (its parent and post-mapping target is the brick
-    scale)."""
+    spacing 2/3; with three scales, scale 2 at spacing 1/2 inside scale 1's
+    fluid (its parent and post-mapping target is the brick scale), as a
+    dense box or itself brick-stored over a smaller ball (exchanges between
+    two brick levels)."""
     n = 32
     nu0 = 2e-3
     s0 = Spec((n, n, n), (0.0, 0.0, 0.0), 1.0, nu0, np.zeros(n ** 3, np.uint8), periodic=7)
     centre = (16.2, 15.7, 16.4)
-    lev1, kinds1 = hierarchy.brick_scale((5.0, 5.0, 5.0), (27.0, 27.0, 27.0), 1.5, s0.params(),
+    lo1, hi1, r1 = ((4.0,) * 3, (28.0,) * 3, 10.0) if brick2 else ((5.0,) * 3, (27.0,) * 3, 8.5)
+    lev1, kinds1 = hierarchy.brick_scale(lo1, hi1, 1.5, s0.params(),
                                          lambda px, py, pz: (px - centre[0]) ** 2 + (py - centre[1]) ** 2
-                                         + (pz - centre[2]) ** 2 <= 8.5 ** 2,
+                                         + (pz - centre[2]) ** 2 <= r1 ** 2,
                                          scalar=True, storage=F32)
     assert lev1.n_bricks < (lev1.nx // 8) * (lev1.ny // 8) * (lev1.nz // 8)
     s1 = _spec_with((lev1.nx, lev1.ny, lev1.nz), tuple(lev1.c.origin), lev1.c.dx, nu0, kinds1, 0)
     specs = [s0, s1]
     levs = [s0.level(True), lev1]
-    if n_scales == 3:
+    if n_scales == 3 and not brick2:
         sh2 = (14, 13, 12)
         s2 = Spec(sh2, (13.1, 12.8, 13.3), 0.5, nu0, hierarchy.shell_flags(*sh2), parent=1)
         specs.append(s2)
         levs.append(s2.level(True))
+    elif n_scales == 3:
+        lev2, kinds2 = hierarchy.brick_scale((11.0, 11.0, 11.0), (21.0, 21.0, 21.0), 2.0, s0.params(),
+                                             lambda px, py, pz: (px - centre[0]) ** 2 + (py - centre[1]) ** 2
+                                             + (pz - centre[2]) ** 2 <= 3.0 ** 2,
+                                             scalar=True, storage=F32)
+        assert lev2.n_bricks < (lev2.nx // 8) * (lev2.ny // 8) * (lev2.nz // 8)
+        specs.append(_spec_with((lev2.nx, lev2.ny, lev2.nz), tuple(lev2.c.origin), lev2.c.dx, nu0,
+                                kinds2, 1))
+        levs.append(lev2)
     oscs = []
     for sp, lev in zip(specs, levs):
         rho, u, s = smooth_state(sp, 50)

@@ -531,6 +531,10 @@ def main():
                     help="skip the 512x256x256 three-scale plume variant")
     ap.add_argument("--no-gradient-mode", action="store_true",
                     help="skip the finite-difference gradient-mode variant")
+    ap.add_argument("--plume-spinup", type=int, default=300,
+                    help="reference-scale steps before the plume's finer scales are placed")
+    ap.add_argument("--plume-steps", type=int, default=40,
+                    help="timed reference steps of the plume's multi-scale runs")
     ap.add_argument("--no-far-field", action="store_true",
                     help="skip the open-jet variant with a far-field scale")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -576,7 +580,7 @@ def main():
               file=sys.stderr, flush=True)
 
     if not args.no_plume:
-        pl = run_plume(512, 256, 256, 300, 40)
+        pl = run_plume(512, 256, 256, args.plume_spinup, args.plume_steps)
         variants["plume_multiscale_512x256x256"] = pl
         print(f"[bench] plume: {pl['scales']} scales, cells {pl['cells_per_scale']}, "
               f"{pl['ms_per_reference_step']:.2f} ms/reference step, "

@@ -34,6 +34,32 @@ struct ExchArgs {
     float kappa_s;   // scalar non-equilibrium rescaling
 };
 
+// The workgroups of a launch are handed out to the 8 XCDs in turn (hardware
+// block b, in dispatch order, runs on XCD b % 8), and each XCD has its own
+// L2.  xcd_block maps the hardware block index to a logical one so that
+// every XCD walks one contiguous range of logical blocks: blocks that share
+// cache lines meet in the same L2.  A bijection of [0, nb): XCD x runs
+// nb / 8 blocks, one more if x < nb % 8.
+__host__ __device__ constexpr int xcd_block(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+constexpr bool xcd_block_is_bijective(int nb)
+{
+    bool seen[64] = {};
+    for (int b = 0; b < nb; ++b) {
+        const int l = xcd_block(b, nb);
+        if (l < 0 || l >= nb || seen[l]) return false;
+        seen[l] = true;
+    }
+    return true;
+}
+static_assert(xcd_block_is_bijective(1) && xcd_block_is_bijective(7) && xcd_block_is_bijective(8) &&
+                  xcd_block_is_bijective(13) && xcd_block_is_bijective(64),
+              "xcd_block must permute the blocks");
+
 __device__ __forceinline__ int wrap_or_clamp(int i, int n, bool periodic)
 {
     if (periodic) {

@@ -101,6 +101,53 @@ __host__ __device__ __forceinline__ void to_moments(float (&v)[27], float ux, fl
     sweep_fwd<9, 1, 3>(v, uz);
 }
 
+// The x sweep split in two.  Its first half does not depend on u: every
+// x-line (a-, a0, a+) becomes (s0, s1, s2) = (a- + a0 + a+, a+ - a-, a+ + a-).
+// The macroscopic moments are sums of these line values, so the collision
+// forms them there instead of summing the 27 populations three times over.
+__host__ __device__ __forceinline__ void xsweep_sums(float (&v)[27])
+{
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+        const int t = 3 * l;
+        const float am = v[t], a0 = v[t + 1], ap = v[t + 2];
+        v[t] = am + a0 + ap;
+        v[t + 1] = ap - am;
+        v[t + 2] = ap + am;
+    }
+}
+
+// dr = sum h, j = sum c h from the line values of xsweep_sums (line l = 3
+// (cz + 1) + (cy + 1) starts at slot 3 l)
+__host__ __device__ __forceinline__ void moments_of_sums(const float (&v)[27], float& dr, float& jx,
+                                                         float& jy, float& jz)
+{
+    float s[9], d[9];
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+        s[l] = v[3 * l];
+        d[l] = v[3 * l + 1];
+    }
+    dr = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7])) + s[8];
+    jx = ((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7])) + d[8];
+    jy = ((s[2] - s[0]) + (s[5] - s[3])) + (s[8] - s[6]);
+    jz = ((s[6] - s[0]) + (s[7] - s[1])) + (s[8] - s[2]);
+}
+
+// second half of the x sweep: (s0, s1, s2) -> central moments (k0, k1, k2)
+// about u, as fwd3 finishes them
+__host__ __device__ __forceinline__ void xsweep_finish(float (&v)[27], float u)
+{
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+        const int t = 3 * l;
+        const float s0 = v[t], s1 = v[t + 1], s2 = v[t + 2];
+        const float k1 = s1 - u * s0;
+        v[t + 1] = k1;
+        v[t + 2] = s2 - u * (s1 + k1);
+    }
+}
+
 __host__ __device__ __forceinline__ void from_moments(float (&v)[27], float ux, float uy, float uz)
 {
     sweep_inv<9, 1, 3>(v, uz);
@@ -192,14 +239,17 @@ __host__ __device__ __forceinline__ CellMacro cm_collide(float (&v)[27], const R
                                                float Fz, bool active = true, float g_given = -1.0f)
 {
     float dr, jx, jy, jz;
-    moments0(v, dr, jx, jy, jz);
+    xsweep_sums(v);
+    moments_of_sums(v, dr, jx, jy, jz);
     const float rho = 1.0f + dr;
     const float inv_rho = rcp(rho);
     const float ux = (jx + 0.5f * Fx) * inv_rho;
     const float uy = (jy + 0.5f * Fy) * inv_rho;
     const float uz = (jz + 0.5f * Fz) * inv_rho;
 
-    to_moments(v, ux, uy, uz);
+    xsweep_finish(v, ux);
+    sweep_fwd<3, 1, 9>(v, uy);
+    sweep_fwd<9, 1, 3>(v, uz);
     float d[27];
     deviation_equilibrium(d, dr, ux, uy, uz);
 

@@ -325,9 +325,16 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
 
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        if (kOff32 && !kTime)
-            Io<T>::st(plane_at(fo + i * P, cell), v[tensor_slot(i)]);
-        else
+        if (kOff32 && !kTime) {
+            // the plane base stays a uniform SGPR pair, so every store is
+            // base + the one 32-bit lane offset; without the empty asm the
+            // compiler chains 64-bit VALU adds from plane to plane
+            using G16 = __attribute__((address_space(1))) _Float16;
+            G16* base = (G16*)(fo + i * P);
+            asm("" : "+s"(base));
+            G16* p = (G16*)((__attribute__((address_space(1))) char*)base + (uint32_t)cell * 2u);
+            __builtin_nontemporal_store(static_cast<_Float16>(v[tensor_slot(i)]), p);
+        } else
             store_out<T, kTime>(a, fo, i * P + cell, v[tensor_slot(i)]);
     }
 

@@ -28,7 +28,7 @@ namespace cslbm {
 __host__ __device__ __forceinline__ void fwd3_rev(float am, float a0, float ap, float u, float& b0,
                                                   float& b1, float& b2, float& ub)
 {
-    const float s0 = am + a0 + ap;
+    const float s0 = (ap + am) + a0;   // as fwd3 forms it
     const float s1 = ap - am;
     const float s0b = b0 - u * b1 + u * u * b2;
     const float s1b = b1 - 2.0f * u * b2;

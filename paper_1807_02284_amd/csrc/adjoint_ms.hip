@@ -458,15 +458,24 @@ __device__ __forceinline__ void sum_columns(const GatherWs& g, int64_t n_t, cons
     }
 }
 
+// Sub-box of the source level that holds every corner of an interior
+// target (the only cells the interpolation pass flags)
+struct SrcBox {
+    int x0, y0, z0, nx, ny, nz;
+};
+
 template <bool kScalar, bool kNode>
-__global__ void __launch_bounds__(256) k_exadj_sources(const ExchAdjArgs a, const GatherWs g)
+__global__ void __launch_bounds__(256) k_exadj_sources(const ExchAdjArgs a, const GatherWs g,
+                                                       const SrcBox b)
 {
     const ExchArgs& e = a.e;
-    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t n_src = (int64_t)e.snx * e.sny * e.snz;
-    if (s >= n_src || !g.touched[s]) return;
+    const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (l >= (int64_t)b.nx * b.ny * b.nz) return;
+    const int sxyz[3] = {b.x0 + (int)(l % b.nx), b.y0 + (int)((l / b.nx) % b.ny),
+                         b.z0 + (int)(l / ((int64_t)b.nx * b.ny))};
+    const int64_t s = sxyz[0] + (int64_t)e.snx * (sxyz[1] + (int64_t)e.sny * sxyz[2]);
+    if (!g.touched[s]) return;
     g.touched[s] = 0;
-    const int sxyz[3] = {(int)(s % e.snx), (int)((s / e.snx) % e.sny), (int)(s / ((int64_t)e.snx * e.sny))};
     const int nd[3] = {e.dnx, e.dny, e.dnz};
     // per axis: destination indices whose stencil can hold source index s,
     // q(j) in [s - 1, s + 1), with one index of margin each side
@@ -561,6 +570,25 @@ __global__ void __launch_bounds__(256) k_zero(float* p, int64_t n)
 
 static unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// The source indices an interior target's stencil can reach: the targets lie
+// in dst's box, so per axis floor(q) .. floor(q) + 1 over the box's extent in
+// source coordinates q, with one index of margin each side for rounding,
+// clipped to the source box (corners of interior targets never wrap).
+static SrcBox source_box(const cslbm_level* src, const cslbm_level* dst)
+{
+    const int sn[3] = {src->nx, src->ny, src->nz}, dn[3] = {dst->nx, dst->ny, dst->nz};
+    int lo[3], cnt[3];
+    for (int d = 0; d < 3; ++d) {
+        const double q0 = (dst->origin[d] - src->origin[d]) / src->dx;
+        const double q1 = (dst->origin[d] + (dn[d] - 1) * dst->dx - src->origin[d]) / src->dx;
+        const double qa = std::floor(std::min(q0, q1)), qb = std::floor(std::max(q0, q1));
+        const double l = std::max(0.0, qa - 1.0), h = std::min((double)(sn[d] - 1), qb + 2.0);
+        lo[d] = (int)l;
+        cnt[d] = h >= l ? (int)(h - l) + 1 : 0;
+    }
+    return SrcBox{lo[0], lo[1], lo[2], cnt[0], cnt[1], cnt[2]};
+}
+
 // adjoint of launch_exchange(src, fA, fB, w, dst, ..., cells): the
 // destination adjoint lam_d (mu_d) at the cells goes to the source adjoints
 static int launch_exchange_adjoint(const cslbm_level* src, const void* fA, const void* fB,
@@ -589,7 +617,9 @@ static int launch_exchange_adjoint(const cslbm_level* src, const void* fA, const
     // plus one index each side: 2 src->dx / dst->dx + 4 indices at most.
     if (gw && 2.0 * src->dx / dst->dx + 4.0 <= (double)kMaxCand) {
         const GatherWs g = *gw;
-        const dim3 sgrid(grid_for((int64_t)src->nx * src->ny * src->nz));
+        const SrcBox sb = source_box(src, dst);
+        const int64_t n_box = (int64_t)sb.nx * sb.ny * sb.nz;
+        const dim3 sgrid(grid_for(n_box > 0 ? n_box : 1));
         const bool blend = a.ca != 0.0f && a.cb != 0.0f;
 #define CSLBM_GATHER(S_, N_)                                                                   \
         if (blend)                                                                             \
@@ -597,7 +627,7 @@ static int launch_exchange_adjoint(const cslbm_level* src, const void* fA, const
         else                                                                                   \
             hipLaunchKernelGGL((k_exadj_interp<S_, N_, false>), grid, block, 0, stream, a, g); \
         hipLaunchKernelGGL((k_exadj_vjp<S_, N_>), grid, block, 0, stream, a, g);              \
-        hipLaunchKernelGGL((k_exadj_sources<S_, N_>), sgrid, block, 0, stream, a, g);
+        hipLaunchKernelGGL((k_exadj_sources<S_, N_>), sgrid, block, 0, stream, a, g, sb);
         if (scalar && node) {
             CSLBM_GATHER(true, true)
         } else if (scalar) {

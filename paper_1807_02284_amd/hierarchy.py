@@ -54,10 +54,9 @@ def post_cells(coarse_kinds: np.ndarray, coarse_shape, coarse_origin, coarse_dx,
 
     The stencil is separable: along each axis a coarse index uses the fine
     index b and, when its fraction is not 0, b + 1.  Staying inside the box
-    is a product of per-axis conditions; the non-FLUID fine cells (ghost
-    shell, padding, solids) then rule out the coarse cells that use them,
-    found through per-axis inverse maps (at most two coarse indices per
-    fine index per axis)."""
+    is a product of per-axis conditions; the corners are then gathered from
+    the fine FLUID mask axis by axis (a corner of weight 0 is pointed at b,
+    which is checked anyway).  Runs on the GPU when there is one."""
     cnx, cny, cnz = coarse_shape
     fnx, fny, fnz = fine_shape
     fn = (fnx, fny, fnz)
@@ -67,33 +66,27 @@ def post_cells(coarse_kinds: np.ndarray, coarse_shape, coarse_origin, coarse_dx,
           for a in range(3)]
     if any(h < l for l, h in zip(lo, hi)):
         return np.zeros(0, np.int32)
-    inside, inv = [], []
+    dev = torch.device("cuda") if torch.cuda.is_available() else torch.device("cpu")
+    inside, corner = [], []
     for a in range(3):
         b, t = _axis_stencil(lo[a], hi[a], coarse_origin[a], coarse_dx, fine_origin[a], fine_dx)
         up = t != 0.0                                   # b + 1 has non-zero weight
-        inside.append((b >= 0) & (b < fn[a]) & (~up | (b + 1 < fn[a])))
-        # inverse map: fine index -> up to two coarse (candidate-box) indices
-        m = np.full((fn[a] + 1, 2), -1, np.int64)
-        idx = np.arange(b.size)
-        for f_idx, sel, slot in ((b, np.ones(b.size, bool), 0), (b + 1, up, 1)):
-            ok = sel & (f_idx >= 0) & (f_idx < fn[a])
-            m[f_idx[ok], slot] = idx[ok]
-        inv.append(m)
-    ck = np.asarray(coarse_kinds).reshape(cnz, cny, cnx)
-    ok = ck[lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1] == FLUID
+        inside.append(torch.as_tensor((b >= 0) & (b < fn[a]) & (~up | (b + 1 < fn[a])), device=dev))
+        corner.append([torch.as_tensor(np.clip(b + o * up, 0, fn[a] - 1), device=dev) for o in (0, 1)])
+    ck = np.asarray(coarse_kinds).reshape(cnz, cny, cnx)[lo[2]:hi[2] + 1, lo[1]:hi[1] + 1, lo[0]:hi[0] + 1]
+    ok = torch.as_tensor(ck == FLUID, device=dev)
     ok &= inside[2][:, None, None] & inside[1][None, :, None] & inside[0][None, None, :]
-    # coarse cells that use a non-FLUID fine cell
-    bz, by, bx = np.nonzero(np.asarray(fine_kinds).reshape(fnz, fny, fnx) != FLUID)
-    for sz in range(2):
-        for sy in range(2):
-            for sx in range(2):
-                iz, iy, ix = inv[2][bz, sz], inv[1][by, sy], inv[0][bx, sx]
-                hit = (iz >= 0) & (iy >= 0) & (ix >= 0)
-                ok[iz[hit], iy[hit], ix[hit]] = False
-    flat = (np.arange(lo[0], hi[0] + 1, dtype=np.int32)[None, None, :] +
-            np.int32(cnx) * (np.arange(lo[1], hi[1] + 1, dtype=np.int32)[None, :, None] +
-                             np.int32(cny) * np.arange(lo[2], hi[2] + 1, dtype=np.int32)[:, None, None]))
-    return flat[ok]
+    fluid = torch.as_tensor(np.asarray(fine_kinds).reshape(fnz, fny, fnx) == FLUID, device=dev)
+    for oz in range(2):
+        fz = fluid.index_select(0, corner[2][oz])
+        for oy in range(2):
+            fzy = fz.index_select(1, corner[1][oy])
+            for ox in range(2):
+                ok &= fzy.index_select(2, corner[0][ox])
+    k = torch.nonzero(ok).cpu().numpy()
+    if k.size == 0:
+        return np.zeros(0, np.int32)
+    return ((k[:, 2] + lo[0]) + cnx * ((k[:, 1] + lo[1]) + cny * (k[:, 0] + lo[2]))).astype(np.int32)
 
 
 def check_prior_stencils(parent_kinds, parent_shape, parent_origin, parent_dx, parent_periodic,
@@ -319,20 +312,21 @@ class Hierarchy:
 # ---------------------------------------------------------------------------
 # dynamic scale construction (section "Scale construction", dynamic scales)
 # ---------------------------------------------------------------------------
-def region_box(omega: np.ndarray, speed: np.ndarray, shape, thresholds, dilate: int, lo_limit,
-               hi_limit):
+def region_box(omega, speed, shape, thresholds, dilate: int, lo_limit, hi_limit):
     """Bounding box (inclusive level-0 cell bounds, x/y/z order) of the cells
     kept by the two thresholds of the dynamic construction, |curl u| >
     thresholds[0] and then |u| > thresholds[1], dilated by `dilate` cells
     and clipped to [lo_limit, hi_limit]; None when no cell passes."""
     nx, ny, nz = shape
-    w = ((np.asarray(omega) > thresholds[0]) & (np.asarray(speed) > thresholds[1])).reshape(nz, ny, nx)
+    om = torch.as_tensor(omega)   # numpy or torch (then on its device)
+    sp = torch.as_tensor(speed, device=om.device)
+    w = ((om > thresholds[0]) & (sp > thresholds[1])).reshape(nz, ny, nx)
     # the bounding box from the three projections of the mask
-    xs = np.flatnonzero(w.any(axis=(0, 1)))
+    xs = np.flatnonzero(w.any(dim=1).any(dim=0).cpu().numpy())
     if xs.size == 0:
         return None
-    ys = np.flatnonzero(w.any(axis=(0, 2)))
-    zs = np.flatnonzero(w.any(axis=(1, 2)))
+    ys = np.flatnonzero(w.any(dim=2).any(dim=0).cpu().numpy())
+    zs = np.flatnonzero(w.any(dim=2).any(dim=1).cpu().numpy())
     lo = [int(xs[0]) - dilate, int(ys[0]) - dilate, int(zs[0]) - dilate]
     hi = [int(xs[-1]) + dilate, int(ys[-1]) + dilate, int(zs[-1]) + dilate]
     lo = [max(lo[a], lo_limit[a]) for a in range(3)]
@@ -501,16 +495,19 @@ def kept_cells(old: Level, old_kinds: np.ndarray, new: Level, new_kinds: np.ndar
     hi = [min(o_old[a] + shp_old[a], o_new[a] + shp_new[a]) for a in range(3)]
     if any(h <= l for l, h in zip(lo, hi)):
         return np.zeros(0, np.int32), np.zeros(0, np.int32)
-    gx, gy, gz = (np.arange(lo[a], hi[a]) for a in range(3))
+    # on the GPU when there is one (tens of millions of cells)
+    dev = torch.device("cuda") if torch.cuda.is_available() else torch.device("cpu")
+    gx, gy, gz = (torch.arange(lo[a], hi[a], device=dev) for a in range(3))
 
     def cells(o, shp):
         return ((gx - o[0])[None, None, :] +
-                shp[0] * ((gy - o[1])[None, :, None] + shp[1] * (gz - o[2])[:, None, None]))
+                shp[0] * ((gy - o[1])[None, :, None] + shp[1] * (gz - o[2])[:, None, None])).reshape(-1)
 
-    c_old = cells(o_old, shp_old).reshape(-1)
-    c_new = cells(o_new, shp_new).reshape(-1)
-    keep = (old_kinds[c_old] == FLUID) & (new_kinds[c_new] == FLUID)
-    return c_old[keep].astype(np.int32), c_new[keep].astype(np.int32)
+    c_old, c_new = cells(o_old, shp_old), cells(o_new, shp_new)
+    fl_old = torch.as_tensor(np.asarray(old_kinds) == FLUID, device=dev)
+    fl_new = torch.as_tensor(np.asarray(new_kinds) == FLUID, device=dev)
+    keep = fl_old[c_old] & fl_new[c_new]
+    return (c_old[keep].to(torch.int32).cpu().numpy(), c_new[keep].to(torch.int32).cpu().numpy())
 
 
 def copy_cells(src: Level, src_cells: np.ndarray, dst: Level, dst_cells: np.ndarray, stream=None):
@@ -523,6 +520,32 @@ def copy_cells(src: Level, src_cells: np.ndarray, dst: Level, dst_cells: np.ndar
     torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
 
 
+def _cube_dilate(m: torch.Tensor, r: int) -> torch.Tensor:
+    """Dilation of a bool [nz][ny][nx] mask by the cube of half-width r
+    (cells outside the array count as False): three 1-D max-pools, the same
+    as r iterations with the 3x3x3 cube."""
+    if r <= 0:
+        return m
+    dt = torch.float16 if m.is_cuda else torch.float32
+    x = m.to(dt)[None, None]
+    for k in ((2 * r + 1, 1, 1), (1, 2 * r + 1, 1), (1, 1, 2 * r + 1)):
+        x = torch.nn.functional.max_pool3d(x, kernel_size=k, stride=1, padding=tuple(v // 2 for v in k))
+    return x[0, 0] > 0
+
+
+def _cube_erode(m: torch.Tensor, r: int) -> torch.Tensor:
+    """Erosion of a bool mask by the cube of half-width r, cells outside the
+    array counting as False (so the faces erode): the complement dilated,
+    with the outside padded in."""
+    if r <= 0:
+        return m
+    dt = torch.float16 if m.is_cuda else torch.float32
+    x = torch.nn.functional.pad((~m).to(dt)[None, None], (r, r, r, r, r, r), value=1.0)
+    for k in ((2 * r + 1, 1, 1), (1, 2 * r + 1, 1), (1, 1, 2 * r + 1)):
+        x = torch.nn.functional.max_pool3d(x, kernel_size=k, stride=1)
+    return ~(x[0, 0] > 0)
+
+
 def brick_regions(omega, speed, kinds0, shape, thresholds, alphas, *, margin: int = 3,
                   dilate: int = 2, nest: int = 2):
     """Regions (bool [nz][ny][nx] over the reference scale) of brick-stored
@@ -532,33 +555,36 @@ def brick_regions(omega, speed, kinds0, shape, thresholds, alphas, *, margin: in
     shrinking of the deeper scales; then the region is cut to its parent's
     region shrunk by `nest` plus one brick of the scale (the reference: the
     box less `margin`), so that the scale's stored bricks and ghost layer lie
-    on its parent's fluid.  Stops at the first empty region."""
+    on its parent's fluid.  Stops at the first empty region.  omega and speed
+    may be torch tensors: the morphology then runs on their device."""
     nx, ny, nz = shape
+    om = torch.as_tensor(omega).reshape(nz, ny, nx)
+    sp = torch.as_tensor(speed, device=om.device).reshape(nz, ny, nx)
+    dev = om.device
     solid = np.asarray(kinds0).reshape(nz, ny, nx) == _capi.SOLID
     solid[:, :, [0, -1]] = False
     solid[:, [0, -1], :] = False
     solid[[0, -1], :, :] = False
     labels, _ = ndimage.label(solid)
-    cube = np.ones((3, 3, 3), bool)   # distances in the max norm: bricks and stencils are cubes
+    # distances in the max norm (bricks and stencils are cubes)
     shrink = [nest + math.ceil(8 / a) for a in alphas]
-    allowed = np.zeros((nz, ny, nx), bool)
+    allowed = torch.zeros((nz, ny, nx), dtype=torch.bool, device=dev)
     allowed[margin:nz - margin, margin:ny - margin, margin:nx - margin] = True
     regions = []
     for k, thr in enumerate(thresholds):
-        keep = ((np.asarray(omega) > thr[0]) & (np.asarray(speed) > thr[1])).reshape(nz, ny, nx)
-        if not keep.any():
+        keep = (om > thr[0]) & (sp > thr[1])
+        if not bool(keep.any()):
             break
-        if dilate > 0:
-            keep = ndimage.binary_dilation(keep, structure=cube, iterations=dilate)
-        touched = np.unique(labels[ndimage.binary_dilation(keep, structure=cube) & (labels > 0)])
+        keep = _cube_dilate(keep, dilate)
+        near = _cube_dilate(keep, 1).cpu().numpy()
+        touched = np.unique(labels[near & (labels > 0)])
         if touched.size:
-            objects = np.isin(labels, touched)
-            keep |= ndimage.binary_dilation(objects, structure=cube,
-                                            iterations=nest + 1 + sum(shrink[k + 1:]))
-        region = keep & ndimage.binary_erosion(allowed, structure=cube, iterations=shrink[k])
-        if not region.any():
+            objects = torch.as_tensor(np.isin(labels, touched), device=dev)
+            keep |= _cube_dilate(objects, nest + 1 + sum(shrink[k + 1:]))
+        region = keep & _cube_erode(allowed, shrink[k])
+        if not bool(region.any()):
             break
-        regions.append(region)
+        regions.append(region.cpu().numpy())
         allowed = region
     return regions
 
@@ -601,8 +627,7 @@ def dynamic_hierarchy(lev0: Level, kinds0: np.ndarray, thresholds, alphas, *, ma
     region shrunk by `nest` plus one brick of the scale, so that its stored
     bricks and their ghost layer lie on the parent's fluid), instead of the
     region's bounding box."""
-    om, sp = lev0.vorticity(stream)
-    omega, speed = om.cpu().numpy(), sp.cpu().numpy()
+    omega, speed = lev0.vorticity(stream)   # stay on the GPU: thresholds and morphology run there
     shape = (lev0.nx, lev0.ny, lev0.nz)
     lo_lim = [margin] * 3
     hi_lim = [shape[a] - 1 - margin for a in range(3)]

@@ -128,3 +128,22 @@ def test_brick_regions_of_a_plume_like_flow_nest_on_fluid():
                                        dx, ghosts)
         assert bricks.sum() * 512 < np.prod(shp)
         parent = (kinds, shp, origin, dx)
+
+
+def test_cube_morphology_equals_iterated_3x3x3_structure():
+    """Dilation and erosion by a cube of half-width r (three 1-D max-pools)
+    equal scipy's binary morphology with the 3x3x3 structure iterated r
+    times, cells outside the array counting as False."""
+    import torch
+    from scipy import ndimage
+    rng = np.random.default_rng(17)
+    cube = np.ones((3, 3, 3), bool)
+    for trial in range(12):
+        shape = tuple(int(v) for v in rng.integers(4, 26, 3))
+        m = rng.random(shape) < rng.uniform(0.02, 0.9)
+        r = int(rng.integers(1, 6))
+        t = torch.as_tensor(m)
+        np.testing.assert_array_equal(hierarchy._cube_dilate(t, r).numpy(),
+                                      ndimage.binary_dilation(m, structure=cube, iterations=r))
+        np.testing.assert_array_equal(hierarchy._cube_erode(t, r).numpy(),
+                                      ndimage.binary_erosion(m, structure=cube, iterations=r))

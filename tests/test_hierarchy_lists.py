@@ -33,6 +33,27 @@ def test_post_lists_match_oracle(alpha, origin):
     np.testing.assert_array_equal(np.flatnonzero(fine_kinds == oracle.GHOST), ml.shell_ghosts(f))
 
 
+@pytest.mark.parametrize("alpha,origin,solid_frac", [(1.5, (3.3, 2.6, 2.2), 0.6), (2.0, (4.0, 3.0, 5.5), 0.85),
+                                                     (1.25, (2.9, 3.1, 2.7), 0.3)])
+def test_post_lists_match_oracle_when_the_fine_box_is_mostly_solid(alpha, origin, solid_frac):
+    """Fine kinds as a brick level's box view has them (most cells SOLID):
+    the corner gather must rule out every coarse cell whose stencil touches
+    one, as the oracle's cell-by-cell loop does."""
+    n = 16
+    rng = np.random.default_rng(int(alpha * 100) + int(solid_frac * 10))
+    coarse_kinds = np.zeros(n ** 3, np.uint8)
+    fine_shape = (13, 11, 12)
+    fine_kinds = hierarchy.shell_flags(*fine_shape)
+    inner = fine_kinds == 0
+    fine_kinds[inner & (rng.random(fine_kinds.size) < solid_frac)] = oracle.SOLID
+    c = make(n, n, n, (0.0, 0.0, 0.0), 1.0, coarse_kinds, periodic=7)
+    f = make(*fine_shape, origin, 1.0 / alpha, fine_kinds)
+    ref = ml.post_targets(c, f)
+    got = hierarchy.post_cells(coarse_kinds, (n, n, n), (0.0, 0.0, 0.0), 1.0,
+                               fine_kinds, fine_shape, origin, 1.0 / alpha)
+    np.testing.assert_array_equal(np.sort(got.astype(np.int64)), ref)
+
+
 def test_prior_stencil_check_rejects_ghosts_outside_parent():
     n = 8
     kinds = np.zeros(n ** 3, np.uint8)

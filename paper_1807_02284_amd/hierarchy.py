@@ -170,6 +170,8 @@ def drop_overwritten_posts(post: dict, n: int) -> dict:
 def _storage_list(lev: Level, box_cells: np.ndarray) -> np.ndarray:
     """A cell list over a level's box in the level's storage order (int32);
     every listed cell of a brick level must be stored."""
+    if lev.dense_index is None:   # a dense box: storage order is box order
+        return np.asarray(box_cells, np.int32)
     idx = lev.storage_of(np.asarray(box_cells, np.int64))
     if np.any(idx < 0):
         raise ValueError("a listed cell lies in a brick that is not stored")
@@ -546,8 +548,19 @@ def _cube_erode(m: torch.Tensor, r: int) -> torch.Tensor:
     return ~(x[0, 0] > 0)
 
 
+def object_labels(kinds0, shape) -> np.ndarray:
+    """Connected components (face-connected) of the interior objects: SOLID
+    cells of the reference scale off its box faces; 0 elsewhere."""
+    nx, ny, nz = shape
+    solid = np.asarray(kinds0).reshape(nz, ny, nx) == _capi.SOLID
+    solid[:, :, [0, -1]] = False
+    solid[:, [0, -1], :] = False
+    solid[[0, -1], :, :] = False
+    return ndimage.label(solid)[0]
+
+
 def brick_regions(omega, speed, kinds0, shape, thresholds, alphas, *, margin: int = 3,
-                  dilate: int = 2, nest: int = 2):
+                  dilate: int = 2, nest: int = 2, labels=None):
     """Regions (bool [nz][ny][nx] over the reference scale) of brick-stored
     finer scales: the cells kept by each scale's thresholds, dilated; every
     interior object (SOLID cells off the box faces) that a region touches is
@@ -556,16 +569,15 @@ def brick_regions(omega, speed, kinds0, shape, thresholds, alphas, *, margin: in
     region shrunk by `nest` plus one brick of the scale (the reference: the
     box less `margin`), so that the scale's stored bricks and ghost layer lie
     on its parent's fluid.  Stops at the first empty region.  omega and speed
-    may be torch tensors: the morphology then runs on their device."""
+    may be torch tensors: the morphology then runs on their device.  `labels`
+    (object_labels of kinds0) may be passed in when the geometry is reused."""
     nx, ny, nz = shape
     om = torch.as_tensor(omega).reshape(nz, ny, nx)
     sp = torch.as_tensor(speed, device=om.device).reshape(nz, ny, nx)
     dev = om.device
-    solid = np.asarray(kinds0).reshape(nz, ny, nx) == _capi.SOLID
-    solid[:, :, [0, -1]] = False
-    solid[:, [0, -1], :] = False
-    solid[[0, -1], :, :] = False
-    labels, _ = ndimage.label(solid)
+    if labels is None:
+        labels = object_labels(kinds0, shape)
+    lab = torch.as_tensor(labels, device=dev)
     # distances in the max norm (bricks and stencils are cubes)
     shrink = [nest + math.ceil(8 / a) for a in alphas]
     allowed = torch.zeros((nz, ny, nx), dtype=torch.bool, device=dev)
@@ -576,11 +588,12 @@ def brick_regions(omega, speed, kinds0, shape, thresholds, alphas, *, margin: in
         if not bool(keep.any()):
             break
         keep = _cube_dilate(keep, dilate)
-        near = _cube_dilate(keep, 1).cpu().numpy()
-        touched = np.unique(labels[near & (labels > 0)])
-        if touched.size:
-            objects = torch.as_tensor(np.isin(labels, touched), device=dev)
-            keep |= _cube_dilate(objects, nest + 1 + sum(shrink[k + 1:]))
+        touched = torch.unique(lab[_cube_dilate(keep, 1) & (lab > 0)])
+        if touched.numel():
+            # the touched objects' cells (a lookup over the label values)
+            hit = torch.zeros(int(lab.max()) + 1, dtype=torch.bool, device=dev)
+            hit[touched.long()] = True
+            keep |= _cube_dilate(hit[lab.long()], nest + 1 + sum(shrink[k + 1:]))
         region = keep & _cube_erode(allowed, shrink[k])
         if not bool(region.any()):
             break
@@ -632,8 +645,14 @@ def dynamic_hierarchy(lev0: Level, kinds0: np.ndarray, thresholds, alphas, *, ma
     lo_lim = [margin] * 3
     hi_lim = [shape[a] - 1 - margin for a in range(3)]
     levels, kinds, boxes = [lev0], [np.asarray(kinds0, np.uint8)], []
+    labels = None
+    if bricks:
+        # the objects do not move: their labels are kept with the hierarchy
+        old = getattr(previous, "object_labels", None)
+        labels = old if old is not None and tuple(old.shape) == (shape[2], shape[1], shape[0]) \
+            else torch.as_tensor(object_labels(kinds0, shape), device=omega.device)
     regions = brick_regions(omega, speed, kinds0, shape, thresholds, alphas, margin=margin,
-                            dilate=dilate, nest=nest) if bricks else None
+                            dilate=dilate, nest=nest, labels=labels) if bricks else None
     for k_scale, (thr, alpha) in enumerate(zip(thresholds, alphas)):
         if bricks:
             if k_scale >= len(regions):
@@ -662,7 +681,9 @@ def dynamic_hierarchy(lev0: Level, kinds0: np.ndarray, thresholds, alphas, *, ma
         lo_lim = [lo[a] + nest for a in range(3)]
         hi_lim = [hi[a] - nest for a in range(3)]
     torch.cuda.synchronize()
-    return Hierarchy(levels, kinds), boxes
+    H = Hierarchy(levels, kinds)
+    H.object_labels = labels
+    return H, boxes
 
 
 # ---------------------------------------------------------------------------

@@ -159,6 +159,7 @@ class Level:
         table, origin, self.dense_index = brick_layout(mask, self.nx, self.ny, self.nz)
         self.n_bricks = origin.size // 3
         self.n = self.n_bricks * 512
+        self._table = table
         self.brick_table = torch.as_tensor(table, device=self.device)
         self.brick_origin = torch.as_tensor(origin, device=self.device)
 
@@ -168,9 +169,20 @@ class Level:
         dense = np.asarray(dense, dtype=np.int64)
         if self.dense_index is None:
             return dense
-        inv = np.full(self.n_box, -1, np.int64)
-        inv[self.dense_index] = np.arange(self.n)
-        return inv[dense]
+        # through the brick table: 512 * brick + lx + 8 ly + 64 lz, on the
+        # level's device when it has one (the lists run to millions of cells)
+        nx, ny, bnx, bny = self.nx, self.ny, self.nx // 8, self.ny // 8
+        if dense.size and (dense.min() < 0 or dense.max() >= nx * ny * self.nz):
+            raise ValueError("box cell index outside the level's box")
+        table = getattr(self, "brick_table", None)
+        if table is not None and table.is_cuda:
+            d = torch.as_tensor(dense, device=table.device)
+            x, y, z = d % nx, (d // nx) % ny, d // (nx * ny)
+            b = table[(x >> 3) + bnx * ((y >> 3) + bny * (z >> 3))].to(torch.int64)
+            return torch.where(b < 0, -1, b * 512 + (x & 7) + 8 * (y & 7) + 64 * (z & 7)).cpu().numpy()
+        x, y, z = dense % nx, (dense // nx) % ny, dense // (nx * ny)
+        b = self._table[(x >> 3) + bnx * ((y >> 3) + bny * (z >> 3))].astype(np.int64)
+        return np.where(b < 0, -1, b * 512 + (x & 7) + 8 * (y & 7) + 64 * (z & 7))
 
     def to_storage(self, box_values: np.ndarray) -> np.ndarray:
         """Per-cell values over the box ([..., n_box]) in storage order."""

@@ -147,3 +147,23 @@ def test_cube_morphology_equals_iterated_3x3x3_structure():
                                       ndimage.binary_dilation(m, structure=cube, iterations=r))
         np.testing.assert_array_equal(hierarchy._cube_erode(t, r).numpy(),
                                       ndimage.binary_erosion(m, structure=cube, iterations=r))
+
+
+def test_storage_of_inverts_the_layout_through_the_brick_table():
+    """Box index -> storage index through the brick table equals the inverse
+    of the layout's storage -> box map (-1 for cells of unstored bricks)."""
+    import types
+    from paper_1807_02284_amd.level import Level
+    rng = np.random.default_rng(23)
+    nx, ny, nz = 24, 16, 32
+    mask = rng.random((nz // 8, ny // 8, nx // 8)) < 0.5
+    mask.reshape(-1)[0] = True
+    table, origin, dense_index = brick_layout(mask, nx, ny, nz)
+    lev = types.SimpleNamespace(nx=nx, ny=ny, nz=nz, dense_index=dense_index, _table=table)
+    inv = np.full(nx * ny * nz, -1, np.int64)
+    inv[dense_index] = np.arange(dense_index.size)
+    cells = np.arange(nx * ny * nz)
+    np.testing.assert_array_equal(Level.storage_of(lev, cells), inv)
+    import pytest
+    with pytest.raises(ValueError):
+        Level.storage_of(lev, np.array([nx * ny * nz]))

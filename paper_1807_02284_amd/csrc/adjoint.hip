@@ -67,7 +67,7 @@ __device__ __forceinline__ uint32_t adj_links(const AdjArgs& a, int x, int y, in
 }
 
 template <typename T, bool kScalar, bool kFlags>
-__global__ void __launch_bounds__(256) k_adjoint(const AdjArgs a)
+__device__ __forceinline__ void adjoint_cell(const AdjArgs& a)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -155,6 +155,31 @@ __global__ void __launch_bounds__(256) k_adjoint(const AdjArgs a)
         a.dtheta[2 * P + cell] += thb[2];
     }
 }
+
+// One thread per cell: the adjoint of its update, written to its pull sources.
+template <typename T, bool kScalar, bool kFlags>
+__global__ void __launch_bounds__(256) k_adjoint(const AdjArgs a)
+{
+    adjoint_cell<T, kScalar, kFlags>(a);
+}
+
+// Levels without cell kinds: capped at two waves per SIMD.  The collision
+// adjoint keeps most of its forward state live (over 256 registers: one wave
+// per SIMD); under the cap a little of it spills (72-100 B per lane) and the
+// second wave hides the memory latency: measured faster.  Levels with cell
+// kinds spill far more under the cap and keep one wave.
+#define CSLBM_ADJ_PERIODIC(T_, S_)                                                              \
+    template <>                                                                                 \
+    __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))              \
+    k_adjoint<T_, S_, false>(const AdjArgs a)                                                   \
+    {                                                                                           \
+        adjoint_cell<T_, S_, false>(a);                                                         \
+    }
+CSLBM_ADJ_PERIODIC(float, true)
+CSLBM_ADJ_PERIODIC(float, false)
+CSLBM_ADJ_PERIODIC(_Float16, true)
+CSLBM_ADJ_PERIODIC(_Float16, false)
+#undef CSLBM_ADJ_PERIODIC
 
 // Second pass on levels with cell kinds: ghost, outflow and Neumann cells
 // copy their source cell's state (identity Jacobian), so their output

@@ -79,9 +79,9 @@ __device__ __forceinline__ void adjoint_cell(const AdjArgs& a)
     const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
     const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
     const int zm = (z == 0) ? nz - 1 : z - 1, zp = (z == nz - 1) ? 0 : z + 1;
-    const int sx[3] = {xp, x, xm};
-    const int sy[3] = {yp * nx, y * nx, ym * nx};
-    const int sz[3] = {zp * nxy, z * nxy, zm * nxy};
+    int sx[3] = {xp, x, xm};
+    int sy[3] = {yp * nx, y * nx, ym * nx};
+    int sz[3] = {zp * nxy, z * nxy, zm * nxy};
     const T* f = static_cast<const T*>(a.f);
     uint32_t links = 0;
     if (kFlags) {
@@ -135,6 +135,13 @@ __device__ __forceinline__ void adjoint_cell(const AdjArgs& a)
     }
     float hb[27], gb[QS], thb[3];
     cm_collide_adjoint<kScalar>(h, gv, th, a.ap, lam, mu, hb, gb, thb);
+    // The 27 pull sources are formed again for the stores instead of kept
+    // live through the collision adjoint (54 registers): the empty asm
+    // statements hide that the link mask and the neighbour offsets are
+    // unchanged.  With them every variant fits two waves per SIMD unspilled.
+    if (kFlags) asm volatile("" : "+v"(links));
+    asm volatile("" : "+v"(sx[0]), "+v"(sx[1]), "+v"(sx[2]), "+v"(sy[0]), "+v"(sy[1]), "+v"(sy[2]),
+                 "+v"(sz[0]), "+v"(sz[1]), "+v"(sz[2]));
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         int pl;
@@ -156,30 +163,14 @@ __device__ __forceinline__ void adjoint_cell(const AdjArgs& a)
     }
 }
 
-// One thread per cell: the adjoint of its update, written to its pull sources.
+// One thread per cell: the adjoint of its update, written to its pull
+// sources.  Two waves per SIMD (239-252 VGPRs, no scratch): the second wave
+// hides the memory latency of the first.
 template <typename T, bool kScalar, bool kFlags>
-__global__ void __launch_bounds__(256) k_adjoint(const AdjArgs a)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_adjoint(const AdjArgs a)
 {
     adjoint_cell<T, kScalar, kFlags>(a);
 }
-
-// Levels without cell kinds: capped at two waves per SIMD.  The collision
-// adjoint keeps most of its forward state live (over 256 registers: one wave
-// per SIMD); under the cap a little of it spills (72-100 B per lane) and the
-// second wave hides the memory latency: measured faster.  Levels with cell
-// kinds spill far more under the cap and keep one wave.
-#define CSLBM_ADJ_PERIODIC(T_, S_)                                                              \
-    template <>                                                                                 \
-    __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))              \
-    k_adjoint<T_, S_, false>(const AdjArgs a)                                                   \
-    {                                                                                           \
-        adjoint_cell<T_, S_, false>(a);                                                         \
-    }
-CSLBM_ADJ_PERIODIC(float, true)
-CSLBM_ADJ_PERIODIC(float, false)
-CSLBM_ADJ_PERIODIC(_Float16, true)
-CSLBM_ADJ_PERIODIC(_Float16, false)
-#undef CSLBM_ADJ_PERIODIC
 
 // Second pass on levels with cell kinds: ghost, outflow and Neumann cells
 // copy their source cell's state (identity Jacobian), so their output

@@ -391,10 +391,14 @@ __global__ void __launch_bounds__(256) k_exadj_vjp(const ExchAdjArgs a, const Ga
         }
     float vb[27], gb[QS];
     exchange_map_adjoint<kScalar>(v, gi, e.kappa, e.kappa_s, lam, mu, vb, gb);
-    if (g.map[c] == k) {
-        for (int i = 0; i < Q; ++i) g.vb[i * n_t + k] = vb[tensor_slot(i)];
+    // the column addresses are formed again for the stores instead of kept
+    // live through the map adjoint (the empty asm hides that kc == k)
+    int kc = k;
+    asm volatile("" : "+v"(kc));
+    if (g.map[c] == kc) {
+        for (int i = 0; i < Q; ++i) g.vb[i * n_t + kc] = vb[tensor_slot(i)];
         if (kScalar)
-            for (int i = 0; i < QS; ++i) g.vb[(Q + i) * n_t + k] = gb[i];
+            for (int i = 0; i < QS; ++i) g.vb[(Q + i) * n_t + kc] = gb[i];
         return;
     }
     int ix[2], iy[2], iz[2];

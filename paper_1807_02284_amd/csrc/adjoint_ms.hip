@@ -445,7 +445,8 @@ __device__ __forceinline__ float axis_weight(double dorigin, double ddx, double 
 }
 
 constexpr int kMaxCand = 8;   // destination candidates per axis (host checks the spacing ratio)
-constexpr int kList = 8;      // targets collected before their columns are summed
+constexpr int kList = 3;      // targets collected before their columns are summed (3: fewer loads
+                              // in flight, five waves per SIMD; 8 took four)
 
 // sum += weight * column for the collected (k, weight) pairs
 template <bool kScalar>

@@ -932,8 +932,19 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
     hipLaunchKernelGGL(k_fill_value<uint8_t>, dim3(grid_for(W.max_cells)), dim3(256), 0, stream,
                        W.gather.touched, W.max_cells, (uint8_t)0);
     const GatherWs* gw = &W.gather;
+    // lamA[i] receives the prior-mapping adjoints of the finer scale that has
+    // scale i as its parent (the reference scale always has one) and the
+    // time interpolation's l0 term; a scale with neither (the finest one at
+    // integer alpha) keeps it zero, and its clearing and adding are skipped
+    bool uses_lamA[CSLBM_MAX_SCALES] = {};
+    uses_lamA[0] = true;
+    for (int i = 1; i < ns; ++i) {
+        uses_lamA[S[i].parent] = true;
+        if (!sub_steps(S, i).node) uses_lamA[i] = true;
+    }
     for (int i = 0; i < ns; ++i)
-        hipLaunchKernelGGL(k_zero, dim3(grid_for(nelem(i))), dim3(256), 0, stream, W.lamA[i].f, nelem(i));
+        if (uses_lamA[i])
+            hipLaunchKernelGGL(k_zero, dim3(grid_for(nelem(i))), dim3(256), 0, stream, W.lamA[i].f, nelem(i));
     for (int i = ns - 1; i >= 1; --i) {
         const cslbm_scale& sc = S[i];
         const cslbm_level* L = &sc.level;
@@ -973,7 +984,7 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
         // lam[i] and t2 so that the last one writes lam[i].
         const Buf out_final{lamR, muR};
         for (int k = ss.last; k >= 1; --k) {
-            if (k == 1) {
+            if (k == 1 && uses_lamA[i]) {
                 // the first input is also read by the interpolation and by the
                 // next finer scale's prior-maps: their adjoints are in lamA[i]
                 axpby(W.lamA[i].f, lc.f, nf, 1.0f, 1.0f, stream);

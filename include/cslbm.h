@@ -60,8 +60,9 @@ extern "C" {
 #define CSLBM_F32 0
 #define CSLBM_F16S 1
 
-/* cell kinds: low 3 bits of the per-cell flag byte.  Bit 3 (CSLBM_NEAR_WALL)
- * is owned by the library and set by cslbm_prepare_flags. */
+/* cell kinds: low 3 bits of the per-cell flag byte.  Bits 3 (CSLBM_NEAR_WALL)
+ * and 4 (CSLBM_NEAR_FLUID) are owned by the library and set by
+ * cslbm_prepare_flags. */
 #define CSLBM_FLUID 0    /* collided */
 #define CSLBM_SOLID 1    /* obstacle: halfway bounce-back for its neighbours;
                             its own output is the rest state (h = 0, g = 0) */
@@ -72,6 +73,7 @@ extern "C" {
                             boundary treatment"): output = input of the cell one
                             step inward along every non-periodic face it lies on */
 #define CSLBM_NEAR_WALL 8
+#define CSLBM_NEAR_FLUID 16
 
 /* floats in cslbm_level.gmax_buf */
 #define CSLBM_GMAX_BUF 1025
@@ -170,7 +172,10 @@ int64_t cslbm_level_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t storage,
                           int32_t with_scalar);
 
 /* Set bit CSLBM_NEAR_WALL of every fluid cell whose pull stencil reaches a
- * solid cell or leaves the box through a non-periodic face, clear it
+ * solid cell or leaves the box through a non-periodic face, and bit
+ * CSLBM_NEAR_FLUID of every other cell with a fluid cell among its 26
+ * neighbours (in a dense box taken with periodic wrap on every axis, in a
+ * brick level only the stored ones); clear them
  * elsewhere, and (when L->links is set) write each cell's bounce-back mask.
  * Must be called after the kinds in L->flags change and before stepping. */
 int cslbm_prepare_flags(const cslbm_level* L, hipStream_t stream);

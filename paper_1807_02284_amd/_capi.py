@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(PKG, "libcslbm.so")
 OK = 0
 ERR_ARG, ERR_SHAPE, ERR_UNSUPPORTED, ERR_HIP, ERR_NONFINITE = -1, -2, -3, -4, -5
 F32, F16S = 0, 1
-FLUID, SOLID, INLET, OUTFLOW, GHOST, NEUMANN, NEAR_WALL = 0, 1, 2, 3, 4, 5, 8
+FLUID, SOLID, INLET, OUTFLOW, GHOST, NEUMANN, NEAR_WALL, NEAR_FLUID = 0, 1, 2, 3, 4, 5, 8, 16
 GMAX_BUF = 1025
 
 _vp = C.c_void_p

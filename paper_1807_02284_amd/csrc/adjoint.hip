@@ -13,8 +13,13 @@
 // Levels with cell kinds: a fluid cell pulls (x - c_i, i), or its own
 // opposite population (x, opp(i)) across a bounce-back link; no two fluid
 // cells pull the same element, so the fluid pass still writes without
-// atomics, into an adjoint cleared first (elements no fluid cell pulls have
-// adjoint zero).  Solid and inlet outputs do not depend on the state.  Ghost,
+// atomics.  Elements no fluid cell pulls have adjoint zero, written by the
+// passes themselves instead of clearing the output first: cell x owns its
+// natural pull sources (x - c_i, i) (with periodic wrap, every element of the
+// box has one owner) and writes each one's value or zero, except an element a
+// fluid cell bounces into, which that cell writes (non-fluid owners write
+// their zeros in a light pass of their own).  Solid and inlet
+// outputs do not depend on the state.  Ghost,
 // outflow and Neumann cells copy a source cell (their own, the x - 1
 // neighbour, the inward neighbour) through a collision with zero relaxation,
 // the identity: a second pass adds their output adjoints to the source
@@ -66,6 +71,71 @@ __device__ __forceinline__ uint32_t adj_links(const AdjArgs& a, int x, int y, in
     return m;
 }
 
+// Zero the owned elements (natural pull sources) of cell (x, y, z) along the
+// velocities in dirs that no fluid cell pulls.  The owner x does not pull
+// element (x - c_i, i) along these velocities; the only other possible
+// reader is the cell x - c_i itself, by bouncing back along -c_i: it does so
+// exactly when it is fluid and that link is blocked, i.e. x is solid or the
+// link crosses a non-periodic face (the bounce-back masks are prepared from
+// the same kinds).  A cell with no fluid neighbour (near_fluid false) zeroes
+// its elements unchecked.  D3Q7 direction i is D3Q27 velocity i, with the
+// same element positions.
+template <bool kScalar>
+__device__ __forceinline__ void zero_unpulled(const AdjArgs& a, int x, int y, int z,
+                                              const int (&sx)[3], const int (&sy)[3],
+                                              const int (&sz)[3], uint32_t dirs, bool solid,
+                                              bool near_fluid)
+{
+    const int64_t P = a.plane;
+    if (near_fluid) {
+        // every neighbour's kind loaded at once, then the bounced elements masked out
+        uint32_t theirs = 0;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const int src = sx[kCx[i] + 1] + sy[kCy[i] + 1] + sz[kCz[i] + 1];
+            const bool blocked =
+                solid || leaves_box(x, y, z, kCx[i], kCy[i], kCz[i], a.nx, a.ny, a.nz, a.periodic);
+            const bool fluid = (a.flags[src] & kKindMask) == kFluid;
+            theirs |= (blocked && fluid) ? (1u << i) : 0u;
+        }
+        dirs &= ~theirs;
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (!(dirs & (1u << i))) continue;
+        const int src = sx[kCx[i] + 1] + sy[kCy[i] + 1] + sz[kCz[i] + 1];
+        __builtin_nontemporal_store(0.0f, a.lam0 + i * P + src);
+    }
+    if (kScalar) {
+#pragma unroll
+        for (int i = 0; i < QS; ++i) {
+            if (!(dirs & (1u << i))) continue;
+            const int src = sx[kSx[i] + 1] + sy[kSy[i] + 1] + sz[kSz[i] + 1];
+            a.mu0[i * P + src] = 0.0f;
+        }
+    }
+}
+
+// cell offsets of the x, y, z neighbours (+1, 0, -1 along each axis, periodic
+// wrap): the pull source x - c_i is sx[cx + 1] + sy[cy + 1] + sz[cz + 1]
+__device__ __forceinline__ void neighbour_offsets(int x, int y, int z, int nx, int ny, int nz,
+                                                  int (&sx)[3], int (&sy)[3], int (&sz)[3])
+{
+    const int nxy = nx * ny;
+    const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
+    const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
+    const int zm = (z == 0) ? nz - 1 : z - 1, zp = (z == nz - 1) ? 0 : z + 1;
+    sx[0] = xp;
+    sx[1] = x;
+    sx[2] = xm;
+    sy[0] = yp * nx;
+    sy[1] = y * nx;
+    sy[2] = ym * nx;
+    sz[0] = zp * nxy;
+    sz[1] = z * nxy;
+    sz[2] = zm * nxy;
+}
+
 template <typename T, bool kScalar, bool kFlags>
 __device__ __forceinline__ void adjoint_cell(const AdjArgs& a)
 {
@@ -76,18 +146,24 @@ __device__ __forceinline__ void adjoint_cell(const AdjArgs& a)
     const int nx = a.nx, ny = a.ny, nz = a.nz, nxy = nx * ny;
     const int cell = x + nx * y + nxy * z;
     const int64_t P = a.plane;
-    const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
-    const int ym = (y == 0) ? ny - 1 : y - 1, yp = (y == ny - 1) ? 0 : y + 1;
-    const int zm = (z == 0) ? nz - 1 : z - 1, zp = (z == nz - 1) ? 0 : z + 1;
-    int sx[3] = {xp, x, xm};
-    int sy[3] = {yp * nx, y * nx, ym * nx};
-    int sz[3] = {zp * nxy, z * nxy, zm * nxy};
+    int sx[3], sy[3], sz[3];
+    neighbour_offsets(x, y, z, nx, ny, nz, sx, sy, sz);
     const T* f = static_cast<const T*>(a.f);
     uint32_t links = 0;
     if (kFlags) {
         const uint8_t flag = a.flags[cell];
-        if ((flag & kKindMask) != kFluid) return;   // the copy pass handles copying kinds
-        if (flag & kNearWall) links = a.links ? a.links[cell] : adj_links(a, x, y, z, sx, sy, sz);
+        // other kinds: k_adjoint_zeros writes their owned elements, the copy
+        // pass adds the outputs of copying kinds
+        if ((flag & kKindMask) != kFluid) return;
+        if (flag & kNearWall) {
+            links = a.links ? a.links[cell] : adj_links(a, x, y, z, sx, sy, sz);
+            // a blocked link of a fluid cell hands its element to the
+            // neighbour only across a non-periodic face
+            const bool on_face = (!(a.periodic & 1) && (x == 0 || x == nx - 1)) ||
+                                 (!(a.periodic & 2) && (y == 0 || y == ny - 1)) ||
+                                 (!(a.periodic & 4) && (z == 0 || z == nz - 1));
+            zero_unpulled<kScalar>(a, x, y, z, sx, sy, sz, links, false, on_face);
+        }
     }
     // pull source of velocity i: (plane, cell) as in the forward step
     auto source = [&](int i, int& pl) {
@@ -172,6 +248,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
     adjoint_cell<T, kScalar, kFlags>(a);
 }
 
+// Levels with cell kinds, before the fluid pass: the owned elements of the
+// non-fluid cells (no fluid cell pulls them except by bouncing into them).
+// A pass of its own at full occupancy: in the fluid pass, whose registers
+// allow two waves per SIMD, the stores of mostly solid boxes ran slowly.
+template <bool kScalar>
+__global__ void __launch_bounds__(256) k_adjoint_zeros(const AdjArgs a)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= a.nx || y >= a.ny) return;
+    const int cell = x + a.nx * (y + a.ny * z);
+    const uint8_t flag = a.flags[cell];
+    const int kind = flag & kKindMask;
+    if (kind == kFluid) return;
+    int sx[3], sy[3], sz[3];
+    neighbour_offsets(x, y, z, a.nx, a.ny, a.nz, sx, sy, sz);
+    zero_unpulled<kScalar>(a, x, y, z, sx, sy, sz, ~0u, kind == kSolid, (flag & CSLBM_NEAR_FLUID) != 0);
+}
+
 // Second pass on levels with cell kinds: ghost, outflow and Neumann cells
 // copy their source cell's state (identity Jacobian), so their output
 // adjoints are added to the source elements.
@@ -204,10 +300,12 @@ __global__ void __launch_bounds__(256) k_adjoint_copies(const AdjArgs a, bool sc
         for (int i = 0; i < QS; ++i) atomicAdd(a.mu0 + i * P + from, a.mu1[i * P + cell]);
 }
 
-__global__ void __launch_bounds__(256) k_fill_zero(float* p, int64_t n)
+// zero elements n .. plane - 1 of each of the planes
+__global__ void __launch_bounds__(256) k_zero_tail(float* p, int planes, int64_t n, int64_t plane)
 {
+    const int64_t tail = plane - n;
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0.0f;
+    if (i < planes * tail) p[(i / tail) * plane + n + i % tail] = 0.0f;
 }
 
 template <typename T>
@@ -216,10 +314,20 @@ static void launch_adjoint(const AdjArgs& a, bool scalar, hipStream_t st)
     const dim3 block = step_block(a.nx);
     const dim3 grid((a.nx + block.x - 1) / block.x, (a.ny + block.y - 1) / block.y, a.nz);
     if (a.flags) {
-        const int64_t nf = (int64_t)Q * a.plane, ng = (int64_t)QS * a.plane;
-        hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st, a.lam0, nf);
+        // the fluid pass writes every element of the box; the plane padding
+        // beyond it is cleared here
+        const int64_t n = (int64_t)a.nx * a.ny * a.nz, tail = a.plane - n;
+        if (tail > 0) {
+            hipLaunchKernelGGL(k_zero_tail, dim3((unsigned)((Q * tail + 255) / 256)), dim3(256), 0, st,
+                               a.lam0, Q, n, a.plane);
+            if (scalar)
+                hipLaunchKernelGGL(k_zero_tail, dim3((unsigned)((QS * tail + 255) / 256)), dim3(256), 0,
+                                   st, a.mu0, QS, n, a.plane);
+        }
         if (scalar)
-            hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st, a.mu0, ng);
+            hipLaunchKernelGGL(k_adjoint_zeros<true>, grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL(k_adjoint_zeros<false>, grid, block, 0, st, a);
         if (scalar)
             hipLaunchKernelGGL((k_adjoint<T, true, true>), grid, block, 0, st, a);
         else

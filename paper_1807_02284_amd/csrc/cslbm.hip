@@ -65,7 +65,25 @@ __global__ void k_prepare_flags(uint8_t* flags, uint32_t* links, int nx, int ny,
         cell_coords(c, nx, ny, x, y, z);
     const uint8_t kind = flags[c] & kKindMask;
     uint32_t m = 0;
-    if (kind == kFluid) {
+    bool near_fluid = false;
+    if (kind != kFluid) {
+        // some neighbour (periodic wrap on every axis) is fluid: the adjoint
+        // step checks such cells' neighbours before writing zeros
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            int64_t src;
+            if (bm.table) {
+                const int s = brick_neighbour(bm, (int)c, x, y, z, kCx[i], kCy[i], kCz[i]);
+                if (s < 0) continue;
+                src = s;
+            } else {
+                const int xs = (x - kCx[i] + nx) % nx, ys = (y - kCy[i] + ny) % ny,
+                          zs = (z - kCz[i] + nz) % nz;
+                src = xs + (int64_t)nx * (ys + (int64_t)ny * zs);
+            }
+            near_fluid |= (flags[src] & kKindMask) == kFluid;
+        }
+    } else {
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             if (leaves_box(x, y, z, kCx[i], kCy[i], kCz[i], nx, ny, nz, periodic)) {
@@ -90,7 +108,7 @@ __global__ void k_prepare_flags(uint8_t* flags, uint32_t* links, int nx, int ny,
             if ((flags[src] & kKindMask) == kSolid) m |= 1u << i;
         }
     }
-    flags[c] = kind | (m ? kNearWall : 0);
+    flags[c] = kind | (m ? kNearWall : 0) | (near_fluid ? CSLBM_NEAR_FLUID : 0);
     if (links) links[c] = m;
 }
 

@@ -34,6 +34,16 @@ def flagged_case(kind):
         p = Params(nu=0.02, g_max=0.5, tau_s=0.6, beta=2e-3, s_ref=0.5, u_in=(0.04, 0.0, 0.0),
                    s_in=1.0)
         return shape, 0, kinds, p
+    if kind == "walls":
+        # fluid up to the non-periodic y and z faces, which bounce back: the
+        # adjoint's bounce-back writes cross those faces
+        shape = (12, 10, 8)
+        x, y, z = inputs.grid_coords(*shape)
+        kinds = np.zeros(x.size, np.uint8)
+        kinds[(x - 5.5) ** 2 + (y - 4.5) ** 2 + (z - 3.5) ** 2 <= 5.0] = _capi.SOLID
+        kinds[(x == 0) & (y == 0)] = _capi.SOLID
+        p = Params(nu=0.02, g_max=0.5, tau_s=0.6, beta=2e-3, s_ref=0.5)
+        return shape, 1, kinds, p
     shape = (20, 14, 10)
     x, y, z = inputs.grid_coords(*shape)
     kinds = np.zeros(x.size, np.uint8)
@@ -44,7 +54,7 @@ def flagged_case(kind):
     return shape, 4, kinds, p
 
 
-@pytest.mark.parametrize("kind", ["plume", "neumann_ghost"])
+@pytest.mark.parametrize("kind", ["plume", "neumann_ghost", "walls"])
 def test_flagged_step_adjoint_matches_fp64_finite_differences(kind):
     shape, periodic, kinds, p = flagged_case(kind)
     n = int(np.prod(shape))
@@ -95,6 +105,54 @@ def test_flagged_step_adjoint_matches_fp64_finite_differences(kind):
         fd = (L(eps * df, eps * dg) - L(-eps * df, -eps * dg)) / (2 * eps)
         ad = float(np.sum(gf * df) + np.sum(gg * dg))
         assert ad == pytest.approx(fd, rel=1e-3), (seed, ad, fd)
+
+
+@pytest.mark.parametrize("kind", ["plume", "neumann_ghost", "walls"])
+def test_flagged_step_adjoint_writes_every_element(kind):
+    """The flagged adjoint writes each element of its outputs itself (the
+    value, or zero where no fluid cell pulls it) and clears the plane
+    padding: outputs that start as NaN end bit-equal to outputs that start
+    as zero."""
+    shape, periodic, kinds, p = flagged_case(kind)
+    n = int(np.prod(shape))
+    lev = Level(*shape, p, scalar=True, periodic=periodic, flags=kinds)
+    rng = np.random.default_rng(7)
+    lev.init_equilibrium(1.0 + 0.01 * rng.standard_normal(n), 0.03 * rng.standard_normal((3, n)),
+                         0.5 + 0.2 * rng.standard_normal(n))
+    # the flag preparation marks the non-fluid cells with a fluid cell among
+    # their 26 neighbours (periodic wrap on every axis)
+    k3 = kinds.reshape(shape[::-1])
+    near = np.zeros_like(k3, dtype=bool)
+    for d in np.ndindex(3, 3, 3):
+        near |= np.roll(k3 == _capi.FLUID, tuple(np.array(d) - 1), axis=(0, 1, 2))
+    got = lev.flags[:n].cpu().numpy().reshape(shape[::-1])
+    np.testing.assert_array_equal((got & _capi.NEAR_FLUID) != 0, near & (k3 != _capi.FLUID))
+    assert np.array_equal(got & 7, k3)
+    P = lev.plane
+    lam = torch.zeros(27, P, device="cuda")
+    mu = torch.zeros(7, P, device="cuda")
+    lam[:, :n] = torch.as_tensor(rng.standard_normal((27, n)), dtype=torch.float32, device="cuda")
+    mu[:, :n] = torch.as_tensor(rng.standard_normal((7, n)), dtype=torch.float32, device="cuda")
+    lam, mu = lam.reshape(-1), mu.reshape(-1)
+    outs = []
+    for fill in (0.0, float("nan")):
+        lam0 = torch.full_like(lam, fill)
+        mu0 = torch.full_like(mu, fill)
+        lev.adjoint_step(lev.f, lev.g, lam, mu, lam0, mu0, None)
+        torch.cuda.synchronize()
+        outs.append((lam0.cpu().numpy(), mu0.cpu().numpy()))
+    (a, b), (c, d) = outs
+    assert np.all(np.isfinite(c)) and np.all(np.isfinite(d))
+    assert np.array_equal(a.view(np.uint32), c.view(np.uint32))
+    assert np.array_equal(b.view(np.uint32), d.view(np.uint32))
+    assert not a.reshape(27, P)[:, n:].any() and not b.reshape(7, P)[:, n:].any()
+    # solid cells that no fluid cell bounces into keep a zero adjoint
+    deep = (kinds == _capi.SOLID)
+    for axis in range(3):
+        k3 = (kinds == _capi.SOLID).reshape(shape[::-1])
+        deep &= np.roll(k3, 1, axis).reshape(-1) & np.roll(k3, -1, axis).reshape(-1)
+    if deep.any():
+        assert not a.reshape(27, P)[:, :n][:, deep].any()
 
 
 def _exchange_adjoint_gpu(lev_src, lev_dst, cells, w, fA, fB, gA, gB, lam_d, mu_d, gather=False):

@@ -13,14 +13,21 @@ Readings (each also listed in the design doc):
     never collided, written only by prior-mapping;
   * alpha_i = dx_0 / dx_i; the scale's viscosity is alpha_i nu_0 (invariant
     local Reynolds number, eq. S_relation); l = floor(alpha_i) + 1 sub-steps;
-  * before sub-step k the shell is prior-mapped from the parent at the time
-    weight (k - 1) / alpha_i between the parent's states at t_n and
-    t_n + dt_0 (the pull reads the shell at the sub-step's start time);
+  * before each of the first l - 1 sub-steps the shell is prior-mapped from
+    the parent blended in time between its states at t_n and t_n + dt_0;
+    the paper names the two end points but not the time, and the reading
+    here is the sub-step's start time, weight (k - 1) / alpha_i for
+    sub-step k (the pull reads the shell at the start of the sub-step);
+  * before the final sub-step (k = l) the shell is mapped directly from the
+    parent at t_n + dt_0 (weight 1), as section "Temporal alignment and
+    scale mapping" states;
   * after the sub-steps the whole scale is interpolated in time by the
     quadratic through t = 0, (l - 1)/alpha_i, l/alpha_i evaluated at 1, and
     the shell is mapped again from the parent at t_n + dt_0;
-  * post-mapping writes every coarser scale j < i at its FLUID cells whose
-    trilinear stencil in scale i consists of FLUID cells of scale i.
+  * post-mapping writes every larger scale (spacing above the scale's own,
+    far-field scales included) at its FLUID cells whose trilinear stencil
+    in scale i consists of FLUID cells of scale i; finer scales run and
+    post-map in index order.
 
 Far-field scales (spacing larger than the reference scale, alpha_c < 1)
 follow the reversed rules of section "Handling multiple scales": the region
@@ -28,15 +35,20 @@ they share with their parent is GHOST in their flags and is mapped from the
 parent in full (at t_n before their step and again at t_n + dt_0 after it);
 they take one step and interpolate linearly back to t_n + dt_0; they
 post-map only onto the parent's ghost shell; their own outer faces are
-Neumann cells.  They run after every finer scale.
+Neumann cells.  As in Algorithm 1 they advance together with the reference
+scale, before the loop over finer scales.  Their shared region is GHOST,
+so a finer scale (which lies inside the reference window) finds no FLUID
+target in them unless an object is resolved differently on the two scales.
 
 Pins (CPU tests): a finer scale with the reference spacing on coincident
 points reproduces the single-scale run (integer alpha, mapping = identity);
 uniform flow stays uniform on three nested scales at alpha 1.5 and 2; a
 two-scale Taylor-Green vortex (alpha = 1.5) keeps the closed-form decay
-within 2 %.  The time weights at non-integer alpha and the shell and
-post-region rules are readings the paper does not fix: beyond those loose
-checks their parity is unpinned.
+within 2 %; under a uniform body force (momentum linear in time in closed
+form) the shell before every sub-step holds the parent's state at the time
+the schedule names, at alpha 1.5, 2 and 2.5.  The start-time reading of the
+first l - 1 weights and the shell and post-region rules are readings: their
+parity is pinned only by those checks.
 """
 from __future__ import annotations
 
@@ -65,6 +77,7 @@ class OScale:
     g: np.ndarray | None = None  # [7][N] or None
     ghosts: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
     post: dict = field(default_factory=dict)   # coarser scale index -> cells of that scale
+    theta: np.ndarray | None = None             # [3][N] body force, lattice units of this scale
 
     @property
     def n(self):
@@ -72,7 +85,7 @@ class OScale:
 
     def domain(self) -> Domain:
         return Domain(self.nx, self.ny, self.nz, periodic=self.periodic, flags=self.flags,
-                      u_in=self.u_in, s_in=self.s_in)
+                      theta=self.theta, u_in=self.u_in, s_in=self.s_in)
 
     def geom(self) -> dict:
         return dict(nx=self.nx, ny=self.ny, nz=self.nz, periodic=self.periodic,
@@ -134,7 +147,8 @@ def prepare(scales: list[OScale]):
     """Fill the ghost and post-mapping lists of every scale but the reference.
 
     A finer scale's ghosts are its one-cell shell; it post-maps onto every
-    coarser scale j < i.  A coarser (far-field) scale is the reverse
+    larger scale: the scales before it (its parent chain) and the far-field
+    scales.  A coarser (far-field) scale is the reverse
     (section "Handling multiple scales"): its ghosts are the whole region it
     shares with its parent (the finer scale it surrounds), marked GHOST by
     the caller, and it post-maps only onto the parent's ghost shell."""
@@ -146,57 +160,24 @@ def prepare(scales: list[OScale]):
             s.post = {s.parent: shell_ghosts(scales[s.parent])}
         else:
             s.ghosts = shell_ghosts(s)
-            s.post = {j: post_targets(scales[j], s) for j in range(i) if not is_coarse(scales, j)}
+            s.post = {j: post_targets(scales[j], s) for j in range(len(scales))
+                      if j < i or is_coarse(scales, j)}
 
 
 def multiscale_step(scales: list[OScale], n_ref: int = 1):
     """Advance every scale by n_ref reference steps (Algorithm 1)."""
     for _ in range(n_ref):
+        # the reference scale and the far-field scales take their step
+        # (first statement of Algorithm 1's loop)
         s0 = scales[0]
-        A0, B0 = s0.f, None
-        gA0 = s0.g
-        f1, g1 = step(s0.domain(), s0.params, s0.f, s0.g)
-        B0, gB0 = f1, g1
+        A0, gA0 = s0.f, s0.g
+        B0, gB0 = step(s0.domain(), s0.params, s0.f, s0.g)
         states = {0: (A0, B0, gA0, gB0)}
-        for i in range(1, len(scales)):
-            if is_coarse(scales, i):
-                continue
-            s = scales[i]
-            par = scales[s.parent]
-            Ap, Bp, gAp, gBp = states[s.parent]
-            alpha = scales[0].dx / s.dx                  # dx_0 / dx_i
-            l = math.floor(alpha) + 1
-            X0 = s.f.copy()
-            gX0 = None if s.g is None else s.g.copy()
-            cur, gcur = X0.copy(), None if gX0 is None else gX0.copy()
-            hist = [(X0, gX0)]
-            for k in range(1, l + 1):
-                w = (k - 1) / alpha
-                exchange(par.geom(), Ap, Bp, w, s.geom(), s.ghosts, cur, gAp, gBp, gcur)
-                if k == 1:
-                    X0 = cur.copy()
-                    gX0 = None if gcur is None else gcur.copy()
-                    hist[0] = (X0, gX0)
-                cur, gcur = step(s.domain(), s.params, cur, gcur)
-                hist.append((cur, gcur))
-            t = (0.0, (l - 1) / alpha, l / alpha)
-            R = time_interp(hist[0][0], hist[l - 1][0], hist[l][0], t, 1.0).reshape(27, s.n)
-            gR = None
-            if s.g is not None:
-                gR = time_interp(hist[0][1], hist[l - 1][1], hist[l][1], t, 1.0).reshape(7, s.n)
-            exchange(par.geom(), Ap, Bp, 1.0, s.geom(), s.ghosts, R, gAp, gBp, gR)
-            states[i] = (X0, R, gX0, gR)
-            for j in range(i):
-                tgt = s.post.get(j)
-                if tgt is None or tgt.size == 0:
-                    continue
-                Bj, gBj = states[j][1], states[j][3]
-                exchange(s.geom(), R, R, 0.0, scales[j].geom(), tgt, Bj, gR, gR, gBj)
-        # far-field scales, after every finer scale (section "Temporal
-        # alignment and scale mapping"): the overlap is mapped from the parent
-        # at t_n, one step of dt_c = dt_0 / alpha_c, linear interpolation back
-        # to t_n + dt_0, the overlap mapped again at t_n + dt_0, then the
-        # parent's boundary shell is mapped from this scale
+        # far-field scales (section "Temporal alignment and scale mapping"):
+        # the shared region is mapped from the parent at t_n, one step of
+        # dt_c = dt_0 / alpha_c, linear interpolation back to t_n + dt_0, the
+        # shared region mapped again at t_n + dt_0, then the parent's
+        # boundary shell is mapped from this scale
         for i in range(1, len(scales)):
             if not is_coarse(scales, i):
                 continue
@@ -215,6 +196,44 @@ def multiscale_step(scales: list[OScale], n_ref: int = 1):
             tgt = s.post[s.parent]
             if tgt.size:
                 exchange(s.geom(), R, R, 0.0, par.geom(), tgt, Bp, gR, gR, gBp)
+        # finer scales, coarse to fine
+        for i in range(1, len(scales)):
+            if is_coarse(scales, i):
+                continue
+            s = scales[i]
+            par = scales[s.parent]
+            Ap, Bp, gAp, gBp = states[s.parent]
+            alpha = scales[0].dx / s.dx                  # dx_0 / dx_i
+            l = math.floor(alpha) + 1
+            X0 = s.f.copy()
+            gX0 = None if s.g is None else s.g.copy()
+            cur, gcur = X0.copy(), None if gX0 is None else gX0.copy()
+            hist = [(X0, gX0)]
+            for k in range(1, l + 1):
+                # first l - 1 sub-steps: the parent blended at the sub-step's
+                # start time; the final one: the parent at t_n + dt_0
+                w = 1.0 if k == l else (k - 1) / alpha
+                exchange(par.geom(), Ap, Bp, w, s.geom(), s.ghosts, cur, gAp, gBp, gcur)
+                if k == 1:
+                    X0 = cur.copy()
+                    gX0 = None if gcur is None else gcur.copy()
+                    hist[0] = (X0, gX0)
+                cur, gcur = step(s.domain(), s.params, cur, gcur)
+                hist.append((cur, gcur))
+            t = (0.0, (l - 1) / alpha, l / alpha)
+            R = time_interp(hist[0][0], hist[l - 1][0], hist[l][0], t, 1.0).reshape(27, s.n)
+            gR = None
+            if s.g is not None:
+                gR = time_interp(hist[0][1], hist[l - 1][1], hist[l][1], t, 1.0).reshape(7, s.n)
+            exchange(par.geom(), Ap, Bp, 1.0, s.geom(), s.ghosts, R, gAp, gBp, gR)
+            states[i] = (X0, R, gX0, gR)
+            # post-mapping onto every larger scale, in index order
+            for j in sorted(s.post):
+                tgt = s.post[j]
+                if tgt.size == 0:
+                    continue
+                Bj, gBj = states[j][1], states[j][3]
+                exchange(s.geom(), R, R, 0.0, scales[j].geom(), tgt, Bj, gR, gR, gBj)
         for i, s in enumerate(scales):
             s.f = states[i][1]
             s.g = states[i][3]

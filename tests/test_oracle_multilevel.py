@@ -246,3 +246,52 @@ def test_two_scale_taylor_green_keeps_closed_form_decay():
     amp_single = (us[0] * u[0]).sum() / (u[0] * u[0]).sum()
     amp_multi = (um[0] * u[0]).sum() / (u[0] * u[0]).sum()
     assert amp_multi == pytest.approx(amp_single, rel=0.02)
+
+
+@pytest.mark.parametrize("alpha", [1.5, 2.0, 2.5])
+def test_shell_before_each_substep_holds_the_parent_state_at_its_time(alpha, monkeypatch):
+    """Section "Temporal alignment and scale mapping": before each of the
+    first l - 1 sub-steps the finer scale's boundary is mapped from the
+    parent blended between t_n and t_n + dt_0 (read here at the sub-step's
+    start time, (k - 1) dt_f), and before the final sub-step directly from
+    the parent at t_n + dt_0.  A uniform periodic parent under a uniform body
+    force F has the closed-form post-collision momentum j(t_n + t dt_0) =
+    j(t_n) + t F (momentum rises by exactly F per step, linear in time), and
+    the mapping keeps density and momentum, so the shell's momentum before
+    each sub-step names the parent time it was mapped from."""
+    n = 8
+    F0 = np.array([2e-4, -1e-4, 5e-5])
+    u0 = np.array([0.02, 0.01, -0.01])
+    feq = feq_second_order(1.0, u0, C, W)
+    s0 = ml.OScale(n, n, n, 1.0, (0.0, 0.0, 0.0), oracle.Params(nu=1e-3, g_max=0.05),
+                   np.zeros(n ** 3, np.uint8), periodic=7, f=np.tile(feq[:, None], (1, n ** 3)),
+                   theta=np.tile(F0[:, None], (1, n ** 3)))
+    nf = 6
+    fine = box_scale(nf, nf, nf, (2.2, 2.1, 2.3), 1 / alpha, 1e-3 * alpha)
+    fine.f = np.tile(feq[:, None], (1, fine.n))
+    fine.theta = np.tile((F0 / alpha)[:, None], (1, fine.n))
+    scales = [s0, fine]
+    ml.prepare(scales)
+    j0 = C.T @ s0.f[:, 0]
+    seen = []
+    real_step = ml.step
+
+    def spy(dom, params, f, g=None, n_steps=1):
+        if dom.n == fine.n:
+            seen.append(np.asarray(f).reshape(27, fine.n)[:, fine.ghosts].copy())
+        return real_step(dom, params, f, g, n_steps)
+
+    monkeypatch.setattr(ml, "step", spy)
+    ml.multiscale_step(scales, 1)
+    l = math.floor(alpha) + 1
+    assert len(seen) == l
+    for k, shell in enumerate(seen, start=1):
+        t = 1.0 if k == l else (k - 1) / alpha
+        np.testing.assert_allclose(C.T @ shell, np.tile((j0 + t * F0)[:, None], (1, shell.shape[1])),
+                                   rtol=0, atol=2e-15)
+    # the parent itself, outside the cells post-mapped from the finer
+    # scale: exactly F more momentum after the reference step
+    out = np.setdiff1d(np.arange(n ** 3), fine.post[0])
+    assert 0 < out.size < n ** 3
+    np.testing.assert_allclose(C.T @ scales[0].f[:, out], np.tile((j0 + F0)[:, None], (1, out.size)),
+                               rtol=0, atol=2e-15)

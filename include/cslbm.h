@@ -215,8 +215,13 @@ int cslbm_get_populations(const cslbm_level* L, float* f, float* g, int32_t shif
  * buffers are back in their original roles. */
 int cslbm_step(cslbm_level* L, int32_t n_steps, hipStream_t stream);
 
-/* Macroscopic fields of the stored state: rho = sum f~, u = (sum c f~ -
- * F/2)/rho, s = sum g (dense arrays; any output may be NULL). */
+/* Macroscopic fields of the stored state (the density and velocity that
+ * follow eq. lbe: rho = sum_i f_i, u = sum_i c_i f_i / rho, read back after
+ * the paper's iterations): rho = sum f~, u = (sum c f~ - F/2)/rho with the
+ * body force F of the level (0 without one), s = sum g.  Outputs are dense
+ * device float arrays of N = nx*ny*nz cells in storage order (u as
+ * [3][N]); any output may be NULL.  Errors: CSLBM_ERR_ARG for a bad level,
+ * CSLBM_ERR_HIP for a failed launch. */
 int cslbm_read_macro(const cslbm_level* L, float* rho, float* u, float* s, hipStream_t stream);
 
 /* Vorticity magnitude |curl u| of the stored state into omega (dense [N]),

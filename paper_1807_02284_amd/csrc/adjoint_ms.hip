@@ -905,8 +905,8 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
                           scalar ? const_cast<float*>(g_in[i]) : nullptr};
         for (int k = 1; k <= ss.last; ++k) {
             const Buf& cur = W.cur[i][k - 1];
-            rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], (k - 1) / ss.alpha, L, cur.f, cur.g,
-                                 sc.ghost_cells, sc.n_ghost, stream);
+            rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], prior_weight(k, ss.l, ss.alpha), L,
+                                 cur.f, cur.g, sc.ghost_cells, sc.n_ghost, stream);
             if (rc) return rc;
             if (k < ss.l) {
                 const Buf& out = (ss.node && k == ss.last) ? W.R[i] : W.cur[i][k];
@@ -990,7 +990,7 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
                 axpby(W.lamA[i].f, lc.f, nf, 1.0f, 1.0f, stream);
                 if (scalar) axpby(W.lamA[i].g, lc.g, ngs, 1.0f, 1.0f, stream);
             }
-            rc = launch_exchange_adjoint(P, A[p], B[p], gA[p], gB[p], (k - 1) / ss.alpha, L, lc.f,
+            rc = launch_exchange_adjoint(P, A[p], B[p], gA[p], gB[p], prior_weight(k, ss.l, ss.alpha), L, lc.f,
                                          lc.g, W.lamA[p].f, lam[p], W.lamA[p].g,
                                          scalar ? mu[p] : nullptr, sc.ghost_cells, sc.n_ghost, gw,
                                          stream);

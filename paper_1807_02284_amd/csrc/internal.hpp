@@ -66,4 +66,11 @@ int launch_step_interp(const cslbm_level* L, const void* fin, void* fout, const 
                        float* gout, const void* t0, const float* gt0, double l0, double l1,
                        double l2, hipStream_t stream);
 
+// Time weight between a parent's states at t_n (0) and t_n + dt_0 (1) of the
+// prior-mapping before sub-step k = 1..l of a finer scale with spacing ratio
+// alpha (section "Temporal alignment and scale mapping"): the first l - 1
+// sub-steps read the parent blended in time, here at the sub-step's start
+// time (k - 1) dt_f; the final sub-step reads the parent at t_n + dt_0.
+inline double prior_weight(int k, int l, double alpha) { return k == l ? 1.0 : (k - 1) / alpha; }
+
 }  // namespace cslbm

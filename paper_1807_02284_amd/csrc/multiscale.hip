@@ -305,6 +305,8 @@ int validate_hierarchy(const cslbm_hierarchy* H)
                         S[i].parent, i);
         const cslbm_level* PL = &S[S[i].parent].level;
         if (far_field(S, i)) {
+            if (S[i].parent != 0)
+                return fail(CSLBM_ERR_ARG, "far-field scale %d: its parent must be the reference scale", i);
             if (!(PL->dx < L->dx))
                 return fail(CSLBM_ERR_ARG, "far-field scale %d is not coarser than its parent", i);
             for (int j = 0; j < ns; ++j)
@@ -316,9 +318,11 @@ int validate_hierarchy(const cslbm_hierarchy* H)
                 return fail(CSLBM_ERR_ARG, "scale %d: a finer scale's parent cannot be a far-field scale", i);
             if (!(L->dx <= PL->dx))
                 return fail(CSLBM_ERR_ARG, "scale %d is not finer than its parent", i);
-            for (int j = 0; j < i; ++j)
-                if (far_field(S, j) && S[i].n_post[j] != 0)
-                    return fail(CSLBM_ERR_ARG, "scale %d may not post-map onto far-field scale %d", i, j);
+            for (int j = i; j < ns; ++j)
+                if (!far_field(S, j) && S[i].n_post[j] != 0)
+                    return fail(CSLBM_ERR_ARG,
+                                "scale %d may post-map only onto larger scales (index < %d or far field), not %d",
+                                i, i, j);
         }
         if (!L->flags) return fail(CSLBM_ERR_ARG, "scale %d: needs flags (ghost cells)", i);
         if (!S[i].work_f[0] || !S[i].work_f[1])
@@ -393,6 +397,42 @@ int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t s
             gA[0] = L->g_next;
             gB[0] = L->g;
         }
+        // far-field scales (spacing larger than the reference scale) advance
+        // with the reference scale, before the finer scales (Algorithm 1),
+        // with the reversed rules of section "Handling multiple scales": the
+        // whole region shared with the parent (GHOST cells of this scale) is
+        // mapped from the parent at t_n, the scale takes one step of
+        // dt_c = dt_0 / alpha_c and is interpolated linearly back to
+        // t_n + dt_0 (fused into the step's store), the shared region is
+        // mapped again at t_n + dt_0, and the parent's boundary shell is
+        // post-mapped from this scale.
+        for (int i = 1; i < ns; ++i) {
+            if (!far_field(S, i)) continue;
+            cslbm_scale& sc = S[i];
+            cslbm_level* L = &sc.level;
+            const cslbm_level* P = &S[sc.parent].level;
+            const int p = sc.parent;
+            const double ac = S[0].level.dx / L->dx;
+            void* X0 = L->f;
+            float* gX0 = L->g;
+            void* R = sc.work_f[1];
+            float* gR = sc.work_g[1];
+            int rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], 0.0, L, X0, gX0, sc.ghost_cells,
+                                     sc.n_ghost, stream);
+            if (rc) return rc;
+            rc = launch_step_interp(L, X0, R, gX0, gR, X0, gX0, 1.0 - ac, 0.0, ac, stream);
+            if (rc) return rc;
+            rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], 1.0, L, R, gR, sc.ghost_cells,
+                                 sc.n_ghost, stream);
+            if (rc) return rc;
+            A[i] = X0;
+            B[i] = R;
+            gA[i] = gX0;
+            gB[i] = gR;
+            rc = launch_exchange(L, R, R, gR, gR, 0.0, P, B[p], gB[p], sc.post_cells[p], sc.n_post[p],
+                                 stream);
+            if (rc) return rc;
+        }
         // finer scales, coarse to fine
         for (int i = 1; i < ns; ++i) {
             if (far_field(S, i)) continue;
@@ -425,9 +465,10 @@ int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t s
             void* R = sc.work_f[1];
             float* gR = sc.work_g[1];
             for (int k = 1; k <= last; ++k) {
-                // prior-mapping of the boundary shell at the sub-step's start time
-                int rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], (k - 1) / alpha, L, cur, gcur,
-                                         sc.ghost_cells, sc.n_ghost, stream);
+                // prior-mapping of the boundary shell: the parent blended at
+                // the sub-step's start time, or at t_n + dt_0 before the last
+                int rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], prior_weight(k, l, alpha), L,
+                                         cur, gcur, sc.ghost_cells, sc.n_ghost, stream);
                 if (rc) return rc;
                 if (k < l) {
                     const int slot = (k - 1) & 1;
@@ -454,47 +495,14 @@ int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t s
             B[i] = R;
             gA[i] = gX0;
             gB[i] = gR;
-            // post-mapping to every coarser scale (section "Handling multiple scales")
-            for (int j = 0; j < i; ++j) {
+            // post-mapping onto every larger scale, far-field scales included
+            // (section "Handling multiple scales"), in index order
+            for (int j = 0; j < ns; ++j) {
+                if (j == i || sc.n_post[j] == 0) continue;
                 rc = launch_exchange(L, R, R, gR, gR, 0.0, &S[j].level, B[j], gB[j],
                                      sc.post_cells[j], sc.n_post[j], stream);
                 if (rc) return rc;
             }
-        }
-        // far-field scales (spacing larger than the reference scale), after
-        // every finer scale, with the reversed rules of section "Handling
-        // multiple scales": the whole region shared with the parent (GHOST
-        // cells of this scale) is mapped from the parent at t_n, the scale
-        // takes one step of dt_c = dt_0 / alpha_c and is interpolated linearly
-        // back to t_n + dt_0 (fused into the step's store), the shared region
-        // is mapped again at t_n + dt_0, and the parent's boundary shell is
-        // post-mapped from this scale.
-        for (int i = 1; i < ns; ++i) {
-            if (!far_field(S, i)) continue;
-            cslbm_scale& sc = S[i];
-            cslbm_level* L = &sc.level;
-            const cslbm_level* P = &S[sc.parent].level;
-            const int p = sc.parent;
-            const double ac = S[0].level.dx / L->dx;
-            void* X0 = L->f;
-            float* gX0 = L->g;
-            void* R = sc.work_f[1];
-            float* gR = sc.work_g[1];
-            int rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], 0.0, L, X0, gX0, sc.ghost_cells,
-                                     sc.n_ghost, stream);
-            if (rc) return rc;
-            rc = launch_step_interp(L, X0, R, gX0, gR, X0, gX0, 1.0 - ac, 0.0, ac, stream);
-            if (rc) return rc;
-            rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], 1.0, L, R, gR, sc.ghost_cells,
-                                 sc.n_ghost, stream);
-            if (rc) return rc;
-            A[i] = X0;
-            B[i] = R;
-            gA[i] = gX0;
-            gB[i] = gR;
-            rc = launch_exchange(L, R, R, gR, gR, 0.0, P, B[p], gB[p], sc.post_cells[p], sc.n_post[p],
-                                 stream);
-            if (rc) return rc;
         }
         // the interpolated states become the scales' states at the new reference time
         for (int i = 1; i < ns; ++i) {

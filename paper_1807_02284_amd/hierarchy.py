@@ -148,14 +148,15 @@ def check_shell_stencils(shell_shape, shell_origin, shell_dx, shell_cells,
 
 def drop_overwritten_posts(post: dict, n: int) -> dict:
     """Post-mapping lists {(fine i, coarse j): cells of j} with every cell
-    removed that a later (finer) scale also post-maps into j.  Scales
-    post-map in index order and nothing reads a coarser scale j between two
+    removed that a later (finer) scale also post-maps into j.  Finer scales
+    post-map in index order and nothing reads a larger scale j between two
     post-mappings into it (prior-mapping reads the parent, which is finer
-    than j), so such a cell keeps only the later value: leaving it out of
-    the earlier list gives the same final state without the duplicate work."""
+    than j; far-field scales have taken their step before), so such a cell
+    keeps only the later value: leaving it out of the earlier list gives the
+    same final state without the duplicate work."""
     out = {}
     for j in range(n):
-        keys = [i for i in range(n - 1, j, -1) if (i, j) in post]
+        keys = [i for i in range(n - 1, -1, -1) if i != j and (i, j) in post]
         if not keys:
             continue
         size = 1 + max(int(np.max(post[(i, j)])) if len(post[(i, j)]) else 0 for i in keys)
@@ -181,9 +182,10 @@ def _storage_list(lev: Level, box_cells: np.ndarray) -> np.ndarray:
 class Hierarchy:
     """Scales 0..n-1 (0 = reference); parents[i] is the nearest coarser scale
     of a finer scale i (default i - 1).  A scale with a larger spacing than
-    scale 0 is a far-field scale: its parent is the finer scale it surrounds
-    (default 0), its GHOST cells are the region it shares with that parent,
-    and it post-maps onto the parent's GHOST shell.  ``kinds`` are over each
+    scale 0 is a far-field scale: its parent is the reference scale, its
+    GHOST cells are the region it shares with it, and it post-maps onto the
+    reference scale's GHOST shell.  A finer scale post-maps onto every
+    larger scale: the scales before it and the far-field scales.  ``kinds`` are over each
     level's box (for a brick level: SOLID outside the stored bricks); the
     cell lists sent to the library are in each level's storage order."""
 
@@ -232,8 +234,10 @@ class Hierarchy:
                                          tuple(lev.c.origin), lev.c.dx, lev.c.periodic)
                     far_post[(i, self.parents[i])] = shell
                 else:
-                    for j in range(i):
-                        if self.far[j]:
+                    # onto every larger scale: the scales before it and the
+                    # far-field scales (section "Handling multiple scales")
+                    for j in range(n):
+                        if j == i or not (j < i or self.far[j]):
                             continue
                         cj = levels[j]
                         cells = post_cells(self.kinds[j], (cj.nx, cj.ny, cj.nz), tuple(cj.c.origin),

@@ -17,6 +17,8 @@ reverse, giving dL/d(initial state) of every scale from dL/d(final state).
 """
 from __future__ import annotations
 
+import dataclasses
+
 import torch
 
 from .level import Level
@@ -43,18 +45,33 @@ class _Rollout(torch.autograd.Function):
             done += k
         _, _, s = lev.read_macro()
         ctx.lev, ctx.checkpoints = lev, checkpoints
+        # the force and parameters of this forward pass: the level may run
+        # other rollouts before backward is called
+        ctx.theta = theta.detach().reshape(3, lev.n).to(torch.float32).clone()
+        ctx.params = dataclasses.replace(lev.params)
         return s.clone()
 
     @staticmethod
     def backward(ctx, grad_s):
         lev: Level = ctx.lev
+        saved_force, saved_params = lev.force.clone(), lev.params
+        lev.force.reshape(3, lev.plane)[:, : lev.n] = ctx.theta
+        lev.set_params(ctx.params)
+        try:
+            return _Rollout._reverse(ctx, lev, grad_s)
+        finally:
+            lev.force.copy_(saved_force)
+            lev.set_params(saved_params)
+
+    @staticmethod
+    def _reverse(ctx, lev: Level, grad_s):
         P = lev.plane
         lam = torch.zeros(27 * P, dtype=torch.float32, device=lev.device)
         lam2 = torch.zeros_like(lam)
         mu = _dense_to_plane(lev, grad_s.detach().reshape(1, -1).expand(7, -1), 7).reshape(-1)
         mu2 = torch.zeros_like(mu)
         dtheta = torch.zeros(3 * P, dtype=torch.float32, device=lev.device)
-        every = max(k for _, k, _, _ in ctx.checkpoints)
+        every = max((k for _, k, _, _ in ctx.checkpoints), default=1)
         f_buf = [torch.empty_like(lev.f) for _ in range(every - 1)]
         g_buf = [torch.empty_like(lev.g) for _ in range(every - 1)]
         for start, k, f0, g0 in reversed(ctx.checkpoints):

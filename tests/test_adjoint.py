@@ -55,7 +55,7 @@ def gpu_grads(p, u0, s0, theta, target, n_steps, every):
     loss.backward()
     torch.cuda.synchronize()
     return (th.grad.double().cpu().numpy(), h0.grad.double().cpu().numpy(),
-            g0.grad.double().cpu().numpy(), float(loss))
+            g0.grad.double().cpu().numpy(), float(loss.detach()))
 
 
 @pytest.mark.parametrize("adaptive", [True, False])
@@ -95,3 +95,55 @@ def test_checkpoint_interval_does_not_change_gradients():
     for x, y in ((a, b), (a, c)):
         for u, v in zip(x[:3], y[:3]):
             np.testing.assert_array_equal(u, v)
+
+
+def test_backward_uses_the_force_of_its_own_forward_pass():
+    """Two rollouts on one level (the second with another force field and
+    gravity coefficient), then the backward pass of the first: its gradients
+    equal those of a single rollout, and the level keeps the second
+    rollout's force and parameters."""
+    n = N1
+    p, u0, s0, theta, target = scene()
+    lev = Level(n, n, n, p, scalar=True, force=np.zeros((3, n ** 3)))
+    lev.init_equilibrium(np.ones(n ** 3), u0, s0)
+    h0, g0 = lev.get_populations(shifted=True)
+    tgt = torch.tensor(target, dtype=torch.float32, device="cuda")
+
+    def run(th_np, params):
+        lev.set_params(params)
+        th = torch.tensor(th_np, dtype=torch.float32, device="cuda", requires_grad=True)
+        h = h0.clone().requires_grad_(True)
+        g = g0.clone().requires_grad_(True)
+        loss = 0.5 * ((rollout(lev, th, h, g, 8, 3) - tgt) ** 2).sum()
+        return loss, th, h, g
+
+    loss1, th1, h1, g1 = run(theta, p)
+    other = Params(**{**p.__dict__, "beta": 3e-3})
+    with torch.no_grad():
+        run(-2.0 * theta, other)
+    loss1.backward()
+    torch.cuda.synchronize()
+    assert lev.params.beta == other.beta
+    force_after = lev.force.reshape(3, lev.plane)[:, : lev.n].double().cpu().numpy()
+    np.testing.assert_array_equal(force_after, np.float32(-2.0 * theta).astype(np.float64))
+    ref = gpu_grads(p, u0, s0, theta, target, 8, every=3)
+    for got, want in zip((th1.grad, h1.grad, g1.grad), ref[:3]):
+        np.testing.assert_array_equal(got.double().cpu().numpy(), want)
+
+
+def test_zero_step_rollout_returns_the_scalar_and_its_gradient():
+    n = N1
+    p, u0, s0, theta, target = scene()
+    lev = Level(n, n, n, p, scalar=True, force=np.zeros((3, n ** 3)))
+    lev.init_equilibrium(np.ones(n ** 3), u0, s0)
+    h0, g0 = lev.get_populations(shifted=True)
+    th = torch.tensor(theta, dtype=torch.float32, device="cuda", requires_grad=True)
+    h = h0.clone().requires_grad_(True)
+    g = g0.clone().requires_grad_(True)
+    s = rollout(lev, th, h, g, 0, 5)
+    s.sum().backward()
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(s.detach().double().cpu().numpy(), g0.double().cpu().numpy().sum(axis=0),
+                               rtol=1e-6, atol=1e-6)
+    assert float(th.grad.abs().max()) == 0.0 and float(h.grad.abs().max()) == 0.0
+    np.testing.assert_array_equal(g.grad.cpu().numpy(), np.ones((7, n ** 3), np.float32))

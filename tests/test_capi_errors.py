@@ -82,6 +82,18 @@ def test_multiscale_step_argument_checks(lib):
     keep[1].post_cells[1] = 0xA000
     assert ms(C.byref(H), 1, None) == _capi.ERR_ARG
     assert "far-field" in err(lib)
+    # a far-field scale whose parent is not the reference scale
+    L1 = make_level(dx=0.5, flags=0x9000, periodic=0)
+    H, keep = hierarchy_of([L0, L1, far], [-1, 0, 1])
+    assert ms(C.byref(H), 1, None) == _capi.ERR_ARG
+    assert "reference scale" in err(lib)
+    # a finer scale posting onto a later finer scale
+    L2 = make_level(dx=0.25, flags=0x9000, periodic=0)
+    H, keep = hierarchy_of([L0, L1, L2], [-1, 0, 1])
+    keep[1].n_post[2] = 3
+    keep[1].post_cells[2] = 0xA000
+    assert ms(C.byref(H), 1, None) == _capi.ERR_ARG
+    assert "larger scales" in err(lib)
     # the gradient mode is single-level only
     Lg = make_level(p_grad_mode=1)
     H, keep = hierarchy_of([Lg], [-1])

@@ -86,6 +86,26 @@ def test_one_step_fp32_populations(nx, ny, nz, seed, adaptive, g_max):
     assert rel_err(got, f1) <= 1e-6
 
 
+@pytest.mark.parametrize("nx,ny,nz,seed,adaptive,g_max", CASES)
+def test_one_step_fp32_populations_rough_inputs(nx, ny, nz, seed, adaptive, g_max):
+    """Per-cell independent random velocity up to 0.08 per component and
+    random density: after the pull every cell is far from equilibrium and
+    some post-collision populations come close to zero, where the error is
+    taken relative to the lattice weight (rel_err)."""
+    n = nx * ny * nz
+    p = Params(nu=0.01, g_max=g_max, adaptive=adaptive)
+    rho = 1.0 + 0.02 * inputs.perturbation(n, seed + 10)
+    u = 0.08 * inputs.perturbation((3, n), seed + 11)
+    noise = 2e-4 * inputs.perturbation((27, n), seed + 12)
+    lev = Level(nx, ny, nz, p)
+    dom = odomain(nx, ny, nz)
+    f0, _ = perturbed_start(lev, dom, rho, u, noise)
+    lev.step(1)
+    f1, _ = oracle.step(dom, oparams(p), f0)
+    got, _ = gpu_f64(lev)
+    assert rel_err(got, f1) <= 1e-6
+
+
 @pytest.mark.parametrize("nx,ny,nz,seed,adaptive,g_max", CASES[:2])
 def test_ten_steps_fp32_populations(nx, ny, nz, seed, adaptive, g_max):
     n = nx * ny * nz

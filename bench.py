@@ -18,6 +18,7 @@ import argparse
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -28,6 +29,7 @@ METRIC = "D3Q27 MLUPS + % HBM roofline; FP16-store and adjoint vs FP32 plain ste
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = {"f32": 216, "f16s": 108}   # 27 reads + 27 writes per update
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_traffic.json")
+REPS = 5          # timed windows per measurement; the median is reported
 STEP_KERNEL_SOURCES = ("step.hip", "brick.hpp", "cm_collide.hpp", "internal.hpp", "lattice.hpp")
 
 
@@ -57,18 +59,40 @@ def measured_traffic(storage: str, n: int):
     return entry.get("bytes_per_launch")
 
 
-def time_steps(lev, steps: int, warmup: int):
+def timed_windows(enqueue, reps: int = REPS):
+    """Durations (ms) of `reps` windows of GPU work, each bracketed by HIP
+    events on the stream the library launches on (torch's current stream)
+    and by a device synchronisation on both sides; `enqueue()` enqueues one
+    window."""
     import torch
     stream = torch.cuda.current_stream()
+    out = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        enqueue()
+        b.record(stream)
+        torch.cuda.synchronize()
+        out.append(a.elapsed_time(b))
+    return out
+
+
+def per_unit(windows, units: int):
+    """Median window time per unit of work (step, launch, reference step)
+    and the spread over the windows."""
+    return statistics.median(windows) / units, {
+        "repetitions": len(windows), "statistic": "median",
+        "min": min(windows) / units, "max": max(windows) / units}
+
+
+def time_steps(lev, steps: int, warmup: int, reps: int = REPS):
+    """`warmup` untimed steps, then `reps` timed windows of `steps` steps
+    (one C call each: `steps` kernel launches on the current stream).
+    Returns (median ms per step, spread)."""
     lev.step(warmup)
-    torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    lev.step(steps)          # one C call: `steps` kernel launches on `stream`
-    end.record(stream)
-    torch.cuda.synchronize()
-    return start.elapsed_time(end)   # ms
+    return per_unit(timed_windows(lambda: lev.step(steps), reps), steps)
 
 
 def kinetic_energy(lev) -> float:
@@ -89,17 +113,17 @@ def run_gpu(n: int, storage: str, steps: int, warmup: int):
     lev.init_equilibrium(rho, u)
     c0 = lev.conserved()
     e0 = kinetic_energy(lev)
-    ms = time_steps(lev, steps, warmup)
+    ms_step, spread = time_steps(lev, steps, warmup)
     c1 = lev.conserved()
     e1 = kinetic_energy(lev)
     bad = lev.count_nonfinite()
     cells = n ** 3
-    ms_step = ms / steps
-    mlups = cells * steps / (ms * 1e-3) / 1e6
+    mlups = cells / (ms_step * 1e-3) / 1e6
     bytes_launch = cells * BYTES_PER_LUP[storage]
     achieved = bytes_launch / (ms_step * 1e-3) / 1e9
     out = {
         "ms_per_step": ms_step,
+        "timing": spread,
         "mlups": mlups,
         "achieved_gbs": achieved,
         "bytes_per_launch": bytes_launch,
@@ -113,10 +137,12 @@ def run_gpu(n: int, storage: str, steps: int, warmup: int):
     return out
 
 
-def run_precision(n: int, steps: int):
+def run_precision(n: int, steps: int, ref_slice=None):
     """Taylor-Green (2D vortex extruded in z, u0 = 0.05, tau = 0.6, adaptive
     on) at n^3: FP16 storage against FP32 storage after `steps` steps, both
-    against the closed-form decay; MLUPS of both."""
+    against the closed-form decay and, when `ref_slice` (the FP64 oracle's
+    velocity [3][n*n] of one z-slice after the same steps; the field does
+    not vary along z) is given, against the FP64 oracle; MLUPS of both."""
     import numpy as np
     import torch
     from paper_1807_02284_amd import inputs
@@ -129,11 +155,12 @@ def run_precision(n: int, steps: int):
     for name, st in (("f32", F32), ("f16s", F16S)):
         lev = Level(n, n, n, p, storage=st)
         lev.init_equilibrium(rho, u)
-        ms = time_steps(lev, steps, 0)
+        assert steps % REPS == 0
+        ms, spread = time_steps(lev, steps // REPS, 0)      # exactly `steps` steps in all
         _, ug, _ = lev.read_macro()
         fields[name] = ug.double()
-        out[name] = {"ms_per_step": ms / steps, "mlups": n ** 3 * steps / (ms * 1e-3) / 1e6,
-                     "achieved_gbs": n ** 3 * BYTES_PER_LUP[name] / (ms / steps * 1e-3) / 1e9}
+        out[name] = {"ms_per_step": ms, "timing": spread, "mlups": n ** 3 / (ms * 1e-3) / 1e6,
+                     "achieved_gbs": n ** 3 * BYTES_PER_LUP[name] / (ms * 1e-3) / 1e9}
         del lev
         torch.cuda.empty_cache()
 
@@ -157,15 +184,43 @@ def run_precision(n: int, steps: int):
     for name in ("f32", "f16s"):
         a = float((fields[name] * u0).sum() / (u0 * u0).sum())
         out[f"{name}_mode_amplitude_rel_err"] = abs(a - amp) / amp
+    if ref_slice is not None:
+        ref = torch.tensor(ref_slice, dtype=torch.float64, device=fields["f32"].device)
+        ref = ref.reshape(3, 1, n * n).expand(3, n, n * n).reshape(3, n ** 3)
+        wref = vort(ref)
+        for name in ("f32", "f16s"):
+            out[f"{name}_vs_fp64_oracle_velocity_rel_l2"] = rl2(fields[name], ref)
+            out[f"{name}_vs_fp64_oracle_vorticity_rel_l2"] = rl2(vort(fields[name]), wref)
+        out["fp64_oracle"] = (f"{n}x{n}x1 periodic slice, {steps} steps; the extruded vortex "
+                              "does not vary along z, so it equals every z-slice of the 3D run")
     return out
+
+
+def oracle_tgv_slice(n: int, steps: int):
+    """FP64 oracle velocity [3][n*n] of the extruded Taylor-Green vortex after
+    `steps` steps, on one periodic z-slice (n x n x 1: the pull from z +- 1
+    wraps onto the slice itself, which is exact for a field constant in z)."""
+    import oracle
+    from paper_1807_02284_amd import inputs
+
+    rho, u = inputs.taylor_green_2d(n, n, 1, 0.05)
+    dom = oracle.Domain(n, n, 1)
+    p = oracle.Params(nu=0.1 / 3.0, g_max=0.1)
+    f, _ = oracle.init(dom, rho, u)
+    f, _ = oracle.step(dom, p, f, n_steps=steps)
+    _, uo, _ = oracle.macro(dom, p, f)
+    return uo
 
 
 def run_adjoint(n: int, steps: int, every: int):
     """Differentiable buoyant smoke at n^3 (periodic; blob sigma = n/16 at
-    (n/2, n/2, n/4); beta = 1e-4, s_ref = initial mean; theta = 0):
-    forward `steps` steps keeping every `every`-th state, then the
-    checkpointed backward (recompute + adjoint).  Reports ms per step of the
-    plain forward step and of the adjoint kernel."""
+    (n/2, n/2, n/4); beta = 1e-4, s_ref = initial mean): the target is the
+    final smoke scalar of a seeded target run (the same scene driven by a
+    seeded smooth random body force of amplitude 1e-5); the differentiated
+    run starts from theta = 0, goes forward `steps` steps keeping every
+    `every`-th state, then the checkpointed backward (recompute + adjoint)
+    gives dL/dtheta of L = 1/2 sum (s - s_target)^2.  Reports ms per step of
+    the plain forward step and of the adjoint kernel."""
     import numpy as np
     import torch
     from paper_1807_02284_amd import inputs
@@ -174,12 +229,15 @@ def run_adjoint(n: int, steps: int, every: int):
 
     s0 = inputs.gaussian_blob(n, n, n, (n / 2, n / 2, n / 4), n / 16.0)
     p = Params(nu=1e-3, g_max=0.1, tau_s=0.51, beta=1e-4, s_ref=float(s0.mean()))
-    lev = Level(n, n, n, p, scalar=True, force=np.zeros((3, n ** 3)))
+    theta_target = inputs.smooth_random_field(n, n, n, 1e-5, 1835, k_max=4)
+    lev = Level(n, n, n, p, scalar=True, force=theta_target)
     lev.init_equilibrium(None, np.zeros((3, n ** 3)), s0)
     h0, g0 = lev.get_populations(shifted=True)
+    h0, g0 = h0.clone(), g0.clone()
+    lev.step(steps)                              # the seeded target run
+    _, _, target = lev.read_macro()
+    target = target.clone()
     theta = torch.zeros(3, n ** 3, device="cuda", requires_grad=True)
-    target = torch.tensor(0.8 * inputs.gaussian_blob(n, n, n, (n / 2 + 4, n / 2, n / 4 + 8), n / 16.0),
-                          dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     e[0].record()
@@ -198,28 +256,30 @@ def run_adjoint(n: int, steps: int, every: int):
     dth = torch.zeros(3 * lev.plane, device="cuda")
     for _ in range(3):
         lev.adjoint_step(lev.f, lev.g, lam, mu, lam2, mu2, dth)
-    torch.cuda.synchronize()
-    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = 20
-    a0.record()
-    for _ in range(reps):
-        lev.adjoint_step(lev.f, lev.g, lam, mu, lam2, mu2, dth)
-    a1.record()
-    torch.cuda.synchronize()
-    adj_ms = a0.elapsed_time(a1) / reps
-    step_ms = time_steps(lev, reps, 2) / reps
+
+    def adjoint_window():
+        for _ in range(reps):
+            lev.adjoint_step(lev.f, lev.g, lam, mu, lam2, mu2, dth)
+
+    adj_ms, adj_spread = per_unit(timed_windows(adjoint_window), reps)
+    step_ms, step_spread = time_steps(lev, reps, 2)
     cells = n ** 3
     out = {
         "forward_ms_per_step": fwd_ms / steps,
         "backward_ms_per_step": bwd_ms / steps,
         "plain_step_ms": step_ms,
+        "plain_step_timing": step_spread,
         "adjoint_kernel_ms": adj_ms,
+        "adjoint_kernel_timing": adj_spread,
         "adjoint_vs_plain_step_time": adj_ms / step_ms,
         "backward_vs_forward_time": bwd_ms / fwd_ms,
         "adjoint_mlups": cells / (adj_ms * 1e-3) / 1e6,
         "adjoint_achieved_gbs": cells * 444 / (adj_ms * 1e-3) / 1e9,
         "plain_step_achieved_gbs": cells * 284 / (step_ms * 1e-3) / 1e9,
         "bytes_per_lup": {"plain_step_scalar_force": 284, "adjoint": 444},
+        "target": "final smoke scalar of a run driven by a seeded smooth random force "
+                  "(amplitude 1e-5, seed 1835)",
         "loss": float(loss.detach()),
         "grad_theta_norm": float(theta.grad.norm()),
     }
@@ -253,8 +313,9 @@ def run_plume(nx: int, ny: int, nz: int, spinup: int, n_ref: int):
     s0 = np.where(jet & (x < 64 * sc), 1.0, 0.0).astype(np.float32)
     lev0.init_equilibrium(None, u, s0)
     del x, y, z, u, s0, jet
-    # reference-scale collide-stream alone (flags + scalar: 273 B/LUP)
-    ms0 = time_steps(lev0, spinup, 10)
+    # reference-scale collide-stream alone (flags + scalar: 273 B/LUP), over
+    # the spin-up: REPS windows of spinup / REPS steps
+    ms0, spread0 = time_steps(lev0, spinup // REPS, 10)
     n0 = nx * ny * nz
     centre = (160.0 * sc, ny / 2.0, nz / 2.0)
     r = 24.0 * sc
@@ -273,13 +334,8 @@ def run_plume(nx: int, ny: int, nz: int, spinup: int, n_ref: int):
     cells = [lv.n for lv in H.levels]
     lups = sum(c * k for c, k in zip(cells, subs))
     H.step(2)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    H.step(n_ref)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / n_ref
+    win = max(1, n_ref // REPS)
+    ms, spread = per_unit(timed_windows(lambda: H.step(win)), win)
     # adjoint of one reference step (forward recompute into the workspace,
     # then the reverse schedule) from the current states, arbitrary adjoints
     ws = torch.empty(H.adjoint_workspace_bytes(), dtype=torch.uint8, device="cuda")
@@ -289,14 +345,7 @@ def run_plume(nx: int, ny: int, nz: int, spinup: int, n_ref: int):
     lam = [1e-3 * torch.randn(27 * lv.plane, device="cuda", generator=gen) for lv in H.levels]
     mu = [1e-3 * torch.randn(7 * lv.plane, device="cuda", generator=gen) for lv in H.levels]
     H.adjoint_step(f_in, g_in, lam, mu, ws)
-    torch.cuda.synchronize()
-    n_adj = 3
-    e0.record()
-    for _ in range(n_adj):
-        H.adjoint_step(f_in, g_in, lam, mu, ws)
-    e1.record()
-    torch.cuda.synchronize()
-    adj_ms = e0.elapsed_time(e1) / n_adj
+    adj_ms, adj_spread = per_unit(timed_windows(lambda: H.adjoint_step(f_in, g_in, lam, mu, ws)), 1)
     adj_finite = bool(all(torch.isfinite(x).all() for x in lam + mu))
     ws_gb = ws.numel() / 1e9
     del ws, f_in, g_in, lam, mu
@@ -321,12 +370,7 @@ def run_plume(nx: int, ny: int, nz: int, spinup: int, n_ref: int):
     cells_b = [lv.n for lv in Hb.levels]
     subs_b = subs[: len(cells_b)]
     Hb.step(2)
-    torch.cuda.synchronize()
-    e0.record()
-    Hb.step(n_ref)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_b = e0.elapsed_time(e1) / n_ref
+    ms_b, spread_b = per_unit(timed_windows(lambda: Hb.step(win)), win)
     bad_b = sum(lv.count_nonfinite() for lv in Hb.levels)
     lups_b = sum(c * k for c, k in zip(cells_b, subs_b))
     # the brick regions rebuilt from the current flow, timed like the boxes'
@@ -347,6 +391,7 @@ def run_plume(nx: int, ny: int, nz: int, spinup: int, n_ref: int):
         "coverage_of_reference_volume": [
             float(np.prod([hi[a] - lo[a] + 1 for a in range(3)]) / n0) for lo, hi in boxes],
         "ms_per_reference_step": ms,
+        "timing": spread,
         "region_rebuild_s": rebuild_s,
         "boxes_after_rebuild_level0_units": [[list(map(int, lo)), list(map(int, hi))]
                                              for lo, hi in boxes2],
@@ -354,15 +399,17 @@ def run_plume(nx: int, ny: int, nz: int, spinup: int, n_ref: int):
         "lattice_updates_per_reference_step": lups,
         "mlups_all_scales": lups / (ms * 1e-3) / 1e6,
         "adjoint_ms_per_reference_step": adj_ms,
+        "adjoint_timing": adj_spread,
         "adjoint_vs_forward_reference_step": adj_ms / ms,
         "adjoint_workspace_gb": ws_gb,
         "adjoint_finite": adj_finite,
-        "reference_scale_step_ms": ms0 / spinup,
-        "reference_scale_mlups": n0 / (ms0 / spinup * 1e-3) / 1e6,
-        "reference_scale_achieved_gbs": n0 * 273 / (ms0 / spinup * 1e-3) / 1e9,
+        "reference_scale_step_ms": ms0,
+        "reference_scale_timing": spread0,
+        "reference_scale_mlups": n0 / (ms0 * 1e-3) / 1e6,
+        "reference_scale_achieved_gbs": n0 * 273 / (ms0 * 1e-3) / 1e9,
         "bytes_per_lup_collide_stream": 273,
         "nonfinite": bad,
-        "bricks": {"cells_per_scale": cells_b, "ms_per_reference_step": ms_b,
+        "bricks": {"cells_per_scale": cells_b, "ms_per_reference_step": ms_b, "timing": spread_b,
                    "lattice_updates_per_reference_step": lups_b,
                    "mlups_all_scales": lups_b / (ms_b * 1e-3) / 1e6,
                    "speedup_vs_boxes": ms / ms_b, "region_rebuild_s": rebuild_b,
@@ -393,10 +440,11 @@ def run_gradient_mode(n: int, steps: int, compare_steps: int):
         lev = Level(n, n, n, Params(nu=1e-5, g_max=0.1, adaptive=True, grad_mode=mode))
         lev.init_equilibrium(rho, u)
         if mode == 1:
-            ms = time_steps(lev, steps, 10)
-            out["ms_per_step"] = ms / steps
-            out["mlups"] = n ** 3 * steps / (ms * 1e-3) / 1e6
-            out["achieved_gbs"] = n ** 3 * 240 / (ms / steps * 1e-3) / 1e9
+            ms, spread = time_steps(lev, steps // REPS, 10)
+            out["ms_per_step"] = ms
+            out["timing"] = spread
+            out["mlups"] = n ** 3 / (ms * 1e-3) / 1e6
+            out["achieved_gbs"] = n ** 3 * 240 / (ms * 1e-3) / 1e9
             lev.init_equilibrium(rho, u)
         lev.step(compare_steps)
         _, ug, _ = lev.read_macro()
@@ -407,9 +455,10 @@ def run_gradient_mode(n: int, steps: int, compare_steps: int):
     # the running-maximum option: the field maximum is reduced before each step
     lev = Level(n, n, n, Params(nu=1e-5, g_max=0.1, adaptive=True, grad_mode=1, gmax_running=True))
     lev.init_equilibrium(rho, u)
-    ms = time_steps(lev, steps, 10)
-    out["running_max_ms_per_step"] = ms / steps
-    out["running_max_mlups"] = n ** 3 * steps / (ms * 1e-3) / 1e6
+    ms, spread = time_steps(lev, steps // REPS, 10)
+    out["running_max_ms_per_step"] = ms
+    out["running_max_timing"] = spread
+    out["running_max_mlups"] = n ** 3 / (ms * 1e-3) / 1e6
     out["running_max_last_gmax"] = float(lev.gmax_buf[-1])
     del lev
     torch.cuda.empty_cache()
@@ -463,15 +512,10 @@ def run_far_field(nx: int, ny: int, nz: int, pad: int, spinup: int, n_ref: int):
     far.init_equilibrium(None, np.zeros((3, far.n), np.float32), np.zeros(far.n, np.float32))
     H = hierarchy.Hierarchy([lev0, far], [kinds, kinds_c])
     H.step(spinup)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    H.step(n_ref)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / n_ref
+    win = max(1, n_ref // REPS)
+    ms, spread = per_unit(timed_windows(lambda: H.step(win)), win)
     # the reference scale alone (flags + scalar), for the share of the exchange
-    ms0 = time_steps(lev0, 20, 2) / 20
+    ms0, spread0 = time_steps(lev0, 20, 2)
     cells = [lev0.n, far.n]
     bad = lev0.count_nonfinite() + far.count_nonfinite()
     out = {
@@ -482,8 +526,10 @@ def run_far_field(nx: int, ny: int, nz: int, pad: int, spinup: int, n_ref: int):
         "reference_shell_cells": int(np.count_nonzero(kinds == _capi.GHOST)),
         "cells_per_scale": cells,
         "ms_per_reference_step": ms,
+        "timing": spread,
         "mlups_all_scales": sum(cells) / (ms * 1e-3) / 1e6,
         "reference_scale_step_ms": ms0,
+        "reference_scale_timing": spread0,
         "nonfinite": int(bad),
     }
     del H, lev0, far
@@ -560,13 +606,16 @@ def main():
     torch.cuda.set_device(0)
 
     main_run = run_gpu(args.n, "f32", args.steps, args.warmup)
+    t = main_run["timing"]
     print(f"[bench] f32 {args.n}^3: {main_run['mlups']:.0f} MLUPS, "
-          f"{main_run['ms_per_step']:.4f} ms/step", file=sys.stderr, flush=True)
+          f"{main_run['ms_per_step']:.4f} ms/step (median of {t['repetitions']} windows of "
+          f"{args.steps} steps; {t['min']:.4f}-{t['max']:.4f})", file=sys.stderr, flush=True)
     variants = {}
     if not args.no_variants:
         v = run_gpu(args.n, "f16s", args.steps, args.warmup)
         variants["f16s"] = {
             "value": v["mlups"], "unit": "MLUPS", "ms_per_step": v["ms_per_step"],
+            "timing": v["timing"],
             "vs_f32_plain_step": v["mlups"] / main_run["mlups"],
             "roofline_frac": v["achieved_gbs"] / HBM_PEAK_GBS,
             "achieved_gbs": v["achieved_gbs"], "bytes_per_lup": BYTES_PER_LUP["f16s"],
@@ -574,10 +623,16 @@ def main():
         print(f"[bench] f16s {args.n}^3: {v['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
 
     if not args.no_precision:
-        pr = run_precision(384, 100)
+        # the FP64 oracle's field for the precision comparison (oracle leg of
+        # the benchmark, skipped with the CPU baseline)
+        ref_slice = None if args.no_cpu_baseline else oracle_tgv_slice(384, 100)
+        pr = run_precision(384, 100, ref_slice)
         variants["precision_tgv_384"] = pr
         print(f"[bench] 384^3 TGV: f32 {pr['f32']['mlups']:.0f} MLUPS, f16s {pr['f16s']['mlups']:.0f} "
-              f"MLUPS, f16s vs f32 velocity rel L2 {pr['f16s_vs_f32_velocity_rel_l2']:.2e}",
+              f"MLUPS, f16s vs f32 velocity rel L2 {pr['f16s_vs_f32_velocity_rel_l2']:.2e}"
+              + ("" if ref_slice is None else
+                 f", vs FP64 oracle: f32 {pr['f32_vs_fp64_oracle_velocity_rel_l2']:.2e}, "
+                 f"f16s {pr['f16s_vs_fp64_oracle_velocity_rel_l2']:.2e}"),
               file=sys.stderr, flush=True)
     if not args.no_adjoint:
         ad = run_adjoint(128, 200, 20)
@@ -628,6 +683,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": main_run["ms_per_step"],
+        "timing": {**main_run["timing"], "window_steps": args.steps},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -13,6 +13,7 @@ from paper_1807_02284_amd.rollout import rollout
 pytestmark = pytest.mark.gpu
 
 N1 = 16
+W = oracle.weights()
 
 
 def scene(adaptive=True, g_max=1.0):
@@ -147,3 +148,79 @@ def test_zero_step_rollout_returns_the_scalar_and_its_gradient():
                                rtol=1e-6, atol=1e-6)
     assert float(th.grad.abs().max()) == 0.0 and float(h.grad.abs().max()) == 0.0
     np.testing.assert_array_equal(g.grad.cpu().numpy(), np.ones((7, n ** 3), np.float32))
+
+
+def test_adjoint_over_the_fp64_trajectory_in_the_differentiable_config_regime():
+    """The regime of the 128^3 differentiable smoke (nu = 1e-3, S = 1.988;
+    adaptive on with g_max = 0.1; tau_s = 0.51; beta = 1e-4, s_ref = the
+    initial mean), at 16^3 over 24 steps with the loss against a seeded
+    target run.  The adjoint steps are chained over the oracle's FP64
+    forward trajectory rounded to FP32, so the comparison with central
+    differences of the FP64 oracle measures the adjoint itself, not the
+    divergence of an FP32 forward trajectory from the FP64 one."""
+    n, steps = N1, 24
+    N = n ** 3
+    s0 = inputs.gaussian_blob(n, n, n, (8, 8, 4), 1.0)
+    p = Params(nu=1e-3, g_max=0.1, adaptive=True, tau_s=0.51, beta=1e-4, s_ref=float(s0.mean()))
+    op = oracle.Params(nu=p.nu, g_max=p.g_max, adaptive=True, tau_s=p.tau_s, beta=p.beta,
+                       s_ref=p.s_ref)
+    u0 = inputs.smooth_random_field(n, n, n, 0.02, 81, k_max=2)
+    theta = inputs.smooth_random_field(n, n, n, 1e-4, 82, k_max=2)
+    theta_t = inputs.smooth_random_field(n, n, n, 1e-5, 83, k_max=3)
+    f0, g0 = oracle.init(oracle.Domain(n, n, n), np.ones(N), u0, s=s0)
+
+    def final_s(th, dh=None, dg=None):
+        dom = oracle.Domain(n, n, n, theta=th)
+        f, g = oracle.step(dom, op, f0 if dh is None else f0 + dh, g0 if dg is None else g0 + dg,
+                           n_steps=steps)
+        return oracle.macro(dom, op, f, g)[2]
+
+    target = final_s(theta_t)
+
+    def loss(th, dh=None, dg=None):
+        return 0.5 * np.sum((final_s(th, dh, dg) - target) ** 2)
+
+    dom = oracle.Domain(n, n, n, theta=theta)
+    traj = [(f0, g0)]
+    for _ in range(steps):
+        traj.append(oracle.step(dom, op, *traj[-1]))
+    s_end = oracle.macro(dom, op, *traj[-1])[2]
+
+    lev = Level(n, n, n, p, scalar=True, force=theta)
+    P = lev.plane
+
+    def planes(x, rows):
+        t = torch.zeros(rows, P, dtype=torch.float32, device="cuda")
+        t[:, :N] = torch.tensor(np.asarray(x).reshape(rows, N), dtype=torch.float32, device="cuda")
+        return t.reshape(-1)
+
+    lam = torch.zeros(27 * P, dtype=torch.float32, device="cuda")
+    lam2 = torch.zeros_like(lam)
+    mu = planes(np.tile(s_end - target, (7, 1)), 7)
+    mu2 = torch.zeros_like(mu)
+    dth = torch.zeros(3 * P, dtype=torch.float32, device="cuda")
+    for k in reversed(range(steps)):
+        fk, gk = traj[k]
+        lev.adjoint_step(planes(fk - W[:, None], 27), planes(gk, 7), lam, mu, lam2, mu2, dth)
+        lam, lam2 = lam2, lam
+        mu, mu2 = mu2, mu
+    torch.cuda.synchronize()
+    gth = dth.reshape(3, P)[:, :N].double().cpu().numpy()
+    gh = lam.reshape(27, P)[:, :N].double().cpu().numpy()
+    gg = mu.reshape(7, P)[:, :N].double().cpu().numpy()
+    for k in range(3):
+        v = inputs.smooth_random_field(n, n, n, 1e-4, 90 + k, k_max=3)
+        eps = 1e-3
+        fd = (loss(theta + eps * v) - loss(theta - eps * v)) / (2 * eps)
+        ad = float(np.sum(gth * v))
+        print(f"theta direction {k}: adjoint {ad:.6e}, central difference {fd:.6e}", flush=True)
+        assert ad == pytest.approx(fd, rel=1e-3), (k, ad, fd)
+    vh = 1e-5 * inputs.perturbation((27, N), 95)
+    vg = 1e-4 * inputs.perturbation((7, N), 96)
+    for name, dh, dg, gi in (("f0", vh, None, gh), ("g0", None, vg, gg)):
+        eps = 1e-2
+        fd = (loss(theta, None if dh is None else eps * dh, None if dg is None else eps * dg)
+              - loss(theta, None if dh is None else -eps * dh, None if dg is None else -eps * dg)) / (2 * eps)
+        ad = float(np.sum(gi * (dh if dh is not None else dg)))
+        print(f"{name} direction: adjoint {ad:.6e}, central difference {fd:.6e}", flush=True)
+        assert ad == pytest.approx(fd, rel=1e-3)

@@ -273,6 +273,44 @@ def test_reduced_plume_three_scales_match_oracle():
         assert np.max(np.abs(gpu_g(lev) - osc.g)) <= 1e-5
 
 
+def test_reduced_plume_100_reference_steps_at_the_plume_viscosity():
+    """The reduced plume (96x48x48, sphere radius 4.5, the same two finer
+    boxes at alpha 1.5 and 2) at the plume's viscosity nu0 = 1e-4 (tau0 =
+    0.5003: rounding differences are barely damped) over 100 reference
+    steps, both sides given the same masks.  Compared per scale: velocity
+    relative L2, the largest population error relative to max(|f|, w_i),
+    and the smoke scalar."""
+    nx, ny, nz = 96, 48, 48
+    specs = plume_specs(nx, ny, nz, 1e-4)
+    levs, oscs = [], []
+    for sp in specs:
+        rho, u, s = smooth_state(sp, 41)
+        u[0] += 0.04
+        lev = sp.level(True)
+        lev.init_equilibrium(rho, u, s)
+        osc = sp.oscale()
+        osc.f, osc.g = oracle.init(osc.domain(), rho, u, s=s)
+        levs.append(lev)
+        oscs.append(osc)
+    H = hierarchy.Hierarchy(levs, [sp.kinds for sp in specs], [sp.parent for sp in specs])
+    ml.prepare(oscs)
+    H.step(100)
+    ml.multiscale_step(oscs, 100)
+    torch.cuda.synchronize()
+    for i, (lev, osc) in enumerate(zip(levs, oscs)):
+        fluid = osc.flags == 0
+        _, ug, sg = lev.read_macro()
+        _, uo, so = oracle.macro(osc.domain(), osc.params, osc.f, osc.g)
+        ug = ug.double().cpu().numpy()[:, fluid]
+        eu = np.linalg.norm(ug - uo[:, fluid]) / np.linalg.norm(uo[:, fluid])
+        ep = rel_err(gpu_pop(lev), osc.f)
+        es = np.max(np.abs(gpu_g(lev) - osc.g))
+        print(f"scale {i}: velocity rel L2 {eu:.2e}, populations {ep:.2e}, scalar {es:.2e}", flush=True)
+        assert eu <= 1e-5
+        assert ep <= 1e-5
+        assert es <= 1e-5
+
+
 def test_vorticity_matches_central_differences():
     """|curl u| (placement of dynamic scales) of an initialised state equals
     central differences of the input field; one-sided at non-periodic faces."""

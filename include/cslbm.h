@@ -239,6 +239,20 @@ int cslbm_vorticity(const cslbm_level* L, float* omega, float* speed, hipStream_
  * without scalar).  out is a HOST array; synchronises the stream. */
 int cslbm_conserved_f64(const cslbm_level* L, double out[5], hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the totals
+ * of cslbm_conserved_f64, same kernels and reduction order (bitwise equal
+ * results), written to totals, a caller-owned DEVICE array of 5 doubles, on
+ * the stream without synchronising.  The per-block partials live in a
+ * library-held device array of 1024 x 6 doubles (48 KiB) per GPU, kept until
+ * the process ends; the reduction grid is fixed, so every level size fits.
+ * Calls no allocator.  Every call on one GPU shares that array: calls that
+ * overlap in time on one GPU (different streams or threads) race.  The
+ * current device must be the one the stream and the level belong to.
+ * Errors: CSLBM_ERR_ARG for a bad level or NULL totals, CSLBM_ERR_HIP if the
+ * scratch address cannot be looked up or a launch fails. */
+int cslbm_conserved_f64_noalloc(const cslbm_level* L, double* totals, hipStream_t stream);
+
 /* Count NaN/Inf values in L->f (and L->g).  *n_bad is a HOST int64.
  * Returns CSLBM_ERR_NONFINITE when the count is non-zero; synchronises. */
 int cslbm_check_finite(const cslbm_level* L, int64_t* n_bad, hipStream_t stream);

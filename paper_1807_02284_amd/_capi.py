@@ -109,6 +109,7 @@ _SIGNATURES = {
     "cslbm_read_macro": (C.c_int, [C.POINTER(CslbmLevel), _vp, _vp, _vp, _vp]),
     "cslbm_vorticity": (C.c_int, [C.POINTER(CslbmLevel), _vp, _vp, _vp]),
     "cslbm_conserved_f64": (C.c_int, [C.POINTER(CslbmLevel), C.POINTER(C.c_double), _vp]),
+    "cslbm_conserved_f64_noalloc": (C.c_int, [C.POINTER(CslbmLevel), _vp, _vp]),
     "cslbm_check_finite": (C.c_int, [C.POINTER(CslbmLevel), C.POINTER(C.c_int64), _vp]),
     "cslbm_exchange": (C.c_int, [C.POINTER(CslbmLevel), _vp, _vp, _vp, _vp, C.c_double,
                                  C.POINTER(CslbmLevel), _vp, _vp, _vp, C.c_int32, _vp]),

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 
@@ -331,6 +332,39 @@ __global__ void __launch_bounds__(kRedThreads) k_conserved_final(const double* p
         out[3] = sm[4][0];
         out[4] = sm[5][0];
     }
+}
+
+// Scratch of the allocation-free conservation call: the per-block partials
+// of k_conserved_partials (every block writes its own entries, so nothing
+// needs clearing between calls).  One copy per GPU, held until the process
+// ends; host code uses the device address from hipGetSymbolAddress, never
+// the symbol itself.
+constexpr int64_t kScratchDoubles = (int64_t)kRedBlocks * kRedVals;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static double* g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mutex;
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current).
+static int scratch_of_current_device(double** out)
+{
+    int dev = -1;
+    CSLBM_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(CSLBM_ERR_UNSUPPORTED, "device index %d outside [0, %d)", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(CSLBM_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return CSLBM_OK;
 }
 
 template <typename T>
@@ -696,6 +730,30 @@ int cslbm_conserved_f64(const cslbm_level* L, double out[5], hipStream_t stream)
     if (es != hipSuccess) return fail(CSLBM_ERR_HIP, "hipStreamSynchronize: %s", hipGetErrorString(es));
     std::memcpy(out, host, sizeof host);
     return CSLBM_OK;
+}
+
+int cslbm_conserved_f64_noalloc(const cslbm_level* L, double* totals, hipStream_t stream)
+{
+    int rc = validate_shape(L);
+    if (rc) return rc;
+    if (!totals) return fail(CSLBM_ERR_ARG, "totals is NULL");
+    // the reduction grid is fixed (grid-stride loop), so every level fits
+    static_assert((int64_t)kRedBlocks * kRedVals <= kScratchDoubles, "partials exceed the scratch");
+    double* partials = nullptr;
+    rc = scratch_of_current_device(&partials);
+    if (rc) return rc;
+    const int64_t N = cells_of(L);
+    if (L->storage == CSLBM_F32)
+        hipLaunchKernelGGL(k_conserved_partials<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, stream,
+                           (const float*)L->f, L->g, L->flags, N, L->plane, partials);
+    else
+        hipLaunchKernelGGL(k_conserved_partials<_Float16>, dim3(kRedBlocks), dim3(kRedThreads), 0,
+                           stream, (const _Float16*)L->f, L->g, L->flags, N, L->plane, partials);
+    rc = check_launch("k_conserved_partials");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_conserved_final, dim3(1), dim3(kRedThreads), 0, stream, partials,
+                       kRedBlocks, totals);
+    return check_launch("k_conserved_final");
 }
 
 int cslbm_check_finite(const cslbm_level* L, int64_t* n_bad, hipStream_t stream)

@@ -86,6 +86,8 @@ def test_negative_step_count_and_null_level(lib):
     assert lib.cslbm_step(C.byref(L), -1, None) == _capi.ERR_ARG
     assert lib.cslbm_step(None, 1, None) == _capi.ERR_ARG
     assert lib.cslbm_conserved_f64(C.byref(L), None, None) == _capi.ERR_ARG
+    assert lib.cslbm_conserved_f64_noalloc(C.byref(L), None, None) == _capi.ERR_ARG
+    assert lib.cslbm_conserved_f64_noalloc(None, 0x5000, None) == _capi.ERR_ARG
     assert lib.cslbm_check_finite(C.byref(L), None, None) == _capi.ERR_ARG
 
 

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "cmr_oracle.c")
 LIB = os.path.join(HERE, "libcmr_oracle.so")
 
-FLUID, SOLID, INLET, OUTFLOW, GHOST, NEUMANN = 0, 1, 2, 3, 4, 5
+FLUID, SOLID, INLET, OUTFLOW, GHOST, NEUMANN, WALL = 0, 1, 2, 3, 4, 5, 6
 
 _dp = C.POINTER(C.c_double)
 
@@ -133,6 +133,7 @@ def lib():
         L.oracle_collide_g.argtypes = [_dp, _dp, C.POINTER(_Params), C.c_double, _dp, _dp]
         L.oracle_exchange.argtypes = [C.POINTER(_Scale), _dp, _dp, _dp, _dp, C.c_double,
                                       C.POINTER(_Scale), C.POINTER(C.c_int64), C.c_int64, _dp, _dp]
+        L.oracle_wall_regularize.argtypes = [_dp, C.POINTER(C.c_int32), _dp, _dp]
         L.oracle_time_interp.argtypes = [_dp, _dp, _dp, C.c_double, C.c_double, C.c_double,
                                          C.c_double, C.c_int64, _dp]
         _lib = L
@@ -323,6 +324,21 @@ def exchange(src: dict, fA, fB, w, dst: dict, cells, f_out, gA=None, gB=None, g_
                                _p(f_out), _p(g_out))
     if rc != 0:
         raise RuntimeError("oracle_exchange failed (stencil outside the source box?)")
+
+
+def wall_regularize(f, n, F=None):
+    """Regularized no-slip wall node (kind WALL) applied to one cell's
+    pulled populations f[27]; n: wall normal (unit axis vector into the
+    wall), F: body force at the node."""
+    f = _f64(f, 27)
+    nn = np.ascontiguousarray(n, dtype=np.int32)
+    assert nn.size == 3
+    Fv = None if F is None else _f64(F, 3)
+    out = np.zeros(27)
+    if lib().oracle_wall_regularize(_p(f), nn.ctypes.data_as(C.POINTER(C.c_int32)), _p(Fv),
+                                    _p(out)) != 0:
+        raise ValueError("bad wall normal")
+    return out
 
 
 def time_interp(s0, s1, s2, t, t_eval):

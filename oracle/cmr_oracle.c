@@ -23,7 +23,8 @@
  *   - body force: velocity shifted by F/2 and source (I - S/2) R with
  *     R = (0, F, 0, ...) in moment space;
  *   - boundaries: halfway bounce-back, Dirichlet equilibrium inlet,
- *     zero-gradient outflow copied from the x-1 neighbour;
+ *     zero-gradient outflow copied from the x-1 neighbour, and the
+ *     regularized no-slip wall node on flat axis-aligned walls;
  *   - passive scalar: D3Q7 BGK with g^eq_i = w_i s (1 + 4 c_i.u).
  */
 #include "cmr_oracle.h"
@@ -392,6 +393,103 @@ static void gather(const oracle_domain* d, const double* f, const double* g,
     }
 }
 
+/* A pull source the node cannot use: outside a non-periodic box or SOLID. */
+static int blocked(const oracle_domain* d, int x, int y, int z, int cx, int cy, int cz)
+{
+    const int64_t src = source_cell(d, x, y, z, cx, cy, cz);
+    return src < 0 || kind_at(d, src) == ORACLE_SOLID;
+}
+
+/* Wall normal of a WALL node (pointing from the node into the wall): the
+ * one axis direction whose neighbour is blocked.  Returns 0 when the node
+ * does not sit on one flat axis-aligned wall: no or several blocked axis
+ * neighbours, or a blocked pull source other than those with c_i.n < 0. */
+static int wall_normal(const oracle_domain* d, int x, int y, int z, int n[3])
+{
+    int found = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+            const int e[3] = {a == 0 ? sgn : 0, a == 1 ? sgn : 0, a == 2 ? sgn : 0};
+            /* the neighbour x + e is the pull source of the velocity -e */
+            if (blocked(d, x, y, z, -e[0], -e[1], -e[2])) {
+                n[0] = e[0];
+                n[1] = e[1];
+                n[2] = e[2];
+                ++found;
+            }
+        }
+    if (found != 1) return 0;
+    for (int i = 0; i < 27; ++i) {
+        const int cn = CX[i] * n[0] + CY[i] * n[1] + CZ[i] * n[2];
+        if (blocked(d, x, y, z, CX[i], CY[i], CZ[i]) != (cn < 0)) return 0;
+    }
+    return 1;
+}
+
+/* Regularized no-slip wall node (Latt & Chopard 2006; Latt et al. 2008,
+ * "Straight velocity boundaries in the lattice Boltzmann method"), the
+ * second-order wall treatment the section "Initialization and boundary
+ * treatment" asks for.  The wall passes through the node and has velocity
+ * zero; with the half-force velocity shift the node's velocity
+ * (j + F/2)/rho vanishes when its momentum is j = -F/2.  On entry fi holds
+ * the pulled populations (those with c_i.n < 0 come from the wall and are
+ * unknown); on exit the regularized pre-collision state:
+ *   rho   from mass and the normal momentum, rho = sum_{c.n=0} f + 2 sum_{c.n>0} f + F.n/2;
+ *   f^eq  the second-order equilibrium at (rho, u_w = -F/(2 rho));
+ *   f^neq known: f - f^eq; unknown: f^neq of the opposite population;
+ *   Pi    = sum_i c_i c_i f^neq_i;
+ *   f_i   = f^eq_i + w_i / (2 cs^4) (c_i c_i - cs^2 I) : Pi    (cs^2 = 1/3). */
+static void regularize_wall(const int n[3], const double F[3], double fi[27])
+{
+    double rho = 0.5 * (F[0] * n[0] + F[1] * n[1] + F[2] * n[2]);
+    for (int i = 0; i < 27; ++i) {
+        const int cn = CX[i] * n[0] + CY[i] * n[1] + CZ[i] * n[2];
+        if (cn == 0) rho += fi[i];
+        else if (cn > 0) rho += 2.0 * fi[i];
+    }
+    const double uw[3] = {-F[0] / (2.0 * rho), -F[1] / (2.0 * rho), -F[2] / (2.0 * rho)};
+    const double uu = uw[0] * uw[0] + uw[1] * uw[1] + uw[2] * uw[2];
+    double feq[27], neq[27];
+    for (int i = 0; i < 27; ++i) {
+        const double cu = CX[i] * uw[0] + CY[i] * uw[1] + CZ[i] * uw[2];
+        feq[i] = weight(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    }
+    for (int i = 0; i < 27; ++i) {
+        const int cn = CX[i] * n[0] + CY[i] * n[1] + CZ[i] * n[2];
+        const int k = (cn < 0) ? opposite(i) : i;
+        neq[i] = fi[k] - feq[k];
+    }
+    double Pi[3][3] = {{0.0}};
+    for (int i = 0; i < 27; ++i) {
+        const int c[3] = {CX[i], CY[i], CZ[i]};
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) Pi[a][b] += c[a] * c[b] * neq[i];
+    }
+    for (int i = 0; i < 27; ++i) {
+        const int c[3] = {CX[i], CY[i], CZ[i]};
+        double q = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) q += (c[a] * c[b] - (a == b ? 1.0 / 3.0 : 0.0)) * Pi[a][b];
+        fi[i] = feq[i] + 4.5 * weight(i) * q;
+    }
+}
+
+int oracle_wall_regularize(const double f[27], const int32_t n[3], const double F[3],
+                           double out[27])
+{
+    int axes = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (n[a] < -1 || n[a] > 1) return -1;
+        axes += n[a] != 0;
+    }
+    if (axes != 1) return -1;
+    const int nn[3] = {n[0], n[1], n[2]};
+    const double Fz[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 27; ++i) out[i] = f[i];
+    regularize_wall(nn, F ? F : Fz, out);
+    return 0;
+}
+
 /* One cell of one step: pull-stream (eq. lbe) with boundary rules, then
  * collide.  fo[27 * stride] / go[7 * stride] receive the output with
  * element stride `stride`. */
@@ -463,6 +561,12 @@ static int step_one(const oracle_domain* d, const oracle_params* p,
     if (d->theta)
         for (int a = 0; a < 3; ++a) F[a] = d->theta[a * N + cell];
     if (g) F[2] += p->beta * (s - p->s_ref);
+
+    if (kind == ORACLE_WALL) {
+        int n[3];
+        if (!wall_normal(d, x, y, z, n)) return -1;
+        regularize_wall(n, F, fi);
+    }
 
     double post[27], diag[6];
     const double Gc = gfield ? gfield[cell] : -1.0;

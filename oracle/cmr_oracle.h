@@ -40,9 +40,19 @@ enum {
     ORACLE_INLET = 2,   /* Dirichlet: output = f^eq(1, u_in), g^eq(s_in, u_in) */
     ORACLE_OUTFLOW = 3, /* zero-gradient: output = input of the x-1 neighbour */
     ORACLE_GHOST = 4,   /* written only by the scale exchange; output = input */
-    ORACLE_NEUMANN = 5  /* far-field zero-gradient on the box faces: output =
+    ORACLE_NEUMANN = 5, /* far-field zero-gradient on the box faces: output =
                            input of the neighbour one cell inward along every
                            non-periodic face the cell lies on */
+    ORACLE_WALL = 6     /* no-slip wall through this node (the second-order
+                           wall of section "Initialization and boundary
+                           treatment"): the regularized boundary condition of
+                           Latt & Chopard (Math. Comput. Simul. 72, 2006;
+                           Latt et al., Phys. Rev. E 77, 056703, 2008) on a
+                           flat wall aligned with a lattice axis: exactly one
+                           of the 6 axis neighbours is SOLID or outside the
+                           box (the wall side, normal n), and the populations
+                           pulled from SOLID or outside sources are exactly
+                           those with c_i.n < 0; anything else is an error */
 };
 
 typedef struct {
@@ -158,6 +168,13 @@ int oracle_exchange(const oracle_scale* src, const double* fA, const double* fB,
 
 /* Lagrange quadratic through (t0, s0), (t1, s1), (t2, s2) evaluated at t:
  * out[k] for k < n (section "Temporal alignment and scale mapping"). */
+/* The regularized no-slip wall node applied to one cell's pulled
+ * populations f (the ORACLE_WALL rule of oracle_step, without the step):
+ * n is the wall normal (a unit axis vector pointing into the wall), F the
+ * body force at the node (may be NULL).  Returns -1 for a bad normal. */
+int oracle_wall_regularize(const double f[27], const int32_t n[3], const double F[3],
+                           double out[27]);
+
 void oracle_time_interp(const double* s0, const double* s1, const double* s2,
                         double t0, double t1, double t2, double t, int64_t n, double* out);
 

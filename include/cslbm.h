@@ -60,9 +60,9 @@ extern "C" {
 #define CSLBM_F32 0
 #define CSLBM_F16S 1
 
-/* cell kinds: low 3 bits of the per-cell flag byte.  Bits 3 (CSLBM_NEAR_WALL)
- * and 4 (CSLBM_NEAR_FLUID) are owned by the library and set by
- * cslbm_prepare_flags. */
+/* cell kinds: low 3 bits of the per-cell flag byte.  Bits 3 (CSLBM_NEAR_WALL),
+ * 4 (CSLBM_NEAR_FLUID) and 5-7 (the wall normal of a CSLBM_WALL cell) are
+ * owned by the library and set by cslbm_prepare_flags. */
 #define CSLBM_FLUID 0    /* collided */
 #define CSLBM_SOLID 1    /* obstacle: halfway bounce-back for its neighbours;
                             its own output is the rest state (h = 0, g = 0) */
@@ -72,8 +72,32 @@ extern "C" {
 #define CSLBM_NEUMANN 5  /* far-field zero gradient (section "Initialization and
                             boundary treatment"): output = input of the cell one
                             step inward along every non-periodic face it lies on */
+#define CSLBM_WALL 6     /* no-slip wall through this node, the second-order
+                            wall treatment of section "Initialization and
+                            boundary treatment" (Latt et al.), written as the
+                            regularized boundary condition of Latt & Chopard
+                            (Math. Comput. Simul. 72, 2006; Latt et al., Phys.
+                            Rev. E 77, 056703, 2008): the node is collided like
+                            a fluid node after its populations are rebuilt as
+                            f^eq(rho, u_w) + w/(2 cs^4) Q:Pi, with rho from
+                            mass and normal momentum, the non-equilibrium of
+                            the populations coming from the wall bounced from
+                            the opposite ones, and u_w = -F/(2 rho) so that
+                            the node's velocity (j + F/2)/rho is zero.  The
+                            node must lie on one flat wall normal to a lattice
+                            axis: exactly one of its 6 axis neighbours is
+                            SOLID or outside a non-periodic face, and its
+                            pull sources that are SOLID or outside are exactly
+                            those of the 9 velocities pointing away from that
+                            wall.  Otherwise cslbm_prepare_flags stores normal
+                            code 7 and the step writes NaN at the cell, which
+                            cslbm_check_finite reports. */
 #define CSLBM_NEAR_WALL 8
 #define CSLBM_NEAR_FLUID 16
+#define CSLBM_WALL_NORMAL_SHIFT 5   /* flags >> 5 of a WALL cell: 1..6 = wall
+                                       normal -x, +x, -y, +y, -z, +z (from the
+                                       node into the wall); 7 = not on one
+                                       flat axis-aligned wall */
 
 /* floats in cslbm_level.gmax_buf */
 #define CSLBM_GMAX_BUF 1025
@@ -146,7 +170,12 @@ typedef struct cslbm_level {
                                  x-fastest order: index 512 b + lx + 8 ly + 64 lz,
                                  and every per-cell array (flags, links,
                                  states, lists) uses that order */
-    int32_t reserved1;
+    int32_t wall_cells;       /* number of CSLBM_WALL cells in flags (0 when
+                                 there are none); the caller keeps it in step
+                                 with the flags.  The step handles wall cells
+                                 in any case; the adjoint calls, which do not
+                                 differentiate them, reject a level with
+                                 wall_cells != 0 (CSLBM_ERR_UNSUPPORTED) */
     double origin[3];         /* physical position of cell (0,0,0) */
     double dx;                /* physical spacing of this scale */
     cslbm_params p;
@@ -326,32 +355,34 @@ typedef struct cslbm_hierarchy {
 /* n_ref_steps reference steps of Algorithm 1.  Per reference step:
  *   - scale 0 takes one step (its states at t_n and t_n + dt_0 stay in
  *     level.f_next and level.f);
- *   - each finer scale i (in index order) with alpha_i = dx_0 / dx_i takes
- *     l = floor(alpha_i) + 1 sub-steps; before sub-step k its ghost cells
- *     are prior-mapped from the parent's states at time weight
- *     (k - 1) / alpha_i; the result is interpolated in time by the
- *     quadratic through 0, (l - 1)/alpha_i, l/alpha_i evaluated at 1; the
- *     ghosts are mapped again at weight 1; then the scale is post-mapped
- *     onto post_cells[j] of every coarser scale j < i (at integer alpha_i
- *     the quadratic's weight on sub-step l is exactly 0 and that sub-step
- *     is not computed; the result is the same);
- *   - then each far-field scale i (level.dx > scale 0's dx; alpha_i =
- *     dx_0 / dx_i < 1; section "Temporal alignment and scale mapping" and
- *     the reversed rules of "Handling multiple scales"), in index order:
- *     its ghost cells (the whole region it shares with its parent, the
- *     finer scale it surrounds) are mapped from the parent at t_n; it takes
- *     one step of dt_i = dt_0 / alpha_i and is interpolated linearly back
- *     to t_n + dt_0, (1 - alpha_i) f(t_n) + alpha_i f(t_n + dt_i); its
- *     ghost cells are mapped again at t_n + dt_0; then post_cells[parent]
- *     (the parent's boundary shell, CSLBM_GHOST cells of the parent) are
- *     mapped from it.  Its outer faces are normally CSLBM_NEUMANN cells;
+ *   - with it, each far-field scale i (level.dx > scale 0's dx; alpha_i =
+ *     dx_0 / dx_i < 1; parent 0; section "Temporal alignment and scale
+ *     mapping" and the reversed rules of "Handling multiple scales"), in
+ *     index order: its ghost cells (the whole region it shares with scale 0)
+ *     are mapped from scale 0 at t_n; it takes one step of dt_i = dt_0 /
+ *     alpha_i and is interpolated linearly back to t_n + dt_0,
+ *     (1 - alpha_i) f(t_n) + alpha_i f(t_n + dt_i); its ghost cells are
+ *     mapped again at t_n + dt_0; then post_cells[0] (scale 0's boundary
+ *     shell, CSLBM_GHOST cells of scale 0) are mapped from it.  Its outer
+ *     faces are normally CSLBM_NEUMANN cells;
+ *   - then each finer scale i (in index order) with alpha_i = dx_0 / dx_i
+ *     takes l = floor(alpha_i) + 1 sub-steps; before sub-step k < l its
+ *     ghost cells are prior-mapped from the parent blended between its
+ *     states at t_n and t_n + dt_0 with weight (k - 1) / alpha_i (the
+ *     sub-step's start time), and before the final sub-step k = l from the
+ *     parent at t_n + dt_0 (weight 1); the result is interpolated in time
+ *     by the quadratic through 0, (l - 1)/alpha_i, l/alpha_i evaluated at 1;
+ *     the ghosts are mapped again at weight 1; then the scale is post-mapped
+ *     onto post_cells[j] of every larger scale j (j < i, or a far-field
+ *     scale), in index order (at integer alpha_i the quadratic's weight on
+ *     sub-step l is exactly 0 and that sub-step is not computed; the result
+ *     is the same);
  *   - the interpolated states become the scales' level.f (pointer swap with
  *     work_f[1] / work_g[1]).
  * Every scale but scale 0 needs flags with CSLBM_GHOST cells; every scale
  * must carry the scalar or none; a finer scale's parent is never a far-field
- * scale and finer scales do not post-map onto far-field scales.  Errors:
- * CSLBM_ERR_ARG for an inconsistent hierarchy (parents, spacings, buffers,
- * lists, singular relaxation times). */
+ * scale.  Errors: CSLBM_ERR_ARG for an inconsistent hierarchy (parents,
+ * spacings, buffers, lists, singular relaxation times). */
 int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t stream);
 
 /* ------------------------------------------------------------------------

@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(PKG, "libcslbm.so")
 OK = 0
 ERR_ARG, ERR_SHAPE, ERR_UNSUPPORTED, ERR_HIP, ERR_NONFINITE = -1, -2, -3, -4, -5
 F32, F16S = 0, 1
-FLUID, SOLID, INLET, OUTFLOW, GHOST, NEUMANN, NEAR_WALL, NEAR_FLUID = 0, 1, 2, 3, 4, 5, 8, 16
+FLUID, SOLID, INLET, OUTFLOW, GHOST, NEUMANN, WALL, NEAR_WALL, NEAR_FLUID = 0, 1, 2, 3, 4, 5, 6, 8, 16
+WALL_NORMAL_SHIFT = 5
 GMAX_BUF = 1025
 
 _vp = C.c_void_p
@@ -61,7 +62,7 @@ class CslbmLevel(C.Structure):
         ("brick_table", _vp),
         ("brick_origin", _vp),
         ("n_bricks", C.c_int32),
-        ("reserved1", C.c_int32),
+        ("wall_cells", C.c_int32),
         ("origin", C.c_double * 3),
         ("dx", C.c_double),
         ("p", CslbmParams),

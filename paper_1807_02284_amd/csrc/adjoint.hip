@@ -393,6 +393,8 @@ int cslbm_adjoint_step(const cslbm_level* L, const float* lam_next, const float*
         return fail(CSLBM_ERR_UNSUPPORTED,
                     "the adjoint step differentiates the local gradient estimate (grad_mode 0)");
     if (L->brick_table) return fail(CSLBM_ERR_UNSUPPORTED, "the adjoint of a brick level");
+    if (L->wall_cells != 0)
+        return fail(CSLBM_ERR_UNSUPPORTED, "the adjoint does not differentiate wall nodes");
     if (!lam_next || !lam) return fail(CSLBM_ERR_ARG, "adjoint buffers are NULL");
     if (lam_next == lam) return fail(CSLBM_ERR_ARG, "lam and lam_next alias");
     const bool scalar = L->g != nullptr;

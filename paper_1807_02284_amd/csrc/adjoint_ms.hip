@@ -773,6 +773,8 @@ static int validate_adjoint_hierarchy(const cslbm_hierarchy* H)
             return fail(CSLBM_ERR_UNSUPPORTED, "scale %d: the multi-scale adjoint needs FP32 storage", i);
         if (L->brick_table)
             return fail(CSLBM_ERR_UNSUPPORTED, "scale %d: brick levels are not differentiated", i);
+        if (L->wall_cells != 0)
+            return fail(CSLBM_ERR_UNSUPPORTED, "scale %d: wall nodes are not differentiated", i);
         if (i > 0 && L->dx > S[0].level.dx)
             return fail(CSLBM_ERR_UNSUPPORTED, "scale %d: far-field scales are not differentiated", i);
         if (i > 0 && S[i].parent != i - 1)
@@ -818,6 +820,8 @@ int cslbm_exchange_adjoint(const cslbm_level* src, const void* fA, const void* f
         return fail(CSLBM_ERR_UNSUPPORTED, "the exchange adjoint reads FP32 source states");
     if (src->brick_table || dst->brick_table)
         return fail(CSLBM_ERR_UNSUPPORTED, "the exchange adjoint of brick levels");
+    if (src->wall_cells != 0 || dst->wall_cells != 0)
+        return fail(CSLBM_ERR_UNSUPPORTED, "the exchange adjoint of levels with wall nodes");
     if (!(src->dx > 0.0) || !(dst->dx > 0.0)) return fail(CSLBM_ERR_ARG, "scale spacings must be positive");
     if (std::fabs(1.0 - shear_rate(src)) < 1e-9)
         return fail(CSLBM_ERR_ARG, "source relaxation time is 1: the mapping is singular");

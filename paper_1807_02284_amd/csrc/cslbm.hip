@@ -67,7 +67,7 @@ __global__ void k_prepare_flags(uint8_t* flags, uint32_t* links, int nx, int ny,
     const uint8_t kind = flags[c] & kKindMask;
     uint32_t m = 0;
     bool near_fluid = false;
-    if (kind != kFluid) {
+    if (kind != kFluid && kind != kWall) {
         // some neighbour (periodic wrap on every axis) is fluid: the adjoint
         // step checks such cells' neighbours before writing zeros
 #pragma unroll
@@ -109,7 +109,35 @@ __global__ void k_prepare_flags(uint8_t* flags, uint32_t* links, int nx, int ny,
             if ((flags[src] & kKindMask) == kSolid) m |= 1u << i;
         }
     }
-    flags[c] = kind | (m ? kNearWall : 0) | (near_fluid ? CSLBM_NEAR_FLUID : 0);
+    // wall node: the normal is minus the one axis velocity whose pull source
+    // is blocked (code k for velocity k = 1..6: n = -c_k), and the blocked
+    // sources must be exactly those of the velocities pointing away from the
+    // wall (c.n < 0); otherwise code 7
+    int wall_code = 0;
+    if (kind == kWall) {
+        int axis_blocked = 0;
+        wall_code = 7;
+#pragma unroll
+        for (int k = 1; k <= 6; ++k)
+            if (m & (1u << k)) {
+                ++axis_blocked;
+                wall_code = k;
+            }
+        if (axis_blocked != 1) {
+            wall_code = 7;
+        } else {
+            uint32_t expect = 0;
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const int cn = -(kCx[i] * kCx[wall_code] + kCy[i] * kCy[wall_code] +
+                                 kCz[i] * kCz[wall_code]);
+                if (cn < 0) expect |= 1u << i;
+            }
+            if (expect != m) wall_code = 7;
+        }
+    }
+    flags[c] = kind | (m ? kNearWall : 0) | (near_fluid ? CSLBM_NEAR_FLUID : 0) |
+               (uint8_t)(wall_code << kWallNormalShift);
     if (links) links[c] = m;
 }
 
@@ -424,6 +452,8 @@ int validate_shape(const cslbm_level* L)
     if ((L->periodic & 7) != 7 && !L->flags)
         return fail(CSLBM_ERR_ARG, "a non-periodic axis needs a flags array (periodic = %d)",
                     L->periodic);
+    if (L->wall_cells < 0 || (L->wall_cells > 0 && !L->flags))
+        return fail(CSLBM_ERR_ARG, "wall_cells = %d needs a flags array holding them", L->wall_cells);
     if (L->brick_table) {
         if (L->nx % kBrickEdge || L->ny % kBrickEdge || L->nz % kBrickEdge)
             return fail(CSLBM_ERR_SHAPE, "a brick level's box %d x %d x %d must be a multiple of 8",

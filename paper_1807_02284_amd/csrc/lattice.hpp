@@ -55,9 +55,11 @@ enum : uint8_t {
     kOutflow = 3,
     kGhost = 4,
     kNeumann = 5,
+    kWall = 6,
 };
 constexpr uint8_t kKindMask = 0x07;
 constexpr uint8_t kNearWall = 0x08;  // set by the library: some pull source is solid
+constexpr int kWallNormalShift = 5;  // wall cells: normal code 1..6 (7: not a flat wall)
 
 // D3Q7 equilibrium g^eq_i = w_i s (1 + 4 c_i.u)  (cs^2 = 1/4)
 __device__ __forceinline__ float scalar_eq(int i, float s, float ux, float uy, float uz)

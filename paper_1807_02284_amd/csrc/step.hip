@@ -14,6 +14,7 @@
 #include "cm_collide.hpp"
 #include "internal.hpp"
 #include "lattice.hpp"
+#include "wall.hpp"
 
 namespace cslbm {
 
@@ -222,9 +223,11 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
     int kind = kFluid;
     uint32_t links = 0;
     int from = cell;
+    int wall_code = 0;
     if (kFlags) {
         const uint8_t flag = a.flags[cell];
         kind = flag & kKindMask;
+        wall_code = flag >> kWallNormalShift;
         if (kBrick) {
             if (flag & kNearWall) links = a.links ? a.links[cell] : bounce_links_brick(a, nbr, cell);
             if (kind == kOutflow) from = brick_source(nbr, cell, 1, 0, 0);
@@ -242,7 +245,9 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
             if (kind == kNeumann) from = inward_cell(a, x, y, z);
         }
     }
-    const bool fluid = kind == kFluid;
+    // wall nodes pull and collide like fluid nodes (their populations are
+    // rebuilt in between)
+    const bool fluid = kind == kFluid || kind == kWall;
     const bool copies = kind == kGhost || kind == kOutflow || kind == kNeumann;
     const bool loads = fluid || copies;
 
@@ -302,6 +307,12 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
         Fz = a.force[2 * P + cell];
     }
     if (kScalar && fluid) Fz += a.beta * (s - a.s_ref);
+    if (kFlags && kind == kWall) {
+        if (wall_code >= 1 && wall_code <= 6)
+            wall_regularize(v, wall_code, Fx, Fy, Fz);
+        else   // not on one flat axis-aligned wall: flag the cell with NaN
+            v[13] = __builtin_nanf("");
+    }
 
     // gradient mode: |grad u|_F of the stored velocity field by central
     // differences (the level is fully periodic: kGradFD excludes flags)
@@ -343,8 +354,8 @@ __global__ void __launch_bounds__(256) k_step(const StepArgs a)
         const float uy = kind == kInlet ? a.u_in[1] : mc.uy;
         const float uz = kind == kInlet ? a.u_in[2] : mc.uz;
         const float sc = kind == kInlet ? a.s_in : s;
-        // fluid: BGK; inlet: equilibrium; ghost/outflow: copy; solid: 0
-        const float relax = kind == kFluid ? a.inv_tau_s : (kind == kInlet ? 1.0f : 0.0f);
+        // fluid and wall: BGK; inlet: equilibrium; ghost/outflow: copy; solid: 0
+        const float relax = fluid ? a.inv_tau_s : (kind == kInlet ? 1.0f : 0.0f);
 #pragma unroll
         for (int i = 0; i < QS; ++i) {
             const float ge = scalar_eq(i, sc, ux, uy, uz);

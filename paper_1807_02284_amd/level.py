@@ -125,10 +125,12 @@ class Level:
             self.g_next = torch.zeros_like(self.g)
         self.flags = None
         self.links = None
+        self.wall_cells = 0
         if flags is not None:
             fl = torch.as_tensor(np.asarray(flags, dtype=np.uint8) if not torch.is_tensor(flags)
                                  else flags).to(self.device, torch.uint8).reshape(-1)
             assert fl.numel() == self.n
+            self.wall_cells = int(((fl & 7) == _capi.WALL).sum())
             self.flags = torch.zeros(self.plane, dtype=torch.uint8, device=self.device)
             self.flags[: self.n] = fl
             self.links = torch.zeros(self.n, dtype=torch.int32, device=self.device)
@@ -204,6 +206,7 @@ class Level:
         self.c.brick_table = _dev_ptr(self.brick_table)
         self.c.brick_origin = _dev_ptr(self.brick_origin)
         self.c.n_bricks = self.n_bricks
+        self.c.wall_cells = self.wall_cells
         self.c.p = self.params.to_c()
 
     def set_params(self, params: Params):
@@ -227,6 +230,7 @@ class Level:
             self.flags = torch.zeros(self.plane, dtype=torch.uint8, device=self.device)
             self.links = torch.zeros(self.n, dtype=torch.int32, device=self.device)
         self.flags[: self.n] = fl
+        self.wall_cells = int(np.count_nonzero((flags & 7) == _capi.WALL))
         self._sync_struct()
         _capi.call("cslbm_prepare_flags", C.byref(self.c), _stream_handle())
 

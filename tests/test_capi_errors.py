@@ -169,3 +169,18 @@ def test_multiscale_adjoint_argument_checks(lib):
     # a far-field scale
     H, keep = hierarchy_of([L0, make_level(dx=2.0, flags=0x9000, periodic=0)], [-1, 0])
     assert ab(C.byref(H)) == -1
+
+
+def test_wall_cell_count_checked_and_adjoints_refuse_wall_nodes(lib):
+    """wall_cells must be >= 0 and needs a flags array; the adjoint calls do
+    not differentiate wall nodes and refuse a level that has them (all
+    before any launch)."""
+    L = make_level(wall_cells=-1)
+    assert lib.cslbm_step(C.byref(L), 1, None) == _capi.ERR_ARG
+    L = make_level(wall_cells=4)
+    assert lib.cslbm_step(C.byref(L), 1, None) == _capi.ERR_ARG
+    assert "wall_cells" in err(lib)
+    L = make_level(wall_cells=4, flags=0x9000, periodic=3)
+    assert lib.cslbm_adjoint_step(C.byref(L), 0x5000, None, 0x6000, None, None, None) == \
+        _capi.ERR_UNSUPPORTED
+    assert "wall" in err(lib)

@@ -660,7 +660,7 @@ int oracle_step(const oracle_domain* d, const oracle_params* p,
         }
     }
     int err = 0;
-#pragma omp parallel for schedule(dynamic, 64) reduction(| : err)
+#pragma omp parallel for schedule(dynamic, 64) reduction(| : err) if (N >= 4096)
     for (int64_t c = 0; c < N; ++c) {
         if (step_one(d, p, f, g, gfield, c, f_out + c, g_out ? g_out + c : NULL, N) != 0) err |= 1;
     }

@@ -30,7 +30,8 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = {"f32": 216, "f16s": 108}   # 27 reads + 27 writes per update
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_traffic.json")
 REPS = 5          # timed windows per measurement; the median is reported
-STEP_KERNEL_SOURCES = ("step.hip", "brick.hpp", "cm_collide.hpp", "internal.hpp", "lattice.hpp")
+STEP_KERNEL_SOURCES = ("step.hip", "brick.hpp", "cm_collide.hpp", "internal.hpp", "lattice.hpp",
+                       "wall.hpp")
 
 
 def kernel_source_hash() -> str:

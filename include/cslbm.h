@@ -344,6 +344,25 @@ typedef struct cslbm_scale {
     int32_t n_post[CSLBM_MAX_SCALES];
     const int32_t* post_cells[CSLBM_MAX_SCALES];  /* device: cells of coarser scale j
                                                      written by post-mapping */
+    int32_t n_ghost_xlo, n_ghost_xhi;   /* the first n_ghost_xlo entries of
+                                           ghost_cells lie on the plane x =
+                                           ghost_xlo, the next n_ghost_xhi on
+                                           x = ghost_xhi (0, 0: no such order) */
+    int32_t ghost_xlo, ghost_xhi;       /* x indices of the two planes of the
+                                           boundary shell normal to x (a box
+                                           padded along x has its shell inside
+                                           the box) */
+    void* stage;                        /* device work space of
+                                           cslbm_stage_bytes(parent, level,
+                                           ghost_xlo, ghost_xhi) bytes, or
+                                           NULL: with it (and the
+                                           x-face counts above) the prior-
+                                           mapping of the x-face ghosts reads a
+                                           compact copy of the parent's few
+                                           columns around each face, made once
+                                           per reference step, instead of one
+                                           cache line per parent row */
+    int64_t stage_bytes;
 } cslbm_scale;
 
 typedef struct cslbm_hierarchy {
@@ -384,6 +403,18 @@ typedef struct cslbm_hierarchy {
  * scale.  Errors: CSLBM_ERR_ARG for an inconsistent hierarchy (parents,
  * spacings, buffers, lists, singular relaxation times). */
 int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t stream);
+
+/* Bytes of the x-face staging work space (cslbm_scale.stage) of a finer
+ * scale `level` whose parent is `parent` and whose boundary shell has its
+ * planes normal to x at x = x_lo and x = x_hi: for each plane, the parent's
+ * populations (and scalar) at both time levels over the columns and rows
+ * the plane's trilinear stencils reach, with one cell of margin.  0 when
+ * staging does not apply (a brick level on either side, or a stencil region
+ * that wraps around a periodic parent axis or leaves the parent); negative
+ * on invalid arguments.  The copy changes only where the prior-mapping
+ * reads its corners: results are bitwise those of the unstaged mapping. */
+int64_t cslbm_stage_bytes(const cslbm_level* parent, const cslbm_level* level, int32_t x_lo,
+                          int32_t x_hi);
 
 /* ------------------------------------------------------------------------
  * Differentiation (build addition; the paper has no adjoint).
@@ -471,10 +502,11 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
                                   const float* const* g_in, float* const* lam, float* const* mu,
                                   void* workspace, int64_t workspace_bytes, hipStream_t stream);
 
-/* sizeof(cslbm_params) and sizeof(cslbm_level) as compiled into the
- * library (HOST pointers), so that bindings can verify their struct layout
- * before the first call.  Always CSLBM_OK. */
-int cslbm_abi_sizes(int64_t* params_bytes, int64_t* level_bytes);
+/* sizeof(cslbm_params), sizeof(cslbm_level) and sizeof(cslbm_scale) as
+ * compiled into the library (HOST pointers, each may be NULL), so that
+ * bindings can verify their struct layout before the first call.  Always
+ * CSLBM_OK. */
+int cslbm_abi_sizes(int64_t* params_bytes, int64_t* level_bytes, int64_t* scale_bytes);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* cslbm_last_error(void);

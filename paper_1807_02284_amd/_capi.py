@@ -82,6 +82,12 @@ class CslbmScale(C.Structure):
         ("ghost_cells", _vp),
         ("n_post", C.c_int32 * MAX_SCALES),
         ("post_cells", _vp * MAX_SCALES),
+        ("n_ghost_xlo", C.c_int32),
+        ("n_ghost_xhi", C.c_int32),
+        ("ghost_xlo", C.c_int32),
+        ("ghost_xhi", C.c_int32),
+        ("stage", _vp),
+        ("stage_bytes", C.c_int64),
     ]
 
 
@@ -111,6 +117,8 @@ _SIGNATURES = {
     "cslbm_vorticity": (C.c_int, [C.POINTER(CslbmLevel), _vp, _vp, _vp]),
     "cslbm_conserved_f64": (C.c_int, [C.POINTER(CslbmLevel), C.POINTER(C.c_double), _vp]),
     "cslbm_conserved_f64_noalloc": (C.c_int, [C.POINTER(CslbmLevel), _vp, _vp]),
+    "cslbm_stage_bytes": (C.c_int64, [C.POINTER(CslbmLevel), C.POINTER(CslbmLevel), C.c_int32,
+                                      C.c_int32]),
     "cslbm_check_finite": (C.c_int, [C.POINTER(CslbmLevel), C.POINTER(C.c_int64), _vp]),
     "cslbm_exchange": (C.c_int, [C.POINTER(CslbmLevel), _vp, _vp, _vp, _vp, C.c_double,
                                  C.POINTER(CslbmLevel), _vp, _vp, _vp, C.c_int32, _vp]),
@@ -129,7 +137,7 @@ _SIGNATURES = {
     "cslbm_multiscale_adjoint_step": (C.c_int, [C.POINTER(CslbmHierarchy), C.POINTER(_vp),
                                                 C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp),
                                                 _vp, C.c_int64, _vp]),
-    "cslbm_abi_sizes": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "cslbm_abi_sizes": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "cslbm_last_error": (C.c_char_p, []),
 }
 
@@ -154,12 +162,14 @@ def load() -> C.CDLL:
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    pb, lb = C.c_int64(0), C.c_int64(0)
-    lib.cslbm_abi_sizes(C.byref(pb), C.byref(lb))
-    if (pb.value, lb.value) != (C.sizeof(CslbmParams), C.sizeof(CslbmLevel)):
+    pb, lb, sb = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+    lib.cslbm_abi_sizes(C.byref(pb), C.byref(lb), C.byref(sb))
+    want = (C.sizeof(CslbmParams), C.sizeof(CslbmLevel), C.sizeof(CslbmScale))
+    if (pb.value, lb.value, sb.value) != want:
         raise RuntimeError(
             f"struct layout mismatch: library has cslbm_params={pb.value} B, cslbm_level="
-            f"{lb.value} B; binding has {C.sizeof(CslbmParams)} B, {C.sizeof(CslbmLevel)} B")
+            f"{lb.value} B, cslbm_scale={sb.value} B; binding has {want[0]} B, {want[1]} B, "
+            f"{want[2]} B")
     _lib = lib
     return lib
 

@@ -822,10 +822,11 @@ int cslbm_check_finite(const cslbm_level* L, int64_t* n_bad, hipStream_t stream)
     return CSLBM_OK;
 }
 
-int cslbm_abi_sizes(int64_t* params_bytes, int64_t* level_bytes)
+int cslbm_abi_sizes(int64_t* params_bytes, int64_t* level_bytes, int64_t* scale_bytes)
 {
     if (params_bytes) *params_bytes = (int64_t)sizeof(cslbm_params);
     if (level_bytes) *level_bytes = (int64_t)sizeof(cslbm_level);
+    if (scale_bytes) *scale_bytes = (int64_t)sizeof(cslbm_scale);
     return CSLBM_OK;
 }
 

@@ -32,6 +32,29 @@ struct ExchArgs {
     float w;
     float kappa;     // stress rescaling
     float kappa_s;   // scalar non-equilibrium rescaling
+    // Staged segments (forward exchange only): the first list entries are
+    // mapped from compact copies of sub-boxes of the source level instead
+    // of the source level itself.  Segment s covers list entries
+    // [st[s].first, st[s].first + st[s].count) and the first st[s].blocks
+    // blocks after the previous segments; the remaining blocks map entries
+    // [main_first, n_cells) from the source level.  A staged copy starts at
+    // source cell st[s].off: the stencil geometry is still that of the source
+    // level (same weights and corners), only the corner indices are shifted.
+    // A corner outside the copy (a list entry that does not belong to its
+    // face) makes the target NaN instead of reading a clamped cell.
+    struct Staged {
+        const void* fA;
+        const void* fB;
+        const float* gA;
+        const float* gB;
+        int nx, ny, nz;
+        int off[3];
+        int64_t plane;
+        int first, count, blocks;
+    };
+    int n_staged;
+    int main_first;
+    Staged st[2];
 };
 
 // The workgroups of a launch are handed out to the 8 XCDs in turn (hardware
@@ -156,6 +179,8 @@ inline ExchArgs exchange_args(const cslbm_level* src, const void* fA, const void
     a.cells = cells;
     a.n_cells = n_cells;
     a.w = (float)w;
+    a.n_staged = 0;
+    a.main_first = 0;
     const double alpha = src->dx / dst->dx;
     const double Ss = shear_rate(src), Sd = shear_rate(dst);
     a.kappa = (float)((1.0 - Sd) / (1.0 - Ss) * Ss / (alpha * Sd));

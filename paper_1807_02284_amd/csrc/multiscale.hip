@@ -14,6 +14,7 @@
 // with the time weight w (section "Temporal alignment and scale mapping").
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <utility>
@@ -82,13 +83,48 @@ __device__ __forceinline__ void map_and_store(const ExchArgs& a, int c, float (&
 template <typename Ts, typename Td, bool kBlend, bool kScalar, bool kNode>
 __global__ void __launch_bounds__(256) k_exchange(const ExchArgs a)
 {
-    const int blk = a.sb.table ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    int blk = a.sb.table ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    // the segment of this block (uniform: selected by the block index)
+    const void* pA = a.fA;
+    const void* pB = a.fB;
+    const float* qA = a.gA;
+    const float* qB = a.gB;
+    int n[3] = {a.snx, a.sny, a.snz};
+    int off[3] = {0, 0, 0};
+    int64_t splane = a.splane;
+    int first = a.main_first, count = a.n_cells - a.main_first;
+    bool staged = false;
+#pragma unroll
+    for (int sgi = 0; sgi < 2; ++sgi) {
+        if (staged || sgi >= a.n_staged) continue;
+        if (blk < a.st[sgi].blocks) {
+            const ExchArgs::Staged& g = a.st[sgi];
+            pA = g.fA;
+            pB = g.fB;
+            qA = g.gA;
+            qB = g.gB;
+            n[0] = g.nx;
+            n[1] = g.ny;
+            n[2] = g.nz;
+            off[0] = g.off[0];
+            off[1] = g.off[1];
+            off[2] = g.off[2];
+            splane = g.plane;
+            first = g.first;
+            count = g.count;
+            staged = true;
+        } else {
+            blk -= a.st[sgi].blocks;
+        }
+    }
     const int k = blk * blockDim.x + threadIdx.x;
-    if (k >= a.n_cells) return;
-    const int c = a.cells[k];
+    if (k >= count) return;
+    const int c = a.cells[first + k];
     int base[3];
     float t[3];
     target_stencil(a, c, base, t);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) base[d] -= off[d];
     if (kNode) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -96,13 +132,13 @@ __global__ void __launch_bounds__(256) k_exchange(const ExchArgs a)
             t[d] = 0.0f;
         }
     }
-    const int n[3] = {a.snx, a.sny, a.snz};
+    const int speriodic = staged ? 0 : a.speriodic;
     int ix[2], iy[2], iz[2];
 #pragma unroll
     for (int o = 0; o < 2; ++o) {
-        ix[o] = wrap_or_clamp(base[0] + o, n[0], a.speriodic & 1);
-        iy[o] = wrap_or_clamp(base[1] + o, n[1], a.speriodic & 2);
-        iz[o] = wrap_or_clamp(base[2] + o, n[2], a.speriodic & 4);
+        ix[o] = wrap_or_clamp(base[0] + o, n[0], speriodic & 1);
+        iy[o] = wrap_or_clamp(base[1] + o, n[1], speriodic & 2);
+        iz[o] = wrap_or_clamp(base[2] + o, n[2], speriodic & 4);
     }
     // A target on a source lattice plane (fraction 0 on that axis) gives the
     // upper corners weight 0: point them at the lower ones so that they hit
@@ -111,8 +147,11 @@ __global__ void __launch_bounds__(256) k_exchange(const ExchArgs a)
     if (t[0] == 0.0f) ix[1] = ix[0];
     if (t[1] == 0.0f) iy[1] = iy[0];
     if (t[2] == 0.0f) iz[1] = iz[0];
-    const Ts* fA = static_cast<const Ts*>(a.fA);
-    const Ts* fB = static_cast<const Ts*>(a.fB);
+    // a staged copy holds the stencils of its face only
+    const bool outside = staged && (base[0] < 0 || base[0] + 1 >= n[0] || base[1] < 0 ||
+                                    base[1] + 1 >= n[1] || base[2] < 0 || base[2] + 1 >= n[2]);
+    const Ts* fA = static_cast<const Ts*>(pA);
+    const Ts* fB = static_cast<const Ts*>(pB);
     const float w = a.w;
     float v[27];
 #pragma unroll
@@ -127,12 +166,14 @@ __global__ void __launch_bounds__(256) k_exchange(const ExchArgs a)
     for (int corner = 0; corner < kCorners; ++corner) {
         const int ox = corner & 1, oy = (corner >> 1) & 1, oz = (corner >> 2) & 1;
         const float wt = corner_weight(t, corner);
-        const int64_t sc = source_cell(a, ox ? ix[1] : ix[0], oy ? iy[1] : iy[0], oz ? iz[1] : iz[0]);
+        const int cxi = ox ? ix[1] : ix[0], cyi = oy ? iy[1] : iy[0], czi = oz ? iz[1] : iz[0];
+        const int64_t sc = staged ? cxi + (int64_t)n[0] * (cyi + (int64_t)n[1] * czi)
+                                  : source_cell(a, cxi, cyi, czi);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const float hA = Io<Ts>::ld(fA + i * a.splane + sc);
+            const float hA = Io<Ts>::ld(fA + i * splane + sc);
             if (kBlend) {
-                const float hB = Io<Ts>::ld(fB + i * a.splane + sc);
+                const float hB = Io<Ts>::ld(fB + i * splane + sc);
                 v[tensor_slot(i)] += wt * ((1.0f - w) * hA + w * hB);
             } else {
                 v[tensor_slot(i)] += wt * hA;
@@ -141,9 +182,9 @@ __global__ void __launch_bounds__(256) k_exchange(const ExchArgs a)
         if (kScalar) {
 #pragma unroll
             for (int i = 0; i < QS; ++i) {
-                const float gA = a.gA[i * a.splane + sc];
+                const float gA = qA[i * splane + sc];
                 if (kBlend) {
-                    const float gB = a.gB[i * a.splane + sc];
+                    const float gB = qB[i * splane + sc];
                     gi[i] += wt * ((1.0f - w) * gA + w * gB);
                 } else {
                     gi[i] += wt * gA;
@@ -151,7 +192,56 @@ __global__ void __launch_bounds__(256) k_exchange(const ExchArgs a)
             }
         }
     }
+    if (outside) v[13] = __builtin_nanf("");
     map_and_store<Td>(a, c, v, gi, kScalar);
+}
+
+// Copy of sub-boxes of a dense level's two time levels (populations and
+// scalar) into the compact staging layout: one thread per (face, plane,
+// cell); cell k of face f's sub-box (x fastest) goes to element
+// plane * S_f + k of that face's time-level blocks.
+struct StageCopy {
+    const void* fA;
+    const void* fB;
+    const float* gA;
+    const float* gB;
+    int64_t P;
+    int pnx, pny;
+    int planes;            // 27, or 34 with the scalar
+    struct Face {
+        int off[3], dim[3];
+        int64_t S, cells, threads;   // threads = planes * cells
+        void* oA;
+        void* oB;
+        float* ogA;
+        float* ogB;
+    } face[2];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_stage(const StageCopy a)
+{
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int f = 0;
+    if (k >= a.face[0].threads) {
+        k -= a.face[0].threads;
+        f = 1;
+        if (k >= a.face[1].threads) return;
+    }
+    const StageCopy::Face& F = a.face[f];
+    const int pl = (int)(k / F.cells);
+    const int64_t e = k - (int64_t)pl * F.cells;
+    const int ix = (int)(e % F.dim[0]), iy = (int)((e / F.dim[0]) % F.dim[1]),
+              iz = (int)(e / ((int64_t)F.dim[0] * F.dim[1]));
+    const int64_t c = (F.off[0] + ix) + (int64_t)a.pnx * ((F.off[1] + iy) + (int64_t)a.pny * (F.off[2] + iz));
+    if (pl < Q) {
+        static_cast<T*>(F.oA)[pl * F.S + e] = static_cast<const T*>(a.fA)[pl * a.P + c];
+        static_cast<T*>(F.oB)[pl * F.S + e] = static_cast<const T*>(a.fB)[pl * a.P + c];
+    } else {
+        const int s = pl - Q;
+        F.ogA[s * F.S + e] = a.gA[s * a.P + c];
+        F.ogB[s * F.S + e] = a.gB[s * a.P + c];
+    }
 }
 
 // Lagrange quadratic in time, element by element over all planes
@@ -202,21 +292,25 @@ static void launch_exchange_kernel(const ExchArgs& a, bool blend, bool scalar, b
 // Every target point of dst is a lattice point of src: the spacing ratio is
 // a whole number and the origins differ by whole source cells.
 
-int launch_exchange(const cslbm_level* src, const void* fA, const void* fB, const float* gA,
-                    const float* gB, double w, const cslbm_level* dst, void* f_out, float* g_out,
-                    const int32_t* cells, int32_t n_cells, hipStream_t stream)
+static int launch_exchange_args(ExchArgs a, const cslbm_level* src, const cslbm_level* dst, double w,
+                                hipStream_t stream)
 {
-    if (n_cells == 0) return CSLBM_OK;
-    ExchArgs a = exchange_args(src, fA, fB, gA, gB, w, dst, f_out, g_out, cells, n_cells);
     const bool scalar = a.gA != nullptr;
     // all the weight on one time level: read only that level
     const bool blend = w > 0.0 && w < 1.0;
     if (!blend && w >= 1.0) {
         a.fA = a.fB;
         a.gA = a.gB;
+        for (int sgi = 0; sgi < a.n_staged; ++sgi) {
+            a.st[sgi].fA = a.st[sgi].fB;
+            a.st[sgi].gA = a.st[sgi].gB;
+        }
     }
     const bool node = nodes_coincide(src, dst);
-    const dim3 grid((n_cells + 255) / 256), block(256);
+    int64_t blocks = (a.n_cells - a.main_first + 255) / 256;
+    for (int sgi = 0; sgi < a.n_staged; ++sgi) blocks += a.st[sgi].blocks;
+    if (blocks == 0) return CSLBM_OK;
+    const dim3 grid((unsigned)blocks), block(256);
     const bool s32 = src->storage == CSLBM_F32, d32 = dst->storage == CSLBM_F32;
     if (s32 && d32)
         launch_exchange_kernel<float, float>(a, blend, scalar, node, grid, block, stream);
@@ -227,6 +321,160 @@ int launch_exchange(const cslbm_level* src, const void* fA, const void* fB, cons
     else
         launch_exchange_kernel<_Float16, _Float16>(a, blend, scalar, node, grid, block, stream);
     return check_launch("k_exchange");
+}
+
+int launch_exchange(const cslbm_level* src, const void* fA, const void* fB, const float* gA,
+                    const float* gB, double w, const cslbm_level* dst, void* f_out, float* g_out,
+                    const int32_t* cells, int32_t n_cells, hipStream_t stream)
+{
+    if (n_cells == 0) return CSLBM_OK;
+    return launch_exchange_args(exchange_args(src, fA, fB, gA, gB, w, dst, f_out, g_out, cells, n_cells),
+                                src, dst, w, stream);
+}
+
+// ---------------------------------------------------------------------------
+// x-face staging of a ghost shell's prior-mapping.  A target on a box face
+// x = const reads 2 cells of each of 4 parent rows per plane: from the
+// parent's x-fastest planes that is one cache line per 8 useful bytes, and
+// neighbouring targets (along y) read different rows.  Copying the parent's
+// few columns around the face into a compact sub-box once per reference
+// step (both time levels) lets those targets read contiguous memory.
+// ---------------------------------------------------------------------------
+struct StageFace {
+    int off[3], dim[3];
+    int64_t S;          // elements per plane (sub-box cells rounded up to 64)
+    int64_t bytes;
+    int64_t popB, gA, gB;   // byte offsets of the sections in the face's block
+};
+
+struct StagePlan {
+    StageFace face[2];
+    int64_t bytes;
+};
+
+static int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
+
+// Sub-boxes of parent P holding the stencils of L's shell planes x = x_lo
+// and x = x_hi (one cell of margin on every side for the rounding of the
+// stencil base); false when staging does not apply.
+static bool stage_plan(const cslbm_level* P, const cslbm_level* L, int x_lo, int x_hi, StagePlan* sp)
+{
+    sp->bytes = 0;
+    if (P->brick_table || L->brick_table) return false;
+    if (x_lo < 0 || x_hi < x_lo || x_hi >= L->nx) return false;
+    const int64_t esz = P->storage == CSLBM_F32 ? 4 : 2;
+    const bool scalar = L->g != nullptr;
+    const int pn[3] = {P->nx, P->ny, P->nz};
+    const int ln[3] = {L->nx, L->ny, L->nz};
+    for (int f = 0; f < 2; ++f) {
+        StageFace& F = sp->face[f];
+        int64_t cells = 1;
+        for (int d = 0; d < 3; ++d) {
+            double qa, qb;
+            if (d == 0) {
+                const int xf = f == 0 ? x_lo : x_hi;
+                qa = qb = (L->origin[0] + xf * L->dx - P->origin[0]) / P->dx;
+            } else {
+                qa = (L->origin[d] - P->origin[d]) / P->dx;
+                qb = (L->origin[d] + (ln[d] - 1) * L->dx - P->origin[d]) / P->dx;
+            }
+            int lo = (int)std::floor(qa) - 1, hi = (int)std::floor(qb) + 2;
+            if (lo < 0 || hi > pn[d] - 1) {
+                if (P->periodic & (1 << d)) return false;   // the stencils wrap
+                lo = std::max(lo, 0);
+                hi = std::min(hi, pn[d] - 1);
+            }
+            if (hi < lo) return false;
+            F.off[d] = lo;
+            F.dim[d] = hi - lo + 1;
+            cells *= F.dim[d];
+        }
+        F.S = (cells + 63) / 64 * 64;
+        const int64_t pop = align256(Q * F.S * esz), gs = scalar ? align256(QS * F.S * 4) : 0;
+        F.popB = pop;
+        F.gA = 2 * pop;
+        F.gB = 2 * pop + gs;
+        F.bytes = 2 * pop + 2 * gs;
+        sp->bytes += F.bytes;
+    }
+    return true;
+}
+
+// copy both faces' sub-boxes of the parent's states A and B into the stage
+// (one launch; one thread per face, plane and cell)
+static int stage_faces(const cslbm_level* P, const StagePlan& sp, const void* A, const void* B,
+                       const float* gA, const float* gB, char* stage, hipStream_t stream)
+{
+    StageCopy c;
+    c.fA = A;
+    c.fB = B;
+    c.gA = gA;
+    c.gB = gB;
+    c.P = P->plane;
+    c.pnx = P->nx;
+    c.pny = P->ny;
+    c.planes = gA ? Q + QS : Q;
+    char* base = stage;
+    int64_t threads = 0;
+    for (int f = 0; f < 2; ++f) {
+        const StageFace& F = sp.face[f];
+        StageCopy::Face& G = c.face[f];
+        for (int d = 0; d < 3; ++d) {
+            G.off[d] = F.off[d];
+            G.dim[d] = F.dim[d];
+        }
+        G.S = F.S;
+        G.cells = (int64_t)F.dim[0] * F.dim[1] * F.dim[2];
+        G.threads = c.planes * G.cells;
+        G.oA = base;
+        G.oB = base + F.popB;
+        G.ogA = gA ? reinterpret_cast<float*>(base + F.gA) : nullptr;
+        G.ogB = gA ? reinterpret_cast<float*>(base + F.gB) : nullptr;
+        threads += G.threads;
+        base += F.bytes;
+    }
+    const dim3 grid((unsigned)((threads + 255) / 256)), block(256);
+    if (P->storage == CSLBM_F32)
+        hipLaunchKernelGGL(k_stage<float>, grid, block, 0, stream, c);
+    else
+        hipLaunchKernelGGL(k_stage<_Float16>, grid, block, 0, stream, c);
+    return check_launch("k_stage");
+}
+
+// Prior-mapping of a shell whose list starts with the n_xlo + n_xhi ghosts
+// of its two planes normal to x: those read the staged copies (one segment
+// per plane), the rest the parent itself, all in one launch.
+static int launch_prior_staged(const cslbm_level* P, const StagePlan& sp, char* stage, const void* A,
+                               const void* B, const float* gA, const float* gB, double w,
+                               const cslbm_level* dst, void* f_out, float* g_out, const int32_t* cells,
+                               int32_t n_xlo, int32_t n_xhi, int32_t n_cells, hipStream_t stream)
+{
+    if (n_cells == 0) return CSLBM_OK;
+    ExchArgs a = exchange_args(P, A, B, gA, gB, w, dst, f_out, g_out, cells, n_cells);
+    const bool scalar = a.gA != nullptr;
+    char* face = stage;
+    int first = 0;
+    a.n_staged = 2;
+    for (int f = 0; f < 2; ++f) {
+        const StageFace& F = sp.face[f];
+        ExchArgs::Staged& g = a.st[f];
+        g.fA = face;
+        g.fB = face + F.popB;
+        g.gA = scalar ? reinterpret_cast<const float*>(face + F.gA) : nullptr;
+        g.gB = scalar ? reinterpret_cast<const float*>(face + F.gB) : nullptr;
+        g.nx = F.dim[0];
+        g.ny = F.dim[1];
+        g.nz = F.dim[2];
+        for (int d = 0; d < 3; ++d) g.off[d] = F.off[d];
+        g.plane = F.S;
+        g.first = first;
+        g.count = f == 0 ? n_xlo : n_xhi;
+        g.blocks = (g.count + 255) / 256;
+        first += g.count;
+        face += F.bytes;
+    }
+    a.main_first = first;
+    return launch_exchange_args(a, P, dst, w, stream);
 }
 
 static int launch_time_interp(const cslbm_level* L, const void* s0, const void* s1, const void* s2,
@@ -334,6 +582,16 @@ int validate_hierarchy(const cslbm_hierarchy* H)
         for (int j = 0; j < ns; ++j)
             if (S[i].n_post[j] < 0 || (S[i].n_post[j] > 0 && !S[i].post_cells[j]))
                 return fail(CSLBM_ERR_ARG, "scale %d: bad post-mapping list for scale %d", i, j);
+        if (S[i].n_ghost_xlo < 0 || S[i].n_ghost_xhi < 0 ||
+            (int64_t)S[i].n_ghost_xlo + S[i].n_ghost_xhi > S[i].n_ghost)
+            return fail(CSLBM_ERR_ARG, "scale %d: x-face ghost counts %d + %d exceed the %d ghosts", i,
+                        S[i].n_ghost_xlo, S[i].n_ghost_xhi, S[i].n_ghost);
+        if (S[i].stage && !far_field(S, i)) {
+            StagePlan sp;
+            if (stage_plan(PL, L, S[i].ghost_xlo, S[i].ghost_xhi, &sp) && S[i].stage_bytes < sp.bytes)
+                return fail(CSLBM_ERR_ARG, "scale %d: stage of %lld bytes, %lld needed", i,
+                            (long long)S[i].stage_bytes, (long long)sp.bytes);
+        }
     }
 
     return CSLBM_OK;
@@ -357,6 +615,19 @@ int cslbm_exchange(const cslbm_level* src, const void* fA, const void* fB, const
     if (g_out && gA && std::fabs(src->p.tau_s - 1.0) < 1e-9)
         return fail(CSLBM_ERR_ARG, "source scalar relaxation time is 1 (singular mapping)");
     return launch_exchange(src, fA, fB, gA, gB, w, dst, f_out, g_out, cells, n_cells, stream);
+}
+
+int64_t cslbm_stage_bytes(const cslbm_level* parent, const cslbm_level* level, int32_t x_lo,
+                          int32_t x_hi)
+{
+    int rc = validate_shape(parent);
+    if (rc) return rc;
+    rc = validate_shape(level);
+    if (rc) return rc;
+    if (!(parent->dx > 0.0) || !(level->dx > 0.0))
+        return fail(CSLBM_ERR_ARG, "scale spacings must be positive");
+    StagePlan sp;
+    return stage_plan(parent, level, x_lo, x_hi, &sp) ? sp.bytes : 0;
 }
 
 int cslbm_time_interp(const cslbm_level* L, const void* s0, const void* s1, const void* s2,
@@ -464,11 +735,27 @@ int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t s
             const int last = node ? l - 1 : l;
             void* R = sc.work_f[1];
             float* gR = sc.work_g[1];
+            // x-face ghosts read a staged copy of the parent's columns around
+            // each face (both time levels, copied once per reference step)
+            StagePlan sp;
+            const int n_xface = sc.n_ghost_xlo + sc.n_ghost_xhi;
+            const bool staged = sc.stage && n_xface > 0 && stage_plan(P, L, sc.ghost_xlo, sc.ghost_xhi, &sp);
+            if (staged) {
+                int rc = stage_faces(P, sp, A[p], B[p], gA[p], gB[p], static_cast<char*>(sc.stage), stream);
+                if (rc) return rc;
+            }
+            auto prior_map = [&](double w, void* out, float* gout) -> int {
+                if (!staged)
+                    return launch_exchange(P, A[p], B[p], gA[p], gB[p], w, L, out, gout, sc.ghost_cells,
+                                           sc.n_ghost, stream);
+                return launch_prior_staged(P, sp, static_cast<char*>(sc.stage), A[p], B[p], gA[p], gB[p],
+                                           w, L, out, gout, sc.ghost_cells, sc.n_ghost_xlo,
+                                           sc.n_ghost_xhi, sc.n_ghost, stream);
+            };
             for (int k = 1; k <= last; ++k) {
                 // prior-mapping of the boundary shell: the parent blended at
                 // the sub-step's start time, or at t_n + dt_0 before the last
-                int rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], prior_weight(k, l, alpha), L,
-                                         cur, gcur, sc.ghost_cells, sc.n_ghost, stream);
+                int rc = prior_map(prior_weight(k, l, alpha), cur, gcur);
                 if (rc) return rc;
                 if (k < l) {
                     const int slot = (k - 1) & 1;
@@ -487,9 +774,7 @@ int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t s
                     if (rc) return rc;
                 }
             }
-            int rc;
-            rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], 1.0, L, R, gR, sc.ghost_cells,
-                                 sc.n_ghost, stream);
+            int rc = prior_map(1.0, R, gR);
             if (rc) return rc;
             A[i] = X0;
             B[i] = R;

@@ -189,7 +189,8 @@ class Hierarchy:
     level's box (for a brick level: SOLID outside the stored bricks); the
     cell lists sent to the library are in each level's storage order."""
 
-    def __init__(self, levels: list[Level], kinds: list[np.ndarray], parents=None):
+    def __init__(self, levels: list[Level], kinds: list[np.ndarray], parents=None, *,
+                 stage_xfaces: bool = True):
         assert len(levels) == len(kinds) and 1 <= len(levels) <= _capi.MAX_SCALES
         self.levels = levels
         self.kinds = [np.asarray(k, np.uint8) for k in kinds]
@@ -204,6 +205,7 @@ class Hierarchy:
         self.parents = list(parents)
         self.work = []
         self.lists = []
+        self.stages = []
         self.post = {}
         far_post = {}
         self.c_scales = (_capi.CslbmScale * n)()
@@ -221,6 +223,25 @@ class Hierarchy:
                 check_prior_stencils(self.kinds[self.parents[i]], (par.nx, par.ny, par.nz),
                                      tuple(par.c.origin), par.c.dx, par.c.periodic,
                                      (lev.nx, lev.ny, lev.nz), tuple(lev.c.origin), lev.c.dx, ghosts)
+                if (stage_xfaces and not self.far[i] and lev.dense_index is None
+                        and par.dense_index is None):
+                    # ghosts on the shell's two planes normal to x first (each
+                    # in (z, y) order): their prior-mapping reads a staged copy
+                    # of the parent's columns around the plane
+                    gx = ghosts % lev.nx
+                    x_lo, x_hi = (int(gx.min()), int(gx.max())) if ghosts.size else (0, 0)
+                    lo = gx == x_lo
+                    hi = (gx == x_hi) & ~lo
+                    ghosts = np.concatenate([ghosts[lo], ghosts[hi], ghosts[~(lo | hi)]])
+                    par._sync_struct()
+                    lev._sync_struct()
+                    nb = int(_capi.load().cslbm_stage_bytes(C.byref(par.c), C.byref(lev.c), x_lo, x_hi))
+                    if nb > 0:
+                        st = torch.empty(nb, dtype=torch.uint8, device=dev)
+                        self.stages.append(st)
+                        sc.n_ghost_xlo, sc.n_ghost_xhi = int(lo.sum()), int(hi.sum())
+                        sc.ghost_xlo, sc.ghost_xhi = x_lo, x_hi
+                        sc.stage, sc.stage_bytes = st.data_ptr(), nb
                 g_t = torch.as_tensor(_storage_list(lev, ghosts), device=dev)
                 self.lists.append(g_t)
                 sc.n_ghost = ghosts.size
@@ -625,7 +646,7 @@ def region_box_fn(region: np.ndarray):
 
 def dynamic_hierarchy(lev0: Level, kinds0: np.ndarray, thresholds, alphas, *, margin: int = 3,
                       dilate: int = 2, nest: int = 2, solid_fn=None, stream=None, previous=None,
-                      bricks: bool = False):
+                      bricks: bool = False, stage_xfaces: bool = True):
     """Scales set by thresholds: scale k covers the bounding box of the cells
     with |curl u| > thresholds[k-1][0] and |u| > thresholds[k-1][1]
     (dilated), kept `margin` cells from the domain faces and `nest` cells
@@ -685,7 +706,7 @@ def dynamic_hierarchy(lev0: Level, kinds0: np.ndarray, thresholds, alphas, *, ma
         lo_lim = [lo[a] + nest for a in range(3)]
         hi_lim = [hi[a] - nest for a in range(3)]
     torch.cuda.synchronize()
-    H = Hierarchy(levels, kinds)
+    H = Hierarchy(levels, kinds, stage_xfaces=stage_xfaces)
     H.object_labels = labels
     return H, boxes
 

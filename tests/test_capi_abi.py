@@ -95,3 +95,26 @@ def test_scalar_relaxation_time_checked(lib):
     L = make_level(g=0x3000, g_next=0x4000, p_tau_s=0.5)
     assert lib.cslbm_step(C.byref(L), 1, None) == _capi.ERR_ARG
     assert "tau_s" in lib.cslbm_last_error().decode()
+
+
+def test_stage_bytes_of_a_padded_box_inside_its_parent(lib):
+    """x-face staging work space: two planes x 2 time levels x (27 float
+    planes + 7 scalar planes) over a sub-box of at most 4 parent columns and
+    the rows the plane's stencils reach; 0 when a plane's stencils leave the
+    parent (here the padding column beyond the shell), negative for a bad
+    level."""
+    P = make_level(periodic=0, flags=0x9000)
+    P.nx, P.ny, P.nz = 512, 256, 256
+    P.plane = lib.cslbm_plane_stride(512, 256, 256)
+    P.dx = 1.0
+    L = make_level(periodic=0, flags=0x9100, g=0x3000, g_next=0x4000)
+    L.nx, L.ny, L.nz = 768, 116, 116          # 759 cells padded to 768 along x
+    L.plane = lib.cslbm_plane_stride(768, 116, 116)
+    L.dx = 1 / 1.5
+    L.origin[0], L.origin[1], L.origin[2] = 3.0, 89.0, 89.0
+    n = lib.cslbm_stage_bytes(C.byref(P), C.byref(L), 0, 758)
+    rows = 80 * 80                            # parent rows 88..167 along y and z
+    per_face = 2 * (27 * 4 + 7 * 4) * 4 * rows
+    assert n == per_face * 2
+    assert lib.cslbm_stage_bytes(C.byref(P), C.byref(L), 0, 767) == 0
+    assert lib.cslbm_stage_bytes(C.byref(P), None, 0, 758) < 0

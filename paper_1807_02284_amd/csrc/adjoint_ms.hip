@@ -907,10 +907,13 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
         // mapping rewrites only the GHOST cells, whose old values never enter
         W.cur[i][0] = Buf{static_cast<float*>(const_cast<void*>(f_in[i])),
                           scalar ? const_cast<float*>(g_in[i]) : nullptr};
+        bool staged = false;
+        rc = prior_stage(sc, P, A[p], B[p], gA[p], gB[p], &staged, stream);
+        if (rc) return rc;
         for (int k = 1; k <= ss.last; ++k) {
             const Buf& cur = W.cur[i][k - 1];
-            rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], prior_weight(k, ss.l, ss.alpha), L,
-                                 cur.f, cur.g, sc.ghost_cells, sc.n_ghost, stream);
+            rc = prior_map(sc, staged, P, A[p], B[p], gA[p], gB[p], prior_weight(k, ss.l, ss.alpha),
+                           cur.f, cur.g, stream);
             if (rc) return rc;
             if (k < ss.l) {
                 const Buf& out = (ss.node && k == ss.last) ? W.R[i] : W.cur[i][k];
@@ -921,8 +924,7 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
             }
             if (rc) return rc;
         }
-        rc = launch_exchange(P, A[p], B[p], gA[p], gB[p], 1.0, L, W.R[i].f, W.R[i].g, sc.ghost_cells,
-                             sc.n_ghost, stream);
+        rc = prior_map(sc, staged, P, A[p], B[p], gA[p], gB[p], 1.0, W.R[i].f, W.R[i].g, stream);
         if (rc) return rc;
         A[i] = W.cur[i][0].f;
         gA[i] = W.cur[i][0].g;

@@ -193,6 +193,17 @@ int launch_exchange(const cslbm_level* src, const void* fA, const void* fB, cons
                     const float* gB, double w, const cslbm_level* dst, void* f_out, float* g_out,
                     const int32_t* cells, int32_t n_cells, hipStream_t stream);
 
+// Prior-mapping of finer scale sc's boundary shell from its parent P
+// (states A at t_n and B at t_n + dt_0, time weight w).  prior_stage copies
+// the parent's columns around the shell's two planes normal to x into
+// sc.stage when the scale has them listed and a stage (sets *staged);
+// prior_map then reads those planes' stencils from the copy, bitwise the
+// same result as reading the parent.  Arguments validated.
+int prior_stage(const cslbm_scale& sc, const cslbm_level* P, const void* A, const void* B,
+                const float* gA, const float* gB, bool* staged, hipStream_t stream);
+int prior_map(const cslbm_scale& sc, bool staged, const cslbm_level* P, const void* A, const void* B,
+              const float* gA, const float* gB, double w, void* out, float* gout, hipStream_t stream);
+
 // Adjoint of one collide-stream step of level L from the input state
 // (fin, gin): lam = dL/d(input) from lam_next = dL/d(output) (likewise mu for
 // the scalar), dtheta accumulated when not null.  Arguments validated.

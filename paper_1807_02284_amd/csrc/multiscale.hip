@@ -477,6 +477,26 @@ static int launch_prior_staged(const cslbm_level* P, const StagePlan& sp, char* 
     return launch_exchange_args(a, P, dst, w, stream);
 }
 
+int prior_stage(const cslbm_scale& sc, const cslbm_level* P, const void* A, const void* B,
+                const float* gA, const float* gB, bool* staged, hipStream_t stream)
+{
+    StagePlan sp;
+    *staged = sc.stage && sc.n_ghost_xlo + sc.n_ghost_xhi > 0 &&
+              stage_plan(P, &sc.level, sc.ghost_xlo, sc.ghost_xhi, &sp);
+    return *staged ? stage_faces(P, sp, A, B, gA, gB, static_cast<char*>(sc.stage), stream) : CSLBM_OK;
+}
+
+int prior_map(const cslbm_scale& sc, bool staged, const cslbm_level* P, const void* A, const void* B,
+              const float* gA, const float* gB, double w, void* out, float* gout, hipStream_t stream)
+{
+    const cslbm_level* L = &sc.level;
+    StagePlan sp;
+    if (!staged || !stage_plan(P, L, sc.ghost_xlo, sc.ghost_xhi, &sp))
+        return launch_exchange(P, A, B, gA, gB, w, L, out, gout, sc.ghost_cells, sc.n_ghost, stream);
+    return launch_prior_staged(P, sp, static_cast<char*>(sc.stage), A, B, gA, gB, w, L, out, gout,
+                               sc.ghost_cells, sc.n_ghost_xlo, sc.n_ghost_xhi, sc.n_ghost, stream);
+}
+
 static int launch_time_interp(const cslbm_level* L, const void* s0, const void* s1, const void* s2,
                               const float* g0, const float* g1, const float* g2, const double t[3],
                               double te, void* out, float* g_out, hipStream_t stream)
@@ -737,25 +757,16 @@ int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t s
             float* gR = sc.work_g[1];
             // x-face ghosts read a staged copy of the parent's columns around
             // each face (both time levels, copied once per reference step)
-            StagePlan sp;
-            const int n_xface = sc.n_ghost_xlo + sc.n_ghost_xhi;
-            const bool staged = sc.stage && n_xface > 0 && stage_plan(P, L, sc.ghost_xlo, sc.ghost_xhi, &sp);
-            if (staged) {
-                int rc = stage_faces(P, sp, A[p], B[p], gA[p], gB[p], static_cast<char*>(sc.stage), stream);
+            bool staged = false;
+            {
+                int rc = prior_stage(sc, P, A[p], B[p], gA[p], gB[p], &staged, stream);
                 if (rc) return rc;
             }
-            auto prior_map = [&](double w, void* out, float* gout) -> int {
-                if (!staged)
-                    return launch_exchange(P, A[p], B[p], gA[p], gB[p], w, L, out, gout, sc.ghost_cells,
-                                           sc.n_ghost, stream);
-                return launch_prior_staged(P, sp, static_cast<char*>(sc.stage), A[p], B[p], gA[p], gB[p],
-                                           w, L, out, gout, sc.ghost_cells, sc.n_ghost_xlo,
-                                           sc.n_ghost_xhi, sc.n_ghost, stream);
-            };
             for (int k = 1; k <= last; ++k) {
                 // prior-mapping of the boundary shell: the parent blended at
                 // the sub-step's start time, or at t_n + dt_0 before the last
-                int rc = prior_map(prior_weight(k, l, alpha), cur, gcur);
+                int rc = prior_map(sc, staged, P, A[p], B[p], gA[p], gB[p], prior_weight(k, l, alpha),
+                                   cur, gcur, stream);
                 if (rc) return rc;
                 if (k < l) {
                     const int slot = (k - 1) & 1;
@@ -774,7 +785,7 @@ int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t s
                     if (rc) return rc;
                 }
             }
-            int rc = prior_map(1.0, R, gR);
+            int rc = prior_map(sc, staged, P, A[p], B[p], gA[p], gB[p], 1.0, R, gR, stream);
             if (rc) return rc;
             A[i] = X0;
             B[i] = R;

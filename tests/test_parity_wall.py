@@ -109,3 +109,27 @@ def test_wall_node_off_a_flat_wall_is_flagged_nonfinite_and_adjoint_rejects_wall
     with pytest.raises(_capi.CslbmError):
         z0 = torch.zeros(27 * lev.plane, device="cuda")
         lev.adjoint_step(lev.f, None, z0, None, torch.zeros_like(z0), None, None)
+
+
+def test_wall_nodes_with_binary16_storage_within_rounding_bound():
+    """Binary16 storage of f - w with wall nodes: one step against the oracle
+    started from the same stored values, within the rounding of the output
+    to binary16 (half an ulp of |h|, or the subnormal spacing) plus FP32."""
+    from paper_1807_02284_amd.level import F16S
+    nx, ny, nz = 40, 9, 8
+    n = nx * ny * nz
+    p = Params(nu=0.01, g_max=0.05)
+    kinds = wall_kinds(nx, ny, nz)
+    force = inputs.smooth_random_field(nx, ny, nz, 2e-4, 44)
+    rho, u = start_fields(nx, ny, nz, 8, u_amp=0.05)
+    dom = odomain(nx, ny, nz, periodic=3, flags=kinds, theta=force)
+    feq, _ = oracle.init(dom, rho, u)
+    W = oracle.weights()
+    h16 = (feq - W[:, None] + 2e-4 * inputs.perturbation((27, n), 45)).astype(np.float16)
+    lev = Level(nx, ny, nz, p, storage=F16S, periodic=3, flags=kinds, force=force)
+    lev.set_populations(torch.as_tensor(h16.astype(np.float32)), shifted=True)
+    lev.step(1)
+    f1, _ = oracle.step(dom, oparams(p), h16.astype(np.float64) + W[:, None])
+    got, _ = gpu_f64(lev)
+    bound = np.abs(f1 - W[:, None]) * 2.0 ** -11 + 2.0 ** -25 + 2e-7 * np.abs(f1)
+    assert np.all(np.abs(got - f1) <= bound)

@@ -61,23 +61,22 @@ def measured_traffic(storage: str, n: int):
 
 
 def timed_windows(enqueue, reps: int = REPS):
-    """Durations (ms) of `reps` windows of GPU work, each bracketed by HIP
-    events on the stream the library launches on (torch's current stream)
-    and by a device synchronisation on both sides; `enqueue()` enqueues one
-    window."""
+    """Durations (ms) of `reps` consecutive windows of GPU work on the stream
+    the library launches on (torch's current stream): a device
+    synchronisation, an event, then per window `enqueue()` (one window of
+    work) followed by an event, and a synchronisation at the end.  The
+    windows run back to back, so none but the first starts from an idle
+    GPU; the median over them is reported."""
     import torch
     stream = torch.cuda.current_stream()
-    out = []
-    for _ in range(reps):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        a.record(stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for r in range(reps):
         enqueue()
-        b.record(stream)
-        torch.cuda.synchronize()
-        out.append(a.elapsed_time(b))
-    return out
+        ev[r + 1].record(stream)
+    torch.cuda.synchronize()
+    return [ev[r].elapsed_time(ev[r + 1]) for r in range(reps)]
 
 
 def per_unit(windows, units: int):

@@ -420,3 +420,66 @@ def test_multiscale_adjoint_scope_is_checked():
     H, _, _ = build_pair(specs, 21)
     with pytest.raises(_capi.CslbmError):
         H.adjoint_workspace_bytes()
+
+
+def test_multiscale_adjoint_over_the_fp64_trajectory_with_the_adaptive_factor():
+    """Three scales at nu0 = 2e-3 (S = 1.976 on the reference scale) with the
+    adaptive factor on, four reference steps.  The adjoint of each reference
+    step is evaluated at the oracle's FP64 state at its start (rounded to
+    FP32), so the chained adjoint is compared with central differences of
+    the FP64 oracle without the FP32 trajectory's drift in the direction of
+    a small non-equilibrium stress (which sets the adaptive factor's
+    derivative)."""
+    specs = chain_specs(2e-3, True)
+    H, levs, oscs = build_pair(specs, 20)
+    n_ref = 4
+    f0 = [gpu_pop(lev) for lev in levs]
+    g0 = [gpu_g(lev) for lev in levs]
+
+    def oracle_from(df, dg):
+        sc = [sp.oscale() for sp in specs]
+        for s, a, b, da, db in zip(sc, f0, g0, df, dg):
+            s.f, s.g = a + da, b + db
+        ml.prepare(sc)
+        return sc
+
+    sc = oracle_from([0 * f for f in f0], [0 * g for g in g0])
+    traj = [([s.f.copy() for s in sc], [s.g.copy() for s in sc])]
+    for _ in range(n_ref):
+        ml.multiscale_step(sc, 1)
+        traj.append(([s.f.copy() for s in sc], [s.g.copy() for s in sc]))
+
+    def planes(lev, x, rows):
+        t = torch.zeros(rows, lev.plane, dtype=torch.float32, device="cuda")
+        t[:, : lev.n] = torch.as_tensor(np.asarray(x).reshape(rows, lev.n), dtype=torch.float32,
+                                        device="cuda")
+        return t.reshape(-1)
+
+    rng = np.random.default_rng(7)
+    Tf = [rng.standard_normal((27, lev.n)) for lev in levs]
+    Tg = [rng.standard_normal((7, lev.n)) for lev in levs]
+    lam = [planes(lev, t, 27) for lev, t in zip(levs, Tf)]
+    mu = [planes(lev, t, 7) for lev, t in zip(levs, Tg)]
+    ws = torch.empty(H.adjoint_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    for n in reversed(range(n_ref)):
+        fs, gs = traj[n]
+        f_in = [planes(lev, f - W[:, None], 27) for lev, f in zip(levs, fs)]
+        g_in = [planes(lev, g, 7) for lev, g in zip(levs, gs)]
+        H.adjoint_step(f_in, g_in, lam, mu, ws)
+    torch.cuda.synchronize()
+    gf = [l.reshape(27, lev.plane)[:, : lev.n].double().cpu().numpy() for l, lev in zip(lam, levs)]
+    gg = [m.reshape(7, lev.plane)[:, : lev.n].double().cpu().numpy() for m, lev in zip(mu, levs)]
+    for seed in (41, 42, 43):
+        r = np.random.default_rng(seed)
+        df = [1e-7 * r.standard_normal(f.shape) for f in f0]
+        dg = [1e-7 * r.standard_normal(g.shape) for g in g0]
+        sp = oracle_from(df, dg)
+        ml.multiscale_step(sp, n_ref)
+        sm = oracle_from([-d for d in df], [-d for d in dg])
+        ml.multiscale_step(sm, n_ref)
+        fd = (_loss([s.f for s in sp], [s.g for s in sp], Tf, Tg) -
+              _loss([s.f for s in sm], [s.g for s in sm], Tf, Tg)) / 2.0
+        ad = sum(float(np.sum(a * d)) for a, d in zip(gf, df)) + \
+            sum(float(np.sum(a * d)) for a, d in zip(gg, dg))
+        print(f"direction {seed}: adjoint {ad:.9e}, central difference {fd:.9e}", flush=True)
+        assert ad == pytest.approx(fd, rel=2e-4), (seed, ad, fd)

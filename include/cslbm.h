@@ -363,6 +363,26 @@ typedef struct cslbm_scale {
                                            per reference step, instead of one
                                            cache line per parent row */
     int64_t stage_bytes;
+    const int32_t* post_tiles[CSLBM_MAX_SCALES];  /* device, or NULL: post_cells[j]
+                                           grouped into n_post_tiles[j] runs of
+                                           consecutive entries, run t from entry
+                                           post_tiles[j][t] to post_tiles[j][t+1]
+                                           - 1 (n_post_tiles[j] + 1 ascending
+                                           offsets, 0 first, n_post[j] last, at
+                                           most 256 entries a run; a run outside
+                                           these bounds is clipped to them).  When
+                                           both scales are dense boxes, scale i
+                                           has no periodic axis and scale j's
+                                           cells are not all lattice points of
+                                           scale i, each run is mapped by one
+                                           workgroup that reads the scale-i cells
+                                           its stencils reach once into LDS; with
+                                           runs that are tiles of neighbouring
+                                           cells (a few rows of one plane) that
+                                           reads far fewer bytes than gathering
+                                           every target's 8 corners.  The result
+                                           is the same bit for bit. */
+    int32_t n_post_tiles[CSLBM_MAX_SCALES];
 } cslbm_scale;
 
 typedef struct cslbm_hierarchy {

@@ -88,6 +88,8 @@ class CslbmScale(C.Structure):
         ("ghost_xhi", C.c_int32),
         ("stage", _vp),
         ("stage_bytes", C.c_int64),
+        ("post_tiles", _vp * MAX_SCALES),
+        ("n_post_tiles", C.c_int32 * MAX_SCALES),
     ]
 
 

@@ -24,6 +24,7 @@
 #include "exchange.hpp"
 #include "internal.hpp"
 #include "lattice.hpp"
+#include "tile.hpp"
 
 namespace cslbm {
 
@@ -573,6 +574,72 @@ __global__ void __launch_bounds__(256) k_zero(float* p, int64_t n)
     if (i < n) p[i] = 0.0f;
 }
 
+// Passes A1 and A2 in one for a post-mapping list in tile runs (tile.hpp):
+// the run's source box is staged through LDS, every target's interpolated
+// state stays in registers, the map's vector-Jacobian product follows, and
+// only its result is written to column k.  The index map and corner flags
+// are set as pass A1 sets them, and a target outside the gather is
+// scattered with atomics as pass A2 scatters it, so the source pass reads
+// the same columns bit for bit.  e.fA / e.gA hold the time level that
+// carries the weight (no blending).
+template <bool kScalar>
+__global__ void __launch_bounds__(256) k_exadj_tiled(const ExchAdjArgs a, const GatherWs g,
+                                                     const int32_t* runs)
+{
+    __shared__ TileLds lds;
+    const ExchArgs& e = a.e;
+    TileTarget T;
+    float v[27], gi[QS];
+    if (!tile_interp<float, kScalar>(e, runs, lds, T, v, gi)) return;
+    if (!T.active) return;
+    const int c = T.c;
+    float lam[27], mu[QS] = {0, 0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < Q; ++i) {
+        lam[tensor_slot(i)] = a.lam_d[i * e.dplane + c];
+        a.lam_d[i * e.dplane + c] = 0.0f;
+    }
+    if (kScalar)
+        for (int i = 0; i < QS; ++i) {
+            mu[i] = a.mu_d[i * e.dplane + c];
+            a.mu_d[i * e.dplane + c] = 0.0f;
+        }
+    float vb[27], gb[QS];
+    exchange_map_adjoint<kScalar>(v, gi, e.kappa, e.kappa_s, lam, mu, vb, gb);
+    int ix[2], iy[2], iz[2];
+    float t[3];
+    const bool interior = target_corners<false>(e, c, ix, iy, iz, t);
+    if (interior) {
+        const int64_t n_t = e.n_cells;
+        const int k = T.k;
+        for (int i = 0; i < Q; ++i) g.vb[i * n_t + k] = vb[tensor_slot(i)];
+        if (kScalar)
+            for (int i = 0; i < QS; ++i) g.vb[(Q + i) * n_t + k] = gb[i];
+        g.map[c] = k;
+#pragma unroll
+        for (int corner = 0; corner < 8; ++corner)
+            g.touched[ix[corner & 1] + (int64_t)e.snx * (iy[(corner >> 1) & 1] +
+                                                         (int64_t)e.sny * iz[(corner >> 2) & 1])] = 1;
+        return;
+    }
+    for (int corner = 0; corner < 8; ++corner) {
+        const float wt = corner_weight(t, corner);
+        if (wt == 0.0f) continue;
+        const int64_t sc = ix[corner & 1] + (int64_t)e.snx * (iy[(corner >> 1) & 1] +
+                                                              (int64_t)e.sny * iz[(corner >> 2) & 1]);
+        for (int i = 0; i < Q; ++i) {
+            const float b = wt * vb[tensor_slot(i)];
+            if (a.ca != 0.0f) atomicAdd(a.lam_a + i * e.splane + sc, a.ca * b);
+            if (a.cb != 0.0f) atomicAdd(a.lam_b + i * e.splane + sc, a.cb * b);
+        }
+        if (kScalar)
+            for (int i = 0; i < QS; ++i) {
+                const float b = wt * gb[i];
+                if (a.ca != 0.0f) atomicAdd(a.mu_a + i * e.splane + sc, a.ca * b);
+                if (a.cb != 0.0f) atomicAdd(a.mu_b + i * e.splane + sc, a.cb * b);
+            }
+    }
+}
+
 static unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 // The source indices an interior target's stencil can reach: the targets lie
@@ -601,7 +668,8 @@ static int launch_exchange_adjoint(const cslbm_level* src, const void* fA, const
                                    const cslbm_level* dst, float* lam_d, float* mu_d,
                                    float* lam_a, float* lam_b, float* mu_a, float* mu_b,
                                    const int32_t* cells, int32_t n_cells, const GatherWs* gw,
-                                   hipStream_t stream)
+                                   hipStream_t stream, const int32_t* runs = nullptr,
+                                   int32_t n_runs = 0)
 {
     if (n_cells == 0) return CSLBM_OK;
     const bool scalar = gA != nullptr && mu_d != nullptr;
@@ -626,6 +694,25 @@ static int launch_exchange_adjoint(const cslbm_level* src, const void* fA, const
         const int64_t n_box = (int64_t)sb.nx * sb.ny * sb.nz;
         const dim3 sgrid(grid_for(n_box > 0 ? n_box : 1));
         const bool blend = a.ca != 0.0f && a.cb != 0.0f;
+        if (runs && n_runs > 0 && !blend && !node && a.e.speriodic == 0) {
+            // passes A1 and A2 fused, one workgroup per run
+            ExchAdjArgs t = a;
+            if (a.ca == 0.0f) {
+                t.e.fA = t.e.fB;
+                t.e.gA = t.e.gB;
+            }
+            const dim3 rgrid((unsigned)n_runs);
+            if (scalar)
+                hipLaunchKernelGGL(k_exadj_tiled<true>, rgrid, block, 0, stream, t, g, runs);
+            else
+                hipLaunchKernelGGL(k_exadj_tiled<false>, rgrid, block, 0, stream, t, g, runs);
+            if (scalar)
+                hipLaunchKernelGGL((k_exadj_sources<true, false>), sgrid, block, 0, stream, a, g, sb);
+            else
+                hipLaunchKernelGGL((k_exadj_sources<false, false>), sgrid, block, 0, stream, a, g, sb);
+            hipLaunchKernelGGL(k_exadj_reset, grid, block, 0, stream, g.map, cells, n_cells);
+            return check_launch("k_exchange_adjoint (tiled gather)");
+        }
 #define CSLBM_GATHER(S_, N_)                                                                   \
         if (blend)                                                                             \
             hipLaunchKernelGGL((k_exadj_interp<S_, N_, true>), grid, block, 0, stream, a, g);  \
@@ -963,7 +1050,8 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
         for (int j = i - 1; j >= 0; --j) {
             rc = launch_exchange_adjoint(L, W.R[i].f, W.R[i].f, W.R[i].g, W.R[i].g, 0.0, &S[j].level,
                                          lam[j], scalar ? mu[j] : nullptr, lamR, nullptr, muR,
-                                         nullptr, sc.post_cells[j], sc.n_post[j], gw, stream);
+                                         nullptr, sc.post_cells[j], sc.n_post[j], gw, stream,
+                                         sc.post_tiles[j], sc.n_post_tiles[j]);
             if (rc) return rc;
         }
         // ghost shell of the interpolated state, mapped at weight 1

@@ -189,9 +189,13 @@ inline ExchArgs exchange_args(const cslbm_level* src, const void* fA, const void
 }
 
 // One exchange launch (validated arguments); defined with the kernels.
+// With runs (n_runs + 1 offsets grouping the list into runs of at most 256
+// entries), an exchange from a dense source into a dense destination that
+// the tiled kernel handles maps one run per workgroup through LDS.
 int launch_exchange(const cslbm_level* src, const void* fA, const void* fB, const float* gA,
                     const float* gB, double w, const cslbm_level* dst, void* f_out, float* g_out,
-                    const int32_t* cells, int32_t n_cells, hipStream_t stream);
+                    const int32_t* cells, int32_t n_cells, hipStream_t stream,
+                    const int32_t* runs = nullptr, int32_t n_runs = 0);
 
 // Prior-mapping of finer scale sc's boundary shell from its parent P
 // (states A at t_n and B at t_n + dt_0, time weight w).  prior_stage copies

@@ -24,6 +24,7 @@
 #include "exchange.hpp"
 #include "internal.hpp"
 #include "lattice.hpp"
+#include "tile.hpp"
 
 namespace cslbm {
 
@@ -196,6 +197,20 @@ __global__ void __launch_bounds__(256) k_exchange(const ExchArgs a)
     map_and_store<Td>(a, c, v, gi, kScalar);
 }
 
+// Tiled post-mapping (tile.hpp): one workgroup maps one run of the list.
+// Lanes past the run's end repeat its first entry: they compute the same
+// bits as lane 0 and store them to the same cell.
+template <typename Ts, typename Td, bool kScalar>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_exchange_tiled(const ExchArgs a, const int32_t* runs)
+{
+    __shared__ TileLds lds;
+    TileTarget T;
+    float v[27], gi[QS];
+    if (!tile_interp<Ts, kScalar>(a, runs, lds, T, v, gi)) return;
+    map_and_store<Td>(a, T.c, v, gi, kScalar);
+}
+
 // Copy of sub-boxes of a dense level's two time levels (populations and
 // scalar) into the compact staging layout: one thread per (face, plane,
 // cell); cell k of face f's sub-box (x fastest) goes to element
@@ -323,13 +338,40 @@ static int launch_exchange_args(ExchArgs a, const cslbm_level* src, const cslbm_
     return check_launch("k_exchange");
 }
 
+template <typename Ts, typename Td>
+static void launch_tiled_kernel(const ExchArgs& a, const int32_t* runs, int32_t n_runs, hipStream_t st)
+{
+    const dim3 grid((unsigned)n_runs), block(256);
+    if (a.gA)
+        hipLaunchKernelGGL((k_exchange_tiled<Ts, Td, true>), grid, block, 0, st, a, runs);
+    else
+        hipLaunchKernelGGL((k_exchange_tiled<Ts, Td, false>), grid, block, 0, st, a, runs);
+}
+
 int launch_exchange(const cslbm_level* src, const void* fA, const void* fB, const float* gA,
                     const float* gB, double w, const cslbm_level* dst, void* f_out, float* g_out,
-                    const int32_t* cells, int32_t n_cells, hipStream_t stream)
+                    const int32_t* cells, int32_t n_cells, hipStream_t stream, const int32_t* runs,
+                    int32_t n_runs)
 {
     if (n_cells == 0) return CSLBM_OK;
-    return launch_exchange_args(exchange_args(src, fA, fB, gA, gB, w, dst, f_out, g_out, cells, n_cells),
-                                src, dst, w, stream);
+    ExchArgs a = exchange_args(src, fA, fB, gA, gB, w, dst, f_out, g_out, cells, n_cells);
+    const bool tiled = runs && n_runs > 0 && !(w > 0.0 && w < 1.0) && !a.sb.table && !a.db.table &&
+                       a.speriodic == 0 && !nodes_coincide(src, dst);
+    if (!tiled) return launch_exchange_args(a, src, dst, w, stream);
+    if (w >= 1.0) {
+        a.fA = a.fB;
+        a.gA = a.gB;
+    }
+    const bool s32 = src->storage == CSLBM_F32, d32 = dst->storage == CSLBM_F32;
+    if (s32 && d32)
+        launch_tiled_kernel<float, float>(a, runs, n_runs, stream);
+    else if (s32)
+        launch_tiled_kernel<float, _Float16>(a, runs, n_runs, stream);
+    else if (d32)
+        launch_tiled_kernel<_Float16, float>(a, runs, n_runs, stream);
+    else
+        launch_tiled_kernel<_Float16, _Float16>(a, runs, n_runs, stream);
+    return check_launch("k_exchange_tiled");
 }
 
 // ---------------------------------------------------------------------------
@@ -599,9 +641,14 @@ int validate_hierarchy(const cslbm_hierarchy* H)
             return fail(CSLBM_ERR_ARG, "scale %d: two scalar work buffers are required", i);
         if (S[i].n_ghost < 0 || (S[i].n_ghost > 0 && !S[i].ghost_cells))
             return fail(CSLBM_ERR_ARG, "scale %d: bad ghost list", i);
-        for (int j = 0; j < ns; ++j)
+        for (int j = 0; j < ns; ++j) {
             if (S[i].n_post[j] < 0 || (S[i].n_post[j] > 0 && !S[i].post_cells[j]))
                 return fail(CSLBM_ERR_ARG, "scale %d: bad post-mapping list for scale %d", i, j);
+            if (S[i].n_post_tiles[j] < 0 || S[i].n_post_tiles[j] > S[i].n_post[j] ||
+                (S[i].n_post_tiles[j] > 0 && !S[i].post_tiles[j]))
+                return fail(CSLBM_ERR_ARG, "scale %d: bad run offsets of the post-mapping list for scale %d",
+                            i, j);
+        }
         if (S[i].n_ghost_xlo < 0 || S[i].n_ghost_xhi < 0 ||
             (int64_t)S[i].n_ghost_xlo + S[i].n_ghost_xhi > S[i].n_ghost)
             return fail(CSLBM_ERR_ARG, "scale %d: x-face ghost counts %d + %d exceed the %d ghosts", i,
@@ -796,7 +843,8 @@ int cslbm_multiscale_step(cslbm_hierarchy* H, int32_t n_ref_steps, hipStream_t s
             for (int j = 0; j < ns; ++j) {
                 if (j == i || sc.n_post[j] == 0) continue;
                 rc = launch_exchange(L, R, R, gR, gR, 0.0, &S[j].level, B[j], gB[j],
-                                     sc.post_cells[j], sc.n_post[j], stream);
+                                     sc.post_cells[j], sc.n_post[j], stream, sc.post_tiles[j],
+                                     sc.n_post_tiles[j]);
                 if (rc) return rc;
             }
         }

@@ -1,0 +1,185 @@
+// tile.hpp -- trilinear gather of one run of exchange targets through LDS
+// (section "Spatial scale mapping"), shared by the tiled post-mapping and
+// its adjoint.
+//
+// Dense source and destination, no periodic source axis, targets off the
+// source lattice points.  One workgroup takes one run of the target list
+// (the host groups neighbouring cells of the destination into runs of at
+// most 256: a tile of a few rows).  The source cells the run's stencils
+// reach form a small box (a 32 x 8 x 1 tile at spacing ratio 4/3 reaches at
+// most 44 x 12 x 2 of them); the workgroup copies that box into LDS a few
+// population planes at a time with row-wise coalesced loads, and each
+// target then takes its 8 corners from LDS.  Gathered from global memory
+// instead, every source line is requested by the 2 x-corners of each of the
+// (about 1.5 x 1.5) target rows that reach it and each time it is touched
+// partially.  Corner order and arithmetic are those of the direct gather,
+// so the interpolated states are bitwise the same.  A run whose box exceeds
+// the buffer is gathered directly.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "exchange.hpp"
+#include "internal.hpp"
+#include "lattice.hpp"
+
+namespace cslbm {
+
+constexpr int kTileCap = 1280;                // floats per plane buffer
+constexpr int kTileLoads = kTileCap / 256;    // buffer elements per thread
+constexpr int kTilePlanes = 4;                // planes staged per barrier round trip
+
+struct TileLds {
+    float buf[kTilePlanes * kTileCap];
+    int box[6];
+};
+
+// One target of a run: its cell, list index, stencil base and fractions,
+// and its corner indices along each axis (the upper one equal to the lower
+// where the fraction is 0).  Lanes past the run's end take its first entry.
+struct TileTarget {
+    int c, k;
+    bool active;
+    int base[3], lo[3], hi[3];
+    float t[3];
+};
+
+// Interpolated state of this thread's target (v in tensor order, gi the
+// scalar) from the time level a.fA / a.gA.  Returns false, for every thread
+// of the workgroup, when the run is empty.  Every thread fills its
+// kTileLoads buffer slots without a branch (past the box it reloads the
+// box's last cell): predicated fills made the compiler version the unrolled
+// plane loop.  Each plane's corner sum is pinned where it is computed (an
+// empty asm reads it): a caller whose stores are conditional otherwise had
+// the sums sunk past the barriers, with all 8 x 34 corner values live.
+template <typename Ts, bool kScalar>
+__device__ __forceinline__ bool tile_interp(const ExchArgs& a, const int32_t* runs, TileLds& L,
+                                            TileTarget& T, float (&v)[27], float (&gi)[QS])
+{
+    // runs in tile order: every XCD walks one contiguous range of them, so
+    // the source planes that neighbouring runs share meet in one L2
+    const int r = xcd_block(blockIdx.x, gridDim.x);
+    const int start = max(runs[r], 0), end = min(runs[r + 1], a.n_cells);
+    const int count = min(end - start, 256);
+    if (count <= 0) return false;   // uniform over the workgroup
+    const int tid = threadIdx.x;
+    T.active = tid < count;
+    T.k = start + (T.active ? tid : 0);
+    T.c = a.cells[T.k];
+    target_stencil(a, T.c, T.base, T.t);
+    const int n[3] = {a.snx, a.sny, a.snz};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        T.lo[d] = wrap_or_clamp(T.base[d], n[d], false);
+        T.hi[d] = T.t[d] == 0.0f ? T.lo[d] : wrap_or_clamp(T.base[d] + 1, n[d], false);
+    }
+    // the run's source box: block-wide min of lo and max of hi
+    if (tid < 6) L.box[tid] = tid < 3 ? INT_MAX : INT_MIN;
+    __syncthreads();
+    int m[6] = {T.lo[0], T.lo[1], T.lo[2], T.hi[0], T.hi[1], T.hi[2]};
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1)
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            const int o = __shfl_xor(m[d], s);
+            m[d] = d < 3 ? min(m[d], o) : max(m[d], o);
+        }
+    if ((tid & 63) == 0) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            atomicMin(&L.box[d], m[d]);
+            atomicMax(&L.box[d + 3], m[d + 3]);
+        }
+    }
+    __syncthreads();
+    const int x0 = L.box[0], y0 = L.box[1], z0 = L.box[2];
+    const int bx = L.box[3] - x0 + 1, by = L.box[4] - y0 + 1, bz = L.box[5] - z0 + 1;
+    const int V = bx * by * bz;
+    const Ts* fA = static_cast<const Ts*>(a.fA);
+    const float* qA = a.gA;
+    const int64_t P = a.splane;
+#pragma unroll
+    for (int q = 0; q < 27; ++q) v[q] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < QS; ++i) gi[i] = 0.0f;
+    if (V > kTileCap) {   // uniform: direct gather
+#pragma unroll 1   // one corner at a time: this rare path must not raise the register count
+        for (int corner = 0; corner < 8; ++corner) {
+            const float wt = corner_weight(T.t, corner);
+            const int cx = corner & 1 ? T.hi[0] : T.lo[0], cy = corner & 2 ? T.hi[1] : T.lo[1];
+            const int cz = corner & 4 ? T.hi[2] : T.lo[2];
+            const int64_t sc = cx + (int64_t)n[0] * (cy + (int64_t)n[1] * cz);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) v[tensor_slot(i)] += wt * Io<Ts>::ld(fA + i * P + sc);
+            if (kScalar)
+#pragma unroll
+                for (int i = 0; i < QS; ++i) gi[i] += wt * qA[i * P + sc];
+        }
+        return true;
+    }
+    // source offsets of this thread's box elements (the same in every plane)
+    const int64_t origin = x0 + (int64_t)n[0] * (y0 + (int64_t)n[1] * z0);
+    int eoff[kTileLoads];
+#pragma unroll
+    for (int k = 0; k < kTileLoads; ++k) {
+        const int e = min(tid + 256 * k, V - 1);
+        const int ex = e % bx, ey = (e / bx) % by, ez = e / (bx * by);
+        eoff[k] = ex + n[0] * (ey + n[1] * ez);
+    }
+    int cl[8];
+    float wt[8];
+#pragma unroll
+    for (int corner = 0; corner < 8; ++corner) {
+        const int cx = corner & 1 ? T.hi[0] : T.lo[0], cy = corner & 2 ? T.hi[1] : T.lo[1];
+        const int cz = corner & 4 ? T.hi[2] : T.lo[2];
+        cl[corner] = (cx - x0) + bx * ((cy - y0) + by * (cz - z0));
+        wt[corner] = corner_weight(T.t, corner);
+    }
+    // kTilePlanes planes per phase: one barrier round trip moves that many
+    // planes, and the next phase's loads are in flight while this phase is
+    // summed from LDS
+    constexpr int NP = kScalar ? Q + QS : Q;
+    constexpr int NG = (NP + kTilePlanes - 1) / kTilePlanes;
+    float pre[kTilePlanes][kTileLoads];
+    auto fetch = [&](int grp) {
+#pragma unroll
+        for (int p = 0; p < kTilePlanes; ++p) {
+            const int i = grp * kTilePlanes + p;
+            if (i < NP)
+#pragma unroll
+                for (int k = 0; k < kTileLoads; ++k)
+                    pre[p][k] = i < Q ? Io<Ts>::ld(fA + i * P + origin + eoff[k])
+                                      : qA[(i - Q) * P + origin + eoff[k]];
+        }
+    };
+    fetch(0);
+#pragma unroll
+    for (int grp = 0; grp < NG; ++grp) {
+        if (grp) __syncthreads();   // every thread has summed the previous phase
+#pragma unroll
+        for (int p = 0; p < kTilePlanes; ++p)
+            if (grp * kTilePlanes + p < NP)
+#pragma unroll
+                for (int k = 0; k < kTileLoads; ++k) L.buf[p * kTileCap + tid + 256 * k] = pre[p][k];
+        __syncthreads();
+        if (grp + 1 < NG) fetch(grp + 1);
+#pragma unroll
+        for (int p = 0; p < kTilePlanes; ++p) {
+            const int i = grp * kTilePlanes + p;
+            if (i >= NP) continue;
+            float s = 0.0f;
+#pragma unroll
+            for (int corner = 0; corner < 8; ++corner) s += wt[corner] * L.buf[p * kTileCap + cl[corner]];
+            asm volatile("" : : "v"(s));
+            if (i < Q)
+                v[tensor_slot(i)] = s;
+            else
+                gi[i - Q] = s;
+        }
+    }
+    return true;
+}
+
+}  // namespace cslbm

@@ -168,6 +168,51 @@ def drop_overwritten_posts(post: dict, n: int) -> dict:
     return out
 
 
+POST_RUN = 256          # entries of a run: one workgroup of the tiled post-mapping
+POST_TILE_BUFFER = 1280  # source cells of a run's box that fit in the kernel's LDS buffer
+POST_TILE_MIN_FILL = 128  # mean entries a tile below which the direct gather is used: a
+                          # workgroup stages its whole source box however few targets it maps
+
+
+def post_tile_runs(cells: np.ndarray, shape, ratio: float, tile=None, order: str = "x"):
+    """A post-mapping list into a dense box regrouped into tiles of
+    neighbouring cells, and the run offsets of the tiles.
+
+    A tile is tx x ty x tz cells (at most 256); a tile's cells are in box
+    order.  order "x": the tiles follow each other x fastest, then y, then z
+    (neighbouring runs share partly used source lines, which then meet in
+    one L2: measured faster); "z": z fastest, then x, then y.  ``ratio`` is the spacing of the
+    list's scale over that of the source scale (> 1).  Without ``tile``, tz
+    is 1 and tx x ty is the first of 64 x 4, 64 x 2, 64 x 1, 32 x 2, ... whose
+    source cells (at most floor((t - 1) * ratio) + 2 per axis, plus one for
+    rounding, and 2 source planes) fit the kernel's buffer.  Returns (cells in tile order, int32 offsets
+    with one entry more than there are tiles)."""
+    c = np.asarray(cells, np.int64)
+    nx, ny = shape[0], shape[1]
+    if tile is None:
+        # rows of 64 (one wavefront a row: whole-line stores, long source
+        # rows) measured faster than squarer tiles that reach fewer source
+        # cells per target; the deepest such tile that fits the buffer
+        tz = 1
+        for tx, ty in ((64, 4), (64, 2), (64, 1), (32, 2), (32, 1), (16, 1), (8, 1), (4, 1)):
+            box = (math.floor((tx - 1) * ratio) + 3) * (math.floor((ty - 1) * ratio) + 3) * 2
+            if box <= POST_TILE_BUFFER:
+                break
+    else:
+        tx, ty, tz = tile
+        assert tx * ty * tz <= POST_RUN
+    x, y, z = c % nx, (c // nx) % ny, c // (nx * ny)
+    kx, ky, kz = x // tx, y // ty, z // tz
+    major = (kz, kx, ky) if order == "z" else (kx, ky, kz)
+    order_idx = np.lexsort((x, y, z) + major)
+    c = c[order_idx]
+    key = np.stack([kx[order_idx], ky[order_idx], kz[order_idx]])
+    starts = np.flatnonzero(np.any(key[:, 1:] != key[:, :-1], axis=0)) + 1 if c.size else np.zeros(0, np.int64)
+    offsets = np.concatenate([[0], starts, [c.size]]).astype(np.int32)
+    assert np.all(np.diff(offsets) <= POST_RUN)
+    return c.astype(np.int32), offsets
+
+
 def _storage_list(lev: Level, box_cells: np.ndarray) -> np.ndarray:
     """A cell list over a level's box in the level's storage order (int32);
     every listed cell of a brick level must be stored."""
@@ -190,7 +235,8 @@ class Hierarchy:
     cell lists sent to the library are in each level's storage order."""
 
     def __init__(self, levels: list[Level], kinds: list[np.ndarray], parents=None, *,
-                 stage_xfaces: bool = True):
+                 stage_xfaces: bool = True, tile_posts: bool = True,
+                 tile_min_fill: int = POST_TILE_MIN_FILL):
         assert len(levels) == len(kinds) and 1 <= len(levels) <= _capi.MAX_SCALES
         self.levels = levels
         self.kinds = [np.asarray(k, np.uint8) for k in kinds]
@@ -271,6 +317,19 @@ class Hierarchy:
         self.post_full = {**self.post, **far_post}
         self.post = {**drop_overwritten_posts(self.post, n), **far_post}
         for (i, j), cells in self.post.items():
+            if (tile_posts and cells.size and levels[i].dense_index is None
+                    and levels[j].dense_index is None and levels[i].c.dx < levels[j].c.dx):
+                # a finer dense scale into a coarser dense one: tiles of the
+                # coarser box, each mapped by one workgroup through LDS
+                tiled, runs = post_tile_runs(cells, (levels[j].nx, levels[j].ny),
+                                             levels[j].c.dx / levels[i].c.dx)
+                if tiled.size >= tile_min_fill * (runs.size - 1):
+                    cells = tiled
+                    self.post[(i, j)] = cells
+                    r_t = torch.as_tensor(runs, device=dev)
+                    self.lists.append(r_t)
+                    self.c_scales[i].n_post_tiles[j] = runs.size - 1
+                    self.c_scales[i].post_tiles[j] = r_t.data_ptr()
             t = torch.as_tensor(_storage_list(levels[j], cells), device=dev)
             self.lists.append(t)
             self.c_scales[i].n_post[j] = cells.size
@@ -646,7 +705,7 @@ def region_box_fn(region: np.ndarray):
 
 def dynamic_hierarchy(lev0: Level, kinds0: np.ndarray, thresholds, alphas, *, margin: int = 3,
                       dilate: int = 2, nest: int = 2, solid_fn=None, stream=None, previous=None,
-                      bricks: bool = False, stage_xfaces: bool = True):
+                      bricks: bool = False, stage_xfaces: bool = True, tile_posts: bool = True):
     """Scales set by thresholds: scale k covers the bounding box of the cells
     with |curl u| > thresholds[k-1][0] and |u| > thresholds[k-1][1]
     (dilated), kept `margin` cells from the domain faces and `nest` cells
@@ -706,7 +765,7 @@ def dynamic_hierarchy(lev0: Level, kinds0: np.ndarray, thresholds, alphas, *, ma
         lo_lim = [lo[a] + nest for a in range(3)]
         hi_lim = [hi[a] - nest for a in range(3)]
     torch.cuda.synchronize()
-    H = Hierarchy(levels, kinds, stage_xfaces=stage_xfaces)
+    H = Hierarchy(levels, kinds, stage_xfaces=stage_xfaces, tile_posts=tile_posts)
     H.object_labels = labels
     return H, boxes
 

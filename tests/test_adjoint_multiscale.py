@@ -380,7 +380,10 @@ def test_reduced_plume_multiscale_adjoint_matches_fp64_finite_differences():
         lev = sp.level(True)
         lev.init_equilibrium(rho, u, s)
         levs.append(lev)
-    H = hierarchy.Hierarchy(levs, [sp.kinds for sp in specs], [sp.parent for sp in specs])
+    # post-mapping lists in tiles (each run mapped through LDS)
+    H = hierarchy.Hierarchy(levs, [sp.kinds for sp in specs], [sp.parent for sp in specs],
+                            tile_min_fill=0)
+    assert H.c_scales[2].n_post_tiles[1] > 0 and H.c_scales[1].n_post_tiles[0] > 0
     f0 = [gpu_pop(lev) for lev in levs]
     g0 = [gpu_g(lev) for lev in levs]
     n_ref = 2
@@ -412,6 +415,40 @@ def test_reduced_plume_multiscale_adjoint_matches_fp64_finite_differences():
     ad = sum(float(np.sum(a * d)) for a, d in zip(gf, df)) + \
         sum(float(np.sum(a * d)) for a, d in zip(gg, dg))
     assert ad == pytest.approx(fd, rel=2e-5), (ad, fd)
+
+
+def test_tiled_post_mapping_adjoint_gives_bitwise_the_gathered_adjoint():
+    """With the post-mapping lists in tile runs, each run's interpolation and
+    map adjoint run in one workgroup through LDS: the columns, index map and
+    flags are those of the per-target passes, so one multi-scale adjoint step
+    of the reduced plume is bitwise that of the untiled lists."""
+    nx, ny, nz = 96, 48, 48
+    specs = plume_specs(nx, ny, nz, 1e-3)
+    out = []
+    for tiles in (True, False):
+        levs = []
+        for sp in specs:
+            rho, u, s = smooth_state(sp, 40)
+            u[0] += 0.04
+            lev = sp.level(True)
+            lev.init_equilibrium(rho, u, s)
+            levs.append(lev)
+        H = hierarchy.Hierarchy(levs, [sp.kinds for sp in specs], [sp.parent for sp in specs],
+                                tile_posts=tiles, tile_min_fill=0)
+        assert (H.c_scales[2].n_post_tiles[1] > 0) == tiles
+        H.step(2)
+        f_in = [lev.f.clone() for lev in levs]
+        g_in = [lev.g.clone() for lev in levs]
+        gen = torch.Generator(device="cuda").manual_seed(5)
+        lam = [torch.randn(27 * lev.plane, device="cuda", generator=gen) for lev in levs]
+        mu = [torch.randn(7 * lev.plane, device="cuda", generator=gen) for lev in levs]
+        ws = torch.empty(H.adjoint_workspace_bytes(), dtype=torch.uint8, device="cuda")
+        H.adjoint_step(f_in, g_in, lam, mu, ws)
+        torch.cuda.synchronize()
+        out.append([x.cpu().numpy() for x in lam + mu])
+        assert all(np.all(np.isfinite(x)) for x in out[-1])
+    for a, b in zip(*out):
+        np.testing.assert_array_equal(a, b)
 
 
 def test_multiscale_adjoint_scope_is_checked():

@@ -94,6 +94,16 @@ def test_multiscale_step_argument_checks(lib):
     keep[1].post_cells[2] = 0xA000
     assert ms(C.byref(H), 1, None) == _capi.ERR_ARG
     assert "larger scales" in err(lib)
+    # run offsets of a post-mapping list: more runs than entries, a negative
+    # count, or a count without offsets
+    H, keep = hierarchy_of([L0, L1], [-1, 0])
+    keep[1].n_post[0] = 3
+    keep[1].post_cells[0] = 0xA000
+    for n_runs, ptr in ((4, 0xB000), (-1, 0xB000), (2, None)):
+        keep[1].n_post_tiles[0] = n_runs
+        keep[1].post_tiles[0] = ptr
+        assert ms(C.byref(H), 1, None) == _capi.ERR_ARG
+        assert "run offsets" in err(lib)
     # the gradient mode is single-level only
     Lg = make_level(p_grad_mode=1)
     H, keep = hierarchy_of([Lg], [-1])

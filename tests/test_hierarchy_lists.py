@@ -180,3 +180,37 @@ def test_region_box_is_the_dilated_clipped_bounding_box_of_both_thresholds():
     assert hierarchy.region_box(om, sp, shape, (1.0, 1.0), 2, [2, 2, 2], [27, 17, 13]) is None
     # a region thinner than 3 cells after clipping is dropped
     assert hierarchy.region_box(om, sp, shape, (5e-3, 2e-2), 0, [2, 2, 2], [27, 17, 6]) is None
+
+
+@pytest.mark.parametrize("ratio,origin", [(4 / 3, (3.3, 2.6, 2.2)), (1.5, (0.4, 1.1, 0.7)),
+                                          (2.0, (1.25, 0.75, 0.25)), (3.2, (0.3, 0.9, 1.6))])
+def test_post_tile_runs_partition_the_list_into_plane_tiles_whose_source_box_fits(ratio, origin):
+    """Runs of the tiled post-mapping: a permutation of the list, at most 256
+    entries a run, each run inside one plane with its cells in box order,
+    and the source cells its trilinear stencils reach (the corner b + 1 only
+    where the fraction is not 0, as the kernel does) fit the kernel's
+    buffer, so no tile falls back to the direct gather."""
+    shape = (70, 33, 9)
+    nx, ny, nz = shape
+    rng = np.random.default_rng(3)
+    x, y, z = inputs.grid_coords(*shape)
+    keep = (x >= 3) & (x < 61) & (y >= 2) & (y < 31) & (rng.random(x.size) > 0.1)
+    cells = np.flatnonzero(keep).astype(np.int32)
+    out, runs = hierarchy.post_tile_runs(cells, shape, ratio)
+    np.testing.assert_array_equal(np.sort(out), np.sort(cells))
+    assert runs[0] == 0 and runs[-1] == cells.size
+    sizes = np.diff(runs)
+    assert np.all(sizes >= 1) and np.all(sizes <= hierarchy.POST_RUN)
+    fine_dx = 1.0 / ratio
+    for a, b in zip(runs[:-1], runs[1:]):
+        c = out[a:b].astype(np.int64)
+        assert np.all(np.diff(c) > 0)
+        cx, cy, cz = c % nx, (c // nx) % ny, c // (nx * ny)
+        assert np.all(cz == cz[0])
+        vol = 1
+        for p, o in ((cx, origin[0]), (cy, origin[1]), (cz, origin[2])):
+            q = (p * 1.0 - o) / fine_dx
+            base = np.floor(q)
+            top = np.where(q - base != 0.0, base + 1, base)
+            vol *= int(top.max() - base.min() + 1)
+        assert vol <= hierarchy.POST_TILE_BUFFER, (ratio, vol)

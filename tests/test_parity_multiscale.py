@@ -346,6 +346,74 @@ def test_x_face_staging_gives_bitwise_the_unstaged_result(storage):
         np.testing.assert_array_equal(ga, gb)
 
 
+def _plume_states(storage, **hier_opts):
+    """The reduced plume's hierarchy (both finer boxes) and its levels,
+    initialised from one smooth field."""
+    nx, ny, nz = 96, 48, 48
+    specs = plume_specs(nx, ny, nz, 1e-3)
+    levs = []
+    for sp in specs:
+        rho, u, s = smooth_state(sp, 40)
+        u[0] += 0.04
+        lev = Level(*sp.shape, sp.params(), scalar=True, periodic=sp.periodic, flags=sp.kinds,
+                    origin=sp.origin, dx=sp.dx, storage=storage)
+        lev.init_equilibrium(rho, u, s)
+        levs.append(lev)
+    H = hierarchy.Hierarchy(levs, [sp.kinds for sp in specs], [sp.parent for sp in specs], **hier_opts)
+    return H, levs
+
+
+@pytest.mark.parametrize("storage", [F32, F16S])
+def test_tiled_post_mapping_gives_bitwise_the_gathered_result(storage):
+    """Post-mapping lists regrouped into tiles (scale 2 -> 1 at ratio 4/3,
+    scale 1 -> 0 at 1.5, however sparsely filled; scale 2 -> 0 sits on
+    coarse lattice points and the library gathers it) and mapped one tile per workgroup
+    through LDS: the same corners, weights and summation order, so every
+    scale's state after several reference steps is bitwise that of the
+    direct gather."""
+    states = []
+    for tiles in (True, False):
+        H, levs = _plume_states(storage, tile_posts=tiles, tile_min_fill=0)
+        n_tiles = {(i, j): H.c_scales[i].n_post_tiles[j] for i in (1, 2) for j in range(i)}
+        if tiles:
+            assert n_tiles[(2, 1)] > 0 and n_tiles[(1, 0)] > 0
+        else:
+            assert all(v == 0 for v in n_tiles.values())
+        H.step(6)
+        torch.cuda.synchronize()
+        states.append([(lev.f.cpu().numpy().copy(), lev.g.cpu().numpy().copy()) for lev in levs])
+        assert all(lev.count_nonfinite() == 0 for lev in levs)
+    for (fa, ga), (fb, gb) in zip(*states):
+        np.testing.assert_array_equal(fa, fb)
+        np.testing.assert_array_equal(ga, gb)
+
+
+def test_runs_that_are_not_tiles_give_bitwise_the_gathered_result():
+    """Runs of 256 consecutive entries of the box-ordered lists: runs inside
+    one plane are staged through LDS, runs that cross planes reach a source
+    box larger than the buffer and are gathered directly by the same kernel;
+    the last run is partial.  Either way the result is bitwise the plain
+    gather's."""
+    states = []
+    keep = []
+    for runs in (True, False):
+        H, levs = _plume_states(F32, tile_posts=False)
+        if runs:
+            for i, j in ((2, 1), (1, 0)):
+                n = H.c_scales[i].n_post[j]
+                offsets = np.append(np.arange(0, n, 256), n).astype(np.int32)
+                t = torch.as_tensor(offsets, device="cuda")
+                keep.append(t)
+                H.c_scales[i].post_tiles[j] = t.data_ptr()
+                H.c_scales[i].n_post_tiles[j] = offsets.size - 1
+        H.step(4)
+        torch.cuda.synchronize()
+        states.append([(lev.f.cpu().numpy().copy(), lev.g.cpu().numpy().copy()) for lev in levs])
+    for (fa, ga), (fb, gb) in zip(*states):
+        np.testing.assert_array_equal(fa, fb)
+        np.testing.assert_array_equal(ga, gb)
+
+
 def test_vorticity_matches_central_differences():
     """|curl u| (placement of dynamic scales) of an initialised state equals
     central differences of the input field; one-sided at non-periodic faces."""

@@ -14,6 +14,7 @@ pytestmark = pytest.mark.gpu
 
 N1 = 16
 W = oracle.weights()
+TARGET_STEPS = 12
 
 
 def scene(adaptive=True, g_max=1.0):
@@ -23,7 +24,16 @@ def scene(adaptive=True, g_max=1.0):
                s_ref=float(s0.mean()))
     u0 = inputs.smooth_random_field(n, n, n, 0.02, 51, k_max=2)
     theta = inputs.smooth_random_field(n, n, n, 1e-4, 52, k_max=2)
-    target = 0.8 * inputs.gaussian_blob(n, n, n, (9, 7, 7), 2.0)
+    # the target: final smoke scalar of a seeded target run, the same scene
+    # driven by another smooth body force for TARGET_STEPS steps (FP64
+    # oracle; strong enough that s - target stays far above FP32 rounding)
+    theta_t = inputs.smooth_random_field(n, n, n, 1e-3, 53, k_max=2)
+    dom = oracle.Domain(n, n, n, theta=theta_t)
+    op = oracle.Params(nu=p.nu, g_max=p.g_max, adaptive=p.adaptive, tau_s=p.tau_s, beta=p.beta,
+                       s_ref=p.s_ref)
+    f, g = oracle.init(dom, np.ones(n ** 3), u0, s=s0)
+    f, g = oracle.step(dom, op, f, g, n_steps=TARGET_STEPS)
+    _, _, target = oracle.macro(dom, op, f, g)
     return p, u0, s0, theta, target
 
 

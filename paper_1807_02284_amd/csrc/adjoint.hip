@@ -295,9 +295,21 @@ __global__ void __launch_bounds__(256) k_adjoint_copies(const AdjArgs a, bool sc
         return;
     }
     const int64_t P = a.plane;
-    for (int i = 0; i < Q; ++i) atomicAdd(a.lam0 + i * P + from, a.lam1[i * P + cell]);
-    if (scalar)
-        for (int i = 0; i < QS; ++i) atomicAdd(a.mu0 + i * P + from, a.mu1[i * P + cell]);
+    // every value loaded before the first atomic: a load-wait-atomic chain
+    // per element (the wait covers the previous atomic as well) made each
+    // copying wave 2 x 34 memory round trips long
+    float l1[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) l1[i] = a.lam1[i * P + cell];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) atomicAdd(a.lam0 + i * P + from, l1[i]);
+    if (scalar) {
+        float m1[QS];
+#pragma unroll
+        for (int i = 0; i < QS; ++i) m1[i] = a.mu1[i * P + cell];
+#pragma unroll
+        for (int i = 0; i < QS; ++i) atomicAdd(a.mu0 + i * P + from, m1[i]);
+    }
 }
 
 // zero elements n .. plane - 1 of each of the planes

@@ -146,14 +146,18 @@ def check_shell_stencils(shell_shape, shell_origin, shell_dx, shell_cells,
             raise ValueError("a boundary cell's stencil touches a solid far-field cell")
 
 
-def drop_overwritten_posts(post: dict, n: int) -> dict:
+def drop_overwritten_posts(post: dict, n: int, parents=None) -> dict:
     """Post-mapping lists {(fine i, coarse j): cells of j} with every cell
     removed that a later (finer) scale also post-maps into j.  Finer scales
-    post-map in index order and nothing reads a larger scale j between two
-    post-mappings into it (prior-mapping reads the parent, which is finer
-    than j; far-field scales have taken their step before), so such a cell
-    keeps only the later value: leaving it out of the earlier list gives the
-    same final state without the duplicate work."""
+    post-map in index order; when no scale after i reads j (prior-mapping
+    reads the parent, and no later scale has j as its parent; far-field
+    scales have taken their step before), a cell of j keeps only the later
+    value, so leaving it out of i's list gives the same final state without
+    the duplicate work.  ``parents`` (default: a chain, parent of k is
+    k - 1) tells which later scales read j: if one does, i's list into j is
+    kept whole, since that scale's prior-mappings see i's values."""
+    if parents is None:
+        parents = [-1] + list(range(n - 1))
     out = {}
     for j in range(n):
         keys = [i for i in range(n - 1, -1, -1) if i != j and (i, j) in post]
@@ -163,7 +167,8 @@ def drop_overwritten_posts(post: dict, n: int) -> dict:
         later = np.zeros(size, bool)
         for i in keys:
             cells = np.asarray(post[(i, j)], np.int32)
-            out[(i, j)] = cells[~later[cells]]
+            read_later = any(parents[k] == j for k in range(i + 1, n))
+            out[(i, j)] = cells if read_later else cells[~later[cells]]
             later[cells] = True
     return out
 
@@ -315,7 +320,7 @@ class Hierarchy:
             sc.work_f = (C.c_void_p * 2)(*[None if w is None else w.data_ptr() for w in work_f])
             sc.work_g = (C.c_void_p * 2)(*[None if w is None else w.data_ptr() for w in work_g])
         self.post_full = {**self.post, **far_post}
-        self.post = {**drop_overwritten_posts(self.post, n), **far_post}
+        self.post = {**drop_overwritten_posts(self.post, n, self.parents), **far_post}
         for (i, j), cells in self.post.items():
             if (tile_posts and cells.size and levels[i].dense_index is None
                     and levels[j].dense_index is None and levels[i].c.dx < levels[j].c.dx):

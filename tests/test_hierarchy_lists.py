@@ -116,6 +116,52 @@ def _three_scales(n=12):
     return scales
 
 
+def _siblings(n=12):
+    """Two finer scales that are both children of the reference scale, the
+    second overlapping the first."""
+    rho = np.ones(n ** 3)
+    u = inputs.smooth_random_field(n, n, n, 0.04, 78, k_max=2)
+    dom = oracle.Domain(n, n, n)
+    f0, _ = oracle.init(dom, rho, u)
+    nu0 = 2e-3
+    s0 = ml.OScale(n, n, n, 1.0, (0.0, 0.0, 0.0), oracle.Params(nu=nu0, g_max=0.05),
+                   np.zeros(n ** 3, np.uint8), periodic=7, f=f0)
+    s1 = ml.OScale(10, 10, 10, 1 / 1.5, (1.3, 2.4, 2.6), oracle.Params(nu=nu0 * 1.5, g_max=0.05),
+                   hierarchy.shell_flags(10, 10, 10), periodic=0, parent=0)
+    s2 = ml.OScale(9, 9, 9, 0.5, (5.1, 3.3, 3.2), oracle.Params(nu=nu0 * 2.0, g_max=0.05),
+                   hierarchy.shell_flags(9, 9, 9), periodic=0, parent=0)
+    scales = [s0, s1, s2]
+    for s in scales[1:]:
+        s.f = np.zeros((27, s.n))
+        oracle.exchange(s0.geom(), s0.f, s0.f, 0.0, s.geom(), np.arange(s.n), s.f)
+    ml.prepare(scales)
+    return scales
+
+
+def test_posts_read_by_a_later_sibling_are_kept_whole():
+    """With sibling scales (both children of the reference), the second's
+    prior-mappings read reference cells that the first post-maps: its list
+    into the reference must stay whole.  The oracle run with the kept lists
+    equals the full-list run bit for bit; dropping by the chain rule would
+    not."""
+    full = _siblings()
+    lists = {(i, j): full[i].post[j] for i in range(1, 3) for j in range(i)}
+    assert lists[(2, 0)].size > 0 and lists[(1, 0)].size > 0
+    assert np.intersect1d(lists[(1, 0)], lists[(2, 0)]).size > 0
+    kept = hierarchy.drop_overwritten_posts(lists, 3, [-1, 0, 0])
+    chain = hierarchy.drop_overwritten_posts(lists, 3)
+    np.testing.assert_array_equal(kept[(1, 0)], lists[(1, 0)])
+    assert chain[(1, 0)].size < lists[(1, 0)].size
+    ml.multiscale_step(full, 2)
+    for red_lists, same in ((kept, True), (chain, False)):
+        red = _siblings()
+        for (i, j), cells in red_lists.items():
+            red[i].post[j] = np.asarray(cells, np.int64)
+        ml.multiscale_step(red, 2)
+        equal = all(np.array_equal(a.f, b.f) for a, b in zip(full, red))
+        assert equal == same
+
+
 def test_dropping_overwritten_post_cells_leaves_the_oracle_state_bit_identical():
     """Three scales (alpha 1.5 and 2, nested): the oracle's Algorithm-1 run
     with the reduced post-mapping lists equals the run with the full lists

@@ -199,6 +199,31 @@ def test_three_scale_reference_steps_match_oracle():
         assert np.max(np.abs(gpu_g(lev) - osc.g)) <= 1e-5
 
 
+def test_sibling_scales_of_the_reference_match_oracle():
+    """Two finer scales that are both children of the reference scale, the
+    second overlapping the first: scale 2's prior-mappings read reference
+    cells that scale 1 has post-mapped, and scale 2 also post-maps into
+    scale 1.  The library runs post-mappings on a second stream; the
+    reference-scale reads of scale 2 must wait for scale 1's post into the
+    reference, as Algorithm 1 orders them."""
+    n = 24
+    nu0 = 2e-3
+    s0 = Spec((n, n, n), (0.0, 0.0, 0.0), 1.0, nu0, np.zeros(n ** 3, np.uint8), periodic=7)
+    sh1 = (13, 12, 12)
+    s1 = Spec(sh1, (2.3, 5.4, 5.6), 1 / 1.5, nu0, hierarchy.shell_flags(*sh1), parent=0)
+    sh2 = (11, 10, 10)
+    s2 = Spec(sh2, (8.1, 6.3, 6.2), 0.5, nu0, hierarchy.shell_flags(*sh2), parent=0)
+    H, levs, oscs = build_pair([s0, s1, s2], 22)
+    assert H.parents == [-1, 0, 0]
+    assert H.post_full[(2, 1)].size > 0 and H.post_full[(1, 0)].size > 0
+    H.step(3)
+    ml.multiscale_step(oscs, 3)
+    torch.cuda.synchronize()
+    for lev, osc in zip(levs, oscs):
+        assert rel_err(gpu_pop(lev), osc.f) <= 1e-5
+        assert np.max(np.abs(gpu_g(lev) - osc.g)) <= 1e-5
+
+
 def test_alpha_one_two_scale_gpu_run_equals_single_scale_gpu_run():
     n = 20
     nu0 = 5e-3

@@ -661,6 +661,37 @@ static SrcBox source_box(const cslbm_level* src, const cslbm_level* dst)
     return SrcBox{lo[0], lo[1], lo[2], cnt[0], cnt[1], cnt[2]};
 }
 
+// Every corner of every target lies in source_box(src, dst) unless a
+// stencil can wrap around a periodic axis of src (the dst box then comes
+// within one cell of that axis' ends).
+static bool source_box_holds_stencils(const cslbm_level* src, const cslbm_level* dst)
+{
+    const int sn[3] = {src->nx, src->ny, src->nz}, dn[3] = {dst->nx, dst->ny, dst->nz};
+    for (int d = 0; d < 3; ++d) {
+        if (!((src->periodic >> d) & 1)) continue;
+        const double q0 = (dst->origin[d] - src->origin[d]) / src->dx;
+        const double q1 = (dst->origin[d] + (dn[d] - 1) * dst->dx - src->origin[d]) / src->dx;
+        if (std::floor(std::min(q0, q1)) < 0.0 || std::floor(std::max(q0, q1)) + 1.0 > sn[d] - 1) return false;
+    }
+    return true;
+}
+
+// z (planes of `plane` elements) += x over the cells of box b of an nx x ny
+// level, or z = 0 there when x is null
+__global__ void __launch_bounds__(256) k_box_add(const float* x, float* z, int planes, int64_t plane, int nx,
+                                                 int ny, const SrcBox b)
+{
+    const int64_t nb = (int64_t)b.nx * b.ny * b.nz;
+    const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (l >= nb * planes) return;
+    const int pl = (int)(l / nb);
+    const int64_t r = l - pl * nb;
+    const int cx = b.x0 + (int)(r % b.nx), cy = b.y0 + (int)((r / b.nx) % b.ny);
+    const int cz = b.z0 + (int)(r / ((int64_t)b.nx * b.ny));
+    const int64_t e = pl * plane + cx + (int64_t)nx * (cy + (int64_t)ny * cz);
+    z[e] = x ? z[e] + x[e] : 0.0f;
+}
+
 // adjoint of launch_exchange(src, fA, fB, w, dst, ..., cells): the
 // destination adjoint lam_d (mu_d) at the cells goes to the source adjoints
 static int launch_exchange_adjoint(const cslbm_level* src, const void* fA, const void* fB,
@@ -1035,9 +1066,27 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
         uses_lamA[S[i].parent] = true;
         if (!sub_steps(S, i).node) uses_lamA[i] = true;
     }
-    for (int i = 0; i < ns; ++i)
-        if (uses_lamA[i])
+    // The reference scale's lamA receives only scale 1's prior-mapping
+    // adjoints, inside the source sub-box scale 1's box reaches: when no
+    // stencil wraps, only that sub-box is cleared here and added at the end
+    // (the reference scale is the largest: clearing and summing it whole
+    // moved four full buffers)
+    // (a reference scale alone: lamA is never written, the box is empty)
+    const SrcBox ref_box = ns > 1 ? source_box(&S[0].level, &S[1].level) : SrcBox{0, 0, 0, 0, 0, 0};
+    const bool ref_boxed = ns == 1 || source_box_holds_stencils(&S[0].level, &S[1].level);
+    const int planes0 = Q + (scalar ? QS : 0);
+    for (int i = 0; i < ns; ++i) {
+        if (!uses_lamA[i]) continue;
+        if (i == 0 && ref_boxed) {
+            const int64_t nb = (int64_t)ref_box.nx * ref_box.ny * ref_box.nz * planes0;
+            if (nb > 0)
+                hipLaunchKernelGGL(k_box_add, dim3(grid_for(nb)), dim3(256), 0, stream, nullptr,
+                                   W.lamA[0].f, planes0, S[0].level.plane, S[0].level.nx, S[0].level.ny,
+                                   ref_box);
+        } else {
             hipLaunchKernelGGL(k_zero, dim3(grid_for(nelem(i))), dim3(256), 0, stream, W.lamA[i].f, nelem(i));
+        }
+    }
     for (int i = ns - 1; i >= 1; --i) {
         const cslbm_scale& sc = S[i];
         const cslbm_level* L = &sc.level;
@@ -1108,10 +1157,24 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
                                  scalar ? mu[0] : nullptr, W.t1[0].f, W.t1[0].g, nullptr, stream);
         if (rc) return rc;
         const int64_t nf = (int64_t)Q * L->plane, ngs = (int64_t)QS * L->plane;
-        hipLaunchKernelGGL(k_sum, dim3(grid_for(nf)), dim3(256), 0, stream, W.t1[0].f, W.lamA[0].f, lam[0], nf);
-        if (scalar)
-            hipLaunchKernelGGL(k_sum, dim3(grid_for(ngs)), dim3(256), 0, stream, W.t1[0].g, W.lamA[0].g,
-                               mu[0], ngs);
+        if (ref_boxed) {
+            CSLBM_HIP_TRY(hipMemcpyAsync(lam[0], W.t1[0].f, nf * 4, hipMemcpyDeviceToDevice, stream));
+            if (scalar)
+                CSLBM_HIP_TRY(hipMemcpyAsync(mu[0], W.t1[0].g, ngs * 4, hipMemcpyDeviceToDevice, stream));
+            const int64_t nb = (int64_t)ref_box.nx * ref_box.ny * ref_box.nz;
+            if (nb > 0) {
+                hipLaunchKernelGGL(k_box_add, dim3(grid_for(nb * Q)), dim3(256), 0, stream, W.lamA[0].f, lam[0],
+                                   Q, L->plane, L->nx, L->ny, ref_box);
+                if (scalar)
+                    hipLaunchKernelGGL(k_box_add, dim3(grid_for(nb * QS)), dim3(256), 0, stream, W.lamA[0].g,
+                                       mu[0], QS, L->plane, L->nx, L->ny, ref_box);
+            }
+        } else {
+            hipLaunchKernelGGL(k_sum, dim3(grid_for(nf)), dim3(256), 0, stream, W.t1[0].f, W.lamA[0].f, lam[0], nf);
+            if (scalar)
+                hipLaunchKernelGGL(k_sum, dim3(grid_for(ngs)), dim3(256), 0, stream, W.t1[0].g, W.lamA[0].g,
+                                   mu[0], ngs);
+        }
     }
     return check_launch("cslbm_multiscale_adjoint_step");
 }

@@ -677,19 +677,20 @@ static bool source_box_holds_stencils(const cslbm_level* src, const cslbm_level*
 }
 
 // z (planes of `plane` elements) += x over the cells of box b of an nx x ny
-// level, or z = 0 there when x is null
+// level, or z = 0 there when x is null: one thread per box cell (boxes are
+// validated below 2^31 cells), all planes
 __global__ void __launch_bounds__(256) k_box_add(const float* x, float* z, int planes, int64_t plane, int nx,
                                                  int ny, const SrcBox b)
 {
-    const int64_t nb = (int64_t)b.nx * b.ny * b.nz;
-    const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (l >= nb * planes) return;
-    const int pl = (int)(l / nb);
-    const int64_t r = l - pl * nb;
-    const int cx = b.x0 + (int)(r % b.nx), cy = b.y0 + (int)((r / b.nx) % b.ny);
-    const int cz = b.z0 + (int)(r / ((int64_t)b.nx * b.ny));
-    const int64_t e = pl * plane + cx + (int64_t)nx * (cy + (int64_t)ny * cz);
-    z[e] = x ? z[e] + x[e] : 0.0f;
+    const unsigned r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= (unsigned)b.nx * b.ny * b.nz) return;
+    const unsigned bxy = (unsigned)b.nx * b.ny;
+    const int cx = b.x0 + (int)(r % b.nx), cy = b.y0 + (int)((r / b.nx) % b.ny), cz = b.z0 + (int)(r / bxy);
+    const int64_t c = cx + (int64_t)nx * (cy + (int64_t)ny * cz);
+    for (int pl = 0; pl < planes; ++pl) {
+        const int64_t e = pl * plane + c;
+        z[e] = x ? z[e] + x[e] : 0.0f;
+    }
 }
 
 // adjoint of launch_exchange(src, fA, fB, w, dst, ..., cells): the
@@ -1078,7 +1079,7 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
     for (int i = 0; i < ns; ++i) {
         if (!uses_lamA[i]) continue;
         if (i == 0 && ref_boxed) {
-            const int64_t nb = (int64_t)ref_box.nx * ref_box.ny * ref_box.nz * planes0;
+            const int64_t nb = (int64_t)ref_box.nx * ref_box.ny * ref_box.nz;
             if (nb > 0)
                 hipLaunchKernelGGL(k_box_add, dim3(grid_for(nb)), dim3(256), 0, stream, nullptr,
                                    W.lamA[0].f, planes0, S[0].level.plane, S[0].level.nx, S[0].level.ny,
@@ -1163,11 +1164,11 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
                 CSLBM_HIP_TRY(hipMemcpyAsync(mu[0], W.t1[0].g, ngs * 4, hipMemcpyDeviceToDevice, stream));
             const int64_t nb = (int64_t)ref_box.nx * ref_box.ny * ref_box.nz;
             if (nb > 0) {
-                hipLaunchKernelGGL(k_box_add, dim3(grid_for(nb * Q)), dim3(256), 0, stream, W.lamA[0].f, lam[0],
-                                   Q, L->plane, L->nx, L->ny, ref_box);
+                hipLaunchKernelGGL(k_box_add, dim3(grid_for(nb)), dim3(256), 0, stream, W.lamA[0].f, lam[0], Q,
+                                   L->plane, L->nx, L->ny, ref_box);
                 if (scalar)
-                    hipLaunchKernelGGL(k_box_add, dim3(grid_for(nb * QS)), dim3(256), 0, stream, W.lamA[0].g,
-                                       mu[0], QS, L->plane, L->nx, L->ny, ref_box);
+                    hipLaunchKernelGGL(k_box_add, dim3(grid_for(nb)), dim3(256), 0, stream, W.lamA[0].g, mu[0],
+                                       QS, L->plane, L->nx, L->ny, ref_box);
             }
         } else {
             hipLaunchKernelGGL(k_sum, dim3(grid_for(nf)), dim3(256), 0, stream, W.t1[0].f, W.lamA[0].f, lam[0], nf);

@@ -561,6 +561,17 @@ __global__ void __launch_bounds__(256) k_axpby(const float* x, float* y, int64_t
     if (i < n) y[i] = alpha * x[i] + beta * y[i];
 }
 
+// two such updates from one x: y = a1 x + b1 y and z = a2 x + b2 z (x read once)
+__global__ void __launch_bounds__(256) k_axpby2(const float* x, float* y, float* z, int64_t n, float a1,
+                                                float b1, float a2, float b2)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float xi = x[i];
+    y[i] = a1 * xi + b1 * y[i];
+    z[i] = a2 * xi + b2 * z[i];
+}
+
 // z = x + y over n elements
 __global__ void __launch_bounds__(256) k_sum(const float* x, const float* y, float* z, int64_t n)
 {
@@ -1116,11 +1127,12 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
         rc = launch_adjoint_into(L, in_last.f, in_last.g, lamR, muR, lc.f, lc.g, nullptr, stream);
         if (rc) return rc;
         if (!ss.node) {
-            axpby(lamR, lc.f, nf, (float)ss.l1, (float)ss.l2, stream);
-            axpby(lamR, W.lamA[i].f, nf, (float)ss.l0, 1.0f, stream);
+            // lc = l1 lamR + l2 lc and lamA += l0 lamR, lamR read once
+            hipLaunchKernelGGL(k_axpby2, dim3(grid_for(nf)), dim3(256), 0, stream, lamR, lc.f, W.lamA[i].f, nf,
+                               (float)ss.l1, (float)ss.l2, (float)ss.l0, 1.0f);
             if (scalar) {
-                axpby(muR, lc.g, ngs, (float)ss.l1, (float)ss.l2, stream);
-                axpby(muR, W.lamA[i].g, ngs, (float)ss.l0, 1.0f, stream);
+                hipLaunchKernelGGL(k_axpby2, dim3(grid_for(ngs)), dim3(256), 0, stream, muR, lc.g, W.lamA[i].g,
+                                   ngs, (float)ss.l1, (float)ss.l2, (float)ss.l0, 1.0f);
             }
         }
         // lam[i] is free from here on.  lc = adjoint of the input of sub-step

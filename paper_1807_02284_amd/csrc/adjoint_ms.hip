@@ -369,6 +369,17 @@ __global__ void __launch_bounds__(256) k_exadj_interp(const ExchAdjArgs a, const
 // interpolated state (column k) and the target's adjoint (then cleared);
 // the result replaces column k, or is scattered with atomics for a target
 // outside the gather (stencil wrapped or clamped).
+// lam[., c] = 0 and mu[., c] = 0 (the destination adjoint, once read)
+template <bool kScalar>
+__device__ __forceinline__ void clear_column(float* lam, float* mu, int64_t plane, int c)
+{
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lam[i * plane + c] = 0.0f;
+    if (kScalar)
+#pragma unroll
+        for (int i = 0; i < QS; ++i) mu[i * plane + c] = 0.0f;
+}
+
 template <bool kScalar, bool kNode>
 __global__ void __launch_bounds__(256) k_exadj_vjp(const ExchAdjArgs a, const GatherWs g)
 {
@@ -379,17 +390,20 @@ __global__ void __launch_bounds__(256) k_exadj_vjp(const ExchAdjArgs a, const Ga
     const int64_t n_t = e.n_cells;
     float v[27], gi[QS] = {0, 0, 0, 0, 0, 0, 0};
     float lam[27], mu[QS] = {0, 0, 0, 0, 0, 0, 0};
+    // every element loaded before the destination adjoint is cleared: all
+    // loads in flight together
+#pragma unroll
     for (int i = 0; i < Q; ++i) {
         v[tensor_slot(i)] = g.vb[i * n_t + k];
         lam[tensor_slot(i)] = a.lam_d[i * e.dplane + c];
-        a.lam_d[i * e.dplane + c] = 0.0f;
     }
     if (kScalar)
+#pragma unroll
         for (int i = 0; i < QS; ++i) {
             gi[i] = g.vb[(Q + i) * n_t + k];
             mu[i] = a.mu_d[i * e.dplane + c];
-            a.mu_d[i * e.dplane + c] = 0.0f;
         }
+    clear_column<kScalar>(a.lam_d, a.mu_d, e.dplane, c);
     float vb[27], gb[QS];
     exchange_map_adjoint<kScalar>(v, gi, e.kappa, e.kappa_s, lam, mu, vb, gb);
     // the column addresses are formed again for the stores instead of kept
@@ -397,8 +411,10 @@ __global__ void __launch_bounds__(256) k_exadj_vjp(const ExchAdjArgs a, const Ga
     int kc = k;
     asm volatile("" : "+v"(kc));
     if (g.map[c] == kc) {
+#pragma unroll
         for (int i = 0; i < Q; ++i) g.vb[i * n_t + kc] = vb[tensor_slot(i)];
         if (kScalar)
+#pragma unroll
             for (int i = 0; i < QS; ++i) g.vb[(Q + i) * n_t + kc] = gb[i];
         return;
     }
@@ -458,9 +474,45 @@ __device__ __forceinline__ void sum_columns(const GatherWs& g, int64_t n_t, cons
 #pragma unroll
     for (int e = 0; e < kList; ++e) {
         if (e >= nk) break;
+#pragma unroll
         for (int i = 0; i < Q; ++i) acc[i] += ww[e] * g.vb[i * n_t + kk[e]];
         if (kScalar)
+#pragma unroll
             for (int i = 0; i < QS; ++i) gacc[i] += ww[e] * g.vb[(Q + i) * n_t + kk[e]];
+    }
+}
+
+// lam[., s] += c acc and mu[., s] += c gacc in two halves (planes 0-13 of
+// lam, then 14-26 and mu): within a half every element is loaded before the
+// first store, so its loads are in flight together (a store between them
+// would order each later load after it), and a half keeps few addresses live.
+template <int kLo, int kHi>
+__device__ __forceinline__ void add_planes(float* p, int64_t plane, int64_t s, float c, const float* acc)
+{
+    float v[kHi - kLo];
+#pragma unroll
+    for (int i = kLo; i < kHi; ++i) v[i - kLo] = p[i * plane + s];
+#pragma unroll
+    for (int i = kLo; i < kHi; ++i) p[i * plane + s] = v[i - kLo] + c * acc[i];
+}
+
+template <bool kScalar>
+__device__ __forceinline__ void add_column(float* lam, float* mu, int64_t plane, int64_t s, float c,
+                                           const float (&acc)[27], const float (&gacc)[QS])
+{
+    add_planes<0, 14>(lam, plane, s, c, acc);
+    if (kScalar) {
+        float v[Q - 14], u[QS];
+#pragma unroll
+        for (int i = 14; i < Q; ++i) v[i - 14] = lam[i * plane + s];
+#pragma unroll
+        for (int i = 0; i < QS; ++i) u[i] = mu[i * plane + s];
+#pragma unroll
+        for (int i = 14; i < Q; ++i) lam[i * plane + s] = v[i - 14] + c * acc[i];
+#pragma unroll
+        for (int i = 0; i < QS; ++i) mu[i * plane + s] = u[i] + c * gacc[i];
+    } else {
+        add_planes<14, Q>(lam, plane, s, c, acc);
     }
 }
 
@@ -470,7 +522,42 @@ struct SrcBox {
     int x0, y0, z0, nx, ny, nz;
 };
 
-template <bool kScalar, bool kNode>
+// Narrow window: the destination spacing exceeds the source spacing (or the
+// nodes coincide), so per axis at most two destination indices put weight on
+// a source index, found among kNarrowCand candidates.
+constexpr int kNarrowCand = 5;   // ceil(2 src dx / dst dx) + 3 <= 5
+
+// The nonzero weights of source index s along one axis over the candidate
+// window [lo, hi] (at most kMaxCand indices), in increasing index order; the
+// host picks kG at least as large as their count.
+template <int kG>
+__device__ __forceinline__ int axis_nonzero(double dorigin, double ddx, double sorigin, double sdx, int lo,
+                                            int hi, int s, int (&j)[kG], float (&w)[kG])
+{
+    int n = 0;
+#pragma unroll
+    for (int m = 0; m < kG; ++m) {
+        j[m] = 0;
+        w[m] = 0.0f;
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxCand; ++c) {
+        const int jc = lo + c;
+        const float wc = jc <= hi ? axis_weight<false>(dorigin, ddx, sorigin, sdx, jc, s) : 0.0f;
+        if (wc != 0.0f) {
+#pragma unroll
+            for (int m = 0; m < kG; ++m)
+                if (m == n) {
+                    j[m] = jc;
+                    w[m] = wc;
+                }
+            ++n;
+        }
+    }
+    return n;
+}
+
+template <bool kScalar, bool kNode, int kG>
 __global__ void __launch_bounds__(256) k_exadj_sources(const ExchAdjArgs a, const GatherWs g,
                                                        const SrcBox b)
 {
@@ -482,62 +569,152 @@ __global__ void __launch_bounds__(256) k_exadj_sources(const ExchAdjArgs a, cons
     const int64_t s = sxyz[0] + (int64_t)e.snx * (sxyz[1] + (int64_t)e.sny * sxyz[2]);
     if (!g.touched[s]) return;
     g.touched[s] = 0;
+    constexpr bool kNarrow = kG == 2;
     const int nd[3] = {e.dnx, e.dny, e.dnz};
+    const double dorg[3] = {e.dorigin[0], e.dorigin[1], e.dorigin[2]};
+    const double sorg[3] = {e.sorigin[0], e.sorigin[1], e.sorigin[2]};
     // per axis: destination indices whose stencil can hold source index s,
     // q(j) in [s - 1, s + 1), with one index of margin each side
     int lo[3], hi[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double jl = ((sxyz[d] - 1) * e.sdx + e.sorigin[d] - e.dorigin[d]) / e.ddx;
+        const double jl = ((sxyz[d] - 1) * e.sdx + sorg[d] - dorg[d]) / e.ddx;
         lo[d] = max(0, (int)floor(jl) - 1);
-        hi[d] = min(nd[d] - 1, (int)floor(jl) - 2 + kMaxCand);
+        hi[d] = min(nd[d] - 1, (int)floor(jl) - 2 + (kNarrow ? kNarrowCand : kMaxCand));
     }
     const int64_t n_t = e.n_cells;
     float acc[27];
 #pragma unroll
     for (int q = 0; q < 27; ++q) acc[q] = 0.0f;
     float gacc[QS] = {0, 0, 0, 0, 0, 0, 0};
-    // the targets found are collected first and their columns summed in
-    // batches: the lanes of a wave then load together instead of inside a
-    // loop nest whose taken branches differ from lane to lane
-    int kk[kList];
-    float ww[kList];
-    int nk = 0;
-    for (int jz = lo[2]; jz <= hi[2]; ++jz) {
-        const float wz = axis_weight<kNode>(e.dorigin[2], e.ddx, e.sorigin[2], e.sdx, jz, sxyz[2]);
-        if (wz == 0.0f) continue;
-        for (int jy = lo[1]; jy <= hi[1]; ++jy) {
-            const float wy = axis_weight<kNode>(e.dorigin[1], e.ddx, e.sorigin[1], e.sdx, jy, sxyz[1]);
-            if (wy == 0.0f) continue;
-            for (int jx = lo[0]; jx <= hi[0]; ++jx) {
-                const float wx = axis_weight<kNode>(e.dorigin[0], e.ddx, e.sorigin[0], e.sdx, jx, sxyz[0]);
-                if (wx == 0.0f) continue;
-                const int k = g.map[jx + e.dnx * (jy + e.dny * jz)];
-                if (k < 0) continue;
-                const float wt = (wx * wy) * wz;
+    if constexpr (kNarrow) {
+        // the (at most two) nonzero weights per axis, in increasing index order
+        int jj[3][2];
+        float wj[3][2];
+        int nj[3];
 #pragma unroll
-                for (int m = 0; m < kList; ++m)
-                    if (m == nk) {
-                        kk[m] = k;
-                        ww[m] = wt;
+        for (int d = 0; d < 3; ++d) {
+            jj[d][0] = jj[d][1] = 0;
+            wj[d][0] = wj[d][1] = 0.0f;
+            nj[d] = 0;
+#pragma unroll
+            for (int c = 0; c < kNarrowCand; ++c) {
+                const int j = lo[d] + c;
+                const float w = j <= hi[d] ? axis_weight<kNode>(dorg[d], e.ddx, sorg[d], e.sdx, j, sxyz[d]) : 0.0f;
+                if (w != 0.0f) {
+                    if (nj[d] == 0) {
+                        jj[d][0] = j;
+                        wj[d][0] = w;
+                    } else {
+                        jj[d][1] = j;
+                        wj[d][1] = w;
                     }
-                if (++nk == kList) {
-                    sum_columns<kScalar>(g, n_t, kk, ww, nk, acc, gacc);
-                    nk = 0;
+                    ++nj[d];
                 }
             }
         }
-    }
-    sum_columns<kScalar>(g, n_t, kk, ww, nk, acc, gacc);
-    for (int i = 0; i < Q; ++i) {
-        if (a.ca != 0.0f) a.lam_a[i * e.splane + s] += a.ca * acc[i];
-        if (a.cb != 0.0f) a.lam_b[i * e.splane + s] += a.cb * acc[i];
-    }
-    if (kScalar)
-        for (int i = 0; i < QS; ++i) {
-            if (a.ca != 0.0f) a.mu_a[i * e.splane + s] += a.ca * gacc[i];
-            if (a.cb != 0.0f) a.mu_b[i * e.splane + s] += a.cb * gacc[i];
+        // more than two (excluded on the host) would drop a target: loud
+        if (nj[0] > 2 || nj[1] > 2 || nj[2] > 2) acc[0] = __builtin_nanf("");
+        // the index map of all (up to eight) destination cells read at once,
+        // then the targets found packed in loop-nest order (z, y, x ascending)
+        int km[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int ix = c & 1, iy = (c >> 1) & 1, iz = c >> 2;
+            const bool ok = ix < nj[0] && iy < nj[1] && iz < nj[2];
+            const int k = g.map[ok ? jj[0][ix] + e.dnx * (jj[1][iy] + e.dny * jj[2][iz]) : 0];
+            km[c] = ok ? k : -1;
         }
+        int kk[8];
+        float ww[8];
+        int nk = 0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            kk[c] = 0;
+            ww[c] = 0.0f;
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            if (km[c] < 0) continue;
+            const float wt = (wj[0][c & 1] * wj[1][(c >> 1) & 1]) * wj[2][c >> 2];
+#pragma unroll
+            for (int m = 0; m <= c; ++m)
+                if (m == nk) {
+                    kk[m] = km[c];
+                    ww[m] = wt;
+                }
+            ++nk;
+        }
+        // columns summed kList targets at a time
+#pragma unroll
+        for (int base = 0; base < 8; base += kList) {
+            if (base >= nk) break;
+#pragma unroll
+            for (int m = base; m < base + kList && m < 8; ++m) {
+                if (m >= nk) break;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) acc[i] += ww[m] * g.vb[i * n_t + kk[m]];
+                if (kScalar)
+#pragma unroll
+                    for (int i = 0; i < QS; ++i) gacc[i] += ww[m] * g.vb[(Q + i) * n_t + kk[m]];
+            }
+        }
+    } else {
+        // wide window (destination spacing at most the source spacing): the
+        // (at most kG) nonzero weights along y and x, then per nonzero z
+        // plane the index map of its kG x kG destination cells read at once
+        int jy[kG], jx[kG];
+        float wy[kG], wx[kG];
+        const int ny = axis_nonzero<kG>(dorg[1], e.ddx, sorg[1], e.sdx, lo[1], hi[1], sxyz[1], jy, wy);
+        const int nx = axis_nonzero<kG>(dorg[0], e.ddx, sorg[0], e.sdx, lo[0], hi[0], sxyz[0], jx, wx);
+        if (nx > kG || ny > kG) acc[0] = __builtin_nanf("");   // excluded on the host
+        for (int jz = lo[2]; jz <= hi[2]; ++jz) {
+            const float wz = axis_weight<false>(dorg[2], e.ddx, sorg[2], e.sdx, jz, sxyz[2]);
+            if (wz == 0.0f) continue;
+            constexpr int kP = kG * kG;
+            int km[kP];
+#pragma unroll
+            for (int c = 0; c < kP; ++c) {
+                const int ix = c % kG, iy = c / kG;
+                const bool ok = ix < nx && iy < ny;
+                const int k = g.map[ok ? jx[ix] + e.dnx * (jy[iy] + e.dny * jz) : 0];
+                km[c] = ok ? k : -1;
+            }
+            // the targets found, packed in loop-nest order (y, x ascending)
+            int kk[kP];
+            float ww[kP];
+            int nk = 0;
+#pragma unroll
+            for (int c = 0; c < kP; ++c) {
+                kk[c] = 0;
+                ww[c] = 0.0f;
+            }
+#pragma unroll
+            for (int c = 0; c < kP; ++c) {
+                if (km[c] < 0) continue;
+                const float wt = (wx[c % kG] * wy[c / kG]) * wz;
+#pragma unroll
+                for (int m = 0; m <= c; ++m)
+                    if (m == nk) {
+                        kk[m] = km[c];
+                        ww[m] = wt;
+                    }
+                ++nk;
+            }
+            // one target at a time (a uniform index into the packed list)
+#pragma unroll 1
+            for (int m = 0; m < kP; ++m) {
+                if (m >= nk) break;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) acc[i] += ww[m] * g.vb[i * n_t + kk[m]];
+                if (kScalar)
+#pragma unroll
+                    for (int i = 0; i < QS; ++i) gacc[i] += ww[m] * g.vb[(Q + i) * n_t + kk[m]];
+            }
+        }
+    }
+    if (a.ca != 0.0f) add_column<kScalar>(a.lam_a, a.mu_a, e.splane, s, a.ca, acc, gacc);
+    if (a.cb != 0.0f) add_column<kScalar>(a.lam_b, a.mu_b, e.splane, s, a.cb, acc, gacc);
 }
 
 __global__ void __launch_bounds__(256) k_exadj_reset(int32_t* map, const int32_t* cells, int n)
@@ -605,15 +782,12 @@ __global__ void __launch_bounds__(256) k_exadj_tiled(const ExchAdjArgs a, const 
     if (!T.active) return;
     const int c = T.c;
     float lam[27], mu[QS] = {0, 0, 0, 0, 0, 0, 0};
-    for (int i = 0; i < Q; ++i) {
-        lam[tensor_slot(i)] = a.lam_d[i * e.dplane + c];
-        a.lam_d[i * e.dplane + c] = 0.0f;
-    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lam[tensor_slot(i)] = a.lam_d[i * e.dplane + c];
     if (kScalar)
-        for (int i = 0; i < QS; ++i) {
-            mu[i] = a.mu_d[i * e.dplane + c];
-            a.mu_d[i * e.dplane + c] = 0.0f;
-        }
+#pragma unroll
+        for (int i = 0; i < QS; ++i) mu[i] = a.mu_d[i * e.dplane + c];
+    clear_column<kScalar>(a.lam_d, a.mu_d, e.dplane, c);
     float vb[27], gb[QS];
     exchange_map_adjoint<kScalar>(v, gi, e.kappa, e.kappa_s, lam, mu, vb, gb);
     int ix[2], iy[2], iz[2];
@@ -622,8 +796,10 @@ __global__ void __launch_bounds__(256) k_exadj_tiled(const ExchAdjArgs a, const 
     if (interior) {
         const int64_t n_t = e.n_cells;
         const int k = T.k;
+#pragma unroll
         for (int i = 0; i < Q; ++i) g.vb[i * n_t + k] = vb[tensor_slot(i)];
         if (kScalar)
+#pragma unroll
             for (int i = 0; i < QS; ++i) g.vb[(Q + i) * n_t + k] = gb[i];
         g.map[c] = k;
 #pragma unroll
@@ -704,6 +880,35 @@ __global__ void __launch_bounds__(256) k_box_add(const float* x, float* z, int p
     }
 }
 
+// Most destination points with a nonzero weight on one source index along an
+// axis, for destination spacing r (in source cells, r <= 1).  The weights are
+// nonzero for q in (s - 1, s + 1 - 2^-25) (q the destination point in source
+// units; the upper end is where the FP32 fraction rounds to 1), so n points
+// need (n - 1) r' < 2 - 2^-25, r' the spacing of the computed q, within 1e-9
+// of r.
+static int max_nonzero_per_axis(double r)
+{
+    const double x = (2.0 - std::ldexp(1.0, -25)) / (r - 1e-9);
+    return (int)std::ceil(x);
+}
+
+// source pass with kG nonzero destination weights per axis at most (2:
+// narrow window over all three axes at once; 3, 4: per z plane)
+template <bool kScalar, bool kNode>
+static void launch_sources(const ExchAdjArgs& a, const GatherWs& g, const SrcBox& sb, int kg, dim3 sgrid,
+                           hipStream_t stream)
+{
+    const dim3 block(256);
+    if (kg <= 2)
+        hipLaunchKernelGGL((k_exadj_sources<kScalar, kNode, 2>), sgrid, block, 0, stream, a, g, sb);
+    else if (kNode)
+        return;   // coincident nodes always take the narrow window
+    else if (kg == 3)
+        hipLaunchKernelGGL((k_exadj_sources<kScalar, false, 3>), sgrid, block, 0, stream, a, g, sb);
+    else
+        hipLaunchKernelGGL((k_exadj_sources<kScalar, false, 4>), sgrid, block, 0, stream, a, g, sb);
+}
+
 // adjoint of launch_exchange(src, fA, fB, w, dst, ..., cells): the
 // destination adjoint lam_d (mu_d) at the cells goes to the source adjoints
 static int launch_exchange_adjoint(const cslbm_level* src, const void* fA, const void* fB,
@@ -727,11 +932,17 @@ static int launch_exchange_adjoint(const cslbm_level* src, const void* fA, const
     a.mu_b = mu_b;
     a.ca = w >= 1.0 ? 0.0f : (float)(1.0 - w);
     a.cb = w <= 0.0 ? 0.0f : (float)w;
-    const bool node = nodes_coincide(src, dst);
     const dim3 grid(grid_for(n_cells)), block(256);
     // The candidate window of the gather pass spans q(j) in [s - 1, s + 1)
     // plus one index each side: 2 src->dx / dst->dx + 4 indices at most.
-    if (gw && 2.0 * src->dx / dst->dx + 4.0 <= (double)kMaxCand) {
+    // Per axis the nonzero weights of a source index belong to the
+    // destination points q in (s - 1, s + 1) (source units; nodes:
+    // [s - 1/2, s + 1/2)), spaced r = dst dx / src dx apart: at most two for
+    // r > 1 or nodes, else max_nonzero_per_axis(r) (4 for r = 1/2).
+    const double r = dst->dx / src->dx;
+    const bool node = nodes_coincide(src, dst);
+    const int kg = (node || r > 1.0 + 1e-6) ? 2 : max_nonzero_per_axis(r);
+    if (gw && 2.0 * src->dx / dst->dx + 4.0 <= (double)kMaxCand && kg <= 4) {
         const GatherWs g = *gw;
         const SrcBox sb = source_box(src, dst);
         const int64_t n_box = (int64_t)sb.nx * sb.ny * sb.nz;
@@ -750,9 +961,9 @@ static int launch_exchange_adjoint(const cslbm_level* src, const void* fA, const
             else
                 hipLaunchKernelGGL(k_exadj_tiled<false>, rgrid, block, 0, stream, t, g, runs);
             if (scalar)
-                hipLaunchKernelGGL((k_exadj_sources<true, false>), sgrid, block, 0, stream, a, g, sb);
+                launch_sources<true, false>(a, g, sb, kg, sgrid, stream);
             else
-                hipLaunchKernelGGL((k_exadj_sources<false, false>), sgrid, block, 0, stream, a, g, sb);
+                launch_sources<false, false>(a, g, sb, kg, sgrid, stream);
             hipLaunchKernelGGL(k_exadj_reset, grid, block, 0, stream, g.map, cells, n_cells);
             return check_launch("k_exchange_adjoint (tiled gather)");
         }
@@ -762,7 +973,7 @@ static int launch_exchange_adjoint(const cslbm_level* src, const void* fA, const
         else                                                                                   \
             hipLaunchKernelGGL((k_exadj_interp<S_, N_, false>), grid, block, 0, stream, a, g); \
         hipLaunchKernelGGL((k_exadj_vjp<S_, N_>), grid, block, 0, stream, a, g);              \
-        hipLaunchKernelGGL((k_exadj_sources<S_, N_>), sgrid, block, 0, stream, a, g, sb);
+        launch_sources<S_, N_>(a, g, sb, kg, sgrid, stream);
         if (scalar && node) {
             CSLBM_GATHER(true, true)
         } else if (scalar) {

@@ -506,7 +506,9 @@ int64_t cslbm_multiscale_adjoint_bytes(const cslbm_hierarchy* H);
  *                     does (their old values never enter the step); all
  *                     other elements are read only
  *   lam[i], mu[i]     in: dL/d(state of scale i at t_n + dt_0) [27|7][plane];
- *                     out: dL/d(state of scale i at t_n)
+ *                     out: dL/d(state of scale i at t_n) (the elements of a
+ *                     plane past its nx*ny*nz cells are no part of it and
+ *                     are left unspecified)
  *   workspace         DEVICE, at least cslbm_multiscale_adjoint_bytes(H)
  * The forward step is recomputed from f_in into the workspace (the level
  * structs' own f / f_next / work buffers are not touched), the flags, lists,

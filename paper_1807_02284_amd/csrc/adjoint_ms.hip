@@ -863,21 +863,46 @@ static bool source_box_holds_stencils(const cslbm_level* src, const cslbm_level*
     return true;
 }
 
-// z (planes of `plane` elements) += x over the cells of box b of an nx x ny
-// level, or z = 0 there when x is null: one thread per box cell (boxes are
-// validated below 2^31 cells), all planes
-__global__ void __launch_bounds__(256) k_box_add(const float* x, float* z, int planes, int64_t plane, int nx,
-                                                 int ny, const SrcBox b)
+// z = 0 over the cells of box b of an nx x ny level, all `planes` planes of
+// `plane` elements: one thread per box cell (boxes are validated below 2^31
+// cells)
+__global__ void __launch_bounds__(256) k_box_zero(float* z, int planes, int64_t plane, int nx, int ny,
+                                                  const SrcBox b)
 {
     const unsigned r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= (unsigned)b.nx * b.ny * b.nz) return;
     const unsigned bxy = (unsigned)b.nx * b.ny;
     const int cx = b.x0 + (int)(r % b.nx), cy = b.y0 + (int)((r / b.nx) % b.ny), cz = b.z0 + (int)(r / bxy);
     const int64_t c = cx + (int64_t)nx * (cy + (int64_t)ny * cz);
-    for (int pl = 0; pl < planes; ++pl) {
-        const int64_t e = pl * plane + c;
-        z[e] = x ? z[e] + x[e] : 0.0f;
+    for (int pl = 0; pl < planes; ++pl) z[pl * plane + c] = 0.0f;
+}
+
+// z = x, plus y over the cells of box b, for the kPlanes planes of every
+// cell of an nx x ny x nz level (one thread per cell, grid of the step
+// kernels; all loads before the first store)
+template <int kPlanes>
+__global__ void __launch_bounds__(256) k_copy_add_box(const float* x, const float* y, float* z, int64_t plane,
+                                                      int nx, int ny, const SrcBox b)
+{
+    const int cx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int cy = blockIdx.y * blockDim.y + threadIdx.y;
+    const int cz = blockIdx.z;
+    if (cx >= nx || cy >= ny) return;
+    const int64_t c = cx + (int64_t)nx * (cy + (int64_t)ny * cz);
+    const bool in_box = (unsigned)(cx - b.x0) < (unsigned)b.nx && (unsigned)(cy - b.y0) < (unsigned)b.ny &&
+                        (unsigned)(cz - b.z0) < (unsigned)b.nz;
+    float v[kPlanes];
+#pragma unroll
+    for (int i = 0; i < kPlanes; ++i) v[i] = x[i * plane + c];
+    if (in_box) {
+        float u[kPlanes];
+#pragma unroll
+        for (int i = 0; i < kPlanes; ++i) u[i] = y[i * plane + c];
+#pragma unroll
+        for (int i = 0; i < kPlanes; ++i) v[i] += u[i];
     }
+#pragma unroll
+    for (int i = 0; i < kPlanes; ++i) z[i * plane + c] = v[i];
 }
 
 // Most destination points with a nonzero weight on one source index along an
@@ -1303,9 +1328,8 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
         if (i == 0 && ref_boxed) {
             const int64_t nb = (int64_t)ref_box.nx * ref_box.ny * ref_box.nz;
             if (nb > 0)
-                hipLaunchKernelGGL(k_box_add, dim3(grid_for(nb)), dim3(256), 0, stream, nullptr,
-                                   W.lamA[0].f, planes0, S[0].level.plane, S[0].level.nx, S[0].level.ny,
-                                   ref_box);
+                hipLaunchKernelGGL(k_box_zero, dim3(grid_for(nb)), dim3(256), 0, stream, W.lamA[0].f, planes0,
+                                   S[0].level.plane, S[0].level.nx, S[0].level.ny, ref_box);
         } else {
             hipLaunchKernelGGL(k_zero, dim3(grid_for(nelem(i))), dim3(256), 0, stream, W.lamA[i].f, nelem(i));
         }
@@ -1382,17 +1406,14 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
         if (rc) return rc;
         const int64_t nf = (int64_t)Q * L->plane, ngs = (int64_t)QS * L->plane;
         if (ref_boxed) {
-            CSLBM_HIP_TRY(hipMemcpyAsync(lam[0], W.t1[0].f, nf * 4, hipMemcpyDeviceToDevice, stream));
+            // lam[0] = t1, plus lamA[0] over the box where it can be nonzero
+            const dim3 cb = step_block(L->nx);
+            const dim3 cg((L->nx + cb.x - 1) / cb.x, (L->ny + cb.y - 1) / cb.y, L->nz);
+            hipLaunchKernelGGL(k_copy_add_box<Q>, cg, cb, 0, stream, W.t1[0].f, W.lamA[0].f, lam[0], L->plane,
+                               L->nx, L->ny, ref_box);
             if (scalar)
-                CSLBM_HIP_TRY(hipMemcpyAsync(mu[0], W.t1[0].g, ngs * 4, hipMemcpyDeviceToDevice, stream));
-            const int64_t nb = (int64_t)ref_box.nx * ref_box.ny * ref_box.nz;
-            if (nb > 0) {
-                hipLaunchKernelGGL(k_box_add, dim3(grid_for(nb)), dim3(256), 0, stream, W.lamA[0].f, lam[0], Q,
+                hipLaunchKernelGGL(k_copy_add_box<QS>, cg, cb, 0, stream, W.t1[0].g, W.lamA[0].g, mu[0],
                                    L->plane, L->nx, L->ny, ref_box);
-                if (scalar)
-                    hipLaunchKernelGGL(k_box_add, dim3(grid_for(nb)), dim3(256), 0, stream, W.lamA[0].g, mu[0],
-                                       QS, L->plane, L->nx, L->ny, ref_box);
-            }
         } else {
             hipLaunchKernelGGL(k_sum, dim3(grid_for(nf)), dim3(256), 0, stream, W.t1[0].f, W.lamA[0].f, lam[0], nf);
             if (scalar)

@@ -166,14 +166,18 @@ __global__ void k_set_pop(T* f, float* g, int64_t N, int64_t P, const float* src
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= N) return;
+    float v[Q], u[QS];   // all loads before the first store
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const float v = src[i * N + c];
-        Io<T>::st(f + i * P + c, shifted ? v : v - weight(i));
-    }
-    if (g && gsrc)
+    for (int i = 0; i < Q; ++i) v[i] = src[i * N + c];
+    const bool scalar = g && gsrc;
+    if (scalar)
 #pragma unroll
-        for (int i = 0; i < QS; ++i) g[i * P + c] = gsrc[i * N + c];
+        for (int i = 0; i < QS; ++i) u[i] = gsrc[i * N + c];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) Io<T>::st(f + i * P + c, shifted ? v[i] : v[i] - weight(i));
+    if (scalar)
+#pragma unroll
+        for (int i = 0; i < QS; ++i) g[i * P + c] = u[i];
 }
 
 // Population copy between two levels of one storage type, cell list to
@@ -186,11 +190,20 @@ __global__ void __launch_bounds__(256) k_copy_cells(const T* f, const float* g, 
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int64_t a = src[k], b = dst[k];
+    // all loads before the first store: a store between them would order
+    // each later load after it (the compiler cannot rule out overlap)
+    T v[Q];
+    float u[QS];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) fo[i * Po + b] = f[i * P + a];
+    for (int i = 0; i < Q; ++i) v[i] = f[i * P + a];
     if (g)
 #pragma unroll
-        for (int i = 0; i < QS; ++i) go[i * Po + b] = g[i * P + a];
+        for (int i = 0; i < QS; ++i) u[i] = g[i * P + a];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) fo[i * Po + b] = v[i];
+    if (g)
+#pragma unroll
+        for (int i = 0; i < QS; ++i) go[i * Po + b] = u[i];
 }
 
 template <typename T>
@@ -199,14 +212,18 @@ __global__ void k_get_pop(const T* f, const float* g, int64_t N, int64_t P, floa
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= N) return;
+    float h[Q], u[QS];   // all loads before the first store
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const float h = Io<T>::ld(f + i * P + c);
-        dst[i * N + c] = shifted ? h : h + weight(i);
-    }
-    if (g && gdst)
+    for (int i = 0; i < Q; ++i) h[i] = Io<T>::ld(f + i * P + c);
+    const bool scalar = g && gdst;
+    if (scalar)
 #pragma unroll
-        for (int i = 0; i < QS; ++i) gdst[i * N + c] = g[i * P + c];
+        for (int i = 0; i < QS; ++i) u[i] = g[i * P + c];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dst[i * N + c] = shifted ? h[i] : h[i] + weight(i);
+    if (scalar)
+#pragma unroll
+        for (int i = 0; i < QS; ++i) gdst[i * N + c] = u[i];
 }
 
 template <typename T>

@@ -268,17 +268,34 @@ __global__ void __launch_bounds__(256) k_time_interp(const T* s0, const T* s1, c
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= N) return;
+    // nine planes at a time, all their loads before their stores (a store
+    // between loads would order each later load after it; the output may be
+    // one of the inputs, element for element)
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int64_t e = i * P + c;
-        Io<T>::st(out + e, l0 * Io<T>::ld(s0 + e) + l1 * Io<T>::ld(s1 + e) + l2 * Io<T>::ld(s2 + e));
+    for (int i0 = 0; i0 < Q; i0 += 9) {
+        float a[9], b[9], d[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const int64_t e = (i0 + i) * P + c;
+            a[i] = Io<T>::ld(s0 + e);
+            b[i] = Io<T>::ld(s1 + e);
+            d[i] = Io<T>::ld(s2 + e);
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Io<T>::st(out + (i0 + i) * P + c, l0 * a[i] + l1 * b[i] + l2 * d[i]);
     }
-    if (gout)
+    if (gout) {
+        float a[QS], b[QS], d[QS];
 #pragma unroll
         for (int i = 0; i < QS; ++i) {
             const int64_t e = i * P + c;
-            gout[e] = l0 * g0[e] + l1 * g1[e] + l2 * g2[e];
+            a[i] = g0[e];
+            b[i] = g1[e];
+            d[i] = g2[e];
         }
+#pragma unroll
+        for (int i = 0; i < QS; ++i) gout[i * P + c] = l0 * a[i] + l1 * b[i] + l2 * d[i];
+    }
 }
 
 // ---------------------------------------------------------------------------

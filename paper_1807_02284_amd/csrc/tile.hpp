@@ -19,6 +19,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <climits>
 
 #include "exchange.hpp"
@@ -30,6 +32,22 @@ namespace cslbm {
 constexpr int kTileCap = 1280;                // floats per plane buffer
 constexpr int kTileLoads = kTileCap / 256;    // buffer elements per thread
 constexpr int kTilePlanes = 4;                // planes staged per barrier round trip
+
+__device__ __forceinline__ uint32_t raw_bits(float v) { return __float_as_uint(v); }
+__device__ __forceinline__ uint32_t raw_bits(_Float16 v) { return __builtin_bit_cast(uint16_t, v); }
+
+template <typename T>
+__device__ __forceinline__ float from_bits(uint32_t b);
+template <>
+__device__ __forceinline__ float from_bits<float>(uint32_t b)
+{
+    return __uint_as_float(b);
+}
+template <>
+__device__ __forceinline__ float from_bits<_Float16>(uint32_t b)
+{
+    return static_cast<float>(__builtin_bit_cast(_Float16, (uint16_t)b));
+}
 
 struct TileLds {
     float buf[kTilePlanes * kTileCap];
@@ -142,16 +160,25 @@ __device__ __forceinline__ bool tile_interp(const ExchArgs& a, const int32_t* ru
     // summed from LDS
     constexpr int NP = kScalar ? Q + QS : Q;
     constexpr int NG = (NP + kTilePlanes - 1) / kTilePlanes;
-    float pre[kTilePlanes][kTileLoads];
+    // binary16 elements stay raw bits until the LDS write: converted where
+    // they were loaded, each load was waited for before the next was issued
+    constexpr bool kHalf = std::is_same<Ts, _Float16>::value;
+    using Pre = typename std::conditional<kHalf, uint32_t, float>::type;
+    Pre pre[kTilePlanes][kTileLoads];
     auto fetch = [&](int grp) {
 #pragma unroll
         for (int p = 0; p < kTilePlanes; ++p) {
             const int i = grp * kTilePlanes + p;
             if (i < NP)
 #pragma unroll
-                for (int k = 0; k < kTileLoads; ++k)
-                    pre[p][k] = i < Q ? Io<Ts>::ld(fA + i * P + origin + eoff[k])
-                                      : qA[(i - Q) * P + origin + eoff[k]];
+                for (int k = 0; k < kTileLoads; ++k) {
+                    if constexpr (kHalf)
+                        pre[p][k] = i < Q ? raw_bits(*(fA + i * P + origin + eoff[k]))
+                                          : raw_bits(qA[(i - Q) * P + origin + eoff[k]]);
+                    else
+                        pre[p][k] = i < Q ? Io<Ts>::ld(fA + i * P + origin + eoff[k])
+                                          : qA[(i - Q) * P + origin + eoff[k]];
+                }
         }
     };
     fetch(0);
@@ -162,7 +189,14 @@ __device__ __forceinline__ bool tile_interp(const ExchArgs& a, const int32_t* ru
         for (int p = 0; p < kTilePlanes; ++p)
             if (grp * kTilePlanes + p < NP)
 #pragma unroll
-                for (int k = 0; k < kTileLoads; ++k) L.buf[p * kTileCap + tid + 256 * k] = pre[p][k];
+                for (int k = 0; k < kTileLoads; ++k) {
+                    if constexpr (kHalf)
+                        L.buf[p * kTileCap + tid + 256 * k] = grp * kTilePlanes + p < Q
+                                                                  ? from_bits<_Float16>(pre[p][k])
+                                                                  : from_bits<float>(pre[p][k]);
+                    else
+                        L.buf[p * kTileCap + tid + 256 * k] = pre[p][k];
+                }
         __syncthreads();
         if (grp + 1 < NG) fetch(grp + 1);
 #pragma unroll

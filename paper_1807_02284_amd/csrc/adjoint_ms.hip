@@ -306,33 +306,82 @@ template <bool kScalar, bool kNode, bool kBlend>
 __global__ void __launch_bounds__(256) k_exadj_interp(const ExchAdjArgs a, const GatherWs g)
 {
     const ExchArgs& e = a.e;
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= e.n_cells) return;
+    // without blending the host passes the time level that carries the weight
+    const bool use_b = !kBlend && a.cb != 0.0f;
+    // the segment of this block (uniform): a staged copy of the parent's
+    // columns around one x-face of the shell, or the source level itself
+    int blk = blockIdx.x;
+    const float* fA = static_cast<const float*>(use_b ? e.fB : e.fA);
+    const float* fB = static_cast<const float*>(e.fB);
+    const float* gA = use_b ? e.gB : e.gA;
+    const float* gB = e.gB;
+    int sn[3] = {e.snx, e.sny, e.snz};
+    int off[3] = {0, 0, 0};
+    int64_t splane = e.splane;
+    int first = e.main_first, count = e.n_cells - e.main_first;
+    bool staged = false;
+#pragma unroll
+    for (int sgi = 0; sgi < 2; ++sgi) {
+        if (staged || sgi >= e.n_staged) continue;
+        if (blk < e.st[sgi].blocks) {
+            const ExchArgs::Staged& st = e.st[sgi];
+            fA = static_cast<const float*>(use_b ? st.fB : st.fA);
+            fB = static_cast<const float*>(st.fB);
+            gA = use_b ? st.gB : st.gA;
+            gB = st.gB;
+            sn[0] = st.nx;
+            sn[1] = st.ny;
+            sn[2] = st.nz;
+            off[0] = st.off[0];
+            off[1] = st.off[1];
+            off[2] = st.off[2];
+            splane = st.plane;
+            first = st.first;
+            count = st.count;
+            staged = true;
+        } else {
+            blk -= e.st[sgi].blocks;
+        }
+    }
+    const int kl = blk * blockDim.x + threadIdx.x;
+    if (kl >= count) return;
+    const int k = first + kl;
     const int c = e.cells[k];
     int ix[2], iy[2], iz[2];
     float t[3];
     const bool interior = target_corners<kNode>(e, c, ix, iy, iz, t);
-    // without blending the host passes the time level that carries the weight
-    const float* fA = static_cast<const float*>(kBlend || a.cb == 0.0f ? e.fA : e.fB);
-    const float* fB = static_cast<const float*>(e.fB);
-    const float* gA = kBlend || a.cb == 0.0f ? e.gA : e.gB;
-    const float* gB = e.gB;
+    // corners in the segment's storage (a staged copy holds only its face's
+    // stencils: a corner outside it makes the target NaN)
+    int lx[2], ly[2], lz[2];
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+        lx[o] = ix[o] - off[0];
+        ly[o] = iy[o] - off[1];
+        lz[o] = iz[o] - off[2];
+    }
+    const bool outside = staged && (min(lx[0], lx[1]) < 0 || max(lx[0], lx[1]) >= sn[0] || min(ly[0], ly[1]) < 0 ||
+                                    max(ly[0], ly[1]) >= sn[1] || min(lz[0], lz[1]) < 0 ||
+                                    max(lz[0], lz[1]) >= sn[2]);
     const float w = e.w;
     constexpr int kCorners = kNode ? 1 : 8;
     float v[27];
 #pragma unroll
     for (int q = 0; q < 27; ++q) v[q] = 0.0f;
     float gi[QS] = {0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
+    // four corners per pass (two blended: 136 loads in flight either way),
+    // summed in order 0..7
+    constexpr int kPass = kBlend ? 2 : 4;
+#pragma unroll kPass
     for (int corner = 0; corner < kCorners; ++corner) {
         const float wt = corner_weight(t, corner);
-        const int64_t sc = ix[corner & 1] + (int64_t)e.snx * (iy[(corner >> 1) & 1] +
-                                                              (int64_t)e.sny * iz[(corner >> 2) & 1]);
+        const int64_t sc = outside ? 0
+                                   : lx[corner & 1] + (int64_t)sn[0] * (ly[(corner >> 1) & 1] +
+                                                                        (int64_t)sn[1] * lz[(corner >> 2) & 1]);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const float hA = fA[i * e.splane + sc];
+            const float hA = fA[i * splane + sc];
             if (kBlend) {
-                const float hB = fB[i * e.splane + sc];
+                const float hB = fB[i * splane + sc];
                 v[i] += wt * ((1.0f - w) * hA + w * hB);
             } else {
                 v[i] += wt * hA;
@@ -341,15 +390,16 @@ __global__ void __launch_bounds__(256) k_exadj_interp(const ExchAdjArgs a, const
         if (kScalar)
 #pragma unroll
             for (int i = 0; i < QS; ++i) {
-                const float g0 = gA[i * e.splane + sc];
+                const float g0 = gA[i * splane + sc];
                 if (kBlend) {
-                    const float g1 = gB[i * e.splane + sc];
+                    const float g1 = gB[i * splane + sc];
                     gi[i] += wt * ((1.0f - w) * g0 + w * g1);
                 } else {
                     gi[i] += wt * g0;
                 }
             }
     }
+    if (outside) v[13] = __builtin_nanf("");
     const int64_t n_t = e.n_cells;
 #pragma unroll
     for (int i = 0; i < Q; ++i) g.vb[i * n_t + k] = v[i];
@@ -934,6 +984,22 @@ static void launch_sources(const ExchAdjArgs& a, const GatherWs& g, const SrcBox
         hipLaunchKernelGGL((k_exadj_sources<kScalar, false, 4>), sgrid, block, 0, stream, a, g, sb);
 }
 
+// Whether scale i's x-face stage overlaps another scale's (a caller may let
+// scales share one): then the recompute's copy for scale i may be gone.
+static bool stage_shared(const cslbm_scale* S, int ns, int i)
+{
+    if (!S[i].stage) return false;
+    const char* a0 = static_cast<const char*>(S[i].stage);
+    const char* a1 = a0 + S[i].stage_bytes;
+    for (int j = 0; j < ns; ++j) {
+        if (j == i || !S[j].stage) continue;
+        const char* b0 = static_cast<const char*>(S[j].stage);
+        const char* b1 = b0 + S[j].stage_bytes;
+        if (a0 < b1 && b0 < a1) return true;
+    }
+    return false;
+}
+
 // adjoint of launch_exchange(src, fA, fB, w, dst, ..., cells): the
 // destination adjoint lam_d (mu_d) at the cells goes to the source adjoints
 static int launch_exchange_adjoint(const cslbm_level* src, const void* fA, const void* fB,
@@ -942,13 +1008,18 @@ static int launch_exchange_adjoint(const cslbm_level* src, const void* fA, const
                                    float* lam_a, float* lam_b, float* mu_a, float* mu_b,
                                    const int32_t* cells, int32_t n_cells, const GatherWs* gw,
                                    hipStream_t stream, const int32_t* runs = nullptr,
-                                   int32_t n_runs = 0)
+                                   int32_t n_runs = 0, const cslbm_scale* stage_sc = nullptr,
+                                   bool staged = false)
 {
     if (n_cells == 0) return CSLBM_OK;
     const bool scalar = gA != nullptr && mu_d != nullptr;
     ExchAdjArgs a;
     a.e = exchange_args(src, fA, fB, scalar ? gA : nullptr, scalar ? gB : nullptr, w, dst, nullptr,
                         scalar ? mu_d : nullptr, cells, n_cells);
+    // a prior-mapping of stage_sc's shell whose x-face entries the forward
+    // step read from the staged copies: the interpolation pass reads them
+    // there too (the same values, contiguous)
+    if (stage_sc) prior_segments(*stage_sc, staged, src, a.e);
     a.lam_d = lam_d;
     a.mu_d = scalar ? mu_d : nullptr;
     a.lam_a = lam_a;
@@ -992,11 +1063,15 @@ static int launch_exchange_adjoint(const cslbm_level* src, const void* fA, const
             hipLaunchKernelGGL(k_exadj_reset, grid, block, 0, stream, g.map, cells, n_cells);
             return check_launch("k_exchange_adjoint (tiled gather)");
         }
+        // the interpolation pass runs the staged segments' blocks first
+        int64_t iblocks = (n_cells - a.e.main_first + 255) / 256;
+        for (int sgi = 0; sgi < a.e.n_staged; ++sgi) iblocks += a.e.st[sgi].blocks;
+        const dim3 igrid((unsigned)iblocks);
 #define CSLBM_GATHER(S_, N_)                                                                   \
         if (blend)                                                                             \
-            hipLaunchKernelGGL((k_exadj_interp<S_, N_, true>), grid, block, 0, stream, a, g);  \
+            hipLaunchKernelGGL((k_exadj_interp<S_, N_, true>), igrid, block, 0, stream, a, g); \
         else                                                                                   \
-            hipLaunchKernelGGL((k_exadj_interp<S_, N_, false>), grid, block, 0, stream, a, g); \
+            hipLaunchKernelGGL((k_exadj_interp<S_, N_, false>), igrid, block, 0, stream, a, g); \
         hipLaunchKernelGGL((k_exadj_vjp<S_, N_>), grid, block, 0, stream, a, g);              \
         launch_sources<S_, N_>(a, g, sb, kg, sgrid, stream);
         if (scalar && node) {
@@ -1250,6 +1325,7 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
     auto nelem = [&](int i) { return ((int64_t)Q + (scalar ? QS : 0)) * S[i].level.plane; };
 
     // ---- forward recompute of the reference step from the states at t_n ----
+    bool stage_used[CSLBM_MAX_SCALES] = {};
     const void* A[CSLBM_MAX_SCALES];
     const void* B[CSLBM_MAX_SCALES];
     const float* gA[CSLBM_MAX_SCALES];
@@ -1276,6 +1352,7 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
         bool staged = false;
         rc = prior_stage(sc, P, A[p], B[p], gA[p], gB[p], &staged, stream);
         if (rc) return rc;
+        stage_used[i] = staged;
         for (int k = 1; k <= ss.last; ++k) {
             const Buf& cur = W.cur[i][k - 1];
             rc = prior_map(sc, staged, P, A[p], B[p], gA[p], gB[p], prior_weight(k, ss.l, ss.alpha),
@@ -1350,10 +1427,20 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
                                          sc.post_tiles[j], sc.n_post_tiles[j]);
             if (rc) return rc;
         }
+        // the parent's columns around the shell's x-faces as the recompute
+        // staged them: still in place unless another scale's stage overlaps
+        // this one's (then staged again)
+        bool staged = false;
+        if (stage_shared(S, ns, i)) {
+            rc = prior_stage(sc, P, A[p], B[p], gA[p], gB[p], &staged, stream);
+            if (rc) return rc;
+        } else {
+            staged = stage_used[i];
+        }
         // ghost shell of the interpolated state, mapped at weight 1
         rc = launch_exchange_adjoint(P, A[p], B[p], gA[p], gB[p], 1.0, L, lamR, muR, W.lamA[p].f,
                                      lam[p], W.lamA[p].g, scalar ? mu[p] : nullptr, sc.ghost_cells,
-                                     sc.n_ghost, gw, stream);
+                                     sc.n_ghost, gw, stream, nullptr, 0, &sc, staged);
         if (rc) return rc;
         // last sub-step: R = l0 cur_1 + l1 cur_l + l2 step(cur_l), or R = step(cur_last)
         const int64_t nf = (int64_t)Q * L->plane, ngs = (int64_t)QS * L->plane;
@@ -1384,7 +1471,7 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
             rc = launch_exchange_adjoint(P, A[p], B[p], gA[p], gB[p], prior_weight(k, ss.l, ss.alpha), L, lc.f,
                                          lc.g, W.lamA[p].f, lam[p], W.lamA[p].g,
                                          scalar ? mu[p] : nullptr, sc.ghost_cells, sc.n_ghost, gw,
-                                         stream);
+                                         stream, nullptr, 0, &sc, staged);
             if (rc) return rc;
             if (k == 1) break;
             const Buf out = ((k - 2) % 2 == 0) ? out_final : W.t2[i];

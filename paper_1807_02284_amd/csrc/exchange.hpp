@@ -207,6 +207,9 @@ int prior_stage(const cslbm_scale& sc, const cslbm_level* P, const void* A, cons
                 const float* gA, const float* gB, bool* staged, hipStream_t stream);
 int prior_map(const cslbm_scale& sc, bool staged, const cslbm_level* P, const void* A, const void* B,
               const float* gA, const float* gB, double w, void* out, float* gout, hipStream_t stream);
+// The staged segments of that prior-mapping (a built by exchange_args over
+// sc's ghost list): false, a unchanged, when it is not staged.
+bool prior_segments(const cslbm_scale& sc, bool staged, const cslbm_level* P, ExchArgs& a);
 
 // Adjoint of one collide-stream step of level L from the input state
 // (fin, gin): lam = dL/d(input) from lam_next = dL/d(output) (likewise mu for

@@ -500,6 +500,8 @@ static int stage_faces(const cslbm_level* P, const StagePlan& sp, const void* A,
     return check_launch("k_stage");
 }
 
+static void set_stage_segments(const StagePlan& sp, char* stage, int32_t n_xlo, int32_t n_xhi, ExchArgs& a);
+
 // Prior-mapping of a shell whose list starts with the n_xlo + n_xhi ghosts
 // of its two planes normal to x: those read the staged copies (one segment
 // per plane), the rest the parent itself, all in one launch.
@@ -510,6 +512,15 @@ static int launch_prior_staged(const cslbm_level* P, const StagePlan& sp, char* 
 {
     if (n_cells == 0) return CSLBM_OK;
     ExchArgs a = exchange_args(P, A, B, gA, gB, w, dst, f_out, g_out, cells, n_cells);
+    set_stage_segments(sp, stage, n_xlo, n_xhi, a);
+    return launch_exchange_args(a, P, dst, w, stream);
+}
+
+// The staged segments of a shell's list (the n_xlo + n_xhi x-face entries
+// first) over the faces of plan sp in stage; the scalar sections only when
+// a carries the scalar.
+static void set_stage_segments(const StagePlan& sp, char* stage, int32_t n_xlo, int32_t n_xhi, ExchArgs& a)
+{
     const bool scalar = a.gA != nullptr;
     char* face = stage;
     int first = 0;
@@ -533,7 +544,14 @@ static int launch_prior_staged(const cslbm_level* P, const StagePlan& sp, char* 
         face += F.bytes;
     }
     a.main_first = first;
-    return launch_exchange_args(a, P, dst, w, stream);
+}
+
+bool prior_segments(const cslbm_scale& sc, bool staged, const cslbm_level* P, ExchArgs& a)
+{
+    StagePlan sp;
+    if (!staged || !stage_plan(P, &sc.level, sc.ghost_xlo, sc.ghost_xhi, &sp)) return false;
+    set_stage_segments(sp, static_cast<char*>(sc.stage), sc.n_ghost_xlo, sc.n_ghost_xhi, a);
+    return true;
 }
 
 int prior_stage(const cslbm_scale& sc, const cslbm_level* P, const void* A, const void* B,

@@ -453,6 +453,51 @@ def test_tiled_post_mapping_adjoint_gives_bitwise_the_gathered_adjoint():
         np.testing.assert_array_equal(a, b)
 
 
+def test_staged_shell_interpolation_gives_bitwise_the_unstaged_adjoint():
+    """The interpolation pass of the ghost-shell adjoints reads the x-face
+    entries from the staged copies of the parent's columns, as the forward
+    step does: one multi-scale adjoint step of the reduced plume is bitwise
+    that of the hierarchy without staging, with a stage per scale (the
+    recompute's copies are read) and with one stage shared by both finer
+    scales (each scale's copy is made again before its adjoints)."""
+    nx, ny, nz = 96, 48, 48
+    specs = plume_specs(nx, ny, nz, 1e-3)
+    out = []
+    for mode in ("private", "shared", "unstaged"):
+        staged = mode != "unstaged"
+        levs = []
+        for sp in specs:
+            rho, u, s = smooth_state(sp, 40)
+            u[0] += 0.04
+            lev = sp.level(True)
+            lev.init_equilibrium(rho, u, s)
+            levs.append(lev)
+        H = hierarchy.Hierarchy(levs, [sp.kinds for sp in specs], [sp.parent for sp in specs],
+                                stage_xfaces=staged)
+        for i in (1, 2):
+            sc = H.c_scales[i]
+            assert bool(sc.stage) == staged and (sc.n_ghost_xlo > 0) == staged
+        if mode == "shared":
+            shared = torch.empty(max(H.c_scales[i].stage_bytes for i in (1, 2)), dtype=torch.uint8,
+                                 device="cuda")
+            for i in (1, 2):
+                H.c_scales[i].stage = shared.data_ptr()
+        H.step(2)
+        f_in = [lev.f.clone() for lev in levs]
+        g_in = [lev.g.clone() for lev in levs]
+        gen = torch.Generator(device="cuda").manual_seed(7)
+        lam = [torch.randn(27 * lev.plane, device="cuda", generator=gen) for lev in levs]
+        mu = [torch.randn(7 * lev.plane, device="cuda", generator=gen) for lev in levs]
+        ws = torch.empty(H.adjoint_workspace_bytes(), dtype=torch.uint8, device="cuda")
+        H.adjoint_step(f_in, g_in, lam, mu, ws)
+        torch.cuda.synchronize()
+        out.append([x.cpu().numpy() for x in lam + mu])
+        assert all(np.all(np.isfinite(x)) for x in out[-1])
+    for other in out[:2]:
+        for a, b in zip(other, out[2]):
+            np.testing.assert_array_equal(a, b)
+
+
 def test_multiscale_adjoint_scope_is_checked():
     specs = chain_specs()
     specs[2].parent = 0                       # not a chain

@@ -218,6 +218,82 @@ def post_tile_runs(cells: np.ndarray, shape, ratio: float, tile=None, order: str
     return c.astype(np.int32), offsets
 
 
+POST_PLATE_KEEP = 0.75   # a plate tile is kept when at least this fraction of its cells is listed
+
+
+def _tile_source_cells(t, ratio: float) -> int:
+    """Source cells the stencils of a tx x ty x tz tile can reach: per axis
+    two planes for one target, else floor((t - 1) ratio) + 3 (one more for
+    the rounding of the stencil base)."""
+    n = 1
+    for d in t:
+        n *= 2 if d == 1 else math.floor((d - 1) * ratio) + 3
+    return n
+
+
+def _plate_tile(axis: int, ratio: float):
+    """The largest tile two cells deep along ``axis`` (at most 256 cells,
+    its source box within the kernel's buffer), longest along x first."""
+    best = None
+    for a in range(64, 0, -1):
+        for b in range(min(128 // a, 64), 0, -1):
+            t = [a, b]
+            t.insert(axis, 2)
+            if _tile_source_cells(t, ratio) <= POST_TILE_BUFFER:
+                key = (a * b, a)
+                if best is None or key > best[0]:
+                    best = (key, tuple(t))
+                break
+    return best[1]
+
+
+def plate_tile_runs(cells: np.ndarray, shape, ratio: float):
+    """A post-mapping list that lies in plates a few cells thick (the margin
+    between nested boxes: the cells of scale 1 that scale 2 does not
+    overwrite) regrouped into tiles lying in those plates.  For the plates
+    normal to z, y and x in turn, tiles two cells deep along that axis (the
+    largest whose source box fits the kernel's buffer, see _plate_tile) over
+    a grid that starts at the smallest listed coordinate; a tile is kept
+    when at least POST_PLATE_KEEP of it is listed.  What no plate tile keeps
+    goes into the tiles of post_tile_runs.  Runs in the order of their first
+    cell, each run's cells in box order.  Returns (cells in run order, int32
+    offsets with one entry more than there are runs)."""
+    c = np.asarray(cells, np.int64)
+    nx, ny = shape[0], shape[1]
+    x, y, z = c % nx, (c // nx) % ny, c // (nx * ny)
+    left = np.ones(c.size, bool)
+    runs = []
+    for axis in (2, 1, 0):
+        idx = np.flatnonzero(left)
+        if idx.size == 0:
+            break
+        t = _plate_tile(axis, ratio)
+        keep = POST_PLATE_KEEP * t[0] * t[1] * t[2]
+        kx = (x[idx] - x[idx].min()) // t[0]
+        ky = (y[idx] - y[idx].min()) // t[1]
+        kz = (z[idx] - z[idx].min()) // t[2]
+        o = np.lexsort((x[idx], y[idx], z[idx], kx, ky, kz))
+        idx = idx[o]
+        key = np.stack([kx[o], ky[o], kz[o]])
+        st = np.flatnonzero(np.r_[True, np.any(key[:, 1:] != key[:, :-1], axis=0)])
+        en = np.r_[st[1:], idx.size]
+        for a, b in zip(st, en):
+            if b - a >= keep:
+                runs.append(idx[a:b])
+                left[idx[a:b]] = False
+    rest = np.flatnonzero(left)
+    if rest.size:
+        rc, ro = post_tile_runs(c[rest], shape, ratio)
+        srt = np.argsort(c[rest])
+        pos = rest[srt[np.searchsorted(c[rest], rc, sorter=srt)]]
+        runs.extend(np.split(pos, ro[1:-1]))
+    runs.sort(key=lambda r: int(c[r[0]]))
+    order = np.concatenate(runs) if runs else np.zeros(0, np.int64)
+    offsets = np.cumsum([0] + [r.size for r in runs]).astype(np.int32)
+    assert np.all(np.diff(offsets) <= POST_RUN)
+    return c[order].astype(np.int32), offsets
+
+
 def _storage_list(lev: Level, box_cells: np.ndarray) -> np.ndarray:
     """A cell list over a level's box in the level's storage order (int32);
     every listed cell of a brick level must be stored."""
@@ -237,11 +313,17 @@ class Hierarchy:
     reference scale's GHOST shell.  A finer scale post-maps onto every
     larger scale: the scales before it and the far-field scales.  ``kinds`` are over each
     level's box (for a brick level: SOLID outside the stored bricks); the
-    cell lists sent to the library are in each level's storage order."""
+    cell lists sent to the library are in each level's storage order.
+
+    A post-mapping list from a finer dense scale into a coarser dense one is
+    grouped into tiles (``tile_posts``) when they hold ``tile_min_fill``
+    targets on average: plane tiles (post_tile_runs), or, where those are too
+    sparse (``tile_plates`` "sparse"; "always": for every such list;
+    "never"), tiles lying in the list's thin plates (plate_tile_runs)."""
 
     def __init__(self, levels: list[Level], kinds: list[np.ndarray], parents=None, *,
                  stage_xfaces: bool = True, tile_posts: bool = True,
-                 tile_min_fill: int = POST_TILE_MIN_FILL):
+                 tile_min_fill: int = POST_TILE_MIN_FILL, tile_plates: str = "sparse"):
         assert len(levels) == len(kinds) and 1 <= len(levels) <= _capi.MAX_SCALES
         self.levels = levels
         self.kinds = [np.asarray(k, np.uint8) for k in kinds]
@@ -326,8 +408,13 @@ class Hierarchy:
                     and levels[j].dense_index is None and levels[i].c.dx < levels[j].c.dx):
                 # a finer dense scale into a coarser dense one: tiles of the
                 # coarser box, each mapped by one workgroup through LDS
-                tiled, runs = post_tile_runs(cells, (levels[j].nx, levels[j].ny),
-                                             levels[j].c.dx / levels[i].c.dx)
+                ratio = levels[j].c.dx / levels[i].c.dx
+                tiled, runs = post_tile_runs(cells, (levels[j].nx, levels[j].ny), ratio)
+                if tile_plates == "always" or (tile_plates == "sparse" and
+                                               tiled.size < tile_min_fill * (runs.size - 1)):
+                    # too sparse for plane tiles: a list in thin plates
+                    # fills tiles lying in those plates
+                    tiled, runs = plate_tile_runs(cells, (levels[j].nx, levels[j].ny), ratio)
                 if tiled.size >= tile_min_fill * (runs.size - 1):
                     cells = tiled
                     self.post[(i, j)] = cells

@@ -419,8 +419,10 @@ def test_reduced_plume_multiscale_adjoint_matches_fp64_finite_differences():
     assert ad == pytest.approx(fd, rel=2e-5), (ad, fd)
 
 
-def test_tiled_post_mapping_adjoint_gives_bitwise_the_gathered_adjoint():
-    """With the post-mapping lists in tile runs, each run's interpolation and
+@pytest.mark.parametrize("plates", ["never", "always"])
+def test_tiled_post_mapping_adjoint_gives_bitwise_the_gathered_adjoint(plates):
+    """With the post-mapping lists in tile runs (plane tiles, or tiles lying
+    in the lists' plates), each run's interpolation and
     map adjoint run in one workgroup through LDS: the columns, index map and
     flags are those of the per-target passes, so one multi-scale adjoint step
     of the reduced plume is bitwise that of the untiled lists."""
@@ -436,8 +438,9 @@ def test_tiled_post_mapping_adjoint_gives_bitwise_the_gathered_adjoint():
             lev.init_equilibrium(rho, u, s)
             levs.append(lev)
         H = hierarchy.Hierarchy(levs, [sp.kinds for sp in specs], [sp.parent for sp in specs],
-                                tile_posts=tiles, tile_min_fill=0)
+                                tile_posts=tiles, tile_min_fill=0, tile_plates=plates)
         assert (H.c_scales[2].n_post_tiles[1] > 0) == tiles
+        assert (H.c_scales[1].n_post_tiles[0] > 0) == tiles
         H.step(2)
         f_in = [lev.f.clone() for lev in levs]
         g_in = [lev.g.clone() for lev in levs]

@@ -228,6 +228,59 @@ def test_region_box_is_the_dilated_clipped_bounding_box_of_both_thresholds():
     assert hierarchy.region_box(om, sp, shape, (5e-3, 2e-2), 0, [2, 2, 2], [27, 17, 6]) is None
 
 
+@pytest.mark.parametrize("ratio", [4.0 / 3.0, 1.5, 2.0, 3.2])
+def test_plate_tile_runs_partition_a_nested_shell_into_filled_tiles_whose_source_box_fits(ratio):
+    """Plate tiles of the cells between two nested boxes (plates two cells
+    thick on all six sides, as the part of scale 1 that scale 2 does not
+    overwrite): a permutation of the list, at most 256 entries a run, each
+    run's cells in box order, every run's source box (the corner b + 1 only
+    where the fraction is not 0) within the kernel's buffer, and tiles far
+    fuller than plane tiles of the same list."""
+    shape = (150, 90, 80)
+    nx, ny, nz = shape
+    x, y, z = inputs.grid_coords(*shape)
+    outer = (x >= 3) & (x <= 146) & (y >= 4) & (y <= 85) & (z >= 2) & (z <= 77)
+    inner = (x >= 5) & (x <= 144) & (y >= 6) & (y <= 83) & (z >= 4) & (z <= 75)
+    cells = np.flatnonzero(outer & ~inner).astype(np.int32)
+    out, runs = hierarchy.plate_tile_runs(cells, shape, ratio)
+    np.testing.assert_array_equal(np.sort(out), np.sort(cells))
+    assert runs[0] == 0 and runs[-1] == cells.size
+    sizes = np.diff(runs)
+    assert np.all(sizes >= 1) and np.all(sizes <= hierarchy.POST_RUN)
+    fine_dx = 1.0 / ratio
+    for a, b in zip(runs[:-1], runs[1:]):
+        c = out[a:b].astype(np.int64)
+        assert np.all(np.diff(c) > 0)
+        vol = 1
+        for p in (c % nx, (c // nx) % ny, c // (nx * ny)):
+            q = (p * 1.0 - 0.25) / fine_dx
+            base = np.floor(q)
+            top = np.where(q - base != 0.0, base + 1, base)
+            vol *= int(top.max() - base.min() + 1)
+        assert vol <= hierarchy.POST_TILE_BUFFER, (ratio, vol)
+    _, plane = hierarchy.post_tile_runs(cells, shape, ratio)
+    assert cells.size / sizes.size > 2.0 * cells.size / (plane.size - 1)
+
+
+def test_plate_tiles_fit_the_buffer_and_lie_two_cells_deep():
+    """The plate tile of each orientation: two cells deep along its axis, at
+    most 256 cells, source box within the buffer, and no larger tile of the
+    same depth would fit."""
+    for ratio in (1.0, 4.0 / 3.0, 1.5, 2.0, 3.2):
+        for axis in (0, 1, 2):
+            t = hierarchy._plate_tile(axis, ratio)
+            assert t[axis] == 2 and t[0] * t[1] * t[2] <= hierarchy.POST_RUN
+            assert hierarchy._tile_source_cells(t, ratio) <= hierarchy.POST_TILE_BUFFER
+            a, b = [t[d] for d in range(3) if d != axis]
+            for grown in ((a + 1, b), (a, b + 1)):
+                if grown[0] * grown[1] * 2 > hierarchy.POST_RUN:
+                    continue
+                g = list(grown)
+                g.insert(axis, 2)
+                assert (hierarchy._tile_source_cells(g, ratio) > hierarchy.POST_TILE_BUFFER
+                        or g[0] * g[1] * g[2] <= t[0] * t[1] * t[2])
+
+
 @pytest.mark.parametrize("ratio,origin", [(4 / 3, (3.3, 2.6, 2.2)), (1.5, (0.4, 1.1, 0.7)),
                                           (2.0, (1.25, 0.75, 0.25)), (3.2, (0.3, 0.9, 1.6))])
 def test_post_tile_runs_partition_the_list_into_plane_tiles_whose_source_box_fits(ratio, origin):

@@ -388,17 +388,19 @@ def _plume_states(storage, **hier_opts):
     return H, levs
 
 
+@pytest.mark.parametrize("plates", ["never", "always"])
 @pytest.mark.parametrize("storage", [F32, F16S])
-def test_tiled_post_mapping_gives_bitwise_the_gathered_result(storage):
+def test_tiled_post_mapping_gives_bitwise_the_gathered_result(storage, plates):
     """Post-mapping lists regrouped into tiles (scale 2 -> 1 at ratio 4/3,
     scale 1 -> 0 at 1.5, however sparsely filled; scale 2 -> 0 sits on
-    coarse lattice points and the library gathers it) and mapped one tile per workgroup
+    coarse lattice points and the library gathers it), plane tiles or tiles
+    lying in the lists' plates, and mapped one tile per workgroup
     through LDS: the same corners, weights and summation order, so every
     scale's state after several reference steps is bitwise that of the
     direct gather."""
     states = []
     for tiles in (True, False):
-        H, levs = _plume_states(storage, tile_posts=tiles, tile_min_fill=0)
+        H, levs = _plume_states(storage, tile_posts=tiles, tile_min_fill=0, tile_plates=plates)
         n_tiles = {(i, j): H.c_scales[i].n_post_tiles[j] for i in (1, 2) for j in range(i)}
         if tiles:
             assert n_tiles[(2, 1)] > 0 and n_tiles[(1, 0)] > 0

@@ -231,14 +231,15 @@ def _tile_source_cells(t, ratio: float) -> int:
     return n
 
 
-def _plate_tile(axis: int, ratio: float):
-    """The largest tile two cells deep along ``axis`` (at most 256 cells,
-    its source box within the kernel's buffer), longest along x first."""
+def _plate_tile(axis: int, ratio: float, depth: int = 2):
+    """The largest tile ``depth`` cells deep along ``axis`` (at most 256
+    cells, its source box within the kernel's buffer), longest along x
+    first."""
     best = None
     for a in range(64, 0, -1):
-        for b in range(min(128 // a, 64), 0, -1):
+        for b in range(min(POST_RUN // (depth * a), 64), 0, -1):
             t = [a, b]
-            t.insert(axis, 2)
+            t.insert(axis, depth)
             if _tile_source_cells(t, ratio) <= POST_TILE_BUFFER:
                 key = (a * b, a)
                 if best is None or key > best[0]:
@@ -251,42 +252,68 @@ def plate_tile_runs(cells: np.ndarray, shape, ratio: float):
     """A post-mapping list that lies in plates a few cells thick (the margin
     between nested boxes: the cells of scale 1 that scale 2 does not
     overwrite) regrouped into tiles lying in those plates.  For the plates
-    normal to z, y and x in turn, tiles two cells deep along that axis (the
-    largest whose source box fits the kernel's buffer, see _plate_tile) over
-    a grid that starts at the smallest listed coordinate; a tile is kept
-    when at least POST_PLATE_KEEP of it is listed.  What no plate tile keeps
-    goes into the tiles of post_tile_runs.  Runs in the order of their first
+    normal to z, y and x in turn, tiles two, three or four cells deep along
+    that axis (whichever keeps most; the largest tile of that depth whose
+    source box fits the kernel's buffer, see _plate_tile) over a grid that
+    starts at the smallest listed coordinate; a tile is kept when at least
+    POST_PLATE_KEEP of it is listed.  What no plate tile keeps is cut, in
+    blocks of 16 x 16 x 16 cells, into runs that end where the next cell
+    would take the run's source box past the buffer.  Runs in the order of their first
     cell, each run's cells in box order.  Returns (cells in run order, int32
     offsets with one entry more than there are runs)."""
     c = np.asarray(cells, np.int64)
     nx, ny = shape[0], shape[1]
-    x, y, z = c % nx, (c // nx) % ny, c // (nx * ny)
+    xyz = (c % nx, (c // nx) % ny, c // (nx * ny))
     left = np.ones(c.size, bool)
     runs = []
+
+    def tiles(idx, t):
+        """the tiles of t over the entries idx that hold enough of them"""
+        k = [(xyz[d][idx] - xyz[d][idx].min()) // t[d] for d in range(3)]
+        o = np.lexsort((xyz[0][idx], xyz[1][idx], xyz[2][idx], k[0], k[1], k[2]))
+        idx = idx[o]
+        key = np.stack([kk[o] for kk in k])
+        st = np.flatnonzero(np.r_[True, np.any(key[:, 1:] != key[:, :-1], axis=0)])
+        en = np.r_[st[1:], idx.size]
+        keep = POST_PLATE_KEEP * t[0] * t[1] * t[2]
+        return [idx[a:b] for a, b in zip(st, en) if b - a >= keep]
+
     for axis in (2, 1, 0):
         idx = np.flatnonzero(left)
         if idx.size == 0:
             break
-        t = _plate_tile(axis, ratio)
-        keep = POST_PLATE_KEEP * t[0] * t[1] * t[2]
-        kx = (x[idx] - x[idx].min()) // t[0]
-        ky = (y[idx] - y[idx].min()) // t[1]
-        kz = (z[idx] - z[idx].min()) // t[2]
-        o = np.lexsort((x[idx], y[idx], z[idx], kx, ky, kz))
-        idx = idx[o]
-        key = np.stack([kx[o], ky[o], kz[o]])
-        st = np.flatnonzero(np.r_[True, np.any(key[:, 1:] != key[:, :-1], axis=0)])
-        en = np.r_[st[1:], idx.size]
-        for a, b in zip(st, en):
-            if b - a >= keep:
-                runs.append(idx[a:b])
-                left[idx[a:b]] = False
+        # plates two, three or four cells thick: the depth that keeps most
+        best = max((tiles(idx, _plate_tile(axis, ratio, depth)) for depth in (2, 3, 4)),
+                   key=lambda kept: sum(r.size for r in kept))
+        for r in best:
+            runs.append(r)
+            left[r] = False
     rest = np.flatnonzero(left)
     if rest.size:
-        rc, ro = post_tile_runs(c[rest], shape, ratio)
-        srt = np.argsort(c[rest])
-        pos = rest[srt[np.searchsorted(c[rest], rc, sorter=srt)]]
-        runs.extend(np.split(pos, ro[1:-1]))
+        # the rest (edges and strips that fill no tile) in blocks of 16^3,
+        # each block's cells in box order, cut into runs as long as their
+        # source box fits the buffer
+        blk = [xyz[d][rest] // 16 for d in range(3)]
+        rest = rest[np.lexsort((xyz[0][rest], xyz[1][rest], xyz[2][rest], blk[0], blk[1], blk[2]))]
+        px, py, pz = (xyz[d][rest].tolist() for d in range(3))
+        span = [2] + [math.floor(e * ratio) + 3 for e in range(1, max(shape) + 1)]   # by extent - 1
+        start = 0
+        x0 = x1 = px[0]
+        y0 = y1 = py[0]
+        z0 = z1 = pz[0]
+        for k in range(1, rest.size):
+            a0, a1 = min(x0, px[k]), max(x1, px[k])
+            b0, b1 = min(y0, py[k]), max(y1, py[k])
+            c0, c1 = min(z0, pz[k]), max(z1, pz[k])
+            if k - start >= POST_RUN or span[a1 - a0] * span[b1 - b0] * span[c1 - c0] > POST_TILE_BUFFER:
+                runs.append(np.sort(rest[start:k]))
+                start = k
+                x0 = x1 = px[k]
+                y0 = y1 = py[k]
+                z0 = z1 = pz[k]
+            else:
+                x0, x1, y0, y1, z0, z1 = a0, a1, b0, b1, c0, c1
+        runs.append(np.sort(rest[start:]))
     runs.sort(key=lambda r: int(c[r[0]]))
     order = np.concatenate(runs) if runs else np.zeros(0, np.int64)
     offsets = np.cumsum([0] + [r.size for r in runs]).astype(np.int32)

@@ -15,7 +15,7 @@ import pytest
 import torch
 
 import oracle
-from paper_1807_02284_amd import inputs
+from paper_1807_02284_amd import hierarchy, inputs
 from paper_1807_02284_amd.level import F16S, F32, Level, Params
 
 pytestmark = pytest.mark.gpu
@@ -148,6 +148,74 @@ def test_plume_reference_scale_first_step_sampled():
     # scalar: absolute error against the cell's largest scalar population
     gscale = np.maximum(np.abs(ref_g).max(axis=0, keepdims=True), 1e-3)
     assert np.max(np.abs(got_g - ref_g) / gscale) <= 1e-6
+
+
+def _full_plume(fast: bool):
+    """The benchmark's three-scale plume at full size (512x256x256 reference
+    scale; boxes [3, 89, 89]-[508, 166, 166] at spacing 1/1.5 and
+    [5, 91, 91]-[506, 164, 164] at 1/2, level-0 units, as the benchmark's
+    thresholds place them) from the benchmark's start state after 20
+    reference-scale steps; ``fast``: plane and plate tiles and x-face
+    staging, else every exchange gathered directly."""
+    nx, ny, nz = 512, 256, 256
+    flags = inputs.plume_flags(nx, ny, nz)
+    p = Params(nu=1e-4, g_max=0.1, tau_s=0.51, u_in=(0.05, 0.0, 0.0), s_in=1.0)
+    x, y, z = inputs.grid_coords(nx, ny, nz)
+    jet = ((y + 0.5 - ny / 2) ** 2 + (z + 0.5 - nz / 2) ** 2 <= 32.0 ** 2) & (flags == 0)
+    u = np.zeros((3, x.size), np.float32)
+    u[0, jet] = 0.05
+    s0 = np.where(jet & (x < 64), 1.0, 0.0).astype(np.float32)
+    del x, y, z, jet
+    lev0 = Level(nx, ny, nz, p, scalar=True, periodic=0, flags=flags)
+    lev0.init_equilibrium(None, u, s0)
+    del u, s0
+    lev0.step(20)
+    sphere = lambda px, py, pz: ((px + 0.5 - 160.0) ** 2 + (py + 0.5 - 128.0) ** 2
+                                 + (pz + 0.5 - 128.0) ** 2 <= 24.0 ** 2)
+    levels, kinds = [lev0], [flags]
+    for lo, hi, alpha in (((3, 89, 89), (508, 166, 166), 1.5), ((5, 91, 91), (506, 164, 164), 2.0)):
+        lev, k = hierarchy.fine_scale(lo, hi, alpha, p, sphere, scalar=True, storage=F32)
+        hierarchy.fill_from_parent(levels[-1], lev)
+        levels.append(lev)
+        kinds.append(k)
+    torch.cuda.synchronize()
+    H = hierarchy.Hierarchy(levels, kinds, stage_xfaces=fast, tile_posts=fast)
+    return H, levels
+
+
+def test_plume_full_size_fast_exchanges_give_bitwise_the_direct_gather():
+    """At the benchmark's size and launch configuration, the exchanges'
+    fast paths (the 2 -> 1 post-mapping in plane tiles through LDS, the
+    1 -> 0 one in plate tiles, the ghost shells' x-faces from staged copies)
+    against every exchange gathered directly (the path the oracle checks
+    target by target at the reduced sizes): two reference steps and one
+    multi-scale adjoint step give bitwise the same states and adjoints."""
+    out = []
+    for fast in (True, False):
+        H, levels = _full_plume(fast)
+        if fast:
+            assert H.c_scales[2].n_post_tiles[1] > 0 and H.c_scales[1].n_post_tiles[0] > 0
+            assert H.c_scales[1].stage and H.c_scales[2].stage
+        H.step(2)
+        f_in = [lev.f.clone() for lev in levels]
+        g_in = [lev.g.clone() for lev in levels]
+        gen = torch.Generator(device="cuda").manual_seed(9)
+        lam = [1e-3 * torch.randn(27 * lev.plane, device="cuda", generator=gen) for lev in levels]
+        mu = [1e-3 * torch.randn(7 * lev.plane, device="cuda", generator=gen) for lev in levels]
+        ws = torch.empty(H.adjoint_workspace_bytes(), dtype=torch.uint8, device="cuda")
+        H.adjoint_step(f_in, g_in, lam, mu, ws)
+        torch.cuda.synchronize()
+        del ws
+        n = [lev.nx * lev.ny * lev.nz for lev in levels]
+        out.append([t.view(27, -1)[:, :c].clone() for t, c in zip(f_in, n)] +
+                   [t.view(7, -1)[:, :c].clone() for t, c in zip(g_in, n)] +
+                   [t.view(27, -1)[:, :c].clone() for t, c in zip(lam, n)] +
+                   [t.view(7, -1)[:, :c].clone() for t, c in zip(mu, n)])
+        assert all(bool(torch.isfinite(t).all()) for t in out[-1])
+        del H, levels, f_in, g_in, lam, mu
+        torch.cuda.empty_cache()
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
 
 
 def test_adjoint_128_one_step_sampled():

@@ -383,6 +383,32 @@ typedef struct cslbm_scale {
                                            every target's 8 corners.  The result
                                            is the same bit for bit. */
     int32_t n_post_tiles[CSLBM_MAX_SCALES];
+    const int32_t* ghost_tiles;         /* device, or NULL: ghost_cells grouped
+                                           into n_ghost_tiles runs of
+                                           consecutive entries, run t from
+                                           entry ghost_tiles[t] to
+                                           ghost_tiles[t+1] - 1 (n_ghost_tiles
+                                           + 1 ascending offsets, 0 first,
+                                           n_ghost last, at most 256 entries a
+                                           run; clipped to the list as above;
+                                           a run that starts among the x-face
+                                           entries of one plane must hold only
+                                           entries of that plane, or its
+                                           targets become NaN).  When this
+                                           scale and its parent are dense boxes,
+                                           the parent has no periodic axis and
+                                           this scale's cells are not all
+                                           parent lattice points, the prior-
+                                           mapping maps each run with one
+                                           workgroup through LDS, as post_tiles
+                                           does (x-face runs from the staged
+                                           copies when there are any): with
+                                           runs that are patches of one face of
+                                           the shell the parent's cells are
+                                           read once per patch instead of once
+                                           per corner of every target.  The
+                                           result is the same bit for bit. */
+    int32_t n_ghost_tiles;
 } cslbm_scale;
 
 typedef struct cslbm_hierarchy {

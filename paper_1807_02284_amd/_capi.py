@@ -90,6 +90,8 @@ class CslbmScale(C.Structure):
         ("stage_bytes", C.c_int64),
         ("post_tiles", _vp * MAX_SCALES),
         ("n_post_tiles", C.c_int32 * MAX_SCALES),
+        ("ghost_tiles", _vp),
+        ("n_ghost_tiles", C.c_int32),
     ]
 
 

@@ -197,17 +197,25 @@ __global__ void __launch_bounds__(256) k_exchange(const ExchArgs a)
     map_and_store<Td>(a, c, v, gi, kScalar);
 }
 
-// Tiled post-mapping (tile.hpp): one workgroup maps one run of the list.
+// Tiled exchange (tile.hpp): one workgroup maps one run of the list.
 // Lanes past the run's end repeat its first entry: they compute the same
-// bits as lane 0 and store them to the same cell.
-template <typename Ts, typename Td, bool kScalar>
+// bits as lane 0 and store them to the same cell.  kShell: runs that are
+// patches of a ghost shell (small source boxes), blended or not; otherwise
+// post-mapping runs (one time level).
+template <typename Ts, typename Td, bool kScalar, bool kShell, bool kBlend>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_exchange_tiled(const ExchArgs a, const int32_t* runs)
 {
-    __shared__ TileLds lds;
     TileTarget T;
     float v[27], gi[QS];
-    if (!tile_interp<Ts, kScalar>(a, runs, lds, T, v, gi)) return;
+    if constexpr (kShell) {
+        __shared__ ShellLds lds;
+        if (!tile_interp<Ts, kScalar, kBlend, kShellLoads, kShellPlanes, true>(a, runs, lds, T, v, gi))
+            return;
+    } else {
+        __shared__ TileLds lds;
+        if (!tile_interp<Ts, kScalar>(a, runs, lds, T, v, gi)) return;
+    }
     map_and_store<Td>(a, T.c, v, gi, kScalar);
 }
 
@@ -356,13 +364,52 @@ static int launch_exchange_args(ExchArgs a, const cslbm_level* src, const cslbm_
 }
 
 template <typename Ts, typename Td>
-static void launch_tiled_kernel(const ExchArgs& a, const int32_t* runs, int32_t n_runs, hipStream_t st)
+static void launch_tiled_kernel(const ExchArgs& a, const int32_t* runs, int32_t n_runs, bool shell,
+                                bool blend, hipStream_t st)
 {
     const dim3 grid((unsigned)n_runs), block(256);
-    if (a.gA)
-        hipLaunchKernelGGL((k_exchange_tiled<Ts, Td, true>), grid, block, 0, st, a, runs);
+    if (!shell) {
+        if (a.gA)
+            hipLaunchKernelGGL((k_exchange_tiled<Ts, Td, true, false, false>), grid, block, 0, st, a, runs);
+        else
+            hipLaunchKernelGGL((k_exchange_tiled<Ts, Td, false, false, false>), grid, block, 0, st, a, runs);
+    } else if (blend) {
+        if (a.gA)
+            hipLaunchKernelGGL((k_exchange_tiled<Ts, Td, true, true, true>), grid, block, 0, st, a, runs);
+        else
+            hipLaunchKernelGGL((k_exchange_tiled<Ts, Td, false, true, true>), grid, block, 0, st, a, runs);
+    } else {
+        if (a.gA)
+            hipLaunchKernelGGL((k_exchange_tiled<Ts, Td, true, true, false>), grid, block, 0, st, a, runs);
+        else
+            hipLaunchKernelGGL((k_exchange_tiled<Ts, Td, false, true, false>), grid, block, 0, st, a, runs);
+    }
+}
+
+// one launch of the tiled kernel over runs of a's list (w in [0, 1]; a
+// time weight strictly between blends the two levels, shell runs only)
+static int launch_tiled(ExchArgs a, const cslbm_level* src, const cslbm_level* dst, double w,
+                        const int32_t* runs, int32_t n_runs, bool shell, hipStream_t stream)
+{
+    const bool blend = w > 0.0 && w < 1.0;
+    if (!blend && w >= 1.0) {
+        a.fA = a.fB;
+        a.gA = a.gB;
+        for (int sgi = 0; sgi < a.n_staged; ++sgi) {
+            a.st[sgi].fA = a.st[sgi].fB;
+            a.st[sgi].gA = a.st[sgi].gB;
+        }
+    }
+    const bool s32 = src->storage == CSLBM_F32, d32 = dst->storage == CSLBM_F32;
+    if (s32 && d32)
+        launch_tiled_kernel<float, float>(a, runs, n_runs, shell, blend, stream);
+    else if (s32)
+        launch_tiled_kernel<float, _Float16>(a, runs, n_runs, shell, blend, stream);
+    else if (d32)
+        launch_tiled_kernel<_Float16, float>(a, runs, n_runs, shell, blend, stream);
     else
-        hipLaunchKernelGGL((k_exchange_tiled<Ts, Td, false>), grid, block, 0, st, a, runs);
+        launch_tiled_kernel<_Float16, _Float16>(a, runs, n_runs, shell, blend, stream);
+    return check_launch("k_exchange_tiled");
 }
 
 int launch_exchange(const cslbm_level* src, const void* fA, const void* fB, const float* gA,
@@ -375,20 +422,7 @@ int launch_exchange(const cslbm_level* src, const void* fA, const void* fB, cons
     const bool tiled = runs && n_runs > 0 && !(w > 0.0 && w < 1.0) && !a.sb.table && !a.db.table &&
                        a.speriodic == 0 && !nodes_coincide(src, dst);
     if (!tiled) return launch_exchange_args(a, src, dst, w, stream);
-    if (w >= 1.0) {
-        a.fA = a.fB;
-        a.gA = a.gB;
-    }
-    const bool s32 = src->storage == CSLBM_F32, d32 = dst->storage == CSLBM_F32;
-    if (s32 && d32)
-        launch_tiled_kernel<float, float>(a, runs, n_runs, stream);
-    else if (s32)
-        launch_tiled_kernel<float, _Float16>(a, runs, n_runs, stream);
-    else if (d32)
-        launch_tiled_kernel<_Float16, float>(a, runs, n_runs, stream);
-    else
-        launch_tiled_kernel<_Float16, _Float16>(a, runs, n_runs, stream);
-    return check_launch("k_exchange_tiled");
+    return launch_tiled(a, src, dst, w, runs, n_runs, false, stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -563,13 +597,31 @@ int prior_stage(const cslbm_scale& sc, const cslbm_level* P, const void* A, cons
     return *staged ? stage_faces(P, sp, A, B, gA, gB, static_cast<char*>(sc.stage), stream) : CSLBM_OK;
 }
 
+// The ghost shell's entries after its x faces go in patch runs through LDS
+// (cslbm_scale.ghost_tiles): dense boxes, no periodic parent axis, targets
+// off the parent's lattice points.
+static bool shell_tiled(const cslbm_scale& sc, const cslbm_level* P)
+{
+    const cslbm_level* L = &sc.level;
+    return sc.ghost_tiles && sc.n_ghost_tiles > 0 && !P->brick_table && !L->brick_table &&
+           P->periodic == 0 && !nodes_coincide(P, L);
+}
+
 int prior_map(const cslbm_scale& sc, bool staged, const cslbm_level* P, const void* A, const void* B,
               const float* gA, const float* gB, double w, void* out, float* gout, hipStream_t stream)
 {
     const cslbm_level* L = &sc.level;
     StagePlan sp;
-    if (!staged || !stage_plan(P, L, sc.ghost_xlo, sc.ghost_xhi, &sp))
-        return launch_exchange(P, A, B, gA, gB, w, L, out, gout, sc.ghost_cells, sc.n_ghost, stream);
+    const bool stage = staged && stage_plan(P, L, sc.ghost_xlo, sc.ghost_xhi, &sp);
+    if (shell_tiled(sc, P)) {
+        // every run in one launch; runs of x-face entries read the staged
+        // copies when there are any
+        if (sc.n_ghost == 0) return CSLBM_OK;
+        ExchArgs a = exchange_args(P, A, B, gA, gB, w, L, out, gout, sc.ghost_cells, sc.n_ghost);
+        if (stage) set_stage_segments(sp, static_cast<char*>(sc.stage), sc.n_ghost_xlo, sc.n_ghost_xhi, a);
+        return launch_tiled(a, P, L, w, sc.ghost_tiles, sc.n_ghost_tiles, true, stream);
+    }
+    if (!stage) return launch_exchange(P, A, B, gA, gB, w, L, out, gout, sc.ghost_cells, sc.n_ghost, stream);
     return launch_prior_staged(P, sp, static_cast<char*>(sc.stage), A, B, gA, gB, w, L, out, gout,
                                sc.ghost_cells, sc.n_ghost_xlo, sc.n_ghost_xhi, sc.n_ghost, stream);
 }
@@ -684,6 +736,9 @@ int validate_hierarchy(const cslbm_hierarchy* H)
                 return fail(CSLBM_ERR_ARG, "scale %d: bad run offsets of the post-mapping list for scale %d",
                             i, j);
         }
+        if (S[i].n_ghost_tiles < 0 || S[i].n_ghost_tiles > S[i].n_ghost ||
+            (S[i].n_ghost_tiles > 0 && !S[i].ghost_tiles))
+            return fail(CSLBM_ERR_ARG, "scale %d: bad run offsets of the ghost list", i);
         if (S[i].n_ghost_xlo < 0 || S[i].n_ghost_xhi < 0 ||
             (int64_t)S[i].n_ghost_xlo + S[i].n_ghost_xhi > S[i].n_ghost)
             return fail(CSLBM_ERR_ARG, "scale %d: x-face ghost counts %d + %d exceed the %d ghosts", i,

@@ -192,7 +192,7 @@ def post_tile_runs(cells: np.ndarray, shape, ratio: float, tile=None, order: str
     source cells (at most floor((t - 1) * ratio) + 2 per axis, plus one for
     rounding, and 2 source planes) fit the kernel's buffer.  Returns (cells in tile order, int32 offsets
     with one entry more than there are tiles)."""
-    c = np.asarray(cells, np.int64)
+    c = np.asarray(cells, np.int32)   # cell indices of a level fit 32 bits
     nx, ny = shape[0], shape[1]
     if tile is None:
         # rows of 64 (one wavefront a row: whole-line stores, long source
@@ -208,17 +208,27 @@ def post_tile_runs(cells: np.ndarray, shape, ratio: float, tile=None, order: str
         assert tx * ty * tz <= POST_RUN
     x, y, z = c % nx, (c // nx) % ny, c // (nx * ny)
     kx, ky, kz = x // tx, y // ty, z // tz
-    major = (kz, kx, ky) if order == "z" else (kx, ky, kz)
-    order_idx = np.lexsort((x, y, z) + major)
+    del x, y, z
+    # one tile number per cell in the tiles' order, cells of a tile in box
+    # order (a stable sort of a list that is in box order already)
+    nkx, nky = int(kx.max(initial=0)) + 1, int(ky.max(initial=0)) + 1
+    nkz = int(kz.max(initial=0)) + 1
+    key = (ky * nkx + kx) * nkz + kz if order == "z" else (kz * nky + ky) * nkx + kx
+    del kx, ky, kz
+    if c.size < 2 or np.all(c[1:] > c[:-1]):
+        order_idx = np.argsort(key, kind="stable")
+    else:
+        order_idx = np.lexsort((c, key))
     c = c[order_idx]
-    key = np.stack([kx[order_idx], ky[order_idx], kz[order_idx]])
-    starts = np.flatnonzero(np.any(key[:, 1:] != key[:, :-1], axis=0)) + 1 if c.size else np.zeros(0, np.int64)
+    key = key[order_idx]
+    starts = np.flatnonzero(key[1:] != key[:-1]) + 1
     offsets = np.concatenate([[0], starts, [c.size]]).astype(np.int32)
     assert np.all(np.diff(offsets) <= POST_RUN)
     return c.astype(np.int32), offsets
 
 
 POST_PLATE_KEEP = 0.75   # a plate tile is kept when at least this fraction of its cells is listed
+SHELL_TILE_BUFFER = 512  # source cells of a ghost-shell patch's box that fit in the shell kernel's buffer
 
 
 def _tile_source_cells(t, ratio: float) -> int:
@@ -231,16 +241,16 @@ def _tile_source_cells(t, ratio: float) -> int:
     return n
 
 
-def _plate_tile(axis: int, ratio: float, depth: int = 2):
+def _plate_tile(axis: int, ratio: float, depth: int = 2, buffer: int = POST_TILE_BUFFER):
     """The largest tile ``depth`` cells deep along ``axis`` (at most 256
-    cells, its source box within the kernel's buffer), longest along x
+    cells, its source box within ``buffer`` cells), longest along x
     first."""
     best = None
     for a in range(64, 0, -1):
         for b in range(min(POST_RUN // (depth * a), 64), 0, -1):
             t = [a, b]
             t.insert(axis, depth)
-            if _tile_source_cells(t, ratio) <= POST_TILE_BUFFER:
+            if _tile_source_cells(t, ratio) <= buffer:
                 key = (a * b, a)
                 if best is None or key > best[0]:
                     best = (key, tuple(t))
@@ -321,6 +331,57 @@ def plate_tile_runs(cells: np.ndarray, shape, ratio: float):
     return c[order].astype(np.int32), offsets
 
 
+def shell_tile_runs(cells: np.ndarray, shape, ratio: float, xface: bool = False):
+    """Ghost cells of a one-cell shell regrouped into patches of its faces:
+    tiles one cell deep of at most 256 cells whose source boxes fit the
+    shell kernel's buffer of SHELL_TILE_BUFFER cells (64 x 4 at spacing
+    ratios 3/4 and 2/3; see _plate_tile), over a grid that starts at the
+    smallest listed coordinate.  A cell on the list's first or last z plane
+    goes to a tile normal to z, else one on its first or last y plane to a
+    tile normal to y, else (not a shell cell) to a tile normal to z in its
+    own plane; with ``xface`` (the entries of one of the shell's planes
+    normal to x, which read a staged copy of the parent) every cell goes to
+    a tile normal to x.  Every tile is a run, partly filled ones included.
+    ``ratio`` is the shell's spacing over its parent's (< 1 for a finer
+    scale).  Returns (cells in run order, int32 offsets with one entry more
+    than there are runs)."""
+    c = np.asarray(cells, np.int64)
+    if c.size == 0:
+        return c.astype(np.int32), np.zeros(1, np.int32)
+    nx, ny = shape[0], shape[1]
+    x, y, z = c % nx, (c // nx) % ny, c // (nx * ny)
+    x, y, z = x - x.min(), y - y.min(), z - z.min()
+    if xface:
+        t = _plate_tile(0, ratio, 1, SHELL_TILE_BUFFER)
+        key = [np.zeros_like(x), x, y // t[1], z // t[2]]
+    else:
+        tz = _plate_tile(2, ratio, 1, SHELL_TILE_BUFFER)
+        ty = _plate_tile(1, ratio, 1, SHELL_TILE_BUFFER)
+        on_y = ((y == 0) | (y == y.max())) & ~((z == 0) | (z == z.max()))
+        key = [on_y.astype(np.int64), np.where(on_y, y, z), x // np.where(on_y, ty[0], tz[0]),
+               np.where(on_y, z // ty[2], y // tz[1])]
+    k = key[0]
+    for part in key[1:]:
+        k = k * (int(part.max()) + 1) + part
+    order = np.lexsort((c, k))
+    k = k[order]
+    starts = np.flatnonzero(k[1:] != k[:-1]) + 1
+    offsets = np.concatenate([[0], starts, [c.size]]).astype(np.int32)
+    assert np.all(np.diff(offsets) <= POST_RUN)
+    return c[order].astype(np.int32), offsets
+
+
+def _nodes_coincide(src: Level, dst: Level) -> bool:
+    """Every lattice point of dst is one of src (dst's spacing a whole
+    multiple of src's, origins whole src cells apart): the library then maps
+    each target from its one source point and uses no tile runs."""
+    r = dst.c.dx / src.c.dx
+    if r < 1.0 - 1e-9 or abs(r - round(r)) > 1e-9:
+        return False
+    return all(abs(o - round(o)) <= 1e-9 for o in
+               ((dst.c.origin[d] - src.c.origin[d]) / src.c.dx for d in range(3)))
+
+
 def _storage_list(lev: Level, box_cells: np.ndarray) -> np.ndarray:
     """A cell list over a level's box in the level's storage order (int32);
     every listed cell of a brick level must be stored."""
@@ -346,11 +407,15 @@ class Hierarchy:
     grouped into tiles (``tile_posts``) when they hold ``tile_min_fill``
     targets on average: plane tiles (post_tile_runs), or, where those are too
     sparse (``tile_plates`` "sparse"; "always": for every such list;
-    "never"), tiles lying in the list's thin plates (plate_tile_runs)."""
+    "never"), tiles lying in the list's thin plates (plate_tile_runs).  The
+    ghost shell of a dense scale in a dense, non-periodic parent is grouped
+    into patches of its faces (``tile_shells``, shell_tile_runs) after its
+    x-face entries."""
 
     def __init__(self, levels: list[Level], kinds: list[np.ndarray], parents=None, *,
                  stage_xfaces: bool = True, tile_posts: bool = True,
-                 tile_min_fill: int = POST_TILE_MIN_FILL, tile_plates: str = "sparse"):
+                 tile_min_fill: int = POST_TILE_MIN_FILL, tile_plates: str = "sparse",
+                 tile_shells: bool = True):
         assert len(levels) == len(kinds) and 1 <= len(levels) <= _capi.MAX_SCALES
         self.levels = levels
         self.kinds = [np.asarray(k, np.uint8) for k in kinds]
@@ -402,6 +467,29 @@ class Hierarchy:
                         sc.n_ghost_xlo, sc.n_ghost_xhi = int(lo.sum()), int(hi.sum())
                         sc.ghost_xlo, sc.ghost_xhi = x_lo, x_hi
                         sc.stage, sc.stage_bytes = st.data_ptr(), nb
+                if (tile_shells and not self.far[i] and lev.dense_index is None
+                        and par.dense_index is None and par.c.periodic == 0 and ghosts.size):
+                    # the shell in patches of its faces, each mapped by one
+                    # workgroup through LDS: each staged x plane's entries
+                    # apart (they read that plane's copy), then the rest
+                    ratio = lev.c.dx / par.c.dx
+                    shape = (lev.nx, lev.ny)
+                    parts, offs, at = [], [np.zeros(1, np.int32)], 0
+                    bounds = np.cumsum([0, sc.n_ghost_xlo, sc.n_ghost_xhi, ghosts.size
+                                        - sc.n_ghost_xlo - sc.n_ghost_xhi])
+                    for k, (a, b) in enumerate(zip(bounds[:-1], bounds[1:])):
+                        if b == a:
+                            continue
+                        t, r = shell_tile_runs(ghosts[a:b], shape, ratio, xface=k < 2)
+                        parts.append(t)
+                        offs.append(r[1:] + at)
+                        at += t.size
+                    ghosts = np.concatenate(parts).astype(np.int32)
+                    runs = np.concatenate(offs).astype(np.int32)
+                    r_t = torch.as_tensor(runs, device=dev)
+                    self.lists.append(r_t)
+                    sc.n_ghost_tiles = runs.size - 1
+                    sc.ghost_tiles = r_t.data_ptr()
                 g_t = torch.as_tensor(_storage_list(lev, ghosts), device=dev)
                 self.lists.append(g_t)
                 sc.n_ghost = ghosts.size
@@ -432,7 +520,8 @@ class Hierarchy:
         self.post = {**drop_overwritten_posts(self.post, n, self.parents), **far_post}
         for (i, j), cells in self.post.items():
             if (tile_posts and cells.size and levels[i].dense_index is None
-                    and levels[j].dense_index is None and levels[i].c.dx < levels[j].c.dx):
+                    and levels[j].dense_index is None and levels[i].c.dx < levels[j].c.dx
+                    and not _nodes_coincide(levels[i], levels[j])):
                 # a finer dense scale into a coarser dense one: tiles of the
                 # coarser box, each mapped by one workgroup through LDS
                 ratio = levels[j].c.dx / levels[i].c.dx

@@ -155,8 +155,8 @@ def _full_plume(fast: bool):
     scale; boxes [3, 89, 89]-[508, 166, 166] at spacing 1/1.5 and
     [5, 91, 91]-[506, 164, 164] at 1/2, level-0 units, as the benchmark's
     thresholds place them) from the benchmark's start state after 20
-    reference-scale steps; ``fast``: plane and plate tiles and x-face
-    staging, else every exchange gathered directly."""
+    reference-scale steps; ``fast``: plane and plate tiles, x-face staging
+    and shell patches, else every exchange gathered directly."""
     nx, ny, nz = 512, 256, 256
     flags = inputs.plume_flags(nx, ny, nz)
     p = Params(nu=1e-4, g_max=0.1, tau_s=0.51, u_in=(0.05, 0.0, 0.0), s_in=1.0)
@@ -179,14 +179,15 @@ def _full_plume(fast: bool):
         levels.append(lev)
         kinds.append(k)
     torch.cuda.synchronize()
-    H = hierarchy.Hierarchy(levels, kinds, stage_xfaces=fast, tile_posts=fast)
+    H = hierarchy.Hierarchy(levels, kinds, stage_xfaces=fast, tile_posts=fast, tile_shells=fast)
     return H, levels
 
 
 def test_plume_full_size_fast_exchanges_give_bitwise_the_direct_gather():
     """At the benchmark's size and launch configuration, the exchanges'
     fast paths (the 2 -> 1 post-mapping in plane tiles through LDS, the
-    1 -> 0 one in plate tiles, the ghost shells' x-faces from staged copies)
+    1 -> 0 one in plate tiles, the ghost shells' x-faces from staged copies
+    and the rest of the shells in patches through LDS)
     against every exchange gathered directly (the path the oracle checks
     target by target at the reduced sizes): two reference steps and one
     multi-scale adjoint step give bitwise the same states and adjoints."""
@@ -196,6 +197,7 @@ def test_plume_full_size_fast_exchanges_give_bitwise_the_direct_gather():
         if fast:
             assert H.c_scales[2].n_post_tiles[1] > 0 and H.c_scales[1].n_post_tiles[0] > 0
             assert H.c_scales[1].stage and H.c_scales[2].stage
+            assert H.c_scales[1].n_ghost_tiles > 0 and H.c_scales[2].n_ghost_tiles > 0
         H.step(2)
         f_in = [lev.f.clone() for lev in levels]
         g_in = [lev.g.clone() for lev in levels]

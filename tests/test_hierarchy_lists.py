@@ -262,6 +262,47 @@ def test_plate_tile_runs_partition_a_nested_shell_into_filled_tiles_whose_source
     assert cells.size / sizes.size > 2.0 * cells.size / (plane.size - 1)
 
 
+@pytest.mark.parametrize("ratio,origin", [(0.75, (3.3, 2.6, 2.2)), (2 / 3, (0.4, 1.1, 0.7)),
+                                          (0.5, (1.25, 0.75, 0.25))])
+def test_shell_tile_runs_partition_a_ghost_shell_into_full_patches_whose_source_box_fits(ratio, origin):
+    """Patch runs of a one-cell ghost shell, an x plane (which reads a
+    staged copy) apart from the rest: a permutation of the list, at most
+    256 entries a run, each run's cells in box order, every run's parent
+    box (the corner b + 1 only where the fraction is not 0, as the kernel
+    does) within the shell kernel's buffer, and runs mostly full."""
+    shape = (150, 61, 47)
+    nx, ny, nz = shape
+    g = np.flatnonzero(hierarchy.shell_flags(*shape) == hierarchy.GHOST)
+    gx = g % nx
+    cells = g[(gx != 0) & (gx != nx - 1)].astype(np.int32)
+    out, runs = hierarchy.shell_tile_runs(cells, shape, ratio)
+    lo = g[gx == 0].astype(np.int32)
+    out_lo, runs_lo = hierarchy.shell_tile_runs(lo, shape, ratio, xface=True)
+    assert lo.size / (runs_lo.size - 1) >= 150
+    _check_shell_runs(out_lo, runs_lo, lo, shape, ratio, origin)
+    _check_shell_runs(out, runs, cells, shape, ratio, origin)
+
+
+def _check_shell_runs(out, runs, cells, shape, ratio, origin):
+    nx, ny, nz = shape
+    np.testing.assert_array_equal(np.sort(out), np.sort(cells))
+    assert runs[0] == 0 and runs[-1] == cells.size
+    sizes = np.diff(runs)
+    assert np.all(sizes >= 1) and np.all(sizes <= hierarchy.POST_RUN)
+    assert cells.size / sizes.size >= 150
+    for a, b in zip(runs[:-1], runs[1:]):
+        c = out[a:b].astype(np.int64)
+        assert np.all(np.diff(c) > 0)
+        xyz = (c % nx, (c // nx) % ny, c // (nx * ny))
+        vol = 1
+        for p, o in zip(xyz, origin):
+            q = o + p * ratio
+            base = np.floor(q)
+            top = np.where(q - base != 0.0, base + 1, base)
+            vol *= int(top.max() - base.min() + 1)
+        assert vol <= hierarchy.SHELL_TILE_BUFFER, (ratio, vol)
+
+
 def test_plate_tiles_fit_the_buffer_and_lie_two_cells_deep():
     """The plate tile of each orientation: two cells deep along its axis, at
     most 256 cells, source box within the buffer, and no larger tile of the

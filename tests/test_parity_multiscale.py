@@ -441,6 +441,61 @@ def test_runs_that_are_not_tiles_give_bitwise_the_gathered_result():
         np.testing.assert_array_equal(ga, gb)
 
 
+@pytest.mark.parametrize("storage", [F32, F16S])
+def test_shell_patches_give_bitwise_the_gathered_result(storage):
+    """The ghost shells after their x-face entries grouped into patches of
+    their faces (one cell deep, 64 x 4 where the parent box fits the
+    buffer), each mapped by one workgroup through LDS, at time weights 0, 1
+    and in between (the two levels blended on their way into LDS): the same
+    corners, weights and summation order, so every scale's state after
+    several reference steps is bitwise that of the direct gather."""
+    states = []
+    for tiles in (True, False):
+        H, levs = _plume_states(storage, tile_shells=tiles)
+        for i in (1, 2):
+            sc = H.c_scales[i]
+            assert (sc.n_ghost_tiles > 0) == tiles
+        H.step(6)
+        torch.cuda.synchronize()
+        states.append([(lev.f.cpu().numpy().copy(), lev.g.cpu().numpy().copy()) for lev in levs])
+        assert all(lev.count_nonfinite() == 0 for lev in levs)
+    for (fa, ga), (fb, gb) in zip(*states):
+        np.testing.assert_array_equal(fa, fb)
+        np.testing.assert_array_equal(ga, gb)
+
+
+def test_shell_runs_that_are_not_patches_give_bitwise_the_gathered_result():
+    """Runs of 256 consecutive entries of the ghost lists in their plain
+    order (each x plane's entries in (z, y) order, then the rest in box
+    order): runs inside one face row reach a source box within the shell
+    kernel's buffer and are staged through LDS, runs that wrap to the next
+    row or face reach a larger box and are gathered directly by the same
+    kernel (from the staged copies for the x planes); each part's last run
+    is partial.  Either way the result is bitwise the plain gather's."""
+    states = []
+    keep = []
+    for runs in (True, False):
+        H, levs = _plume_states(F32, tile_shells=False)
+        if runs:
+            for i in (1, 2):
+                sc = H.c_scales[i]
+                bounds = np.cumsum([0, sc.n_ghost_xlo, sc.n_ghost_xhi])
+                assert sc.n_ghost_xlo > 0 and sc.n_ghost_xhi > 0
+                offsets = np.concatenate([np.arange(a, b, 256) for a, b in
+                                          zip(bounds, [bounds[1], bounds[2], sc.n_ghost])]
+                                         + [[sc.n_ghost]]).astype(np.int32)
+                t = torch.as_tensor(offsets, device="cuda")
+                keep.append(t)
+                sc.ghost_tiles = t.data_ptr()
+                sc.n_ghost_tiles = offsets.size - 1
+        H.step(4)
+        torch.cuda.synchronize()
+        states.append([(lev.f.cpu().numpy().copy(), lev.g.cpu().numpy().copy()) for lev in levs])
+    for (fa, ga), (fb, gb) in zip(*states):
+        np.testing.assert_array_equal(fa, fb)
+        np.testing.assert_array_equal(ga, gb)
+
+
 def test_vorticity_matches_central_differences():
     """|curl u| (placement of dynamic scales) of an initialised state equals
     central differences of the input field; one-sided at non-periodic faces."""

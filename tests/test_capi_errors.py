@@ -104,6 +104,16 @@ def test_multiscale_step_argument_checks(lib):
         keep[1].post_tiles[0] = ptr
         assert ms(C.byref(H), 1, None) == _capi.ERR_ARG
         assert "run offsets" in err(lib)
+    # run offsets of a ghost list: more runs than ghosts, a negative count,
+    # or a count without offsets
+    H, keep = hierarchy_of([L0, L1], [-1, 0])
+    keep[1].n_ghost = 3
+    keep[1].ghost_cells = 0xA000
+    for n_runs, ptr in ((4, 0xB000), (-1, 0xB000), (2, None)):
+        keep[1].n_ghost_tiles = n_runs
+        keep[1].ghost_tiles = ptr
+        assert ms(C.byref(H), 1, None) == _capi.ERR_ARG
+        assert "ghost list" in err(lib)
     # the gradient mode is single-level only
     Lg = make_level(p_grad_mode=1)
     H, keep = hierarchy_of([Lg], [-1])

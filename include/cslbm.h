@@ -399,10 +399,12 @@ typedef struct cslbm_scale {
                                            the parent has no periodic axis and
                                            this scale's cells are not all
                                            parent lattice points, the prior-
-                                           mapping maps each run with one
-                                           workgroup through LDS, as post_tiles
-                                           does (x-face runs from the staged
-                                           copies when there are any): with
+                                           mapping (and its adjoint in
+                                           cslbm_multiscale_adjoint_step) maps
+                                           each run with one workgroup through
+                                           LDS, as post_tiles does (x-face runs
+                                           from the staged copies when there
+                                           are any): with
                                            runs that are patches of one face of
                                            the shell the parent's cells are
                                            read once per patch instead of once

@@ -819,16 +819,24 @@ __global__ void __launch_bounds__(256) k_zero(float* p, int64_t n)
 // are set as pass A1 sets them, and a target outside the gather is
 // scattered with atomics as pass A2 scatters it, so the source pass reads
 // the same columns bit for bit.  e.fA / e.gA hold the time level that
-// carries the weight (no blending).
-template <bool kScalar>
+// carries the weight.  kShell: patch runs of a ghost shell (small boxes, the
+// x-plane runs from the staged copies, both time levels blended with
+// kBlend), as the forward prior-mapping takes them.
+template <bool kScalar, bool kShell = false, bool kBlend = false>
 __global__ void __launch_bounds__(256) k_exadj_tiled(const ExchAdjArgs a, const GatherWs g,
                                                      const int32_t* runs)
 {
-    __shared__ TileLds lds;
     const ExchArgs& e = a.e;
     TileTarget T;
     float v[27], gi[QS];
-    if (!tile_interp<float, kScalar>(e, runs, lds, T, v, gi)) return;
+    if constexpr (kShell) {
+        __shared__ ShellLds lds;
+        if (!tile_interp<float, kScalar, kBlend, kShellLoads, kShellPlanes, true>(e, runs, lds, T, v, gi))
+            return;
+    } else {
+        __shared__ TileLds lds;
+        if (!tile_interp<float, kScalar>(e, runs, lds, T, v, gi)) return;
+    }
     if (!T.active) return;
     const int c = T.c;
     float lam[27], mu[QS] = {0, 0, 0, 0, 0, 0, 0};
@@ -1009,7 +1017,7 @@ static int launch_exchange_adjoint(const cslbm_level* src, const void* fA, const
                                    const int32_t* cells, int32_t n_cells, const GatherWs* gw,
                                    hipStream_t stream, const int32_t* runs = nullptr,
                                    int32_t n_runs = 0, const cslbm_scale* stage_sc = nullptr,
-                                   bool staged = false)
+                                   bool staged = false, bool shell = false)
 {
     if (n_cells == 0) return CSLBM_OK;
     const bool scalar = gA != nullptr && mu_d != nullptr;
@@ -1044,18 +1052,34 @@ static int launch_exchange_adjoint(const cslbm_level* src, const void* fA, const
         const int64_t n_box = (int64_t)sb.nx * sb.ny * sb.nz;
         const dim3 sgrid(grid_for(n_box > 0 ? n_box : 1));
         const bool blend = a.ca != 0.0f && a.cb != 0.0f;
-        if (runs && n_runs > 0 && !blend && !node && a.e.speriodic == 0) {
+        if (runs && n_runs > 0 && (shell || !blend) && !node && a.e.speriodic == 0 && !a.e.sb.table &&
+            !a.e.db.table) {
             // passes A1 and A2 fused, one workgroup per run
             ExchAdjArgs t = a;
             if (a.ca == 0.0f) {
                 t.e.fA = t.e.fB;
                 t.e.gA = t.e.gB;
+                for (int sgi = 0; sgi < t.e.n_staged; ++sgi) {
+                    t.e.st[sgi].fA = t.e.st[sgi].fB;
+                    t.e.st[sgi].gA = t.e.st[sgi].gB;
+                }
             }
             const dim3 rgrid((unsigned)n_runs);
-            if (scalar)
+            if (shell && blend) {
+                if (scalar)
+                    hipLaunchKernelGGL((k_exadj_tiled<true, true, true>), rgrid, block, 0, stream, t, g, runs);
+                else
+                    hipLaunchKernelGGL((k_exadj_tiled<false, true, true>), rgrid, block, 0, stream, t, g, runs);
+            } else if (shell) {
+                if (scalar)
+                    hipLaunchKernelGGL((k_exadj_tiled<true, true, false>), rgrid, block, 0, stream, t, g, runs);
+                else
+                    hipLaunchKernelGGL((k_exadj_tiled<false, true, false>), rgrid, block, 0, stream, t, g, runs);
+            } else if (scalar) {
                 hipLaunchKernelGGL(k_exadj_tiled<true>, rgrid, block, 0, stream, t, g, runs);
-            else
+            } else {
                 hipLaunchKernelGGL(k_exadj_tiled<false>, rgrid, block, 0, stream, t, g, runs);
+            }
             if (scalar)
                 launch_sources<true, false>(a, g, sb, kg, sgrid, stream);
             else
@@ -1440,7 +1464,8 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
         // ghost shell of the interpolated state, mapped at weight 1
         rc = launch_exchange_adjoint(P, A[p], B[p], gA[p], gB[p], 1.0, L, lamR, muR, W.lamA[p].f,
                                      lam[p], W.lamA[p].g, scalar ? mu[p] : nullptr, sc.ghost_cells,
-                                     sc.n_ghost, gw, stream, nullptr, 0, &sc, staged);
+                                     sc.n_ghost, gw, stream, sc.ghost_tiles, sc.n_ghost_tiles, &sc, staged,
+                                     true);
         if (rc) return rc;
         // last sub-step: R = l0 cur_1 + l1 cur_l + l2 step(cur_l), or R = step(cur_last)
         const int64_t nf = (int64_t)Q * L->plane, ngs = (int64_t)QS * L->plane;
@@ -1471,7 +1496,7 @@ int cslbm_multiscale_adjoint_step(const cslbm_hierarchy* H, const void* const* f
             rc = launch_exchange_adjoint(P, A[p], B[p], gA[p], gB[p], prior_weight(k, ss.l, ss.alpha), L, lc.f,
                                          lc.g, W.lamA[p].f, lam[p], W.lamA[p].g,
                                          scalar ? mu[p] : nullptr, sc.ghost_cells, sc.n_ghost, gw,
-                                         stream, nullptr, 0, &sc, staged);
+                                         stream, sc.ghost_tiles, sc.n_ghost_tiles, &sc, staged, true);
             if (rc) return rc;
             if (k == 1) break;
             const Buf out = ((k - 2) % 2 == 0) ? out_final : W.t2[i];

@@ -92,28 +92,38 @@ def post_cells(coarse_kinds: np.ndarray, coarse_shape, coarse_origin, coarse_dx,
 def check_prior_stencils(parent_kinds, parent_shape, parent_origin, parent_dx, parent_periodic,
                          fine_shape, fine_origin, fine_dx, ghosts: np.ndarray):
     """Every ghost of a finer scale must interpolate from FLUID cells of its
-    parent (inside the box on non-periodic axes)."""
+    parent (inside the box on non-periodic axes).  The stencil is separable:
+    per axis and fine index, the parent index of each corner, whether it
+    lies inside and whether its weight is non-zero (the product of the
+    three axes' weights is non-zero exactly when each is)."""
+    g = np.asarray(ghosts, np.int64)
     fnx, fny, _ = fine_shape
-    gx, gy, gz = ghosts % fnx, (ghosts // fnx) % fny, ghosts // (fnx * fny)
-    pts = np.stack([fine_origin[0] + gx * fine_dx, fine_origin[1] + gy * fine_dx,
-                    fine_origin[2] + gz * fine_dx])
-    base, t = _stencil(pts, parent_origin, parent_dx, parent_shape)
-    for corner in range(8):
-        o = np.array([corner & 1, (corner >> 1) & 1, (corner >> 2) & 1])
-        wt = np.ones(ghosts.size)
-        for a in range(3):
-            wt *= t[a] if o[a] else 1.0 - t[a]
-        idx = base + o[:, None]
-        for a in range(3):
+    coord = (g % fnx, (g // fnx) % fny, g // (fnx * fny))
+    pidx, inside, need = [], [], []
+    for a in range(3):
+        q = (fine_origin[a] + np.arange(fine_shape[a]) * fine_dx - parent_origin[a]) / parent_dx
+        base = np.floor(q)
+        t = q - base
+        base = base.astype(np.int64)
+        per = []
+        for o in (0, 1):
+            idx = base + o
             if parent_periodic & (1 << a):
-                idx[a] %= parent_shape[a]
-        inside = np.all((idx >= 0) & (idx < np.array(parent_shape)[:, None]), axis=0)
-        need = wt != 0.0
-        if np.any(need & ~inside):
+                idx %= parent_shape[a]
+            ok = (idx >= 0) & (idx < parent_shape[a])
+            per.append((np.where(ok, idx, 0)[coord[a]], ok[coord[a]], ((t if o else 1.0 - t) != 0.0)[coord[a]]))
+        pidx.append([p_[0] for p_ in per])
+        inside.append([p_[1] for p_ in per])
+        need.append([p_[2] for p_ in per])
+    kinds = np.asarray(parent_kinds)
+    for corner in range(8):
+        o = (corner & 1, (corner >> 1) & 1, (corner >> 2) & 1)
+        nd = need[0][o[0]] & need[1][o[1]] & need[2][o[2]]
+        ins = inside[0][o[0]] & inside[1][o[1]] & inside[2][o[2]]
+        if np.any(nd & ~ins):
             raise ValueError("a ghost cell's prior-mapping stencil leaves its parent box")
-        pc = idx[0] + parent_shape[0] * (idx[1] + parent_shape[1] * idx[2])
-        pc = np.where(inside, pc, 0)
-        if np.any(need & (parent_kinds[pc] != FLUID)):
+        pc = pidx[0][o[0]] + parent_shape[0] * (pidx[1][o[1]] + parent_shape[1] * pidx[2][o[2]])
+        if np.any(nd & (kinds[pc] != FLUID)):
             raise ValueError("a ghost cell's prior-mapping stencil touches a non-fluid parent cell")
 
 

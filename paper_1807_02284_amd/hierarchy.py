@@ -287,13 +287,17 @@ def plate_tile_runs(cells: np.ndarray, shape, ratio: float):
     left = np.ones(c.size, bool)
     runs = []
 
+    ascending = c.size < 2 or bool(np.all(c[1:] > c[:-1]))
+
     def tiles(idx, t):
         """the tiles of t over the entries idx that hold enough of them"""
         k = [(xyz[d][idx] - xyz[d][idx].min()) // t[d] for d in range(3)]
-        o = np.lexsort((xyz[0][idx], xyz[1][idx], xyz[2][idx], k[0], k[1], k[2]))
+        key = (k[2] * (int(k[1].max()) + 1) + k[1]) * (int(k[0].max()) + 1) + k[0]
+        # tiles in (z, y, x) order, each tile's cells in box order
+        o = np.argsort(key, kind="stable") if ascending else np.lexsort((c[idx], key))
         idx = idx[o]
-        key = np.stack([kk[o] for kk in k])
-        st = np.flatnonzero(np.r_[True, np.any(key[:, 1:] != key[:, :-1], axis=0)])
+        key = key[o]
+        st = np.flatnonzero(np.r_[True, key[1:] != key[:-1]])
         en = np.r_[st[1:], idx.size]
         keep = POST_PLATE_KEEP * t[0] * t[1] * t[2]
         return [idx[a:b] for a, b in zip(st, en) if b - a >= keep]

@@ -812,6 +812,65 @@ __global__ void __launch_bounds__(256) k_zero(float* p, int64_t n)
     if (i < n) p[i] = 0.0f;
 }
 
+// Pass A2 of one target whose interpolated state (v in tensor order, gi)
+// is in registers: the map's vector-Jacobian product into column k (index
+// map and corner flags as pass A1 sets them), or scattered with atomics for
+// a target outside the gather, as pass A2 does (k_exadj_tiled keeps its own
+// copy of these steps: through this function the compiler gave it 278
+// VGPRs instead of 182).
+template <bool kScalar, bool kNode>
+__device__ __forceinline__ void vjp_in_registers(const ExchAdjArgs& a, const GatherWs& g, int k, int c,
+                                                 const float (&v)[27], const float (&gi)[QS])
+{
+    const ExchArgs& e = a.e;
+    constexpr int kCorners = kNode ? 1 : 8;
+    float lam[27], mu[QS] = {0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lam[tensor_slot(i)] = a.lam_d[i * e.dplane + c];
+    if (kScalar)
+#pragma unroll
+        for (int i = 0; i < QS; ++i) mu[i] = a.mu_d[i * e.dplane + c];
+    clear_column<kScalar>(a.lam_d, a.mu_d, e.dplane, c);
+    float vb[27], gb[QS];
+    exchange_map_adjoint<kScalar>(v, gi, e.kappa, e.kappa_s, lam, mu, vb, gb);
+    int ix[2], iy[2], iz[2];
+    float t[3];
+    const bool interior = target_corners<kNode>(e, c, ix, iy, iz, t);
+    if (interior) {
+        const int64_t n_t = e.n_cells;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) g.vb[i * n_t + k] = vb[tensor_slot(i)];
+        if (kScalar)
+#pragma unroll
+            for (int i = 0; i < QS; ++i) g.vb[(Q + i) * n_t + k] = gb[i];
+        g.map[c] = k;
+#pragma unroll
+        for (int corner = 0; corner < kCorners; ++corner)
+            g.touched[ix[corner & 1] + (int64_t)e.snx * (iy[(corner >> 1) & 1] +
+                                                         (int64_t)e.sny * iz[(corner >> 2) & 1])] = 1;
+        return;
+    }
+    for (int corner = 0; corner < kCorners; ++corner) {
+        const float wt = corner_weight(t, corner);
+        if (wt == 0.0f) continue;
+        const int64_t sc = ix[corner & 1] + (int64_t)e.snx * (iy[(corner >> 1) & 1] +
+                                                              (int64_t)e.sny * iz[(corner >> 2) & 1]);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const float b = wt * vb[tensor_slot(i)];
+            if (a.ca != 0.0f) atomicAdd(a.lam_a + i * e.splane + sc, a.ca * b);
+            if (a.cb != 0.0f) atomicAdd(a.lam_b + i * e.splane + sc, a.cb * b);
+        }
+        if (kScalar)
+#pragma unroll
+            for (int i = 0; i < QS; ++i) {
+                const float b = wt * gb[i];
+                if (a.ca != 0.0f) atomicAdd(a.mu_a + i * e.splane + sc, a.ca * b);
+                if (a.cb != 0.0f) atomicAdd(a.mu_b + i * e.splane + sc, a.cb * b);
+            }
+    }
+}
+
 // Passes A1 and A2 in one for a post-mapping list in tile runs (tile.hpp):
 // the run's source box is staged through LDS, every target's interpolated
 // state stays in registers, the map's vector-Jacobian product follows, and
@@ -883,6 +942,34 @@ __global__ void __launch_bounds__(256) k_exadj_tiled(const ExchAdjArgs a, const 
                 if (a.cb != 0.0f) atomicAdd(a.mu_b + i * e.splane + sc, a.cb * b);
             }
     }
+}
+
+// Passes A1 and A2 in one for a list whose targets are all source lattice
+// points (one corner of weight 1 each) at one time level: e.fA / e.gA hold
+// the level that carries the weight.  The interpolated state is formed as
+// pass A1 forms it and kept in registers.
+template <bool kScalar>
+__global__ void __launch_bounds__(256) k_exadj_node(const ExchAdjArgs a, const GatherWs g)
+{
+    const ExchArgs& e = a.e;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= e.n_cells) return;
+    const int c = e.cells[k];
+    int ix[2], iy[2], iz[2];
+    float t[3];
+    target_corners<true>(e, c, ix, iy, iz, t);
+    const float wt = corner_weight(t, 0);
+    const int64_t sc = ix[0] + (int64_t)e.snx * (iy[0] + (int64_t)e.sny * iz[0]);
+    const float* fA = static_cast<const float*>(e.fA);
+    float v[27], gi[QS] = {0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < 27; ++q) v[q] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[tensor_slot(i)] += wt * fA[i * e.splane + sc];
+    if (kScalar)
+#pragma unroll
+        for (int i = 0; i < QS; ++i) gi[i] += wt * e.gA[i * e.splane + sc];
+    vjp_in_registers<kScalar, true>(a, g, k, c, v, gi);
 }
 
 static unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -1086,6 +1173,23 @@ static int launch_exchange_adjoint(const cslbm_level* src, const void* fA, const
                 launch_sources<false, false>(a, g, sb, kg, sgrid, stream);
             hipLaunchKernelGGL(k_exadj_reset, grid, block, 0, stream, g.map, cells, n_cells);
             return check_launch("k_exchange_adjoint (tiled gather)");
+        }
+        if (node && !blend && a.e.n_staged == 0) {
+            // passes A1 and A2 fused, one thread per target
+            ExchAdjArgs t = a;
+            if (a.ca == 0.0f) {
+                t.e.fA = t.e.fB;
+                t.e.gA = t.e.gB;
+            }
+            if (scalar) {
+                hipLaunchKernelGGL(k_exadj_node<true>, grid, block, 0, stream, t, g);
+                launch_sources<true, true>(a, g, sb, kg, sgrid, stream);
+            } else {
+                hipLaunchKernelGGL(k_exadj_node<false>, grid, block, 0, stream, t, g);
+                launch_sources<false, true>(a, g, sb, kg, sgrid, stream);
+            }
+            hipLaunchKernelGGL(k_exadj_reset, grid, block, 0, stream, g.map, cells, n_cells);
+            return check_launch("k_exchange_adjoint (node gather)");
         }
         // the interpolation pass runs the staged segments' blocks first
         int64_t iblocks = (n_cells - a.e.main_first + 255) / 256;

@@ -352,10 +352,11 @@ def shell_tile_runs(cells: np.ndarray, shape, ratio: float, xface: bool = False)
     ratios 3/4 and 2/3; see _plate_tile), over a grid that starts at the
     smallest listed coordinate.  A cell on the list's first or last z plane
     goes to a tile normal to z, else one on its first or last y plane to a
-    tile normal to y, else (not a shell cell) to a tile normal to z in its
-    own plane; with ``xface`` (the entries of one of the shell's planes
-    normal to x, which read a staged copy of the parent) every cell goes to
-    a tile normal to x.  Every tile is a run, partly filled ones included.
+    tile normal to y, else one on its first or last x plane to a tile normal
+    to x, else (not a shell cell) to a tile normal to z in its own plane;
+    with ``xface`` (the entries of one of the shell's planes normal to x,
+    which read a staged copy of the parent) every cell goes to a tile normal
+    to x.  Every tile is a run, partly filled ones included.
     ``ratio`` is the shell's spacing over its parent's (< 1 for a finer
     scale).  Returns (cells in run order, int32 offsets with one entry more
     than there are runs)."""
@@ -371,9 +372,15 @@ def shell_tile_runs(cells: np.ndarray, shape, ratio: float, xface: bool = False)
     else:
         tz = _plate_tile(2, ratio, 1, SHELL_TILE_BUFFER)
         ty = _plate_tile(1, ratio, 1, SHELL_TILE_BUFFER)
-        on_y = ((y == 0) | (y == y.max())) & ~((z == 0) | (z == z.max()))
-        key = [on_y.astype(np.int64), np.where(on_y, y, z), x // np.where(on_y, ty[0], tz[0]),
-               np.where(on_y, z // ty[2], y // tz[1])]
+        tx = _plate_tile(0, ratio, 1, SHELL_TILE_BUFFER)
+        on_z = (z == 0) | (z == z.max())
+        on_y = ((y == 0) | (y == y.max())) & ~on_z
+        # the x planes, when they are listed here too (no staged copies)
+        on_x = ((x == 0) | (x == x.max())) & ~on_z & ~on_y
+        face = np.where(on_x, 2, on_y.astype(np.int64))
+        key = [face, np.select([on_x, on_y], [x, y], z),
+               np.select([on_x, on_y], [y // tx[1], x // ty[0]], x // tz[0]),
+               np.select([on_x, on_y], [z // tx[2], z // ty[2]], y // tz[1])]
     k = key[0]
     for part in key[1:]:
         k = k * (int(part.max()) + 1) + part
